@@ -1,0 +1,244 @@
+"""ctypes front-end of the FP64 CPU oracle (oracle/wm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline leg of the benchmark use it; the product package never imports it.
+It accepts the plain data containers of the seeded input generators
+(parameter sets, descriptor arrays, shapes) and returns NumPy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+N_THETA = 24
+
+
+class OrcParams(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "n_levels", "n_cu", "n_simd", "wave", "vgpr_simd", "vgpr_gran", "waves_simd",
+        "lds_cu", "lds_gran", "bytes_inflight_wave", "mwp", "cwp", "combine", "pad_")] + [
+        ("f_clk", C.c_double), ("w_lo_mib", C.c_double), ("c_llc_mib", C.c_double),
+        ("theta", C.c_double * N_THETA)]
+
+
+class OrcDesc(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "F", "B", "r1", "r2", "r3", "K", "u", "W", "vgpr", "lds", "gpack", "grid")] + [
+        ("n", C.c_int64)]
+
+
+class OrcTrace(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("stage", C.c_int32), ("eta_saturated", C.c_int32),
+                ("pad_", C.c_int32)] + [(n, C.c_int64) for n in ("k", "o", "n_wf", "n_r", "n_eff")] + [
+        ("h", C.c_double * 3), ("s", C.c_double * 4)] + [(n, C.c_double) for n in (
+            "S", "Lam", "bw_hbm_eff", "blend_e", "T_c", "T_b", "T_lat", "T_m", "eta", "T_ov", "T")]
+
+
+class OrcTile(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("pad_", C.c_int32)] + [
+        (n, C.c_int64) for n in ("G", "Ks", "g", "v", "s")] + [
+        (n, C.c_double) for n in ("F", "B", "U", "r2")]
+
+
+class OrcCalibOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("pad_", C.c_int32)] + [
+        (n, C.c_double) for n in ("lr", "lr_final", "beta1", "beta2", "eps")] + [
+        ("free_mask", C.c_uint32), ("pad2_", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P, D = C.POINTER(OrcParams), C.POINTER(OrcDesc)
+        vp = C.c_void_p
+        L.orc_occupancy.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
+        L.orc_occupancy.restype = C.c_int64
+        L.orc_h_llc.argtypes = [P, C.c_double]
+        L.orc_h_llc.restype = C.c_double
+        L.orc_bw_hbm_eff.argtypes = [P, C.c_double]
+        L.orc_bw_hbm_eff.restype = C.c_double
+        L.orc_eval.argtypes = [P] + [C.c_double] * 8 + [C.c_int64] * 4 + [C.POINTER(OrcTrace), vp]
+        L.orc_eval.restype = None
+        L.orc_predict.argtypes = [P, D, vp, vp]
+        L.orc_trace.argtypes = [P, D, vp]
+        L.orc_jacobian.argtypes = [P, D, vp]
+        L.orc_roofline.argtypes = [P, D, vp]
+        L.orc_weighted_grad.argtypes = [P, D, vp, C.c_int, vp]
+        L.orc_calibrate.argtypes = [P, D, vp, C.POINTER(OrcCalibOpts), P, vp]
+        L.orc_calibrate.restype = C.c_int
+        L.orc_tile_derive.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
+                                      C.c_int64, C.POINTER(OrcTile)]
+        L.orc_tile_cost.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32]
+        L.orc_tile_cost.restype = C.c_double
+        L.orc_tile_costs.argtypes = [P, C.c_int64] + [vp] * 7
+        L.orc_select_tile.argtypes = [P, C.c_int64] + [vp] * 9
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+def params(p) -> OrcParams:
+    """Marshal a parameter set (any object with the generator's attributes)."""
+    o = OrcParams()
+    for f in ("n_levels", "n_cu", "n_simd", "wave", "vgpr_simd", "vgpr_gran", "waves_simd",
+              "lds_cu", "lds_gran", "bytes_inflight_wave", "mwp", "cwp", "combine"):
+        setattr(o, f, int(getattr(p, f)))
+    o.f_clk = float(p.f_clk)
+    o.w_lo_mib = float(p.w_lo_mib)
+    o.c_llc_mib = float(p.c_llc_mib)
+    for j in range(N_THETA):
+        o.theta[j] = float(p.theta[j])
+    return o
+
+
+def theta_of(o: OrcParams) -> np.ndarray:
+    return np.array([o.theta[j] for j in range(N_THETA)])
+
+
+_FLOATS = ("F", "B", "r1", "r2", "r3", "K", "u", "W")
+_INTS = ("vgpr", "lds", "gpack", "grid")
+
+
+def _desc(d):
+    keep = []
+    o = OrcDesc()
+    for f in _FLOATS:
+        a = np.ascontiguousarray(getattr(d, f), dtype=np.float32)
+        keep.append(a)
+        setattr(o, f, a.ctypes.data)
+    for f in _INTS:
+        a = np.ascontiguousarray(getattr(d, f), dtype=np.int32)
+        keep.append(a)
+        setattr(o, f, a.ctypes.data)
+    o.n = int(keep[0].shape[0])
+    return o, keep
+
+
+def predict(p, d):
+    """FP64 predicted time T [s] and occupancy (WGs/CU; -1 invalid, 0 infeasible)."""
+    o, keep = _desc(d)
+    T = np.empty(o.n, np.float64)
+    occ = np.empty(o.n, np.int32)
+    lib().orc_predict(C.byref(params(p)), C.byref(o), T.ctypes.data, occ.ctypes.data)
+    return T, occ
+
+
+def trace(p, d):
+    """Per-descriptor intermediates as a dict of arrays."""
+    o, keep = _desc(d)
+    buf = (OrcTrace * max(o.n, 1))()
+    lib().orc_trace(C.byref(params(p)), C.byref(o), C.addressof(buf))
+    arr = np.ctypeslib.as_array(buf)[: o.n]
+    return {name: np.array(arr[name]) for name in arr.dtype.names if not name.startswith("pad")}
+
+
+def eval_one(p, F, B, r1, r2, r3, K, u, W, v, s, gpack, G, with_grad=False):
+    tr = OrcTrace()
+    J = np.zeros(N_THETA) if with_grad else None
+    lib().orc_eval(C.byref(params(p)), float(F), float(B), float(r1), float(r2), float(r3),
+                   float(K), float(u), float(W), int(v), int(s), int(gpack), int(G), C.byref(tr),
+                   J.ctypes.data if with_grad else None)
+    return (tr, J) if with_grad else tr
+
+
+def occupancy(p, v, s, g):
+    k = C.c_int64()
+    o = lib().orc_occupancy(C.byref(params(p)), int(v), int(s), int(g), C.byref(k))
+    return int(o), int(k.value)
+
+
+def h_llc(p, W):
+    return lib().orc_h_llc(C.byref(params(p)), float(W))
+
+
+def bw_hbm_eff(p, W):
+    return lib().orc_bw_hbm_eff(C.byref(params(p)), float(W))
+
+
+def jacobian(p, d):
+    o, keep = _desc(d)
+    J = np.empty((o.n, N_THETA), np.float64)
+    lib().orc_jacobian(C.byref(params(p)), C.byref(o), J.ctypes.data)
+    return J
+
+
+def roofline(p, d):
+    o, keep = _desc(d)
+    T = np.empty(o.n, np.float64)
+    lib().orc_roofline(C.byref(params(p)), C.byref(o), T.ctypes.data)
+    return T
+
+
+def vjp(p, d, dL_dT):
+    o, keep = _desc(d)
+    w = np.ascontiguousarray(dL_dT, dtype=np.float32)
+    out = np.zeros(26)
+    lib().orc_weighted_grad(C.byref(params(p)), C.byref(o), w.ctypes.data, 0, out.ctypes.data)
+    return out[2:]
+
+
+def loss_grad(p, d, measured):
+    """(mean relative error, count, dL/dtheta[24]) in FP64."""
+    o, keep = _desc(d)
+    m = np.ascontiguousarray(measured, dtype=np.float32)
+    out = np.zeros(26)
+    lib().orc_weighted_grad(C.byref(params(p)), C.byref(o), m.ctypes.data, 1, out.ctypes.data)
+    return float(out[0]), int(out[1]), out[2:].copy()
+
+
+def calibrate(p0, d, measured, steps=500, lr=0.02, lr_final=0.0, beta1=0.9, beta2=0.999,
+              eps=1e-8, free_mask=0xFFFFFF):
+    o, keep = _desc(d)
+    m = np.ascontiguousarray(measured, dtype=np.float32)
+    opts = OrcCalibOpts(steps=steps, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2,
+                        eps=eps, free_mask=free_mask)
+    pout = OrcParams()
+    hist = np.zeros(max(steps, 1))
+    rc = lib().orc_calibrate(C.byref(params(p0)), C.byref(o), m.ctypes.data, C.byref(opts),
+                             C.byref(pout), hist.ctypes.data)
+    return rc, theta_of(pout), hist[:steps]
+
+
+def tile_derive(M, N, K, t, code, wave=64):
+    o = OrcTile()
+    lib().orc_tile_derive(int(M), int(N), int(K), int(t), int(code), int(wave), C.byref(o))
+    return o
+
+
+def tile_cost(p, M, N, K, t, code):
+    return lib().orc_tile_cost(C.byref(params(p)), int(M), int(N), int(K), int(t), int(code))
+
+
+def _shape_arrays(sh):
+    a = [np.ascontiguousarray(x, dtype=np.int32) for x in (sh.M, sh.N, sh.K, sh.dtype, sh.cand_off)]
+    a.append(np.ascontiguousarray(sh.cand_code, dtype=np.uint32))
+    return a
+
+
+def tile_costs(p, sh):
+    a = _shape_arrays(sh)
+    cost = np.empty(a[-1].shape[0], np.float64)
+    lib().orc_tile_costs(C.byref(params(p)), sh.n, *[x.ctypes.data for x in a], cost.ctypes.data)
+    return cost
+
+
+def select_tile(p, sh):
+    a = _shape_arrays(sh)
+    n = sh.n
+    best = np.empty(n, np.int32)
+    cost = np.empty(n, np.float64)
+    nt = np.empty(n, np.uint8)
+    lib().orc_select_tile(C.byref(params(p)), n, *[x.ctypes.data for x in a], best.ctypes.data,
+                          cost.ctypes.data, nt.ctypes.data)
+    return best, cost, nt

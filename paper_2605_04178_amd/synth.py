@@ -1,0 +1,325 @@
+"""Seeded synthetic inputs for the CDNA wavefront-centric execution-time model.
+
+This module draws random numbers and packs them into arrays; it performs none
+of the model's arithmetic (no occupancy, traffic split, stage times or tile
+derivation). Both the FP64 oracle and the HIP path consume what it returns.
+
+The paper evaluates its model on measured kernels (microbenchmarks, Rodinia,
+SPEChpc; Section V) that are not available here, so these sweeps stand in for
+them. Value ranges follow the paper where it prints them: cache levels and
+latencies (Table "parameters"), 304 CUs / 64 KB LDS / 32 waves per CU
+(Table "arch-params"), utilisation 0.4-0.7 (Table "model-summary"),
+tau_interf = 50 us and tau_sync = 3 us (Table "parameters"), barrier and
+coherence cost 100-200 ns (Table "model-summary").
+
+Everything is NumPy PCG64 seeded; the same seed always gives the same bytes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# parameter-vector slot names (Section IV-B symbols); 24 slots
+# ---------------------------------------------------------------------------
+THETA_NAMES = [
+    "BW_L1", "BW_L2", "BW_LLC", "BW_HBM",          # 0-3   bytes/s
+    "Lat_L1", "Lat_L2", "Lat_LLC", "Lat_HBM",      # 4-7   cycles
+    "P_fp64", "P_fp32", "P_bf16", "P_fp8", "P_int8",  # 8-12 flop/s
+    "T_launch",                                    # 13    s
+    "tau_wg",                                      # 14    s per workgroup
+    "tau_bar",                                     # 15    s per WG round x step
+    "tau_interf",                                  # 16    s per extra concurrent kernel
+    "tau_gpu",                                     # 17    s per extra device
+    "tau_fusion",                                  # 18    s if fused
+    "tau_sync",                                    # 19    s per host sync
+    "alpha", "beta",                               # 20-21 LLC hit-rate exponents
+    "w0", "B_peak",                                # 22-23 working-set blend
+]
+N_THETA = 24
+MIB = float(1 << 20)
+
+# gpack bit layout of the int32 descriptor field: WG threads, dtype, counts
+GPACK_G_BITS = 11
+GPACK_DTYPE_SHIFT = 11
+GPACK_NCONC_SHIFT = 14
+GPACK_NDEV_SHIFT = 17
+GPACK_FUSED_SHIFT = 20
+GPACK_NSYNC_SHIFT = 21
+
+# tile-candidate code layout: mt | nt<<2 | kd<<4 | (waves-1)<<6
+TILE_MN = (32, 64, 128, 256)
+TILE_KD = (16, 32, 64)
+N_TILES = 4 * 4 * 3 * 8
+
+
+@dataclasses.dataclass
+class ParamSet:
+    """Structural integers plus the 24-slot parameter vector theta."""
+    n_levels: int = 4
+    n_cu: int = 304
+    n_simd: int = 4
+    wave: int = 64
+    vgpr_simd: int = 512
+    vgpr_gran: int = 8
+    waves_simd: int = 8
+    lds_cu: int = 65536
+    lds_gran: int = 512
+    bytes_inflight_wave: int = 16384
+    mwp: int = 0
+    cwp: int = 0
+    combine: int = 0            # 0 = max of stages, 1 = occupancy-overlap step
+    f_clk: float = 2.1e9
+    w_lo_mib: float = 205.0
+    c_llc_mib: float = 256.0
+    theta: List[float] = dataclasses.field(default_factory=lambda: [0.0] * N_THETA)
+
+    def copy(self, **kw) -> "ParamSet":
+        d = dataclasses.asdict(self)
+        d["theta"] = list(self.theta)
+        d.update(kw)
+        return ParamSet(**d)
+
+
+@dataclasses.dataclass
+class Descriptors:
+    """Structure-of-arrays kernel descriptors: 8 float32 + 4 int32 arrays."""
+    F: np.ndarray
+    B: np.ndarray
+    r1: np.ndarray
+    r2: np.ndarray
+    r3: np.ndarray
+    K: np.ndarray
+    u: np.ndarray
+    W: np.ndarray
+    vgpr: np.ndarray
+    lds: np.ndarray
+    gpack: np.ndarray
+    grid: np.ndarray
+
+    FLOAT_FIELDS = ("F", "B", "r1", "r2", "r3", "K", "u", "W")
+    INT_FIELDS = ("vgpr", "lds", "gpack", "grid")
+
+    @property
+    def n(self) -> int:
+        return int(self.F.shape[0])
+
+    def fields(self):
+        return [getattr(self, f) for f in self.FLOAT_FIELDS + self.INT_FIELDS]
+
+    def slice(self, a: int, b: int) -> "Descriptors":
+        return Descriptors(*[x[a:b] for x in self.fields()])
+
+    def take(self, idx) -> "Descriptors":
+        return Descriptors(*[np.ascontiguousarray(x[idx]) for x in self.fields()])
+
+    @staticmethod
+    def concat(parts) -> "Descriptors":
+        names = Descriptors.FLOAT_FIELDS + Descriptors.INT_FIELDS
+        return Descriptors(*[np.concatenate([getattr(p, f) for p in parts]) for f in names])
+
+
+def pack_gpack(g, dtype, n_conc=1, n_dev=1, fused=0, n_sync=0):
+    """Bit-pack the small integer descriptor fields (layout above)."""
+    g = np.asarray(g, dtype=np.int64)
+    v = (g | (np.asarray(dtype, np.int64) << GPACK_DTYPE_SHIFT)
+         | ((np.asarray(n_conc, np.int64) - 1) << GPACK_NCONC_SHIFT)
+         | ((np.asarray(n_dev, np.int64) - 1) << GPACK_NDEV_SHIFT)
+         | (np.asarray(fused, np.int64) << GPACK_FUSED_SHIFT)
+         | (np.asarray(n_sync, np.int64) << GPACK_NSYNC_SHIFT))
+    return v.astype(np.int32)
+
+
+def _logu(rng, lo, hi, size=None):
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size))
+
+
+# ---------------------------------------------------------------------------
+# parameter sets
+# ---------------------------------------------------------------------------
+def param_set(seed: int = 0, n_levels: int = 4, combine: int = 0) -> ParamSet:
+    """One CDNA-style parameter set with seeded synthetic values.
+
+    Bandwidths: 4 x log-U[2, 80] TB/s sorted fast-to-slow (L1 .. HBM);
+    latencies: 4 x U[50, 800] cycles sorted ascending; five dtype peaks;
+    overhead constants in the ranges quoted in the module docstring.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    th = [0.0] * N_THETA
+    bw = np.sort(_logu(rng, 2e12, 80e12, 4))[::-1]
+    lat = np.sort(rng.uniform(50.0, 800.0, 4))
+    th[0:4] = [float(x) for x in bw]
+    th[4:8] = [float(x) for x in lat]
+    th[8] = float(_logu(rng, 30e12, 160e12))
+    th[9] = float(_logu(rng, 60e12, 320e12))
+    th[10] = float(_logu(rng, 500e12, 2600e12))
+    th[11] = float(_logu(rng, 1000e12, 5200e12))
+    th[12] = float(_logu(rng, 1000e12, 5200e12))
+    th[13] = float(rng.uniform(2e-6, 12e-6))
+    th[14] = float(_logu(rng, 1e-9, 20e-9))
+    th[15] = float(_logu(rng, 50e-9, 200e-9))
+    th[16] = float(_logu(rng, 10e-6, 100e-6))
+    th[17] = float(_logu(rng, 10e-6, 100e-6))
+    th[18] = float(_logu(rng, 1e-6, 10e-6))
+    th[19] = float(_logu(rng, 1e-6, 10e-6))
+    th[20] = float(rng.uniform(0.5, 3.0))
+    th[21] = float(rng.uniform(0.5, 2.0))
+    th[22] = float(_logu(rng, 16 * MIB, 512 * MIB))
+    th[23] = float(th[3] * rng.uniform(1.1, 1.6))
+    return ParamSet(n_levels=n_levels, combine=combine, theta=th)
+
+
+def mi300a_like() -> ParamSet:
+    """Values the paper prints for MI300A (Tables "arch-params" and
+    "parameters"): 304 CUs, Infinity Cache 17.2 TB/s, HBM 5.3 TB/s,
+    latencies 5/50/150/400 cycles, FP8 1307 TF, FP64 61.3 TF, 64 KB LDS,
+    32 waves per CU, tau_interf 50 us, tau_sync 3 us, coherence 100-200 ns.
+    L1/L2 bandwidths, the FP32/BF16/INT8 peaks, T_launch and the remaining
+    overheads are not printed; the values below for them are placeholders
+    (FP32 and BF16 scaled from FP64/FP8 by MFMA width)."""
+    th = [0.0] * N_THETA
+    th[0:4] = [64e12, 34e12, 17.2e12, 5.3e12]
+    th[4:8] = [5.0, 50.0, 150.0, 400.0]
+    th[8:13] = [61.3e12, 122.6e12, 653.5e12, 1307e12, 1307e12]
+    th[13] = 5e-6
+    th[14] = 5e-9
+    th[15] = 150e-9
+    th[16] = 50e-6
+    th[17] = 50e-6
+    th[18] = 2e-6
+    th[19] = 3e-6
+    th[20] = 1.0
+    th[21] = 1.0
+    th[22] = 64 * MIB
+    th[23] = 5.3e12 * 1.3
+    return ParamSet(n_levels=4, n_cu=304, theta=th)
+
+
+def multi_arch_sets(base_seed: int = 0, n_sets: int = 6, seed0: int = 110) -> List[ParamSet]:
+    """Six architecture variants of the seed-0 base set: 3 or 4 levels,
+    104-304 CUs, bandwidth and peak scales log-U[0.5, 2]."""
+    base = param_set(base_seed)
+    out = []
+    for i in range(n_sets):
+        rng = np.random.Generator(np.random.PCG64(seed0 + i))
+        L = int(rng.integers(3, 5))
+        ncu = int(rng.integers(104, 305))
+        sbw = float(_logu(rng, 0.5, 2.0))
+        spk = float(_logu(rng, 0.5, 2.0))
+        th = list(base.theta)
+        for j in (0, 1, 2, 3, 23):
+            th[j] *= sbw
+        for j in range(8, 13):
+            th[j] *= spk
+        out.append(base.copy(n_levels=L, n_cu=ncu, theta=th))
+    return out
+
+
+def multi_arch_sizes(n_sets: int = 6, seed0: int = 110, lo: int = 1 << 18, hi: int = 1 << 22):
+    out = []
+    for i in range(n_sets):
+        rng = np.random.Generator(np.random.PCG64(10_000 + seed0 + i))
+        out.append(int(round(float(_logu(rng, lo, hi)))))
+    return out
+
+
+def perturb_theta(p: ParamSet, seed: int, factor: float = 1.5, mask=None) -> ParamSet:
+    """theta0 = theta* x exp(U(-ln f, ln f)) on the slots in `mask`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.uniform(-math.log(factor), math.log(factor), N_THETA)
+    th = list(p.theta)
+    for j in range(N_THETA):
+        if mask is None or (mask >> j) & 1:
+            th[j] = th[j] * math.exp(z[j])
+    return p.copy(theta=th)
+
+
+# ---------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------
+def descriptors(n: int, seed: int = 100) -> Descriptors:
+    """Kernel-descriptor sweep: flops log-U[1e6, 1e13], bytes log-U[1e4, 1e11],
+    per-level reuse U(0,1), VGPRs/thread U-int[16, 512], LDS/WG U-int[0, 64 KiB],
+    WG size in {64..1024}, grid round(log-U[1, 2^20]); dtype U{0..4};
+    K round(log-U[1, 4096]); u U[0.4, 0.7]; W = 0 with p = 1/2 else
+    log-U[1 MiB, 4 GiB]; n_conc, n_dev = 1 with p = 1/2 else U{2..8};
+    fused ~ Bernoulli(1/4); n_sync = 0 with p = 1/2 else U{1..15}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f32 = np.float32
+    F = _logu(rng, 1e6, 1e13, n).astype(f32)
+    B = _logu(rng, 1e4, 1e11, n).astype(f32)
+    r1 = rng.random(n, dtype=np.float32)
+    r2 = rng.random(n, dtype=np.float32)
+    r3 = rng.random(n, dtype=np.float32)
+    K = np.round(_logu(rng, 1.0, 4096.0, n)).astype(f32)
+    u = rng.uniform(0.4, 0.7, n).astype(f32)
+    wsel = rng.random(n) < 0.5
+    W = np.where(wsel, 0.0, _logu(rng, MIB, 4096.0 * MIB, n)).astype(f32)
+    vgpr = rng.integers(16, 513, n, dtype=np.int32)
+    lds = rng.integers(0, 65537, n, dtype=np.int32)
+    g = np.array([64, 128, 256, 512, 1024], np.int32)[rng.integers(0, 5, n)]
+    grid = np.round(_logu(rng, 1.0, float(1 << 20), n)).astype(np.int32)
+    dtype = rng.integers(0, 5, n)
+    nconc = np.where(rng.random(n) < 0.5, 1, rng.integers(2, 9, n))
+    ndev = np.where(rng.random(n) < 0.5, 1, rng.integers(2, 9, n))
+    fused = (rng.random(n) < 0.25).astype(np.int64)
+    nsync = np.where(rng.random(n) < 0.5, 0, rng.integers(1, 16, n))
+    gpack = pack_gpack(g, dtype, nconc, ndev, fused, nsync)
+    return Descriptors(F, B, r1, r2, r3, K, u, W, vgpr, lds, gpack, grid)
+
+
+def lognormal_noise(n: int, seed: int = 2, sigma: float = 0.02) -> np.ndarray:
+    """Multiplicative measurement noise exp(sigma * z), z ~ N(0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(sigma * rng.standard_normal(n))
+
+
+# ---------------------------------------------------------------------------
+# GEMM-like shapes and ragged candidate tile lists
+# ---------------------------------------------------------------------------
+def tile_code(mt_code, nt_code, kd_code, wpw):
+    return (np.asarray(mt_code) | (np.asarray(nt_code) << 2) | (np.asarray(kd_code) << 4)
+            | ((np.asarray(wpw) - 1) << 6)).astype(np.uint32)
+
+
+def all_tile_codes() -> np.ndarray:
+    codes = [int(tile_code(a, b, c, w)) for a in range(4) for b in range(4)
+             for c in range(3) for w in range(1, 9)]
+    return np.array(codes, dtype=np.uint32)
+
+
+@dataclasses.dataclass
+class Shapes:
+    M: np.ndarray
+    N: np.ndarray
+    K: np.ndarray
+    dtype: np.ndarray
+    cand_off: np.ndarray   # int32 [n+1], CSR offsets into cand_code
+    cand_code: np.ndarray  # uint32 packed tile codes
+
+    @property
+    def n(self) -> int:
+        return int(self.M.shape[0])
+
+
+def shapes(n: int, seed: int = 102, cmin: int = 8, cmax: int = 96,
+           lo: float = 128.0, hi: float = 16384.0) -> Shapes:
+    """GEMM shapes with M, N, K round(log-U[128, 16384]) and dtype in
+    {fp64, fp32, bf16, fp8}; each gets U-int[8, 96] distinct candidate tiles
+    drawn without replacement from the 384 tiles, in shuffled order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = np.round(_logu(rng, lo, hi, n)).astype(np.int32)
+    N = np.round(_logu(rng, lo, hi, n)).astype(np.int32)
+    K = np.round(_logu(rng, lo, hi, n)).astype(np.int32)
+    dt = rng.integers(0, 4, n).astype(np.int32)
+    cnt = rng.integers(cmin, cmax + 1, n)
+    tiles = all_tile_codes()
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    codes = np.empty(int(off[-1]), np.uint32)
+    for i in range(n):
+        codes[off[i]:off[i + 1]] = tiles[rng.permutation(N_TILES)[:cnt[i]]]
+    return Shapes(M, N, K, dt, off.astype(np.int32), codes)
