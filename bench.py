@@ -1,0 +1,231 @@
+"""Throughput of the CDNA wavefront-model hot path on one MI355X.
+
+One step = one forward sweep (wm_predict) over 2^24 synthetic descriptors in
+HBM (FP32 structure-of-arrays, one parameter set).  `value` is forward
+evaluations per second over the timed steps.  The same JSON line also carries
+the forward+adjoint sweep (wm_loss_grad) over the same descriptors, the tile
+selection sweep (2^16 shapes, ragged 8-96 candidates), device calibration
+(2^20 descriptors, Adam steps in HIP graphs) and the multi-set batched
+calibration, each timed with HIP events on the stream the kernels run on,
+plus the roofline of the forward kernel and the FP64 CPU oracle's rate on a
+bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "model evals/sec (fwd; fwd+adjoint) and % HBM peak at ≤1e-5 rel err vs FP64"
+HBM_PEAK_GBS = 8000.0
+FWD_BYTES = 56      # 8 f32 + 4 i32 read, T f32 + occ i32 written
+ADJ_BYTES = 52      # 8 f32 + 4 i32 + measured f32 read
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup):
+    """(wall ms per step, event ms per step) over `steps` calls after warm-up."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(p, d, seconds=10.0):
+    """The FP64 oracle's forward rate on a bounded sample of the workload."""
+    import oracle
+    n = min(d.n, 1 << 22)
+    sub = d.slice(0, n)
+    oracle.predict(p, sub)          # warm-up (thread pool, page faults)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.predict(p, sub)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds and reps >= 3:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": reps * n / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle predict on the first {n} descriptors of the 2^24 workload, "
+                      f"{reps} repetitions, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--quick", action="store_true", help="forward sweep only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-steps", type=int, default=500)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the batched model "
+              "evaluation shards by descriptor range with no exchange, so run one process per GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_04178_amd import synth, wavemodel as wm
+
+    wm.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device {props.name} CUs={props.multi_processor_count}")
+
+    n = args.n
+    p = synth.param_set(0)
+    log(f"generating {n} descriptors")
+    d = synth.descriptors(n, 101)
+    dd = wm.DeviceDescriptors.from_host(d, dev)
+    T = torch.empty(n, dtype=torch.float32, device=dev)
+    occ = torch.empty(n, dtype=torch.int32, device=dev)
+
+    # ---- forward sweep (the step) ----
+    fwd = lambda: wm.predict(dd, p, out_T=T, out_occ=occ)
+    wall_ms, ev_ms = timed(fwd, args.steps, args.warmup)
+    log(f"forward: {wall_ms:.4f} ms/step wall, {ev_ms:.4f} ms/launch (events)")
+    value = n / (wall_ms * 1e-3)
+    achieved = FWD_BYTES * n / (ev_ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded PCG64 descriptor sweep, inputs resident in HBM)",
+        "config": {"workload": "batched forward: 2^24 kernel descriptors, FP32 SoA "
+                               "(8 f32 + 4 i32 each), one CDNA-style parameter set",
+                   "n_descriptors": n, "param_set": "seed 0, 4 levels, HK_MAX"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "wm::k_predict<4>", "bytes_per_eval": FWD_BYTES,
+                     "avg_launch_us": ev_ms * 1e3},
+    }
+
+    if not args.quick:
+        # ---- forward + adjoint (loss and gradient) over the same descriptors ----
+        ps = synth.param_set(1)
+        Tm, _ = wm.predict(dd, ps, want_occ=False)
+        noise = torch.from_numpy(synth.lognormal_noise(n, 2, 0.02).astype(np.float32)).to(dev)
+        meas = (Tm * noise).contiguous()
+        del Tm, noise
+        p0 = synth.perturb_theta(ps, 3)
+        ws = wm._workspace(wm.workspace_bytes(wm.OP_LOSS_GRAD, n), dev)
+        out = torch.empty(26, dtype=torch.float64, device=dev)
+        lg = lambda: wm.loss_grad(dd, meas, p0, ws=ws, out=out)
+        wall_a, ev_a = timed(lg, max(args.steps // 2, 3), 2)
+        ach_a = ADJ_BYTES * n / (ev_a * 1e-3) / 1e9
+        res["fwd_adjoint"] = {"value": n / (wall_a * 1e-3), "unit": "evals/s", "ms_per_step": wall_a,
+                              "achieved_GBs": ach_a, "hbm_frac": ach_a / HBM_PEAK_GBS,
+                              "bytes_per_eval": ADJ_BYTES, "dtype": "f32 + f64 reductions"}
+        log(f"fwd+adjoint: {wall_a:.4f} ms/step, {ach_a:.0f} GB/s")
+        del meas, ws
+
+        # ---- tile selection ----
+        sh = synth.shapes(1 << 16, 102)
+        dsh = wm.DeviceShapes.from_host(sh, dev)
+        outs = (torch.empty(sh.n, dtype=torch.int32, device=dev),
+                torch.empty(sh.n, dtype=torch.float64, device=dev),
+                torch.empty(sh.n, dtype=torch.uint8, device=dev))
+        sel = lambda: wm.select_tile(dsh, p, out=outs)
+        wall_t, ev_t = timed(sel, args.steps, args.warmup)
+        # the same launch replayed from a captured HIP graph
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            sel()
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(g):
+            sel()
+        wall_g, ev_g = timed(g.replay, args.steps, args.warmup)
+        ncand = int(sh.cand_code.shape[0])
+        res["select_tile"] = {"shapes": sh.n, "candidates": ncand, "ms_per_call": wall_t,
+                              "ms_per_graph_replay": wall_g,
+                              "candidates_per_s": ncand / (wall_g * 1e-3),
+                              "shapes_per_s": sh.n / (wall_g * 1e-3)}
+        log(f"select_tile: {wall_t:.4f} ms/call, {wall_g:.4f} ms/graph replay")
+
+        # ---- calibration: 2^20 descriptors, Adam in captured graphs ----
+        nc = 1 << 20
+        dc = synth.descriptors(nc, 103)
+        ddc = wm.DeviceDescriptors.from_host(dc, dev)
+        Tc, _ = wm.predict(ddc, ps, want_occ=False)
+        mc = (Tc * torch.from_numpy(synth.lognormal_noise(nc, 2, 0.02).astype(np.float32)).to(dev)).contiguous()
+        mask = 0x3FFFFF
+        p0c = synth.perturb_theta(ps, 3, mask=mask)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, th, hist = wm.calibrate(ddc, mc, p0c, steps=args.calib_steps, free_mask=mask)
+        el = time.perf_counter() - t0
+        idx = [j for j in range(24) if mask >> j & 1]
+        err = float(np.max(np.abs(th[idx] / np.array(ps.theta)[idx] - 1)))
+        res["calibrate"] = {"descriptors": nc, "steps": args.calib_steps, "seconds": el,
+                            "fwd_adj_evals_per_s": nc * args.calib_steps / el,
+                            "max_recovery_err": err, "status": rc,
+                            "loss_first_last": [float(hist[0]), float(hist[-1])]}
+        log(f"calibrate: {el:.3f} s, max recovery err {err:.4f}")
+        del ddc, mc, Tc
+
+        # ---- batched calibration of six architectures vs six plain launches ----
+        sets = synth.multi_arch_sets()
+        sizes = synth.multi_arch_sizes()
+        descs, meas_l, p0s, opts = [], [], [], []
+        for k, (pk, nk) in enumerate(zip(sets, sizes)):
+            dk = synth.descriptors(nk, 120 + k)
+            ddk = wm.DeviceDescriptors.from_host(dk, dev)
+            Tk, _ = wm.predict(ddk, pk, want_occ=False)
+            mk = (Tk * torch.from_numpy(synth.lognormal_noise(nk, 130 + k, 0.02).astype(np.float32)).to(dev)).contiguous()
+            mk_mask = 0x3FFFFF if pk.n_levels == 4 else (0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21)))
+            descs.append(ddk)
+            meas_l.append(mk)
+            p0s.append(synth.perturb_theta(pk, 140 + k, mask=mk_mask))
+            opts.append(wm.calib_opts(steps=args.calib_steps, free_mask=mk_mask))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rcb, thb, histb = wm.calibrate_batched(descs, meas_l, p0s, opts)
+        el_b = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for k in range(len(sets)):
+            wm.calibrate(descs[k], meas_l[k], p0s[k], steps=args.calib_steps,
+                         free_mask=opts[k].free_mask)
+        el_p = time.perf_counter() - t0
+        tot = sum(sizes) * args.calib_steps
+        rec = []
+        for k, pk in enumerate(sets):
+            idx = [j for j in range(24) if opts[k].free_mask >> j & 1]
+            rec.append(float(np.max(np.abs(thb[k][idx] / np.array(pk.theta)[idx] - 1))))
+        res["batched"] = {"sets": len(sets), "sizes": sizes, "steps": args.calib_steps,
+                          "persistent_evals_per_s": tot / el_b, "per_set_evals_per_s": tot / el_p,
+                          "speedup": el_p / el_b, "per_set_recovery_err": rec, "status": rcb}
+        log(f"batched: {el_b:.3f} s persistent vs {el_p:.3f} s per-set")
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(p, d)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

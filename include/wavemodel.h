@@ -1,0 +1,248 @@
+/*
+ * wavemodel.h -- C ABI of libwavemodel.so: batched evaluation, adjoint,
+ * calibration and tile selection for the CDNA wavefront-centric
+ * execution-time model (Section IV-B of "Microbenchmark-Driven Analytical
+ * Performance Modeling Across Modern GPU Architectures").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Memory.  Every array argument is DEVICE memory (HIP, gfx950) owned by
+ *    the caller unless the comment says "host".  Structs passed by pointer
+ *    (wm_desc_t, wm_params_t, wm_shapes_t, wm_calib_opts_t) live in host
+ *    memory and are read during the call only.  The library allocates no
+ *    memory: scratch comes from a caller workspace `ws` of `ws_bytes` bytes,
+ *    sized by wm_workspace_bytes(), 256-byte aligned.
+ *  - Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls enqueue work and return without synchronising, except
+ *    wm_calibrate / wm_calibrate_batched / wm_autotune, which synchronise
+ *    `stream` once before returning (they write host results).
+ *  - Errors.  Return value 0 (WM_OK) or a negative status.  Arguments are
+ *    validated on the host before any HIP call, so a bad call never launches
+ *    a kernel.  n == 0 returns WM_OK without a launch (array pointers may
+ *    then be NULL), except that wm_predict_vjp and wm_loss_grad still write
+ *    their zero-valued outputs.  Problems of single
+ *    descriptors are not errors: an invalid descriptor yields T = NaN and
+ *    occ = -1; a resource-infeasible one (zero resident workgroups) yields
+ *    T = +inf and occ = 0.
+ *  - Determinism.  Same inputs on the same device give bitwise-identical
+ *    outputs (no floating-point atomics; fixed-order FP64 reductions).
+ *  - Thread safety.  Calls may come from several host threads; calls whose
+ *    workspaces overlap race.
+ *
+ * Array layouts
+ * -------------
+ *  Descriptors are structure-of-arrays, n entries each: 8 float32 arrays
+ *  (F flops, B bytes, r1/r2/r3 L1/L2/LLC hit rates, K steps per workgroup,
+ *  u compute utilisation, W working-set bytes with 0 = unknown) and 4 int32
+ *  arrays (vgpr VGPRs per thread, lds LDS bytes per workgroup, gpack, grid
+ *  workgroups).  gpack bits: [0,11) workgroup threads g (1..1024), [11,14)
+ *  dtype (0 fp64, 1 fp32, 2 bf16/fp16, 3 fp8, 4 int8), [14,17) concurrent
+ *  kernels - 1, [17,20) devices - 1, [20] fused, [21,25) host syncs;
+ *  bits 25..31 must be zero.  The vector path needs every array 16-byte
+ *  aligned; misaligned arrays take a scalar path with the same results.
+ */
+#ifndef WAVEMODEL_H
+#define WAVEMODEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define WM_OK 0
+#define WM_EINVAL (-1)      /* null pointer, n < 0, invalid parameter set or option */
+#define WM_EWORKSPACE (-2)  /* workspace missing, too small or misaligned */
+#define WM_EHIP (-3)        /* a HIP call failed; see wm_last_hip_error() */
+#define WM_EDIVERGED (-4)   /* calibration loss became non-finite */
+
+#define WM_N_THETA 24
+
+/*
+ * Parameter vector theta (SI units, latencies in cycles), Section IV-B and
+ * Tables "arch-params" / "parameters":
+ *   0-3   BW_L1, BW_L2, BW_LLC, BW_HBM      sustained bandwidth per level, B/s (> 0)
+ *   4-7   Lat_L1, Lat_L2, Lat_LLC, Lat_HBM  load latency per level, cycles (>= 0), Eq. (10)
+ *   8-12  P_fp64, P_fp32, P_bf16, P_fp8, P_int8  sustained peak per dtype, flop/s (> 0), Eq. (11)
+ *   13    T_launch   launch + coherence + cross-XCD constant, s (>= 0), Eq. (13)
+ *   14    tau_wg     per-workgroup dispatch overhead, s (>= 0), Eq. (14)
+ *   15    tau_bar    per round x step synchronisation, s (>= 0)
+ *   16    tau_interf per extra concurrent kernel, s (>= 0)
+ *   17    tau_gpu    per extra device, s (>= 0)
+ *   18    tau_fusion fused-kernel overhead, s (>= 0)
+ *   19    tau_sync   per host synchronisation, s (>= 0), Section IV-E
+ *   20-21 alpha, beta  h_LLC(W) exponents (> 0), Table "hlcc-piecewise"
+ *   22    w0         working-set blend scale, bytes (<= 0 disables), Eq. (16)
+ *   23    B_peak     HBM bandwidth ceiling for small working sets, B/s (> 0), Eq. (16)
+ * With n_levels == 3 (no last-level cache) slots 2, 6, 20, 21 are unused.
+ *
+ * Structural integers are not calibrated.  wave in {32, 64}; vgpr_gran and
+ * lds_gran powers of two; w_lo_mib < c_llc_mib, both exactly representable
+ * as float32; combine 0 = HK_MAX (T_ov + max of compute, bandwidth and
+ * latency stage times, Eq. (1)), 1 = PAPER_ETA (Eq. (9) and Eq. (12)).
+ * mwp / cwp cap the wavefronts counted for overlap (0 = unset).
+ */
+typedef struct {
+    int32_t n_levels, n_cu, n_simd, wave, vgpr_simd, vgpr_gran, waves_simd,
+            lds_cu, lds_gran, bytes_inflight_wave, mwp, cwp, combine, reserved;
+    double f_clk, w_lo_mib, c_llc_mib;
+    double theta[WM_N_THETA];
+} wm_params_t;
+
+typedef struct {
+    const float *F, *B, *r1, *r2, *r3, *K, *u, *W;
+    const int32_t *vgpr, *lds, *gpack, *grid;
+    int64_t n;
+} wm_desc_t;
+
+/* GEMM-like shapes for tile selection: M, N, K >= 1, dtype 0..3
+ * (fp64, fp32, bf16/fp16, fp8), n shapes. */
+typedef struct {
+    const int32_t *M, *N, *K, *dtype;
+    int64_t n;
+} wm_shapes_t;
+
+typedef struct {
+    int32_t steps;        /* Adam steps (>= 1) */
+    int32_t reserved;
+    double lr;            /* initial learning rate on log(theta) (> 0) */
+    double lr_final;      /* geometric decay to this rate at the last step; 0 = constant */
+    double beta1, beta2;  /* Adam moment decay rates, in [0, 1) */
+    double eps;           /* Adam epsilon (> 0) */
+    uint32_t free_mask;   /* bit j set: slot j is fitted; the others stay fixed */
+    uint32_t reserved2;
+} wm_calib_opts_t;
+
+/* ---- host-only helpers (no HIP call) ---- */
+
+/* Text for a status code; never NULL. */
+const char *wm_strerror(int32_t status);
+
+/* HIP error code of the last WM_EHIP on the calling thread (0 if none). */
+int32_t wm_last_hip_error(void);
+
+/* WM_OK if the parameter set is usable by the kernels (units and ranges as
+ * listed above, every derived float32 constant finite), else WM_EINVAL. */
+int32_t wm_validate_params(const wm_params_t *params);
+
+/* Workspace bytes for an operation (0 if none is needed; 0 for bad
+ * arguments):
+ *  WM_OP_PREDICT, WM_OP_ROOFLINE, WM_OP_SELECT_TILE: 0.
+ *  WM_OP_VJP, WM_OP_LOSS_GRAD: per-block FP64 partial sums for n descriptors.
+ *  WM_OP_CALIBRATE: device parameter set, Adam state, a `steps`-entry loss
+ *      history and the partial sums for n descriptors.
+ *  WM_OP_CALIBRATE_BATCHED: the same for n_sets sets holding n descriptors
+ *      in total, plus the work list. */
+#define WM_OP_PREDICT 0
+#define WM_OP_ROOFLINE 1
+#define WM_OP_VJP 2
+#define WM_OP_LOSS_GRAD 3
+#define WM_OP_SELECT_TILE 4
+#define WM_OP_CALIBRATE 5
+#define WM_OP_CALIBRATE_BATCHED 6
+size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps);
+
+/* ---- device calls ---- */
+
+/*
+ * Predicted execution time of every descriptor (Section IV-B): occupancy
+ * from VGPR, wave-slot and LDS limits; workgroup rounds n_r =
+ * ceil(G / (N_CU o)) (Eq. (14)); hit-weighted bandwidth and latency over the
+ * cache levels (Eq. (10)), with h_LLC(W) (Table "hlcc-piecewise") and the
+ * Eq. (16) HBM blend when W > 0; compute time F / (u P_dtype) (Eq. (11));
+ * stage times combined per params->combine plus the overhead terms of
+ * Eq. (13), Eq. (14) and Section IV-E.
+ *   T   [n] float32 seconds (required).
+ *   occ [n] int32 resident workgroups per CU, or NULL to skip.
+ * Computed in float32; error against the FP64 definition is below 1e-5
+ * relative; occupancy is exact.
+ */
+int32_t wm_predict(const wm_desc_t *desc, const wm_params_t *params, float *T, int32_t *occ,
+                   void *stream);
+
+/* Naive roofline max(F / P_dtype, B / BW_HBM) (Section V-A), float32 [n];
+ * NaN for invalid descriptors. */
+int32_t wm_roofline(const wm_desc_t *desc, const wm_params_t *params, float *T, void *stream);
+
+/*
+ * Vector-Jacobian product: dL_dtheta[j] = sum_i dL_dT[i] * dT_i/dtheta_j over
+ * descriptors with finite T (analytic derivative of the model; subgradient at
+ * the max/min switches: first maximal stage, saturated overlap branch when
+ * (N_eff - 1) T_c >= T_m).  dL_dT [n] float32; dL_dtheta [24] float64
+ * device.  Partials are float32; descriptors within 1e-5 of a switch are
+ * re-evaluated in float64; sums are float64 in a fixed order.
+ * Workspace: wm_workspace_bytes(WM_OP_VJP, n, 1, 0).
+ */
+int32_t wm_predict_vjp(const wm_desc_t *desc, const wm_params_t *params, const float *dL_dT,
+                       double *dL_dtheta, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Mean relative error and its gradient: over descriptors with finite T and
+ * finite measured m > 0, loss = mean |T - m| / m and
+ * grad_j = mean sign(T - m) / m * dT/dtheta_j (sign(0) = 0).  Where
+ * |T/m - 1| < 1e-5 in float32 the descriptor is re-evaluated in float64 to
+ * take the sign.  out [26] float64 device: loss, count, grad[24].
+ * Workspace: wm_workspace_bytes(WM_OP_LOSS_GRAD, n, 1, 0).
+ */
+int32_t wm_loss_grad(const wm_desc_t *desc, const float *measured, const wm_params_t *params,
+                     double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adaptive tile selection (Section IV-B: evaluate candidate tiles with the
+ * model and return the fastest).  Each shape i has candidates
+ * cand_code[cand_off[i] .. cand_off[i+1]) (cand_off [n+1] int32,
+ * non-decreasing, cand_off[0] = 0; n_cand = cand_off[n], passed for
+ * validation).  Code = mt | nt << 2 | kd << 4 | (waves - 1) << 6 with
+ * mt, nt in {32, 64, 128, 256}, kd in {16, 32, 64}, waves 1..8; other bits
+ * zero.  The tile becomes a descriptor (grid ceil(M/mt) ceil(N/nt), K loop
+ * ceil(K/kd) steps, padded flops, panel bytes, L2 reuse 1 - unique/loaded,
+ * VGPRs for accumulators and panels, double-buffered LDS) whose predicted
+ * time is its cost.  Outputs per shape: best [n] int32 local index of the
+ * cheapest candidate (ties to the lowest index; -1 if none is feasible),
+ * best_cost [n] float64 its float64 cost (+inf if none), near_tie [n]
+ * uint8 = 1 when the runner-up is within 1e-6 relative.  A float32 sweep
+ * picks the candidates within 3e-5 of the minimum; those are re-evaluated in
+ * float64, which decides.  One persistent launch.
+ */
+int32_t wm_select_tile(const wm_shapes_t *shapes, const int32_t *cand_off,
+                       const uint32_t *cand_code, int64_t n_cand, const wm_params_t *params,
+                       int32_t *best, double *best_cost, uint8_t *near_tie, void *stream);
+
+/*
+ * Calibration (Section IV-D): fit the free slots of theta to measured times
+ * by Adam on log(theta) over the mean relative error (wm_loss_grad), all on
+ * the device; the step loop is captured once as a HIP graph and replayed.
+ * measured [n] float32 device.  p_out (host) receives p0 with the fitted
+ * theta; loss_hist (host, [opts->steps], may be NULL) the loss before each
+ * update.  Returns WM_EDIVERGED if the loss became non-finite; p_out then
+ * holds the last theta with a finite loss.  Synchronises `stream`.
+ * Workspace: wm_workspace_bytes(WM_OP_CALIBRATE, n, 1, opts->steps).
+ */
+int32_t wm_calibrate(const wm_desc_t *desc, const float *measured, const wm_params_t *p0,
+                     const wm_calib_opts_t *opts, wm_params_t *p_out, double *loss_hist,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Several calibration problems (one parameter set and one descriptor set
+ * each; different sizes and hierarchies, as in porting the model to several
+ * architectures by parameters alone, Section IV-B) advanced together: each
+ * step is one persistent launch over a (set, chunk) work list plus one
+ * per-set reduce-and-Adam launch.  sets, measured, p0, opts, p_out: host
+ * arrays of n_sets entries (measured[s] device pointers); every set uses
+ * opts[s] but all must have the same step count; loss_hist host
+ * [n_sets][steps] or NULL.  Workspace: wm_workspace_bytes(
+ * WM_OP_CALIBRATE_BATCHED, sum of n, n_sets, steps).  At most 16 sets.
+ * Synchronises `stream`.
+ */
+int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t *sets, const float *const *measured,
+                             const wm_params_t *p0, const wm_calib_opts_t *opts,
+                             wm_params_t *p_out, double *loss_hist, void *ws, size_t ws_bytes,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVEMODEL_H */

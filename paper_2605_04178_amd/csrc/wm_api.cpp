@@ -1,0 +1,572 @@
+// wm_api.cpp -- the C ABI of libwavemodel.so (include/wavemodel.h): host-side
+// validation, parameter-set images, workspace carving, launches and the
+// HIP-graph capture of the calibration loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/wavemodel.h"
+#include "wm_launch.hpp"
+
+using namespace wm;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+int32_t hip_fail(hipError_t e)
+{
+    g_last_hip = (int32_t)e;
+    return WM_EHIP;
+}
+
+#define WM_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_);    \
+    } while (0)
+
+bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x)
+{
+    int r = 0;
+    while ((1ll << r) < x) ++r;
+    return r;
+}
+bool fin(double x) { return std::isfinite(x); }
+bool f32_exact(double x) { return (double)(float)x == x; }
+bool f32_ok(double x) { return std::isfinite((float)x); }
+bool f32_pos(double x) { return (float)x > 0.0f && std::isfinite((float)x); }
+
+bool params_ok(const wm_params_t* p)
+{
+    if (!p) return false;
+    if (p->n_levels != 3 && p->n_levels != 4) return false;
+    if (p->n_cu < 1 || p->n_cu > 65536) return false;
+    if (p->n_simd < 1 || p->n_simd > 16) return false;
+    if (p->wave != 32 && p->wave != 64) return false;
+    if (p->vgpr_simd < 1 || p->vgpr_simd > 65536) return false;
+    if (!pow2(p->vgpr_gran) || p->vgpr_gran > 65536) return false;
+    if (p->waves_simd < 1 || p->waves_simd > 64) return false;
+    if (p->lds_cu < 0 || p->lds_cu > (1 << 24)) return false;
+    if (!pow2(p->lds_gran) || p->lds_gran > (1 << 20)) return false;
+    if (p->bytes_inflight_wave < 1 || p->bytes_inflight_wave > (1 << 30)) return false;
+    if (p->mwp < 0 || p->cwp < 0) return false;
+    if (p->combine != 0 && p->combine != 1) return false;
+    if (!(fin(p->f_clk) && p->f_clk > 0.0 && f32_pos(1.0 / p->f_clk))) return false;
+    if (!(fin(p->w_lo_mib) && fin(p->c_llc_mib) && p->w_lo_mib >= 0.0 &&
+          p->w_lo_mib < p->c_llc_mib && f32_exact(p->w_lo_mib) && f32_exact(p->c_llc_mib)))
+        return false;
+    const double* th = p->theta;
+    for (int j = 0; j < WM_N_THETA; ++j)
+        if (!fin(th[j])) return false;
+    const bool L4 = p->n_levels == 4;
+    for (int l = 0; l < 4; ++l) {
+        if (l == 2 && !L4) continue;
+        if (!(th[l] > 0.0 && f32_pos(th[l]))) return false;
+        if (!(th[4 + l] >= 0.0 && f32_ok(th[4 + l] / p->f_clk))) return false;
+    }
+    for (int t = 0; t < 5; ++t)
+        if (!(th[8 + t] > 0.0 && f32_pos(1.0 / th[8 + t]))) return false;
+    for (int j = 13; j < 20; ++j)
+        if (!(th[j] >= 0.0 && f32_ok(th[j]))) return false;
+    if (L4 && !(th[20] > 0.0 && th[21] > 0.0 && f32_ok(th[20]) && f32_ok(th[21]))) return false;
+    if (th[22] > 0.0 && !f32_pos(1.0 / th[22])) return false;
+    if (!(th[23] > 0.0 && f32_ok(th[23]) && f32_ok(th[23] - th[3]))) return false;
+    return true;
+}
+
+Struct make_struct(const wm_params_t* p)
+{
+    Struct s;
+    std::memset(&s, 0, sizeof(s));
+    s.n_levels = p->n_levels;
+    s.n_cu = p->n_cu;
+    s.n_simd = p->n_simd;
+    s.wave_shift = ilog2(p->wave);
+    s.vgpr_simd = p->vgpr_simd;
+    s.vgpr_gran_mask = p->vgpr_gran - 1;
+    s.waves_simd = p->waves_simd;
+    s.lds_cu = p->lds_cu;
+    s.lds_gran_mask = p->lds_gran - 1;
+    s.mwp = p->mwp;
+    s.cwp = p->cwp;
+    s.combine = p->combine;
+    s.bytes_inflight_wave = p->bytes_inflight_wave;
+    s.f_clk = p->f_clk;
+    s.w_lo_mib = p->w_lo_mib;
+    s.c_llc_mib = p->c_llc_mib;
+    return s;
+}
+
+Set make_set(const wm_params_t* p)
+{
+    Set S;
+    std::memset(&S, 0, sizeof(S));
+    S.st = make_struct(p);
+    make_const<float>(p->theta, S.st, S.cf);
+    make_const<double>(p->theta, S.st, S.cd);
+    return S;
+}
+
+bool desc_ok(const wm_desc_t* d)
+{
+    if (!d || d->n < 0) return false;
+    if (d->n == 0) return true;
+    const void* ptrs[12] = {d->F, d->B, d->r1, d->r2, d->r3, d->K, d->u, d->W,
+                            d->vgpr, d->lds, d->gpack, d->grid};
+    for (const void* q : ptrs)
+        if (!q) return false;
+    return true;
+}
+
+DescPtrs ptrs_of(const wm_desc_t* d)
+{
+    DescPtrs p;
+    p.F = d->F; p.B = d->B; p.r1 = d->r1; p.r2 = d->r2; p.r3 = d->r3; p.K = d->K; p.u = d->u;
+    p.W = d->W; p.vgpr = d->vgpr; p.lds = d->lds; p.gpack = d->gpack; p.grid = d->grid;
+    return p;
+}
+
+bool aligned16(const wm_desc_t* d)
+{
+    const void* ptrs[12] = {d->F, d->B, d->r1, d->r2, d->r3, d->K, d->u, d->W,
+                            d->vgpr, d->lds, d->gpack, d->grid};
+    for (const void* q : ptrs)
+        if (((uintptr_t)q & 15u) != 0) return false;
+    return true;
+}
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool opts_ok(const wm_calib_opts_t* o)
+{
+    if (!o) return false;
+    if (o->steps < 1) return false;
+    if (!(fin(o->lr) && o->lr > 0.0)) return false;
+    if (!(fin(o->lr_final) && o->lr_final >= 0.0)) return false;
+    if (!(o->beta1 >= 0.0 && o->beta1 < 1.0 && o->beta2 >= 0.0 && o->beta2 < 1.0)) return false;
+    if (!(fin(o->eps) && o->eps > 0.0)) return false;
+    if ((o->free_mask >> WM_N_THETA) != 0u) return false;
+    return true;
+}
+
+AdamOpts adam_of(const wm_calib_opts_t* o)
+{
+    AdamOpts a;
+    std::memset(&a, 0, sizeof(a));
+    a.steps = o->steps;
+    a.lr = o->lr;
+    a.lr_final = o->lr_final;
+    a.beta1 = o->beta1;
+    a.beta2 = o->beta2;
+    a.eps = o->eps;
+    a.free_mask = o->free_mask;
+    return a;
+}
+
+// the slots a parameter set may move: positive everywhere they are fitted
+bool free_slots_ok(const wm_params_t* p, uint32_t mask)
+{
+    for (int j = 0; j < WM_N_THETA; ++j)
+        if (((mask >> j) & 1u) && !(p->theta[j] > 0.0)) return false;
+    return true;
+}
+
+CalibState init_state(const wm_params_t* p, uint32_t mask)
+{
+    CalibState s;
+    std::memset(&s, 0, sizeof(s));
+    for (int j = 0; j < WM_N_THETA; ++j) {
+        s.theta[j] = p->theta[j];
+        s.theta_ok[j] = p->theta[j];
+        s.phi[j] = ((mask >> j) & 1u) ? std::log(p->theta[j]) : 0.0;
+    }
+    return s;
+}
+
+// calibration workspace layout
+struct CalibLayout {
+    size_t set, state, hist, partials, total;
+    int nb;
+};
+
+CalibLayout calib_layout(int64_t n, int32_t steps)
+{
+    CalibLayout L;
+    L.nb = grad_blocks(n);
+    size_t off = 0;
+    L.set = off;
+    off += up256(sizeof(Set));
+    L.state = off;
+    off += up256(sizeof(CalibState));
+    L.hist = off;
+    off += up256(sizeof(double) * (size_t)(steps > 0 ? steps : 1));
+    L.partials = off;
+    off += up256(sizeof(double) * kAcc * (size_t)L.nb);
+    L.total = off;
+    return L;
+}
+
+constexpr int64_t kBatchChunk = 16384;
+constexpr int kBatchMaxBlocks = 1024;
+
+struct BatchLayout {
+    size_t sets, states, opts, descs, meas, items, hist, partials, total;
+    int nb, max_items;
+};
+
+BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
+{
+    BatchLayout L;
+    L.max_items = (int)(n_total / kBatchChunk + n_sets + 1);
+    L.nb = L.max_items < kBatchMaxBlocks ? L.max_items : kBatchMaxBlocks;
+    size_t off = 0;
+    L.sets = off;
+    off += up256(sizeof(Set) * n_sets);
+    L.states = off;
+    off += up256(sizeof(CalibState) * n_sets);
+    L.opts = off;
+    off += up256(sizeof(AdamOpts) * n_sets);
+    L.descs = off;
+    off += up256(sizeof(DescPtrs) * n_sets);
+    L.meas = off;
+    off += up256(sizeof(float*) * n_sets);
+    L.items = off;
+    off += up256(sizeof(WorkItem) * (size_t)L.max_items);
+    L.hist = off;
+    off += up256(sizeof(double) * (size_t)n_sets * (size_t)(steps > 0 ? steps : 1));
+    L.partials = off;
+    off += up256(sizeof(double) * kAcc * (size_t)n_sets * (size_t)L.nb);
+    L.total = off;
+    return L;
+}
+
+bool ws_ok(void* ws, size_t have, size_t need)
+{
+    if (need == 0) return true;
+    return ws && have >= need && ((uintptr_t)ws & 255u) == 0;
+}
+
+// Capture `chunk` steps of a calibration loop on `stream` into an executable
+// graph.  `enqueue_step` records one step's launches.
+template <typename F>
+int32_t capture_steps(hipStream_t stream, int chunk, F enqueue_step, hipGraphExec_t* exec)
+{
+    hipGraph_t graph = nullptr;
+    WM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < chunk && err == hipSuccess; ++i) err = enqueue_step();
+    hipError_t e2 = hipStreamEndCapture(stream, &graph);
+    if (err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(err);
+    }
+    if (e2 != hipSuccess) return hip_fail(e2);
+    hipError_t e3 = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return hip_fail(e3);
+    return WM_OK;
+}
+
+// Run `steps` steps as replays of captured graphs of up to kGraphChunk steps.
+constexpr int kGraphChunk = 50;
+
+template <typename F>
+int32_t run_steps(hipStream_t stream, int steps, F enqueue_step)
+{
+    const int chunk = steps < kGraphChunk ? steps : kGraphChunk;
+    const int full = steps / chunk, rem = steps % chunk;
+    hipGraphExec_t g_full = nullptr, g_rem = nullptr;
+    int32_t rc = capture_steps(stream, chunk, enqueue_step, &g_full);
+    if (rc != WM_OK) return rc;
+    if (rem > 0) {
+        rc = capture_steps(stream, rem, enqueue_step, &g_rem);
+        if (rc != WM_OK) {
+            (void)hipGraphExecDestroy(g_full);
+            return rc;
+        }
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < full && e == hipSuccess; ++i) e = hipGraphLaunch(g_full, stream);
+    if (e == hipSuccess && g_rem) e = hipGraphLaunch(g_rem, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipGraphExecDestroy(g_full);
+    if (g_rem) (void)hipGraphExecDestroy(g_rem);
+    if (e != hipSuccess) return hip_fail(e);
+    return WM_OK;
+}
+
+// A capturable stream: the caller's, or for the null stream a library stream
+// created once per device (after draining the null stream's earlier work).
+std::mutex g_stream_mu;
+std::vector<hipStream_t> g_own_streams;
+
+int32_t capture_stream(void* user, hipStream_t* out)
+{
+    if (user) {
+        *out = (hipStream_t)user;
+        return WM_OK;
+    }
+    int dev = 0;
+    WM_HIP(hipGetDevice(&dev));
+    WM_HIP(hipStreamSynchronize(nullptr));
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    if ((int)g_own_streams.size() <= dev) g_own_streams.resize(dev + 1, nullptr);
+    if (!g_own_streams[dev]) WM_HIP(hipStreamCreateWithFlags(&g_own_streams[dev], hipStreamNonBlocking));
+    *out = g_own_streams[dev];
+    return WM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* wm_strerror(int32_t s)
+{
+    switch (s) {
+    case WM_OK: return "ok";
+    case WM_EINVAL: return "invalid argument";
+    case WM_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case WM_EHIP: return "HIP runtime error";
+    case WM_EDIVERGED: return "calibration diverged";
+    default: return "unknown status";
+    }
+}
+
+int32_t wm_last_hip_error(void) { return g_last_hip; }
+
+int32_t wm_validate_params(const wm_params_t* p) { return params_ok(p) ? WM_OK : WM_EINVAL; }
+
+size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps)
+{
+    if (n < 0) return 0;
+    switch (op) {
+    case WM_OP_VJP:
+    case WM_OP_LOSS_GRAD:
+        return up256(sizeof(double) * kAcc * (size_t)grad_blocks(n));
+    case WM_OP_CALIBRATE:
+        if (steps < 1) return 0;
+        return calib_layout(n, steps).total;
+    case WM_OP_CALIBRATE_BATCHED:
+        if (steps < 1 || n_sets < 1 || n_sets > kMaxSets) return 0;
+        return batch_layout(n, n_sets, steps).total;
+    default:
+        return 0;
+    }
+}
+
+int32_t wm_predict(const wm_desc_t* desc, const wm_params_t* params, float* T, int32_t* occ,
+                   void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params)) return WM_EINVAL;
+    if (desc->n == 0) return WM_OK;
+    if (!T) return WM_EINVAL;
+    const bool vec = aligned16(desc) && ((uintptr_t)T & 15u) == 0 && ((uintptr_t)occ & 15u) == 0;
+    const Set S = make_set(params);
+    WM_HIP(launch_predict(ptrs_of(desc), desc->n, S, T, occ, vec, (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_roofline(const wm_desc_t* desc, const wm_params_t* params, float* T, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params)) return WM_EINVAL;
+    if (desc->n == 0) return WM_OK;
+    if (!T) return WM_EINVAL;
+    const Set S = make_set(params);
+    WM_HIP(launch_roofline(ptrs_of(desc), desc->n, S, T, (hipStream_t)stream));
+    return WM_OK;
+}
+
+static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, const wm_params_t* params,
+                           double* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !out) return WM_EINVAL;
+    if (desc->n > 0 && !w) return WM_EINVAL;
+    const size_t need = wm_workspace_bytes(mode == 1 ? WM_OP_LOSS_GRAD : WM_OP_VJP, desc->n, 1, 0);
+    if (!ws_ok(ws, ws_bytes, need)) return WM_EWORKSPACE;
+    const Set S = make_set(params);
+    const int nb = grad_blocks(desc->n);
+    // n == 0 still writes zeros through the (empty) sweep and reduction
+    WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)ws, nb, out,
+                       (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_predict_vjp(const wm_desc_t* desc, const wm_params_t* params, const float* dL_dT,
+                       double* dL_dtheta, void* ws, size_t ws_bytes, void* stream)
+{
+    return grad_common(0, desc, dL_dT, params, dL_dtheta, ws, ws_bytes, stream);
+}
+
+int32_t wm_loss_grad(const wm_desc_t* desc, const float* measured, const wm_params_t* params,
+                     double* out, void* ws, size_t ws_bytes, void* stream)
+{
+    return grad_common(1, desc, measured, params, out, ws, ws_bytes, stream);
+}
+
+int32_t wm_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
+                       const uint32_t* cand_code, int64_t n_cand, const wm_params_t* params,
+                       int32_t* best, double* best_cost, uint8_t* near_tie, void* stream)
+{
+    if (!shapes || shapes->n < 0 || !params_ok(params) || n_cand < 0) return WM_EINVAL;
+    if (shapes->n == 0) return WM_OK;
+    if (!shapes->M || !shapes->N || !shapes->K || !shapes->dtype || !cand_off || !best ||
+        !best_cost || !near_tie)
+        return WM_EINVAL;
+    if (n_cand > 0 && !cand_code) return WM_EINVAL;
+    if (n_cand > 0x7fffffffll) return WM_EINVAL;
+    ShapePtrs sp;
+    sp.M = shapes->M;
+    sp.N = shapes->N;
+    sp.K = shapes->K;
+    sp.dtype = shapes->dtype;
+    const Set S = make_set(params);
+    WM_HIP(launch_select_tile(sp, cand_off, cand_code, shapes->n, n_cand, S, best, best_cost,
+                              near_tie, 0, (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_params_t* p0,
+                     const wm_calib_opts_t* opts, wm_params_t* p_out, double* loss_hist, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (!desc_ok(desc) || !measured || !params_ok(p0) || !opts_ok(opts) || !p_out) return WM_EINVAL;
+    if (!free_slots_ok(p0, opts->free_mask)) return WM_EINVAL;
+    const CalibLayout L = calib_layout(desc->n, opts->steps);
+    if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
+    hipStream_t s = nullptr;
+    int32_t rc = capture_stream(stream, &s);
+    if (rc != WM_OK) return rc;
+
+    char* base = (char*)ws;
+    Set* S_dev = (Set*)(base + L.set);
+    CalibState* st_dev = (CalibState*)(base + L.state);
+    double* hist_dev = (double*)(base + L.hist);
+    double* part_dev = (double*)(base + L.partials);
+    const Set S = make_set(p0);
+    const CalibState st0 = init_state(p0, opts->free_mask);
+    const AdamOpts ao = adam_of(opts);
+    WM_HIP(hipMemcpyAsync(S_dev, &S, sizeof(S), hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(st_dev, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    WM_HIP(hipStreamSynchronize(s));
+
+    const DescPtrs dp = ptrs_of(desc);
+    const int64_t n = desc->n;
+    const int nb = L.nb;
+    auto step = [&]() -> hipError_t {
+        hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, nb, nullptr, s);
+        if (e != hipSuccess) return e;
+        return launch_adam(part_dev, nb, st_dev, ao, S_dev, hist_dev, s);
+    };
+    rc = run_steps(s, opts->steps, step);
+    if (rc != WM_OK) return rc;
+
+    CalibState st;
+    WM_HIP(hipMemcpyAsync(&st, st_dev, sizeof(st), hipMemcpyDeviceToHost, s));
+    std::vector<double> hist((size_t)opts->steps);
+    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev, sizeof(double) * opts->steps,
+                          hipMemcpyDeviceToHost, s));
+    WM_HIP(hipStreamSynchronize(s));
+    *p_out = *p0;
+    for (int j = 0; j < WM_N_THETA; ++j) p_out->theta[j] = st.diverged ? st.theta_ok[j] : st.theta[j];
+    if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * opts->steps);
+    return st.diverged ? WM_EDIVERGED : WM_OK;
+}
+
+int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float* const* measured,
+                             const wm_params_t* p0, const wm_calib_opts_t* opts,
+                             wm_params_t* p_out, double* loss_hist, void* ws, size_t ws_bytes,
+                             void* stream)
+{
+    if (n_sets < 1 || n_sets > kMaxSets || !sets || !measured || !p0 || !opts || !p_out)
+        return WM_EINVAL;
+    int64_t n_total = 0;
+    for (int s = 0; s < n_sets; ++s) {
+        if (!desc_ok(&sets[s]) || !measured[s] || !params_ok(&p0[s]) || !opts_ok(&opts[s]))
+            return WM_EINVAL;
+        if (!free_slots_ok(&p0[s], opts[s].free_mask)) return WM_EINVAL;
+        if (opts[s].steps != opts[0].steps) return WM_EINVAL;
+        n_total += sets[s].n;
+    }
+    const int steps = opts[0].steps;
+    const BatchLayout L = batch_layout(n_total, n_sets, steps);
+    if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
+
+    // host images
+    std::vector<Set> Sh((size_t)n_sets);
+    std::vector<CalibState> sth((size_t)n_sets);
+    std::vector<AdamOpts> oh((size_t)n_sets);
+    std::vector<DescPtrs> dh((size_t)n_sets);
+    std::vector<const float*> mh((size_t)n_sets);
+    std::vector<WorkItem> items;
+    for (int s = 0; s < n_sets; ++s) {
+        Sh[s] = make_set(&p0[s]);
+        sth[s] = init_state(&p0[s], opts[s].free_mask);
+        oh[s] = adam_of(&opts[s]);
+        dh[s] = ptrs_of(&sets[s]);
+        mh[s] = measured[s];
+        for (int64_t b = 0; b < sets[s].n; b += kBatchChunk) {
+            WorkItem w;
+            w.set = s;
+            w.pad_ = 0;
+            w.begin = b;
+            w.end = b + kBatchChunk < sets[s].n ? b + kBatchChunk : sets[s].n;
+            items.push_back(w);
+        }
+    }
+    const int n_items = (int)items.size();
+    const int nb = n_items < 1 ? 1 : (n_items < L.nb ? n_items : L.nb);
+
+    hipStream_t s = nullptr;
+    int32_t rc = capture_stream(stream, &s);
+    if (rc != WM_OK) return rc;
+    char* base = (char*)ws;
+    Set* S_dev = (Set*)(base + L.sets);
+    CalibState* st_dev = (CalibState*)(base + L.states);
+    AdamOpts* o_dev = (AdamOpts*)(base + L.opts);
+    DescPtrs* d_dev = (DescPtrs*)(base + L.descs);
+    const float** m_dev = (const float**)(base + L.meas);
+    WorkItem* it_dev = (WorkItem*)(base + L.items);
+    double* hist_dev = (double*)(base + L.hist);
+    double* part_dev = (double*)(base + L.partials);
+    WM_HIP(hipMemcpyAsync(S_dev, Sh.data(), sizeof(Set) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(st_dev, sth.data(), sizeof(CalibState) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(o_dev, oh.data(), sizeof(AdamOpts) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(d_dev, dh.data(), sizeof(DescPtrs) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(m_dev, mh.data(), sizeof(float*) * n_sets, hipMemcpyHostToDevice, s));
+    if (n_items > 0)
+        WM_HIP(hipMemcpyAsync(it_dev, items.data(), sizeof(WorkItem) * n_items,
+                              hipMemcpyHostToDevice, s));
+    WM_HIP(hipStreamSynchronize(s));
+
+    auto step = [&]() -> hipError_t {
+        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, part_dev,
+                                           nb, s);
+        if (e != hipSuccess) return e;
+        return launch_adam_batched(part_dev, nb, n_sets, st_dev, o_dev, S_dev, steps, hist_dev, s);
+    };
+    rc = run_steps(s, steps, step);
+    if (rc != WM_OK) return rc;
+
+    WM_HIP(hipMemcpyAsync(sth.data(), st_dev, sizeof(CalibState) * n_sets, hipMemcpyDeviceToHost, s));
+    std::vector<double> hist((size_t)n_sets * steps);
+    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev, sizeof(double) * hist.size(),
+                          hipMemcpyDeviceToHost, s));
+    WM_HIP(hipStreamSynchronize(s));
+    bool div = false;
+    for (int k = 0; k < n_sets; ++k) {
+        p_out[k] = p0[k];
+        for (int j = 0; j < WM_N_THETA; ++j)
+            p_out[k].theta[j] = sth[k].diverged ? sth[k].theta_ok[j] : sth[k].theta[j];
+        div = div || sth[k].diverged;
+    }
+    if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * hist.size());
+    return div ? WM_EDIVERGED : WM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,607 @@
+// wm_kernels.hip -- gfx950 kernels of libwavemodel: forward sweep, naive
+// roofline, adjoint / loss-gradient with fixed-order FP64 reductions, device
+// Adam, occupancy-driven tile selection and the multi-set calibration sweep.
+//
+// Memory layout: descriptors are structure-of-arrays; the forward kernel
+// streams them with 16-byte nontemporal loads (4 descriptors per thread per
+// array) and writes T / occ with nontemporal stores, so a sweep larger than
+// the 256 MB Infinity Cache does not evict anything useful.  The gradient
+// kernels are persistent (grid-stride) and keep 26 FP64 accumulators per
+// thread, reduced across the wave with shuffles, across the block through LDS
+// and across blocks by a second single-block kernel in a fixed order.
+#include "wm_launch.hpp"
+
+namespace wm {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ inline T ntload(const T* p) { return __builtin_nontemporal_load(p); }
+
+__device__ inline Desc<float> load_desc(const DescPtrs& d, int64_t i)
+{
+    Desc<float> x;
+    x.F = ntload(d.F + i);
+    x.B = ntload(d.B + i);
+    x.r1 = ntload(d.r1 + i);
+    x.r2 = ntload(d.r2 + i);
+    x.r3 = ntload(d.r3 + i);
+    x.K = ntload(d.K + i);
+    x.u = ntload(d.u + i);
+    x.W = ntload(d.W + i);
+    x.v = ntload(d.vgpr + i);
+    x.s = ntload(d.lds + i);
+    x.gp = ntload(d.gpack + i);
+    x.G = ntload(d.grid + i);
+    return x;
+}
+
+__device__ inline Desc<double> widen(const Desc<float>& x)
+{
+    Desc<double> y;
+    y.F = x.F; y.B = x.B; y.r1 = x.r1; y.r2 = x.r2; y.r3 = x.r3; y.K = x.K; y.u = x.u; y.W = x.W;
+    y.v = x.v; y.s = x.s; y.gp = x.gp; y.G = x.G;
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// forward sweep
+// ---------------------------------------------------------------------------
+template <int VEC>
+__global__ __launch_bounds__(256) void k_predict(DescPtrs d, int64_t n, Set S,
+                                                  float* __restrict__ T, int32_t* __restrict__ occ)
+{
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    if (i0 >= n) return;
+    if (VEC == 4 && i0 + 4 <= n) {
+        const f4 F = ntload((const f4*)(d.F + i0));
+        const f4 B = ntload((const f4*)(d.B + i0));
+        const f4 r1 = ntload((const f4*)(d.r1 + i0));
+        const f4 r2 = ntload((const f4*)(d.r2 + i0));
+        const f4 r3 = ntload((const f4*)(d.r3 + i0));
+        const f4 K = ntload((const f4*)(d.K + i0));
+        const f4 u = ntload((const f4*)(d.u + i0));
+        const f4 W = ntload((const f4*)(d.W + i0));
+        const i4 v = ntload((const i4*)(d.vgpr + i0));
+        const i4 s = ntload((const i4*)(d.lds + i0));
+        const i4 gp = ntload((const i4*)(d.gpack + i0));
+        const i4 G = ntload((const i4*)(d.grid + i0));
+        f4 t;
+        i4 o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Desc<float> x;
+            x.F = F[j]; x.B = B[j]; x.r1 = r1[j]; x.r2 = r2[j]; x.r3 = r3[j];
+            x.K = K[j]; x.u = u[j]; x.W = W[j]; x.v = v[j]; x.s = s[j]; x.gp = gp[j]; x.G = G[j];
+            Eval<float> E;
+            evaluate<float, false>(S.st, S.cf, x, E);
+            t[j] = E.T;
+            o[j] = E.occ;
+        }
+        __builtin_nontemporal_store(t, (f4*)(T + i0));
+        if (occ) __builtin_nontemporal_store(o, (i4*)(occ + i0));
+    } else {
+        for (int j = 0; j < VEC; ++j) {
+            const int64_t i = i0 + j;
+            if (i >= n) break;
+            Desc<float> x = load_desc(d, i);
+            Eval<float> E;
+            evaluate<float, false>(S.st, S.cf, x, E);
+            __builtin_nontemporal_store(E.T, T + i);
+            if (occ) __builtin_nontemporal_store(E.occ, occ + i);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_roofline(DescPtrs d, int64_t n, Set S,
+                                                   float* __restrict__ T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Desc<float> x = load_desc(d, i);
+    float r = __builtin_nanf("");
+    if (desc_valid(x)) {
+        const int dt = (x.gp >> 11) & 7;
+        float ip = S.cf.inv_peak[0];
+        ip = dt == 1 ? S.cf.inv_peak[1] : ip;
+        ip = dt == 2 ? S.cf.inv_peak[2] : ip;
+        ip = dt == 3 ? S.cf.inv_peak[3] : ip;
+        ip = dt == 4 ? S.cf.inv_peak[4] : ip;
+        const float tc = x.F * ip;
+        const float tb = x.B * __builtin_amdgcn_rcpf(S.cf.bw[3]);
+        r = tc > tb ? tc : tb;
+    }
+    T[i] = r;
+}
+
+hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
+                          bool vec4, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int per = vec4 ? 4 : 1;
+    const int64_t threads = (n + per - 1) / per;
+    const int64_t blocks = (threads + 255) / 256;
+    if (vec4)
+        k_predict<4><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(d, n, S, T, occ);
+    else
+        k_predict<1><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(d, n, S, T, occ);
+    return hipGetLastError();
+}
+
+hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    k_roofline<<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(d, n, S, T);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// block reduction of the 26 FP64 accumulators (fixed order)
+// ---------------------------------------------------------------------------
+__device__ inline void block_reduce_acc(double* acc, double* lds /* [4][26] */, double* out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        acc[j] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) lds[wid * kAcc + j] = acc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < kAcc) {
+        const int nw = blockDim.x >> 6;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * kAcc + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// one descriptor's contribution: mode 0 weight = dL/dT, mode 1 mean relative error
+template <int MODE>
+__device__ inline void grad_one(const Set& S, const Desc<float>& x, float wi, double* acc)
+{
+    Eval<float> E;
+    evaluate<float, true>(S.st, S.cf, x, E);
+    if (!(E.T < __builtin_huge_valf())) return;  // invalid (NaN) or infeasible (+inf)
+    bool redo = E.near_kink;
+    double w;
+    if (MODE == 1) {
+        if (!(wi > 0.0f && wi < __builtin_huge_valf())) return;
+        const float rho = E.T * __builtin_amdgcn_rcpf(wi) - 1.0f;
+        redo = redo || (__builtin_fabsf(rho) <= 1e-5f);
+    }
+    if (!redo) {
+        if (MODE == 1) {
+            const double m = wi, im = 1.0 / m, Td = E.T;
+            acc[0] += __builtin_fabs(Td - m) * im;
+            acc[1] += 1.0;
+            w = Td > m ? im : (Td < m ? -im : 0.0);
+        } else {
+            w = wi;
+        }
+        accumulate_partials<float, double>(S.st, S.cf, E, w, acc);
+    } else {
+        // float64 re-evaluation decides the loss sign and the active branch
+        Eval<double> D;
+        evaluate<double, true>(S.st, S.cd, widen(x), D);
+        if (MODE == 1) {
+            const double m = wi, im = 1.0 / m;
+            acc[0] += __builtin_fabs(D.T - m) * im;
+            acc[1] += 1.0;
+            w = D.T > m ? im : (D.T < m ? -im : 0.0);
+        } else {
+            w = wi;
+        }
+        accumulate_partials<double, double>(S.st, S.cd, D, w, acc);
+    }
+}
+
+template <int MODE, bool PTR>
+__global__ __launch_bounds__(256) void k_grad(DescPtrs d, int64_t n, const float* __restrict__ wv,
+                                               Set sv, const Set* __restrict__ sp,
+                                               double* __restrict__ partials)
+{
+    __shared__ double red[4 * kAcc];
+    const Set& S = PTR ? *sp : sv;
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        Desc<float> x = load_desc(d, i);
+        const float wi = ntload(wv + i);
+        grad_one<MODE>(S, x, wi, acc);
+    }
+    block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
+}
+
+// Fixed-order sum of the per-block partials: thread t adds blocks t, t+256,
+// ...; then a tree over the 256 threads.  mode 1 divides by the count.
+__device__ inline void reduce_partials(const double* __restrict__ partials, int nb, int stride,
+                                       double* sh /* [256] */, double* tot /* [26] */)
+{
+    for (int j = 0; j < kAcc; ++j) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(int64_t)b * stride + j];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int m = blockDim.x >> 1; m >= 1; m >>= 1) {
+            if ((int)threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[j] = sh[0];
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int nb,
+                                                 double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    __shared__ double tot[kAcc];
+    reduce_partials(partials, nb, kAcc, sh, tot);
+    if (threadIdx.x < kAcc) {
+        if (MODE == 1) {
+            const double c = tot[1];
+            const double v = tot[threadIdx.x];
+            out[threadIdx.x] = (threadIdx.x == 1 || c == 0.0) ? v : v / c;
+        } else if (threadIdx.x >= 2) {
+            out[threadIdx.x - 2] = tot[threadIdx.x];
+        }
+    }
+}
+
+int grad_blocks(int64_t n)
+{
+    int64_t b = (n + 1023) / 1024;
+    if (b > kGradMaxBlocks) b = kGradMaxBlocks;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                       const Set* S_dev, double* partials, int nb, double* out, hipStream_t stream)
+{
+    if (mode == 1) {
+        if (S_dev)
+            k_grad<1, true><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+        else
+            k_grad<1, false><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+    } else {
+        if (S_dev)
+            k_grad<0, true><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+        else
+            k_grad<0, false><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !out) return e;
+    if (mode == 1)
+        k_reduce<1><<<1, 256, 0, stream>>>(partials, nb, out);
+    else
+        k_reduce<0><<<1, 256, 0, stream>>>(partials, nb, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// device Adam on log(theta)
+// ---------------------------------------------------------------------------
+// state: theta, phi, m, v (24 each), theta_last_finite (24), flags
+__device__ inline void adam_update(CalibState* st, const double* tot, const AdamOpts& o, Set* S,
+                                   double* loss_hist)
+{
+    // thread 0 of the calling block does the update (24 values); the step
+    // index lives in device memory so one captured graph serves every chunk
+    // of steps
+    if (threadIdx.x != 0) return;
+    const int step_index = st->t;
+    st->t = step_index + 1;
+    const double cnt = tot[1];
+    const double loss = cnt > 0.0 ? tot[0] / cnt : 0.0;
+    if (loss_hist && step_index < o.steps)
+        loss_hist[step_index] = st->diverged ? __builtin_nan("") : loss;
+    if (st->diverged) return;
+    bool finite = __builtin_isfinite(loss);
+    double g[kTheta];
+    for (int j = 0; j < kTheta; ++j) {
+        g[j] = cnt > 0.0 ? tot[2 + j] / cnt : 0.0;
+        finite = finite && __builtin_isfinite(g[j]);
+    }
+    if (!finite) {
+        st->diverged = 1;
+        return;
+    }
+    for (int j = 0; j < kTheta; ++j) st->theta_ok[j] = st->theta[j];
+    const double t = (double)(step_index + 1);
+    double lr = o.lr;
+    if (o.lr_final > 0.0 && o.steps > 1)
+        lr = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
+    const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
+    double th_new[kTheta];
+    bool ok = true;
+    for (int j = 0; j < kTheta; ++j) {
+        th_new[j] = st->theta[j];
+        if (!((o.free_mask >> j) & 1u)) continue;
+        const double gp = st->theta[j] * g[j];
+        st->m[j] = o.beta1 * st->m[j] + (1.0 - o.beta1) * gp;
+        st->v[j] = o.beta2 * st->v[j] + (1.0 - o.beta2) * gp * gp;
+        const double mh = st->m[j] / (1.0 - b1t);
+        const double vh = st->v[j] / (1.0 - b2t);
+        st->phi[j] -= lr * mh / (sqrt(vh) + o.eps);
+        th_new[j] = exp(st->phi[j]);
+        ok = ok && __builtin_isfinite(th_new[j]) && th_new[j] > 0.0;
+    }
+    if (!ok) {
+        st->diverged = 1;
+        return;
+    }
+    for (int j = 0; j < kTheta; ++j) st->theta[j] = th_new[j];
+    make_const<float>(st->theta, S->st, S->cf);
+    make_const<double>(st->theta, S->st, S->cd);
+}
+
+__global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partials, int nb,
+                                               CalibState* st, AdamOpts o, Set* S,
+                                               double* loss_hist)
+{
+    __shared__ double sh[256];
+    __shared__ double tot[kAcc];
+    reduce_partials(partials, nb, kAcc, sh, tot);
+    adam_update(st, tot, o, S, loss_hist);
+}
+
+hipError_t launch_adam(const double* partials, int nb, CalibState* st, const AdamOpts& o, Set* S,
+                       double* loss_hist, hipStream_t stream)
+{
+    k_adam<<<1, 256, 0, stream>>>(partials, nb, st, o, S, loss_hist);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// multi-set calibration sweep: one persistent launch over a (set, chunk)
+// work list; per-block, per-set accumulators staged in LDS
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict__ sets,
+                                                       const float* const* __restrict__ meas,
+                                                       const Set* __restrict__ S_all,
+                                                       const WorkItem* __restrict__ items,
+                                                       int n_items, int n_sets,
+                                                       double* __restrict__ partials)
+{
+    __shared__ double red[4 * kAcc];
+    __shared__ double tot[kAcc];
+    __shared__ double per_set[kMaxSets * kAcc];
+    for (int j = threadIdx.x; j < n_sets * kAcc; j += blockDim.x) per_set[j] = 0.0;
+    __syncthreads();
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int it0 = (int)((int64_t)n_items * b / nb);
+    const int it1 = (int)((int64_t)n_items * (b + 1) / nb);
+    int cur = -1;
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int it = it0; it < it1; ++it) {
+        const WorkItem w = items[it];
+        if (w.set != cur) {
+            if (cur >= 0) {
+                block_reduce_acc(acc, red, tot);
+                if (threadIdx.x < kAcc) per_set[cur * kAcc + threadIdx.x] += tot[threadIdx.x];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+            }
+            cur = w.set;
+        }
+        const DescPtrs d = sets[w.set];
+        const float* m = meas[w.set];
+        const Set& S = S_all[w.set];
+        for (int64_t i = w.begin + threadIdx.x; i < w.end; i += blockDim.x) {
+            Desc<float> x = load_desc(d, i);
+            grad_one<1>(S, x, ntload(m + i), acc);
+        }
+    }
+    if (cur >= 0) {
+        block_reduce_acc(acc, red, tot);
+        if (threadIdx.x < kAcc) per_set[cur * kAcc + threadIdx.x] += tot[threadIdx.x];
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < n_sets * kAcc; j += blockDim.x)
+        partials[(int64_t)b * n_sets * kAcc + j] = per_set[j];
+}
+
+__global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__ partials, int nb,
+                                                       int n_sets, CalibState* st,
+                                                       const AdamOpts* __restrict__ opts,
+                                                       Set* S_all, int steps, double* loss_hist)
+{
+    __shared__ double sh[256];
+    __shared__ double tot[kAcc];
+    const int s = blockIdx.x;
+    reduce_partials(partials + s * kAcc, nb, n_sets * kAcc, sh, tot);
+    adam_update(st + s, tot, opts[s], S_all + s,
+                loss_hist ? loss_hist + (int64_t)s * steps : nullptr);
+}
+
+hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
+                               const WorkItem* items, int n_items, int n_sets, double* partials,
+                               int nb, hipStream_t stream)
+{
+    k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, items, n_items, n_sets, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_batched(const double* partials, int nb, int n_sets, CalibState* st,
+                               const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
+                               hipStream_t stream)
+{
+    k_adam_batched<<<n_sets, 256, 0, stream>>>(partials, nb, n_sets, st, opts, S_all, steps,
+                                                loss_hist);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tile selection
+// ---------------------------------------------------------------------------
+// GEMM tile -> descriptor (integers exact in 64 bits; F, B rounded to R)
+template <typename R>
+__device__ inline bool derive_tile(int32_t M, int32_t N, int32_t Kd, int32_t t, uint32_t code,
+                                   int wave_shift, Desc<R>& x)
+{
+    const uint32_t kdc = (code >> 4) & 3u;
+    if ((code >> 9) != 0u || kdc == 3u || M < 1 || N < 1 || Kd < 1 || t < 0 || t > 3) return false;
+    const int64_t mt = 32ll << (code & 3u), nt = 32ll << ((code >> 2) & 3u), kd = 16ll << kdc;
+    const int64_t wpw = ((code >> 6) & 7u) + 1;
+    const int64_t e = 8 >> t;                 // 8, 4, 2, 1 bytes
+    const int64_t eo = t == 3 ? 2 : e;        // fp8 writes 16-bit results
+    const int64_t acc = t == 0 ? 2 : 1;
+    const int64_t gm = (M + mt - 1) / mt, gn = (N + nt - 1) / nt;
+    const int64_t G = gm * gn, Ks = (Kd + kd - 1) / kd;
+    const int64_t g = wpw << wave_shift;
+    if (G > 0x7fffffffll || g > 1024) return false;
+    const int64_t Fi = 2 * (gm * mt) * (gn * nt) * (Ks * kd);
+    const int64_t Bi = G * Ks * (mt + nt) * kd * e + (int64_t)M * N * eo;
+    const int64_t Ui = ((int64_t)M * Kd + (int64_t)Kd * N) * e + (int64_t)M * N * eo;
+    x.F = (R)Fi;
+    x.B = (R)Bi;
+    const R r2 = (R)1 - (R)Ui * Ar<R>::rcp((R)Bi);
+    x.r2 = r2 > (R)0 ? r2 : (R)0;
+    x.r1 = (R)0;
+    x.r3 = (R)0;
+    x.K = (R)Ks;
+    x.u = (R)1;
+    x.W = (R)0;
+    x.v = (int32_t)((mt * nt * acc + g - 1) / g + ((mt + nt) * kd * e + 4 * g - 1) / (4 * g) + 16);
+    x.s = (int32_t)(2 * (mt + nt) * kd * e);
+    x.gp = (int32_t)g | (t << 11);
+    x.G = (int32_t)G;
+    return true;
+}
+
+template <typename R> __device__ inline const Const<R>& cst(const Set& S);
+template <> __device__ inline const Const<float>& cst<float>(const Set& S) { return S.cf; }
+template <> __device__ inline const Const<double>& cst<double>(const Set& S) { return S.cd; }
+
+// cost of one candidate; invalid codes and infeasible tiles cost +inf
+template <typename R>
+__device__ inline R tile_cost(const Set& S, int32_t M, int32_t N, int32_t K, int32_t t, uint32_t code)
+{
+    const R inf = (R)__builtin_huge_val();
+    Desc<R> x;
+    if (!derive_tile<R>(M, N, K, t, code, S.st.wave_shift, x)) return inf;
+    Eval<R> E;
+    evaluate<R, false>(S.st, cst<R>(S), x, E);
+    return E.T == E.T ? E.T : inf;
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One wave per shape (persistent over shapes).  Pass 1 takes the float32
+// minimum with a packed (cost bits, local index) key; pass 2 re-evaluates in
+// float64 every candidate whose float32 cost is within kTileWindow of that
+// minimum and keeps the smallest and second-smallest float64 costs, the
+// lowest index winning exact ties.
+__global__ __launch_bounds__(256) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ code, int64_t n,
+                                                      int64_t n_cand,
+                                                      Set S, int32_t* __restrict__ best,
+                                                      double* __restrict__ best_cost,
+                                                      uint8_t* __restrict__ near_tie)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+    const double dinf = __builtin_huge_val();
+    for (int64_t i = wave; i < n; i += nwaves) {
+        const int32_t M = sh.M[i], N = sh.N[i], K = sh.K[i], t = sh.dtype[i];
+        // offsets are caller data: clamp them into the candidate array
+        int64_t a = off[i], b = off[i + 1];
+        a = a < 0 ? 0 : (a > n_cand ? n_cand : a);
+        b = b < a ? a : (b > n_cand ? n_cand : b);
+        uint64_t key = ~0ull;
+        for (int64_t j = a + lane; j < b; j += 64) {
+            const float c = tile_cost<float>(S, M, N, K, t, code[j]);
+            const uint64_t k = ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)(j - a);
+            key = k < key ? k : key;
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            const uint64_t o = shfl_xor_u64(key, m);
+            key = o < key ? o : key;
+        }
+        const float c32 = __uint_as_float((uint32_t)(key >> 32));
+        if (key == ~0ull || !(c32 < __builtin_huge_valf())) {
+            if (lane == 0) {
+                best[i] = -1;
+                best_cost[i] = dinf;
+                near_tie[i] = 0;
+            }
+            continue;
+        }
+        const float thr = c32 * (1.0f + kTileWindow);
+        double c1 = dinf, c2 = dinf;
+        int32_t j1 = 0x7fffffff;
+        for (int64_t j = a + lane; j < b; j += 64) {
+            const float c = tile_cost<float>(S, M, N, K, t, code[j]);
+            if (!(c <= thr)) continue;
+            const double cd = tile_cost<double>(S, M, N, K, t, code[j]);
+            const int32_t jl = (int32_t)(j - a);
+            if (cd < c1 || (cd == c1 && jl < j1)) {
+                c2 = c1;
+                c1 = cd;
+                j1 = jl;
+            } else if (cd < c2) {
+                c2 = cd;
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            const double oc1 = __shfl_xor(c1, m, 64);
+            const double oc2 = __shfl_xor(c2, m, 64);
+            const int32_t oj1 = __shfl_xor(j1, m, 64);
+            if (oc1 < c1 || (oc1 == c1 && oj1 < j1)) {
+                c2 = c1 < oc2 ? c1 : oc2;
+                c1 = oc1;
+                j1 = oj1;
+            } else {
+                c2 = oc1 < c2 ? oc1 : c2;
+            }
+        }
+        if (lane == 0) {
+            const bool fin = c1 < dinf;
+            best[i] = fin ? j1 : -1;
+            best_cost[i] = c1;
+            near_tie[i] = (fin && c2 < dinf && (c2 - c1) <= 1e-6 * c1) ? 1 : 0;
+        }
+    }
+}
+
+hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
+                              int64_t n, int64_t n_cand, const Set& S, int32_t* best,
+                              double* best_cost, uint8_t* near_tie, int blocks,
+                              hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    if (blocks <= 0) {
+        int64_t b = (n + 3) / 4;
+        blocks = (int)(b < kTileMaxBlocks ? b : kTileMaxBlocks);
+    }
+    k_select_tile<<<blocks, 256, 0, stream>>>(sh, off, code, n, n_cand, S, best, best_cost,
+                                               near_tie);
+    return hipGetLastError();
+}
+
+}  // namespace wm

@@ -1,0 +1,75 @@
+// wm_launch.hpp -- internal interface between the C ABI layer (wm_api.cpp)
+// and the kernels (wm_kernels.hip).  Not installed; the public interface is
+// include/wavemodel.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wm_model.hpp"
+
+namespace wm {
+
+constexpr int kGradMaxBlocks = 1024;   // persistent gradient grid cap
+constexpr int kTileMaxBlocks = 2048;   // persistent tile-selection grid cap
+constexpr int kMaxSets = 16;           // parameter sets per batched calibration
+constexpr float kTileWindow = 3e-5f;   // float32 window re-evaluated in float64
+
+struct DescPtrs {
+    const float *F, *B, *r1, *r2, *r3, *K, *u, *W;
+    const int32_t *vgpr, *lds, *gpack, *grid;
+};
+
+struct ShapePtrs {
+    const int32_t *M, *N, *K, *dtype;
+};
+
+struct AdamOpts {
+    int32_t steps, pad_;
+    double lr, lr_final, beta1, beta2, eps;
+    uint32_t free_mask, pad2_;
+};
+
+// device-resident calibration state of one parameter set
+struct CalibState {
+    double theta[kTheta];
+    double theta_ok[kTheta];  // theta of the last step whose loss was finite
+    double phi[kTheta];
+    double m[kTheta];
+    double v[kTheta];
+    int32_t diverged;  // set once the loss, a gradient or theta left the finite range
+    int32_t t;         // index of the next step
+};
+
+struct WorkItem {
+    int32_t set, pad_;
+    int64_t begin, end;
+};
+
+int grad_blocks(int64_t n);
+
+hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
+                          bool vec4, hipStream_t stream);
+hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
+                           hipStream_t stream);
+// mode 0: weights are dL/dT, out = dL/dtheta[24]; mode 1: weights are measured
+// times, out = [loss, count, grad[24]].  S_dev != nullptr reads the set from
+// device memory (graph replay with a changing theta).  out == nullptr skips
+// the final reduction.
+hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                       const Set* S_dev, double* partials, int nb, double* out,
+                       hipStream_t stream);
+hipError_t launch_adam(const double* partials, int nb, CalibState* st, const AdamOpts& o, Set* S,
+                       double* loss_hist, hipStream_t stream);
+hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
+                               const WorkItem* items, int n_items, int n_sets, double* partials,
+                               int nb, hipStream_t stream);
+hipError_t launch_adam_batched(const double* partials, int nb, int n_sets, CalibState* st,
+                               const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
+                               hipStream_t stream);
+hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
+                              int64_t n, int64_t n_cand, const Set& S, int32_t* best,
+                              double* best_cost, uint8_t* near_tie, int blocks,
+                              hipStream_t stream);
+
+}  // namespace wm

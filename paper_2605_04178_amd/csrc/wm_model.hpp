@@ -1,0 +1,364 @@
+// wm_model.hpp -- per-descriptor evaluation of the CDNA wavefront-centric
+// execution-time model (Section IV-B), templated on the arithmetic type:
+// float for the bulk sweeps, double for the rare re-evaluations that decide a
+// subgradient, a loss sign or a near-tied tile.
+//
+// The terms, in the order they are evaluated:
+//   occupancy  o = min(VGPR limit, wave-slot limit, LDS limit) workgroups/CU,
+//              generalising the VGPR-limited wavefront count of Section IV-B;
+//   rounds     n_r = ceil(G / (N_CU o)), the N_ctas/(N_CU W_eff) of Eq. (14);
+//   traffic    served fractions s_l = h_l prod_{m<l}(1 - h_m) (Eq. (10)), the
+//              LLC hit rate from Table "hlcc-piecewise" when W > 0, the HBM
+//              bandwidth blended by Eq. (16);
+//   stages     T_c = F/(u P) (Eq. (11)), T_b = B / sum s_l BW_l,
+//              T_lat = n_r (B / (G k L_w)) sum s_l Lat_l / f (Eq. (10) x rounds);
+//   combine    max of the stages (Eq. (1), Eq. (14)) or the occupancy-overlap
+//              step (Eq. (9), Eq. (12)), plus the overheads of Eq. (13),
+//              Eq. (14), the interference / multi-GPU / fusion terms of
+//              Section IV-B and the per-sync term of Section IV-E.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WM_HD __host__ __device__ inline
+
+namespace wm {
+
+constexpr int kTheta = 24;
+constexpr int kAcc = 26;  // loss, count, 24 gradient slots
+
+// structural integers of a parameter set, as the kernels use them
+struct Struct {
+    int32_t n_levels, n_cu, n_simd, wave_shift, vgpr_simd, vgpr_gran_mask, waves_simd, lds_cu,
+        lds_gran_mask, mwp, cwp, combine, bytes_inflight_wave, pad_;
+    double f_clk, w_lo_mib, c_llc_mib;
+};
+
+// theta-derived constants in the arithmetic type R
+template <typename R>
+struct Const {
+    R inv_peak[5];
+    R bw[4];     // L1, L2, LLC, HBM
+    R latf[4];   // Lat_l / f_clk, seconds
+    R ov[7];     // T_launch, tau_wg, tau_bar, tau_interf, tau_gpu, tau_fusion, tau_sync
+    R alpha, beta;
+    R inv_w0;    // 1 / w0 when the Eq. (16) blend is on, else 0
+    R bp_minus_bw;
+    R inv_lw;    // 1 / bytes in flight per wave
+    R inv_f;     // 1 / f_clk
+    R w_lo, c_llc, inv_span;  // MiB
+    int32_t blend_on, pad_;
+};
+
+// Everything a kernel needs about one parameter set.
+struct Set {
+    Struct st;
+    Const<float> cf;
+    Const<double> cd;
+};
+
+template <typename R>
+WM_HD void make_const(const double* th, const Struct& s, Const<R>& c)
+{
+    for (int t = 0; t < 5; ++t) c.inv_peak[t] = (R)(1.0 / th[8 + t]);
+    for (int l = 0; l < 4; ++l) {
+        c.bw[l] = (R)th[l];
+        c.latf[l] = (R)(th[4 + l] / s.f_clk);
+    }
+    for (int j = 0; j < 7; ++j) c.ov[j] = (R)th[13 + j];
+    c.alpha = (R)th[20];
+    c.beta = (R)th[21];
+    c.blend_on = th[22] > 0.0 ? 1 : 0;
+    c.inv_w0 = c.blend_on ? (R)(1.0 / th[22]) : (R)0;
+    c.bp_minus_bw = (R)(th[23] - th[3]);
+    c.inv_lw = (R)(1.0 / (double)s.bytes_inflight_wave);
+    c.inv_f = (R)(1.0 / s.f_clk);
+    c.w_lo = (R)s.w_lo_mib;
+    c.c_llc = (R)s.c_llc_mib;
+    c.inv_span = (R)(1.0 / (s.c_llc_mib - s.w_lo_mib));
+    c.pad_ = 0;
+}
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers: hardware reciprocal in float, IEEE division in double
+// ---------------------------------------------------------------------------
+template <typename R> struct Ar;
+template <> struct Ar<float> {
+    static __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ inline float pw(float x, float y) { return powf(x, y); }
+    static __device__ inline float ex(float x) { return expf(x); }
+    static __device__ inline float lg(float x) { return logf(x); }
+};
+template <> struct Ar<double> {
+    static __device__ inline double rcp(double x) { return 1.0 / x; }
+    static __device__ inline double pw(double x, double y) { return pow(x, y); }
+    static __device__ inline double ex(double x) { return exp(x); }
+    static __device__ inline double lg(double x) { return log(x); }
+};
+
+template <typename R>
+struct Desc {
+    R F, B, r1, r2, r3, K, u, W;
+    int32_t v, s, gp, G;
+};
+
+// ---------------------------------------------------------------------------
+// occupancy (exact integers)
+// ---------------------------------------------------------------------------
+struct Occ {
+    int32_t o, k;
+};
+
+__device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t g)
+{
+    Occ r;
+    r.k = (g + (1 << st.wave_shift) - 1) >> st.wave_shift;
+    int32_t w = 0;
+    if (v <= st.vgpr_simd) {
+        int32_t va = (v + st.vgpr_gran_mask) & ~st.vgpr_gran_mask;
+        w = (uint32_t)st.vgpr_simd / (uint32_t)va;
+        w = w < st.waves_simd ? w : st.waves_simd;
+    }
+    int32_t o = (uint32_t)(st.n_simd * w) / (uint32_t)r.k;
+    if (s > 0) {
+        int32_t ol = 0;
+        if (s <= st.lds_cu) {
+            int32_t sa = (s + st.lds_gran_mask) & ~st.lds_gran_mask;
+            ol = (uint32_t)st.lds_cu / (uint32_t)sa;
+        }
+        o = o < ol ? o : ol;
+    }
+    r.o = o;
+    return r;
+}
+
+template <typename R>
+__device__ inline bool desc_valid(const Desc<R>& d)
+{
+    const R inf = (R)__builtin_huge_val();
+    bool ok = (d.F >= (R)0) & (d.F < inf) & (d.B >= (R)0) & (d.B < inf) & (d.K >= (R)0) &
+              (d.K < inf) & (d.W >= (R)0) & (d.W < inf) & (d.u > (R)0) & (d.u <= (R)1) &
+              (d.r1 >= (R)0) & (d.r1 <= (R)1) & (d.r2 >= (R)0) & (d.r2 <= (R)1) &
+              (d.r3 >= (R)0) & (d.r3 <= (R)1) & (d.v >= 1) & (d.s >= 0) & (d.G >= 1) &
+              ((uint32_t)d.gp < (1u << 25));
+    int32_t g = d.gp & 2047;
+    int32_t dt = (d.gp >> 11) & 7;
+    ok = ok & (g >= 1) & (g <= 1024) & (dt <= 4);
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// one evaluation
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Eval {
+    R T;
+    int32_t occ;       // -1 invalid, 0 infeasible, else o
+    int32_t dt, nr, G;
+    int32_t cnt[4];    // n_conc - 1, n_dev - 1, fused, n_sync
+    int32_t llc_regime;  // 0 none/resident, 1 transition, 2 streaming
+    R h3, s1, s2, s3, sh, a12, S, Lf, e, bwh, W;
+    R Tc, Tb, Tlat, Tm;
+    R wc, wb, wl;      // dT/dT_c, dT/dT_b, dT/dT_lat
+    R nrK, base_log;   // n_r K; ln(base) (transition) or ln(C/W_MiB) (streaming)
+    R q;               // n_r * B / (G k L_w): serialised load batches
+    bool near_kink;    // within 1e-5 relative of a max/min switch
+};
+
+template <typename R, bool FULL>
+__device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<R>& d, Eval<R>& E)
+{
+    typedef Ar<R> A;
+    E.T = (R)__builtin_nan("");
+    E.occ = -1;
+    if (!desc_valid(d)) return;
+    const int32_t g = d.gp & 2047;
+    const int32_t dt = (d.gp >> 11) & 7;
+    E.dt = dt;
+    E.cnt[0] = (d.gp >> 14) & 7;
+    E.cnt[1] = (d.gp >> 17) & 7;
+    E.cnt[2] = (d.gp >> 20) & 1;
+    E.cnt[3] = (d.gp >> 21) & 15;
+    E.G = d.G;
+
+    Occ oc = occupancy(st, d.v, d.s, g);
+    E.occ = oc.o;
+    if (oc.o == 0) {
+        E.T = (R)__builtin_huge_val();
+        return;
+    }
+    const uint32_t per_round = (uint32_t)st.n_cu * (uint32_t)oc.o;
+    const int32_t nr = (int32_t)(((uint32_t)d.G + per_round - 1u) / per_round);
+    E.nr = nr;
+
+    // traffic split
+    R h3 = d.r3;
+    E.llc_regime = 0;
+    E.base_log = (R)0;
+    if (st.n_levels == 4 && d.W > (R)0) {
+        const R Wm = d.W * (R)(1.0 / 1048576.0);
+        if (Wm < c.w_lo) {
+            h3 = (R)1;
+        } else if (Wm <= c.c_llc) {
+            // (1 - (W - W_lo)/(C - W_lo)) written as (C - W)/(C - W_lo): same
+            // value, no cancellation near C
+            const R base = (c.c_llc - Wm) * c.inv_span;
+            h3 = A::pw(base, c.alpha);
+            E.llc_regime = 1;
+            if (FULL) E.base_log = base > (R)0 ? A::lg(base) : (R)0;
+        } else {
+            const R ratio = c.c_llc * A::rcp(Wm);
+            h3 = A::pw(ratio, c.beta);
+            E.llc_regime = 2;
+            if (FULL) E.base_log = A::lg(ratio);
+        }
+    }
+    const R m1 = (R)1 - d.r1;
+    const R s1 = d.r1;
+    const R s2 = m1 * d.r2;
+    const R a12 = m1 * ((R)1 - d.r2);
+    R s3 = (R)0, sh = a12;
+    if (st.n_levels == 4) {
+        s3 = a12 * h3;
+        sh = a12 * ((R)1 - h3);
+    }
+    R e = (R)0, bwh = c.bw[3];
+    if (c.blend_on && d.W > (R)0) {
+        e = A::ex(-d.W * c.inv_w0);
+        bwh = c.bw[3] + c.bp_minus_bw * e;
+    }
+    const R S = s1 * c.bw[0] + s2 * c.bw[1] + s3 * c.bw[2] + sh * bwh;
+    const R Lf = s1 * c.latf[0] + s2 * c.latf[1] + s3 * c.latf[2] + sh * c.latf[3];
+
+    // stage times
+    R ip = c.inv_peak[0];
+    ip = dt == 1 ? c.inv_peak[1] : ip;
+    ip = dt == 2 ? c.inv_peak[2] : ip;
+    ip = dt == 3 ? c.inv_peak[3] : ip;
+    ip = dt == 4 ? c.inv_peak[4] : ip;
+    const R Tc = d.F * ip * A::rcp(d.u);
+    const R Tb = d.B * A::rcp(S);
+    const R q = (R)nr * d.B * A::rcp((R)d.G * (R)oc.k) * c.inv_lw;
+    const R Tlat = q * Lf;
+
+    const R nrK = (R)nr * d.K;
+    const R Tov = c.ov[0] + c.ov[1] * (R)d.G + c.ov[2] * nrK + (R)E.cnt[0] * c.ov[3] +
+                  (R)E.cnt[1] * c.ov[4] + (R)E.cnt[2] * c.ov[5] + (R)E.cnt[3] * c.ov[6];
+
+    R wc = (R)0, wb = (R)0, wl = (R)0, step;
+    const bool mem_b = Tb >= Tlat;
+    const R Tm = mem_b ? Tb : Tlat;
+    bool near = false;
+    const R tol = (R)1e-5;
+    if (st.combine == 0) {
+        if (Tc >= Tb && Tc >= Tlat) {
+            step = Tc;
+            wc = (R)1;
+            if (FULL) near = (Tc - Tm) <= tol * Tc;
+        } else {
+            step = Tm;
+            if (mem_b) wb = (R)1; else wl = (R)1;
+            if (FULL) {
+                const R second = Tc > (mem_b ? Tlat : Tb) ? Tc : (mem_b ? Tlat : Tb);
+                near = (Tm - second) <= tol * Tm;
+            }
+        }
+    } else {
+        int32_t neff = oc.o * oc.k;
+        if (st.mwp > 0) neff = neff < st.mwp ? neff : st.mwp;
+        if (st.cwp > 0) neff = neff < st.cwp ? neff : st.cwp;
+        const R a = (R)(neff - 1);
+        R dTc, dTm;
+        R eta;
+        if (neff == 1) {
+            eta = (R)0;
+            dTc = (R)1;
+            dTm = (R)1;
+        } else if (a * Tc >= Tm) {
+            eta = (R)1;
+            dTc = (R)0.5;
+            dTm = (R)0.5;
+        } else {
+            eta = a * Tc * A::rcp(Tm);
+            const R den = Tm + a * Tc;
+            const R iden2 = A::rcp(den * den);
+            dTc = Tm * Tm * ((R)1 - a) * iden2;
+            dTm = (Tm * Tm + (R)2 * a * Tm * Tc + a * Tc * Tc) * iden2;
+        }
+        const R num = Tm + Tc;
+        step = num == (R)0 ? (R)0 : num * A::rcp((R)1 + eta);
+        wc = dTc;
+        if (mem_b) wb = dTm; else wl = dTm;
+        if (FULL) {
+            const R mn = mem_b ? Tlat : Tb;
+            near = (Tm - mn) <= tol * Tm;
+            if (neff > 1) {
+                const R sw = a * Tc - Tm;
+                near = near || ((sw < (R)0 ? -sw : sw) <= tol * Tm);
+            }
+        }
+    }
+    E.T = Tov + step;
+    if (FULL) {
+        E.h3 = h3; E.s1 = s1; E.s2 = s2; E.s3 = s3; E.sh = sh; E.a12 = a12;
+        E.S = S; E.Lf = Lf; E.e = e; E.bwh = bwh; E.W = d.W;
+        E.Tc = Tc; E.Tb = Tb; E.Tlat = Tlat; E.Tm = Tm;
+        E.wc = wc; E.wb = wb; E.wl = wl; E.nrK = nrK; E.q = q;
+        E.near_kink = near;
+    }
+}
+
+// dT/dtheta_j of an evaluated descriptor times `w`, added into acc[2 + j]
+template <typename R, typename Acc>
+__device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E,
+                                           Acc w, Acc* acc)
+{
+    typedef Ar<R> A;
+    // overhead slots: data only
+    acc[2 + 13] += w;
+    acc[2 + 14] += w * (Acc)E.G;
+    acc[2 + 15] += w * (Acc)E.nrK;
+    acc[2 + 16] += w * (Acc)E.cnt[0];
+    acc[2 + 17] += w * (Acc)E.cnt[1];
+    acc[2 + 18] += w * (Acc)E.cnt[2];
+    acc[2 + 19] += w * (Acc)E.cnt[3];
+    // compute: d(F/(uP))/dP = -T_c / P
+    R ipk = c.inv_peak[0];
+    ipk = E.dt == 1 ? c.inv_peak[1] : ipk;
+    ipk = E.dt == 2 ? c.inv_peak[2] : ipk;
+    ipk = E.dt == 3 ? c.inv_peak[3] : ipk;
+    ipk = E.dt == 4 ? c.inv_peak[4] : ipk;
+    const Acc gP = w * (Acc)(-E.wc * E.Tc * ipk);
+    acc[2 + 8] += E.dt == 0 ? gP : (Acc)0;
+    acc[2 + 9] += E.dt == 1 ? gP : (Acc)0;
+    acc[2 + 10] += E.dt == 2 ? gP : (Acc)0;
+    acc[2 + 11] += E.dt == 3 ? gP : (Acc)0;
+    acc[2 + 12] += E.dt == 4 ? gP : (Acc)0;
+    // bandwidth: dT_b/dX = -(T_b / S) dS/dX
+    const R cb = -E.wb * E.Tb * A::rcp(E.S);
+    const bool blend = c.blend_on && E.W > (R)0;
+    acc[2 + 0] += w * (Acc)(cb * E.s1);
+    acc[2 + 1] += w * (Acc)(cb * E.s2);
+    acc[2 + 2] += w * (Acc)(cb * E.s3);
+    acc[2 + 3] += w * (Acc)(cb * E.sh * (blend ? (R)1 - E.e : (R)1));
+    if (blend) {
+        acc[2 + 23] += w * (Acc)(cb * E.sh * E.e);
+        acc[2 + 22] += w * (Acc)(cb * E.sh * c.bp_minus_bw * E.e * E.W * c.inv_w0 * c.inv_w0);
+    }
+    // latency: T_lat = q * sum s_l Lat_l / f
+    const R cl = E.wl * E.q * c.inv_f;
+    acc[2 + 4] += w * (Acc)(cl * E.s1);
+    acc[2 + 5] += w * (Acc)(cl * E.s2);
+    acc[2 + 6] += w * (Acc)(cl * E.s3);
+    acc[2 + 7] += w * (Acc)(cl * E.sh);
+    // h_LLC(W) exponents through s3 and s_hbm
+    if (E.llc_regime != 0) {
+        const R dTdh = cb * E.a12 * (c.bw[2] - E.bwh) + E.wl * E.q * E.a12 * (c.latf[2] - c.latf[3]);
+        const Acc gh = w * (Acc)(dTdh * E.h3 * E.base_log);
+        acc[2 + 20] += E.llc_regime == 1 ? gh : (Acc)0;
+        acc[2 + 21] += E.llc_regime == 2 ? gh : (Acc)0;
+    }
+}
+
+}  // namespace wm

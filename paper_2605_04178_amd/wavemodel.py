@@ -1,0 +1,343 @@
+"""Python binding of libwavemodel.so (include/wavemodel.h).
+
+Argument marshalling only: every step of the model runs in the HIP kernels of
+the library.  PyTorch supplies device memory and the current stream.  The
+library must be built (``python -m paper_2605_04178_amd.build``); without it
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwavemodel.so")
+N_THETA = 24
+
+WM_OK, WM_EINVAL, WM_EWORKSPACE, WM_EHIP, WM_EDIVERGED = 0, -1, -2, -3, -4
+OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_CALIBRATE_BATCHED = range(7)
+
+EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_workspace_bytes",
+            "wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
+            "wm_calibrate", "wm_calibrate_batched")
+
+
+class WmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = f"{what}: {lib().wm_strerror(status).decode()} ({status})"
+        if status == WM_EHIP:
+            msg += f", hip error {lib().wm_last_hip_error()}"
+        super().__init__(msg)
+
+
+class WmParams(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "n_levels", "n_cu", "n_simd", "wave", "vgpr_simd", "vgpr_gran", "waves_simd", "lds_cu",
+        "lds_gran", "bytes_inflight_wave", "mwp", "cwp", "combine", "reserved")] + [
+        ("f_clk", C.c_double), ("w_lo_mib", C.c_double), ("c_llc_mib", C.c_double),
+        ("theta", C.c_double * N_THETA)]
+
+
+class WmDesc(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "F", "B", "r1", "r2", "r3", "K", "u", "W", "vgpr", "lds", "gpack", "grid")] + [("n", C.c_int64)]
+
+
+class WmShapes(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("M", "N", "K", "dtype")] + [("n", C.c_int64)]
+
+
+class WmCalibOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("reserved", C.c_int32)] + [
+        (n, C.c_double) for n in ("lr", "lr_final", "beta1", "beta2", "eps")] + [
+        ("free_mask", C.c_uint32), ("reserved2", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libwavemodel.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2605_04178_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        P, D = C.POINTER(WmParams), C.POINTER(WmDesc)
+        L.wm_strerror.argtypes = [i32]
+        L.wm_strerror.restype = C.c_char_p
+        L.wm_last_hip_error.argtypes = []
+        L.wm_last_hip_error.restype = i32
+        L.wm_validate_params.argtypes = [P]
+        L.wm_validate_params.restype = i32
+        L.wm_workspace_bytes.argtypes = [i32, i64, i32, i32]
+        L.wm_workspace_bytes.restype = sz
+        L.wm_predict.argtypes = [D, P, vp, vp, vp]
+        L.wm_predict.restype = i32
+        L.wm_roofline.argtypes = [D, P, vp, vp]
+        L.wm_roofline.restype = i32
+        L.wm_predict_vjp.argtypes = [D, P, vp, vp, vp, sz, vp]
+        L.wm_predict_vjp.restype = i32
+        L.wm_loss_grad.argtypes = [D, vp, P, vp, vp, sz, vp]
+        L.wm_loss_grad.restype = i32
+        L.wm_select_tile.argtypes = [C.POINTER(WmShapes), vp, vp, i64, P, vp, vp, vp, vp]
+        L.wm_select_tile.restype = i32
+        L.wm_calibrate.argtypes = [D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
+        L.wm_calibrate.restype = i32
+        L.wm_calibrate_batched.argtypes = [i32, D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
+        L.wm_calibrate_batched.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != WM_OK:
+        raise WmError(rc, what)
+
+
+# ---------------------------------------------------------------------------
+# marshalling
+# ---------------------------------------------------------------------------
+_PFIELDS = ("n_levels", "n_cu", "n_simd", "wave", "vgpr_simd", "vgpr_gran", "waves_simd", "lds_cu",
+            "lds_gran", "bytes_inflight_wave", "mwp", "cwp", "combine")
+
+
+def params_struct(p, theta: Optional[Sequence[float]] = None) -> WmParams:
+    """Marshal any object with the parameter-set attributes (structural ints,
+    f_clk, w_lo_mib, c_llc_mib, theta[24])."""
+    o = WmParams()
+    for f in _PFIELDS:
+        setattr(o, f, int(getattr(p, f)))
+    o.f_clk = float(p.f_clk)
+    o.w_lo_mib = float(p.w_lo_mib)
+    o.c_llc_mib = float(p.c_llc_mib)
+    th = p.theta if theta is None else theta
+    for j in range(N_THETA):
+        o.theta[j] = float(th[j])
+    return o
+
+
+def theta_of(o: WmParams) -> np.ndarray:
+    return np.array([o.theta[j] for j in range(N_THETA)])
+
+
+def validate_params(p) -> bool:
+    return lib().wm_validate_params(C.byref(params_struct(p))) == WM_OK
+
+
+def workspace_bytes(op: int, n: int, n_sets: int = 1, steps: int = 0) -> int:
+    return int(lib().wm_workspace_bytes(op, n, n_sets, steps))
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
+    if nbytes == 0:
+        return None
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+class DeviceDescriptors:
+    """The 12 structure-of-arrays descriptor fields as device tensors."""
+    FLOATS = ("F", "B", "r1", "r2", "r3", "K", "u", "W")
+    INTS = ("vgpr", "lds", "gpack", "grid")
+
+    def __init__(self, tensors: dict):
+        n = None
+        for f in self.FLOATS + self.INTS:
+            t = tensors[f]
+            want = torch.float32 if f in self.FLOATS else torch.int32
+            if t.dtype != want or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError(f"descriptor field {f} must be a contiguous 1-D {want} tensor")
+            if n is None:
+                n = t.shape[0]
+            if t.shape[0] != n:
+                raise ValueError("descriptor fields differ in length")
+            setattr(self, f, t)
+        self.n = int(n)
+        self.device = tensors["F"].device
+
+    @classmethod
+    def from_host(cls, d, device="cuda") -> "DeviceDescriptors":
+        out = {}
+        for f in cls.FLOATS + cls.INTS:
+            a = np.ascontiguousarray(getattr(d, f))
+            out[f] = torch.from_numpy(a).to(device)
+        return cls(out)
+
+    def slice(self, a: int, b: int) -> "DeviceDescriptors":
+        return DeviceDescriptors({f: getattr(self, f)[a:b] for f in self.FLOATS + self.INTS})
+
+    def struct(self) -> WmDesc:
+        o = WmDesc()
+        for f in self.FLOATS + self.INTS:
+            setattr(o, f, getattr(self, f).data_ptr())
+        o.n = self.n
+        return o
+
+
+class DeviceShapes:
+    def __init__(self, M, N, K, dtype, cand_off, cand_code):
+        self.M, self.N, self.K, self.dtype = M, N, K, dtype
+        self.cand_off, self.cand_code = cand_off, cand_code
+        self.n = int(M.shape[0])
+        self.device = M.device
+
+    @classmethod
+    def from_host(cls, sh, device="cuda") -> "DeviceShapes":
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return cls(t(sh.M, np.int32), t(sh.N, np.int32), t(sh.K, np.int32), t(sh.dtype, np.int32),
+                   t(sh.cand_off, np.int32), t(sh.cand_code.view(np.int32), np.int32))
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+def predict(desc: DeviceDescriptors, params, out_T=None, out_occ=None, want_occ=True, stream=None):
+    """Predicted time T (float32 seconds) and occupancy (int32, or None)."""
+    T = out_T if out_T is not None else torch.empty(desc.n, dtype=torch.float32, device=desc.device)
+    occ = out_occ
+    if occ is None and want_occ:
+        occ = torch.empty(desc.n, dtype=torch.int32, device=desc.device)
+    ds = desc.struct()
+    ps = params_struct(params)
+    _check(lib().wm_predict(C.byref(ds), C.byref(ps), _ptr(T), _ptr(occ), _stream(stream)), "wm_predict")
+    return T, occ
+
+
+def roofline(desc: DeviceDescriptors, params, stream=None):
+    T = torch.empty(desc.n, dtype=torch.float32, device=desc.device)
+    _check(lib().wm_roofline(C.byref(desc.struct()), C.byref(params_struct(params)), _ptr(T),
+                             _stream(stream)), "wm_roofline")
+    return T
+
+
+def vjp(desc: DeviceDescriptors, params, dL_dT: torch.Tensor, ws=None, theta=None, stream=None):
+    """dL/dtheta (float64 [24], device) for an upstream gradient dL/dT."""
+    out = torch.empty(N_THETA, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_VJP, desc.n), desc.device)
+    nb = 0 if ws is None else ws.numel()
+    rc = lib().wm_predict_vjp(C.byref(desc.struct()), C.byref(params_struct(params, theta)),
+                              _ptr(dL_dT.contiguous()), _ptr(out), _ptr(ws), nb, _stream(stream))
+    _check(rc, "wm_predict_vjp")
+    return out
+
+
+def loss_grad(desc: DeviceDescriptors, measured: torch.Tensor, params, ws=None, theta=None,
+              out=None, stream=None):
+    """[loss, count, grad[24]] float64 on the device (mean relative error)."""
+    if out is None:
+        out = torch.empty(26, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_LOSS_GRAD, desc.n), desc.device)
+    nb = 0 if ws is None else ws.numel()
+    rc = lib().wm_loss_grad(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(params, theta)),
+                            _ptr(out), _ptr(ws), nb, _stream(stream))
+    _check(rc, "wm_loss_grad")
+    return out
+
+
+def select_tile(shapes: DeviceShapes, params, out=None, stream=None):
+    """(best local index int32, best float64 cost, near-tie uint8) per shape."""
+    dev = shapes.device
+    if out is None:
+        out = (torch.empty(shapes.n, dtype=torch.int32, device=dev),
+               torch.empty(shapes.n, dtype=torch.float64, device=dev),
+               torch.empty(shapes.n, dtype=torch.uint8, device=dev))
+    best, cost, tie = out
+    s = WmShapes(shapes.M.data_ptr(), shapes.N.data_ptr(), shapes.K.data_ptr(),
+                 shapes.dtype.data_ptr(), shapes.n)
+    rc = lib().wm_select_tile(C.byref(s), _ptr(shapes.cand_off), _ptr(shapes.cand_code),
+                              int(shapes.cand_code.numel()), C.byref(params_struct(params)),
+                              _ptr(best), _ptr(cost), _ptr(tie), _stream(stream))
+    _check(rc, "wm_select_tile")
+    return best, cost, tie
+
+
+def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+               free_mask=0xFFFFFF) -> WmCalibOpts:
+    return WmCalibOpts(steps=steps, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2, eps=eps,
+                       free_mask=free_mask)
+
+
+def calibrate(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps=500, lr=0.05,
+              lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None,
+              stream=None, raise_on_diverged=False):
+    """Device Adam on log(theta).  Returns (status, theta float64 [24], loss history)."""
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_CALIBRATE, desc.n, 1, steps), desc.device)
+    pout = WmParams()
+    hist = np.zeros(steps)
+    rc = lib().wm_calibrate(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(p0)),
+                            C.byref(opts), C.byref(pout), hist.ctypes.data, _ptr(ws), ws.numel(),
+                            _stream(stream))
+    if rc not in (WM_OK, WM_EDIVERGED) or (raise_on_diverged and rc != WM_OK):
+        raise WmError(rc, "wm_calibrate")
+    return rc, theta_of(pout), hist
+
+
+def calibrate_batched(descs: List[DeviceDescriptors], measured: List[torch.Tensor], p0s, opts_list,
+                      ws=None, stream=None):
+    """Several calibration problems in one persistent sweep per step.
+    Returns (status, thetas [n_sets, 24], loss history [n_sets, steps])."""
+    k = len(descs)
+    steps = int(opts_list[0].steps)
+    D = (WmDesc * k)(*[d.struct() for d in descs])
+    M = (C.c_void_p * k)(*[m.data_ptr() for m in measured])
+    P0 = (WmParams * k)(*[params_struct(p) for p in p0s])
+    O = (WmCalibOpts * k)(*opts_list)
+    POUT = (WmParams * k)()
+    n_total = sum(d.n for d in descs)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_CALIBRATE_BATCHED, n_total, k, steps), descs[0].device)
+    hist = np.zeros((k, steps))
+    rc = lib().wm_calibrate_batched(k, D, M, P0, O, POUT, hist.ctypes.data, _ptr(ws), ws.numel(),
+                                    _stream(stream))
+    if rc not in (WM_OK, WM_EDIVERGED):
+        raise WmError(rc, "wm_calibrate_batched")
+    return rc, np.stack([theta_of(POUT[i]) for i in range(k)]), hist
+
+
+# ---------------------------------------------------------------------------
+# autograd: T = model(descriptors; theta), dL/dtheta by the adjoint kernel
+# ---------------------------------------------------------------------------
+class WMPredict(torch.autograd.Function):
+    """T = WMPredict.apply(desc, theta, params): theta is a float64 [24] tensor
+    (CPU or device); T is float32 [n] on the descriptors' device.  backward
+    returns dL/dtheta as float64 on theta's device, computed by the adjoint
+    kernel with FP64 reductions."""
+
+    @staticmethod
+    def forward(ctx, desc: DeviceDescriptors, theta: torch.Tensor, params):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        ctx.desc, ctx.params, ctx.theta_np, ctx.theta_dev = desc, params, th, theta.device
+        T = torch.empty(desc.n, dtype=torch.float32, device=desc.device)
+        ds = desc.struct()
+        ps = params_struct(params, th)
+        _check(lib().wm_predict(C.byref(ds), C.byref(ps), _ptr(T), None, _stream()), "wm_predict")
+        return T
+
+    @staticmethod
+    def backward(ctx, dL_dT):
+        g = vjp(ctx.desc, ctx.params, dL_dT.to(torch.float32).contiguous(), theta=ctx.theta_np)
+        return None, g.to(ctx.theta_dev), None

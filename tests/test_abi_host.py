@@ -1,0 +1,204 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the
+header declares, and validates arguments before any HIP call (these calls
+return before touching a device, so they run without a GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2605_04178_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wavemodel.h")
+
+
+@pytest.fixture(scope="module")
+def wmb():
+    from paper_2605_04178_amd import wavemodel
+    wavemodel.lib()
+    return wavemodel
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_calls():
+    names = _declared()
+    for n in ("wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
+              "wm_calibrate", "wm_calibrate_batched", "wm_workspace_bytes", "wm_strerror",
+              "wm_last_hip_error", "wm_validate_params"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(wmb):
+    lib = wmb.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", wmb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(wm_\w+)", out))
+    assert set(_declared()) <= exported
+    assert set(wmb.EXPORTED) <= exported
+
+
+def test_library_is_gfx950_only(wmb):
+    out = subprocess.run(["/opt/rocm/llvm/bin/clang-offload-bundler", "--list", "--type=o",
+                          "--input=" + wmb.LIB_PATH], capture_output=True, text=True)
+    if out.returncode == 0 and out.stdout.strip():
+        targets = [t for t in out.stdout.split() if "amdgcn" in t]
+        assert targets and all("gfx950" in t for t in targets)
+
+
+def test_struct_sizes_match_header(wmb):
+    # 14 int32 + 3 double + 24 double
+    assert C.sizeof(wmb.WmParams) == 14 * 4 + 3 * 8 + 24 * 8
+    assert C.sizeof(wmb.WmDesc) == 12 * 8 + 8
+    assert C.sizeof(wmb.WmCalibOpts) == 4 + 4 + 5 * 8 + 4 + 4
+
+
+def test_strerror(wmb):
+    L = wmb.lib()
+    assert L.wm_strerror(0) == b"ok"
+    for s in (-1, -2, -3, -4, 7):
+        assert isinstance(L.wm_strerror(s), bytes) and L.wm_strerror(s)
+
+
+def _bad_params():
+    base = synth.param_set(0)
+    bad = [dict(n_levels=2), dict(n_cu=0), dict(wave=48), dict(vgpr_gran=3), dict(lds_gran=0),
+           dict(waves_simd=0), dict(combine=2), dict(f_clk=0.0), dict(w_lo_mib=300.0),
+           dict(w_lo_mib=205.1), dict(mwp=-1), dict(bytes_inflight_wave=0), dict(lds_cu=-1)]
+    out = [base.copy(**kw) for kw in bad]
+    for j, v in ((0, 0.0), (3, -1.0), (8, 0.0), (12, float("inf")), (13, -1e-6), (20, 0.0),
+                 (23, 0.0), (5, float("nan")), (4, -1.0)):
+        th = list(base.theta)
+        th[j] = v
+        out.append(base.copy(theta=th))
+    return out
+
+
+def test_validate_params(wmb):
+    assert wmb.validate_params(synth.param_set(0))
+    assert wmb.validate_params(synth.param_set(0, n_levels=3))
+    assert wmb.validate_params(synth.mi300a_like())
+    for p in synth.multi_arch_sets():
+        assert wmb.validate_params(p)
+    for p in _bad_params():
+        assert not wmb.validate_params(p), p
+    # alpha/beta/LLC slots are unused with three levels
+    th = list(synth.param_set(0).theta)
+    th[2], th[6], th[20], th[21] = 0.0, 0.0, 0.0, 0.0
+    assert wmb.validate_params(synth.param_set(0, n_levels=3).copy(theta=th))
+    # w0 <= 0 switches the blend off and is allowed
+    th = list(synth.param_set(0).theta)
+    th[22] = 0.0
+    assert wmb.validate_params(synth.param_set(0).copy(theta=th))
+
+
+def test_workspace_bytes(wmb):
+    assert wmb.workspace_bytes(wmb.OP_PREDICT, 1 << 20) == 0
+    assert wmb.workspace_bytes(wmb.OP_SELECT_TILE, 1 << 20) == 0
+    a = wmb.workspace_bytes(wmb.OP_LOSS_GRAD, 1 << 20)
+    assert a > 0 and a % 256 == 0
+    assert wmb.workspace_bytes(wmb.OP_VJP, 0) > 0
+    assert wmb.workspace_bytes(wmb.OP_CALIBRATE, 1 << 20, 1, 0) == 0
+    assert wmb.workspace_bytes(wmb.OP_CALIBRATE, 1 << 20, 1, 500) > a
+    assert wmb.workspace_bytes(wmb.OP_CALIBRATE_BATCHED, 1 << 20, 17, 10) == 0
+    assert wmb.workspace_bytes(wmb.OP_CALIBRATE_BATCHED, 1 << 20, 6, 10) > 0
+    assert wmb.workspace_bytes(wmb.OP_LOSS_GRAD, -1) == 0
+
+
+def _fake_desc(wmb, n):
+    d = wmb.WmDesc()
+    for i, f in enumerate(wmb.DeviceDescriptors.FLOATS + wmb.DeviceDescriptors.INTS):
+        setattr(d, f, 0x1000 * (i + 1))
+    d.n = n
+    return d
+
+
+def test_argument_errors_before_any_hip_call(wmb):
+    """Every call below is rejected by host validation; none reaches HIP."""
+    L = wmb.lib()
+    p = wmb.params_struct(synth.param_set(0))
+    bad = wmb.params_struct(synth.param_set(0).copy(n_levels=5))
+    d = _fake_desc(wmb, 16)
+    neg = _fake_desc(wmb, -1)
+    T = C.c_void_p(0x2000)
+    assert L.wm_predict(None, C.byref(p), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict(C.byref(d), None, T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict(C.byref(d), C.byref(bad), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict(C.byref(neg), C.byref(p), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict(C.byref(d), C.byref(p), None, None, None) == wmb.WM_EINVAL
+    d0 = _fake_desc(wmb, 0)
+    assert L.wm_predict(C.byref(d0), C.byref(p), None, None, None) == wmb.WM_OK
+    dnull = _fake_desc(wmb, 16)
+    dnull.gpack = None
+    assert L.wm_predict(C.byref(dnull), C.byref(p), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_roofline(C.byref(d), C.byref(bad), T, None) == wmb.WM_EINVAL
+    # gradient calls: missing workspace / too small / misaligned
+    out = C.c_void_p(0x3000)
+    w = C.c_void_p(0x4000)
+    assert L.wm_loss_grad(C.byref(d), w, C.byref(p), out, None, 0, None) == wmb.WM_EWORKSPACE
+    assert L.wm_loss_grad(C.byref(d), w, C.byref(p), out, C.c_void_p(0x10000), 8, None) == wmb.WM_EWORKSPACE
+    need = wmb.workspace_bytes(wmb.OP_LOSS_GRAD, 16)
+    assert L.wm_loss_grad(C.byref(d), w, C.byref(p), out, C.c_void_p(0x10008), need, None) == wmb.WM_EWORKSPACE
+    assert L.wm_loss_grad(C.byref(d), None, C.byref(p), out, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    assert L.wm_predict_vjp(C.byref(d), C.byref(p), w, None, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    # tile selection
+    sh = wmb.WmShapes(0x100, 0x200, 0x300, 0x400, 4)
+    assert L.wm_select_tile(C.byref(sh), None, None, 0, C.byref(p), out, out, out, None) == wmb.WM_EINVAL
+    assert L.wm_select_tile(C.byref(sh), C.c_void_p(0x500), None, 10, C.byref(p), out, out, out, None) == wmb.WM_EINVAL
+    sh0 = wmb.WmShapes(None, None, None, None, 0)
+    assert L.wm_select_tile(C.byref(sh0), None, None, 0, C.byref(p), None, None, None, None) == wmb.WM_OK
+    shn = wmb.WmShapes(0x100, 0x200, 0x300, 0x400, -2)
+    assert L.wm_select_tile(C.byref(shn), C.c_void_p(0x500), None, 0, C.byref(p), out, out, out, None) == wmb.WM_EINVAL
+    # calibration options
+    pout = wmb.WmParams()
+    for kw in (dict(steps=0), dict(lr=0.0), dict(lr=float("nan")), dict(beta1=1.0), dict(eps=0.0),
+               dict(free_mask=1 << 24), dict(lr_final=-1.0)):
+        o = wmb.calib_opts(**{**dict(steps=5), **kw})
+        rc = L.wm_calibrate(C.byref(d), w, C.byref(p), C.byref(o), C.byref(pout), None,
+                            C.c_void_p(0x10000), 1 << 30, None)
+        assert rc == wmb.WM_EINVAL, kw
+    o = wmb.calib_opts(steps=5)
+    assert L.wm_calibrate(C.byref(d), w, C.byref(p), C.byref(o), C.byref(pout), None, None, 0,
+                          None) == wmb.WM_EWORKSPACE
+    # a free slot must be positive (log-space update)
+    th = list(synth.param_set(0).theta)
+    th[13] = 0.0
+    pz = wmb.params_struct(synth.param_set(0).copy(theta=th))
+    assert L.wm_calibrate(C.byref(d), w, C.byref(pz), C.byref(o), C.byref(pout), None,
+                          C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    # batched: set count, mismatched steps
+    D = (wmb.WmDesc * 2)(d, d)
+    M = (C.c_void_p * 2)(0x4000, 0x5000)
+    P0 = (wmb.WmParams * 2)(p, p)
+    O = (wmb.WmCalibOpts * 2)(wmb.calib_opts(steps=5), wmb.calib_opts(steps=6))
+    PO = (wmb.WmParams * 2)()
+    assert L.wm_calibrate_batched(2, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_calibrate_batched(0, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_calibrate_batched(17, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_last_hip_error() == 0
+
+
+def test_product_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2605_04178_amd import wavemodel
+    monkeypatch.setattr(wavemodel, "_lib", None)
+    monkeypatch.setattr(wavemodel, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        wavemodel.lib()
+
+
+def test_product_package_does_not_reference_oracle():
+    pkg = os.path.join(ROOT, "paper_2605_04178_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"(import|from)\s+oracle|liboracle|wm_oracle", src), f

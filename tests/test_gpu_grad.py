@@ -1,0 +1,147 @@
+"""Parity of the adjoint kernels (wm_predict_vjp, wm_loss_grad) and of the
+autograd binding with the FP64 oracle gradient and with finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_04178_amd import synth
+from gpu_common import grad_err, need_gpu, rel_err, say
+
+pytestmark = pytest.mark.gpu
+GTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def wmb():
+    need_gpu()
+    from paper_2605_04178_amd import wavemodel
+    wavemodel.lib()
+    return wavemodel
+
+
+def _measured(orc, p_true, d, sigma=0.02, seed=2):
+    T, occ = orc.predict(p_true, d)
+    return (T * synth.lognormal_noise(d.n, seed, sigma)).astype(np.float32)
+
+
+@pytest.mark.parametrize("L,combine", [(4, 0), (3, 0), (4, 1)])
+def test_loss_grad_parity_at_theta0(wmb, orc, L, combine):
+    n = 1 << 18
+    ps = synth.param_set(1, n_levels=L, combine=combine)
+    d = synth.descriptors(n, 103)
+    m = _measured(orc, ps, d)
+    p0 = synth.perturb_theta(ps, 3)
+    say("loss_grad parity", L, combine)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    out = wmb.loss_grad(dd, mt, p0).cpu().numpy()
+    loss, cnt, g = orc.loss_grad(p0, d, m)
+    assert int(out[1]) == cnt
+    assert abs(out[0] - loss) <= 1e-5 * loss
+    assert grad_err(out[2:], g) <= GTOL, (grad_err(out[2:], g), out[2:], g)
+
+
+def test_loss_grad_parity_near_optimum(wmb, orc):
+    """Close to theta*, |T/m - 1| is small for many descriptors, so the sign of
+    each relative error is decided in FP64 where float32 cannot."""
+    n = 1 << 18
+    ps = synth.param_set(1)
+    d = synth.descriptors(n, 104)
+    m = _measured(orc, ps, d, sigma=0.02)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    for k, f in enumerate((1.0, 1.001, 0.97)):
+        p = ps.copy(theta=[t * (f if j % 3 == k else 1.0) for j, t in enumerate(ps.theta)])
+        out = wmb.loss_grad(dd, mt, p).cpu().numpy()
+        loss, cnt, g = orc.loss_grad(p, d, m)
+        assert int(out[1]) == cnt
+        assert abs(out[0] - loss) <= 1e-5 * loss
+        assert grad_err(out[2:], g) <= GTOL, (f, grad_err(out[2:], g))
+
+
+def test_loss_grad_exact_measurements(wmb, orc):
+    """m = T(theta) exactly (noise-free): every relative error sits on the
+    |.| kink; sign(0) = 0 must hold on both sides."""
+    n = 1 << 16
+    ps = synth.param_set(1)
+    d = synth.descriptors(n, 105)
+    T, _ = orc.predict(ps, d)
+    m = T.astype(np.float32)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    out = wmb.loss_grad(dd, torch.from_numpy(m).cuda(), ps).cpu().numpy()
+    loss, cnt, g = orc.loss_grad(ps, d, m)
+    assert int(out[1]) == cnt
+    assert abs(out[0] - loss) <= 1e-5 * max(loss, 1e-12) + 1e-12
+    assert grad_err(out[2:], g) <= GTOL
+
+
+@pytest.mark.parametrize("L,combine", [(4, 0), (3, 1)])
+def test_vjp_parity(wmb, orc, L, combine):
+    n = 200003
+    p = synth.param_set(0, n_levels=L, combine=combine)
+    d = synth.descriptors(n, 106)
+    w = np.random.default_rng(3).standard_normal(n).astype(np.float32)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    g = wmb.vjp(dd, p, torch.from_numpy(w).cuda()).cpu().numpy()
+    go = orc.vjp(p, d, w)
+    assert grad_err(g, go) <= GTOL, (grad_err(g, go), g, go)
+
+
+def test_vjp_empty_and_deterministic(wmb):
+    p = synth.param_set(0)
+    d0 = wmb.DeviceDescriptors.from_host(synth.descriptors(0, 1))
+    g0 = wmb.vjp(d0, p, torch.zeros(0, device="cuda"))
+    assert torch.count_nonzero(g0).item() == 0
+    dd = wmb.DeviceDescriptors.from_host(synth.descriptors(100000, 107))
+    w = torch.randn(100000, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    a = wmb.vjp(dd, p, w)
+    b = wmb.vjp(dd, p, w)
+    assert torch.equal(a, b)
+
+
+def test_autograd_function_matches_vjp_and_central_differences(wmb, orc):
+    n = 1 << 18
+    p = synth.param_set(0)
+    d = synth.descriptors(n, 108)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    theta = torch.tensor(p.theta, dtype=torch.float64, requires_grad=True)
+    T = wmb.WMPredict.apply(dd, theta, p)
+    fin = torch.isfinite(T)
+    c = torch.from_numpy(np.random.default_rng(4).uniform(0.5, 1.5, n).astype(np.float32)).cuda()
+    c = torch.where(fin, c, torch.zeros_like(c))
+    L = (torch.where(fin, T, torch.zeros_like(T)).double() * c.double()).sum()
+    L.backward()
+    g = theta.grad.numpy()
+    # equals the vjp call and the oracle's FP64 gradient
+    gv = wmb.vjp(dd, p, c).cpu().numpy()
+    assert np.array_equal(g, gv)
+    go = orc.vjp(p, d, c.cpu().numpy())
+    assert grad_err(g, go) <= GTOL
+    # central differences of the float32 forward sweep, h = 1e-4 relative
+    h = 1e-4
+    fd = np.zeros(24)
+    for j in range(24):
+        tp, tm = list(p.theta), list(p.theta)
+        tp[j] *= 1 + h
+        tm[j] *= 1 - h
+        Tp, _ = wmb.predict(dd, p.copy(theta=tp), want_occ=False)
+        Tm, _ = wmb.predict(dd, p.copy(theta=tm), want_occ=False)
+        dp = (torch.where(fin, Tp, torch.zeros_like(Tp)).double() * c.double()).sum()
+        dm = (torch.where(fin, Tm, torch.zeros_like(Tm)).double() * c.double()).sum()
+        fd[j] = (dp - dm).item() / (2 * h * p.theta[j])
+    scale = np.abs(g * np.array(p.theta))
+    rel = np.abs(fd - g) * np.abs(np.array(p.theta)) / np.maximum(scale.max(), 1e-300)
+    assert rel.max() <= 1e-3, (rel, fd, g)
+
+
+def test_loss_grad_workspace_reuse_and_determinism(wmb, orc):
+    n = 300001
+    ps = synth.param_set(1)
+    d = synth.descriptors(n, 109)
+    m = _measured(orc, ps, d)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    ws = wmb._workspace(wmb.workspace_bytes(wmb.OP_LOSS_GRAD, n), "cuda")
+    a = wmb.loss_grad(dd, mt, ps, ws=ws)
+    b = wmb.loss_grad(dd, mt, ps, ws=ws)
+    assert torch.equal(a, b)
