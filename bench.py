@@ -51,6 +51,26 @@ def timed(fn, steps, warmup):
     return wall, e0.elapsed_time(e1) / steps
 
 
+def counted_traffic(kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (profiles/traffic.json), or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2605_04178_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("wm_kernels.hip", "wm_model.hpp", "wm_launch.hpp"))
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    for name, v in rec["kernels"].items():
+        if kernel_prefix in name:
+            return v["read_bytes"] + v["write_bytes"]
+    return None
+
+
 def cpu_baseline(p, d, seconds=10.0):
     """The FP64 oracle's forward rate on a bounded sample of the workload."""
     import oracle
@@ -70,6 +90,35 @@ def cpu_baseline(p, d, seconds=10.0):
                       f"{reps} repetitions, {el:.1f} s"}
 
 
+def profile_run(wm, synth, dd, p, n, dev):
+    import torch
+    T = torch.empty(n, dtype=torch.float32, device=dev)
+    occ = torch.empty(n, dtype=torch.int32, device=dev)
+    for _ in range(5):
+        wm.predict(dd, p, out_T=T, out_occ=occ)
+    torch.cuda.synchronize()
+    log("profile: predict x5 done")
+    meas = (T.clamp(min=1e-6, max=1.0) * 1.01).contiguous()
+    ws = wm._workspace(wm.workspace_bytes(wm.OP_LOSS_GRAD, n), dev)
+    for _ in range(3):
+        wm.loss_grad(dd, meas, p, ws=ws)
+    torch.cuda.synchronize()
+    log("profile: loss_grad x3 done")
+    sh = synth.shapes(1 << 16, 102)
+    dsh = wm.DeviceShapes.from_host(sh, dev)
+    for _ in range(3):
+        wm.select_tile(dsh, p)
+    torch.cuda.synchronize()
+    log("profile: select_tile x3 done")
+    del T, occ, meas, ws
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)           # 1 GiB read + 1 GiB written per launch
+    torch.cuda.synchronize()
+    log("profile: reference copy x3 done (1073741824 bytes each way)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +128,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="forward sweep only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-steps", type=int, default=500)
+    ap.add_argument("--profile", action="store_true",
+                    help="run each hot kernel a few times, then a plain 1 GiB device copy whose "
+                         "known traffic scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the batched model "
@@ -103,6 +155,10 @@ def main():
     T = torch.empty(n, dtype=torch.float32, device=dev)
     occ = torch.empty(n, dtype=torch.int32, device=dev)
 
+    if args.profile:
+        profile_run(wm, synth, dd, p, n, dev)
+        return
+
     # ---- forward sweep (the step) ----
     fwd = lambda: wm.predict(dd, p, out_T=T, out_occ=occ)
     wall_ms, ev_ms = timed(fwd, args.steps, args.warmup)
@@ -118,7 +174,7 @@ def main():
                                "(8 f32 + 4 i32 each), one CDNA-style parameter set",
                    "n_descriptors": n, "param_set": "seed 0, 4 levels, HK_MAX"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic("k_predict<4>"),
                      "kernel": "wm::k_predict<4>", "bytes_per_eval": FWD_BYTES,
                      "avg_launch_us": ev_ms * 1e3},
     }
@@ -138,7 +194,8 @@ def main():
         ach_a = ADJ_BYTES * n / (ev_a * 1e-3) / 1e9
         res["fwd_adjoint"] = {"value": n / (wall_a * 1e-3), "unit": "evals/s", "ms_per_step": wall_a,
                               "achieved_GBs": ach_a, "hbm_frac": ach_a / HBM_PEAK_GBS,
-                              "bytes_per_eval": ADJ_BYTES, "dtype": "f32 + f64 reductions"}
+                              "bytes_per_eval": ADJ_BYTES, "dtype": "f32 + f64 reductions",
+                              "traffic": counted_traffic("k_grad<1")}
         log(f"fwd+adjoint: {wall_a:.4f} ms/step, {ach_a:.0f} GB/s")
         del meas, ws
 
@@ -197,7 +254,7 @@ def main():
             ddk = wm.DeviceDescriptors.from_host(dk, dev)
             Tk, _ = wm.predict(ddk, pk, want_occ=False)
             mk = (Tk * torch.from_numpy(synth.lognormal_noise(nk, 130 + k, 0.02).astype(np.float32)).to(dev)).contiguous()
-            mk_mask = 0x3FFFFF if pk.n_levels == 4 else (0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21)))
+            mk_mask = 0x3FFFFF if pk.n_levels == 4 else (0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21) | (1 << 22)))
             descs.append(ddk)
             meas_l.append(mk)
             p0s.append(synth.perturb_theta(pk, 140 + k, mask=mk_mask))

@@ -463,37 +463,54 @@ typedef struct {
     uint32_t free_mask, pad2_;
 } orc_calib_opts_t;
 
-/* returns 0 on success, 1 if the loss became non-finite (theta = last finite) */
+/*
+ * Returns 0 on success (p_out = theta after the last update) or 1 when the
+ * loss or a gradient became non-finite, or an update left the positive
+ * finite range; p_out is then the last theta whose loss was finite and the
+ * remaining loss-history entries are NaN.
+ */
 int orc_calibrate(const orc_params_t *p0, const orc_desc_t *d, const float *m,
                   const orc_calib_opts_t *o, orc_params_t *p_out, double *loss_hist)
 {
-    orc_params_t p = *p0;
+    orc_params_t p = *p0, last_ok = *p0;
     double phi[N_THETA], mom[N_THETA], vel[N_THETA], out[26];
     for (int j = 0; j < N_THETA; ++j) {
         phi[j] = (o->free_mask >> j & 1u) ? log(p.theta[j]) : 0.0;
         mom[j] = 0.0;
         vel[j] = 0.0;
     }
-    double b1t = 1.0, b2t = 1.0;
     for (int t = 1; t <= o->steps; ++t) {
         orc_weighted_grad(&p, d, m, 1, out);
         if (loss_hist) loss_hist[t - 1] = out[0];
-        if (!isfinite(out[0])) { *p_out = p; return 1; }
-        double lr = o->lr;
-        if (o->lr_final > 0.0 && o->steps > 1)
-            lr = o->lr * pow(o->lr_final / o->lr, (double)(t - 1) / (double)(o->steps - 1));
-        b1t *= o->beta1;
-        b2t *= o->beta2;
-        for (int j = 0; j < N_THETA; ++j) {
-            if (!(o->free_mask >> j & 1u)) continue;
-            double gphi = p.theta[j] * out[2 + j];          /* d/dlog(theta) */
-            mom[j] = o->beta1 * mom[j] + (1.0 - o->beta1) * gphi;
-            vel[j] = o->beta2 * vel[j] + (1.0 - o->beta2) * gphi * gphi;
-            double mh = mom[j] / (1.0 - b1t);
-            double vh = vel[j] / (1.0 - b2t);
-            phi[j] -= lr * mh / (sqrt(vh) + o->eps);
-            p.theta[j] = exp(phi[j]);
+        int finite = isfinite(out[0]);
+        for (int j = 0; j < N_THETA; ++j) finite = finite && isfinite(out[2 + j]);
+        int ok = finite;
+        orc_params_t next = p;
+        if (finite) {
+            last_ok = p;
+            double lr = o->lr;
+            if (o->lr_final > 0.0 && o->steps > 1)
+                lr = o->lr * pow(o->lr_final / o->lr, (double)(t - 1) / (double)(o->steps - 1));
+            double b1t = pow(o->beta1, (double)t), b2t = pow(o->beta2, (double)t);
+            for (int j = 0; j < N_THETA; ++j) {
+                if (!(o->free_mask >> j & 1u)) continue;
+                double gphi = p.theta[j] * out[2 + j];          /* d/dlog(theta) */
+                mom[j] = o->beta1 * mom[j] + (1.0 - o->beta1) * gphi;
+                vel[j] = o->beta2 * vel[j] + (1.0 - o->beta2) * gphi * gphi;
+                double mh = mom[j] / (1.0 - b1t);
+                double vh = vel[j] / (1.0 - b2t);
+                phi[j] -= lr * mh / (sqrt(vh) + o->eps);
+                next.theta[j] = exp(phi[j]);
+                ok = ok && isfinite(next.theta[j]) && next.theta[j] > 0.0;
+            }
         }
+        if (!ok) {
+            if (loss_hist)
+                for (int k = t; k < o->steps; ++k) loss_hist[k] = NAN;
+            *p_out = last_ok;
+            return 1;
+        }
+        p = next;
     }
     *p_out = p;
     return 0;

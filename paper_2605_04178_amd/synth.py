@@ -144,13 +144,22 @@ def param_set(seed: int = 0, n_levels: int = 4, combine: int = 0) -> ParamSet:
     """One CDNA-style parameter set with seeded synthetic values.
 
     Bandwidths: 4 x log-U[2, 80] TB/s sorted fast-to-slow (L1 .. HBM);
-    latencies: 4 x U[50, 800] cycles sorted ascending; five dtype peaks;
-    overhead constants in the ranges quoted in the module docstring.
+    latencies: 4 x U[50, 800] cycles sorted ascending; both redrawn until
+    neighbouring levels differ by at least 1.5x in bandwidth and 50 cycles in
+    latency (a level indistinguishable from the next one leaves the LLC
+    hit-rate exponents unidentifiable); five dtype peaks; overhead constants
+    in the ranges quoted in the module docstring.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     th = [0.0] * N_THETA
-    bw = np.sort(_logu(rng, 2e12, 80e12, 4))[::-1]
-    lat = np.sort(rng.uniform(50.0, 800.0, 4))
+    while True:
+        bw = np.sort(_logu(rng, 2e12, 80e12, 4))[::-1]
+        if np.all(bw[:-1] / bw[1:] >= 1.5):
+            break
+    while True:
+        lat = np.sort(rng.uniform(50.0, 800.0, 4))
+        if np.all(np.diff(lat) >= 50.0):
+            break
     th[0:4] = [float(x) for x in bw]
     th[4:8] = [float(x) for x in lat]
     th[8] = float(_logu(rng, 30e12, 160e12))

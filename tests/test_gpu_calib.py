@@ -1,0 +1,173 @@
+"""Device calibration (wm_calibrate, wm_calibrate_batched): Adam on log(theta)
+in captured HIP graphs.  Recovery of the ground-truth parameters, gradient
+parity with the FP64 oracle along the trajectory, divergence handling, and
+batched-vs-plain agreement."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_04178_amd import synth
+from gpu_common import grad_err, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+MASK_L4 = 0x3FFFFF
+MASK_L3 = 0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21) | (1 << 22))
+
+
+@pytest.fixture(scope="module")
+def wmb():
+    need_gpu()
+    from paper_2605_04178_amd import wavemodel
+    wavemodel.lib()
+    return wavemodel
+
+
+def _problem(orc, n, L=4, sigma=0.02, seed_d=103, seed_p=1, mask=MASK_L4, combine=0):
+    ps = synth.param_set(seed_p, n_levels=L, combine=combine)
+    d = synth.descriptors(n, seed_d)
+    T, _ = orc.predict(ps, d)
+    m = (T * synth.lognormal_noise(n, 2, sigma)).astype(np.float32)
+    p0 = synth.perturb_theta(ps, 3, mask=mask)
+    return ps, d, m, p0
+
+
+def _rec_err(th, ps, mask):
+    idx = [j for j in range(24) if mask >> j & 1]
+    return float(np.max(np.abs(np.asarray(th)[idx] / np.array(ps.theta)[idx] - 1)))
+
+
+@pytest.mark.parametrize("L,mask", [(4, MASK_L4), (3, MASK_L3)])
+def test_calibration_recovers_within_3pct(wmb, orc, L, mask):
+    """2^20 measured times with lognormal noise sigma = 0.02, 500 Adam steps."""
+    n = 1 << 20
+    ps, d, m, p0 = _problem(orc, n, L=L, mask=mask)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    say("calibrate L", L)
+    rc, th, hist = wmb.calibrate(dd, torch.from_numpy(m).cuda(), p0, steps=500, free_mask=mask)
+    assert rc == wmb.WM_OK
+    err = _rec_err(th, ps, mask)
+    say("max recovery error", err)
+    assert err <= 0.03
+    loss0 = orc.loss_grad(p0, d, m)[0]
+    assert abs(hist[0] - loss0) <= 1e-5 * loss0
+    assert hist[-1] < hist[0]
+    # fixed slots did not move
+    for j in range(24):
+        if not (mask >> j & 1):
+            assert th[j] == p0.theta[j]
+
+
+def test_calibration_noiseless_recovery(wmb, orc):
+    n = 1 << 16
+    ps, d, m, p0 = _problem(orc, n, sigma=0.0)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    rc, th, hist = wmb.calibrate(dd, torch.from_numpy(m).cuda(), p0, steps=500, free_mask=MASK_L4)
+    assert rc == wmb.WM_OK
+    assert _rec_err(th, ps, MASK_L4) <= 1e-3
+
+
+def test_gradients_along_the_trajectory(wmb, orc):
+    """GPU loss gradient vs the oracle's FP64 gradient at theta0 and at three
+    points of the GPU's own Adam trajectory."""
+    n = 1 << 18
+    ps, d, m, p0 = _problem(orc, n)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    pts = [p0]
+    for steps in (40, 150, 400):
+        rc, th, _ = wmb.calibrate(dd, mt, p0, steps=steps, free_mask=MASK_L4)
+        pts.append(p0.copy(theta=list(th)))
+    for k, p in enumerate(pts):
+        out = wmb.loss_grad(dd, mt, p).cpu().numpy()
+        loss, cnt, g = orc.loss_grad(p, d, m)
+        assert int(out[1]) == cnt
+        assert abs(out[0] - loss) <= 1e-5 * loss
+        e = grad_err(out[2:], g)
+        say("trajectory point", k, "grad err", e)
+        assert e <= 1e-4
+
+
+def test_calibration_matches_oracle_adam_loss_history(wmb, orc):
+    """Short run: the device Adam follows the oracle's Adam (same loss history
+    to 1e-6 relative over 20 steps)."""
+    n = 1 << 16
+    ps, d, m, p0 = _problem(orc, n, sigma=0.05)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    rc, th, hist = wmb.calibrate(dd, torch.from_numpy(m).cuda(), p0, steps=20, free_mask=MASK_L4)
+    rco, tho, histo = orc.calibrate(p0, d, m, steps=20, lr=0.05, lr_final=1e-3, free_mask=MASK_L4)
+    assert rc == 0 and rco == 0
+    assert np.allclose(hist, histo, rtol=1e-6, atol=0)
+    assert np.allclose(th, tho, rtol=1e-6, atol=0)
+
+
+def test_calibration_divergence_returns_last_finite_theta(wmb, orc):
+    n = 1 << 14
+    ps, d, m, p0 = _problem(orc, n)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    rc, th, hist = wmb.calibrate(dd, torch.from_numpy(m).cuda(), p0, steps=5, lr=1e300,
+                                 lr_final=0.0, free_mask=MASK_L4)
+    assert rc == wmb.WM_EDIVERGED
+    assert np.array_equal(th, np.array(p0.theta))
+    assert np.isfinite(hist[0]) and np.all(np.isnan(hist[1:]))
+    rco, tho, histo = orc.calibrate(p0, d, m, steps=5, lr=1e300, lr_final=0.0, free_mask=MASK_L4)
+    assert rco == 1 and np.array_equal(tho, np.array(p0.theta))
+
+
+def test_calibration_step_counts_around_graph_chunk(wmb, orc):
+    """Step counts that are not a multiple of the captured chunk replay a
+    remainder graph; the loss history must continue seamlessly."""
+    n = 1 << 14
+    ps, d, m, p0 = _problem(orc, n)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    _, th_a, h_a = wmb.calibrate(dd, mt, p0, steps=73, free_mask=MASK_L4)
+    _, th_b, h_b = wmb.calibrate(dd, mt, p0, steps=73, free_mask=MASK_L4)
+    assert np.array_equal(th_a, th_b) and np.array_equal(h_a, h_b)
+    _, th_c, h_c = wmb.calibrate(dd, mt, p0, steps=1, free_mask=MASK_L4)
+    assert h_c[0] == h_a[0]
+
+
+def _batched_problem(orc, wmb, scale_down):
+    sets = synth.multi_arch_sets()
+    sizes = [max(4096, s // scale_down) for s in synth.multi_arch_sizes()]
+    descs, hdesc, meas, p0s, masks = [], [], [], [], []
+    for k, (pk, nk) in enumerate(zip(sets, sizes)):
+        dk = synth.descriptors(nk, 120 + k)
+        Tk, _ = orc.predict(pk, dk)
+        mk = (Tk * synth.lognormal_noise(nk, 130 + k, 0.02)).astype(np.float32)
+        mask = MASK_L4 if pk.n_levels == 4 else MASK_L3
+        hdesc.append(dk)
+        descs.append(wmb.DeviceDescriptors.from_host(dk))
+        meas.append(torch.from_numpy(mk).cuda())
+        p0s.append(synth.perturb_theta(pk, 140 + k, mask=mask))
+        masks.append(mask)
+    return sets, sizes, descs, hdesc, meas, p0s, masks
+
+
+def test_batched_matches_plain_per_set(wmb, orc):
+    sets, sizes, descs, hdesc, meas, p0s, masks = _batched_problem(orc, wmb, 16)
+    steps = 60
+    opts = [wmb.calib_opts(steps=steps, free_mask=mk) for mk in masks]
+    rc, thb, histb = wmb.calibrate_batched(descs, meas, p0s, opts)
+    assert rc == wmb.WM_OK
+    for k in range(len(sets)):
+        rck, thk, histk = wmb.calibrate(descs[k], meas[k], p0s[k], steps=steps, free_mask=masks[k])
+        say("set", k, "n", sizes[k], "L", sets[k].n_levels)
+        assert np.allclose(histb[k], histk, rtol=1e-9, atol=0), k
+        assert np.allclose(thb[k], thk, rtol=1e-9, atol=0), k
+        # first-step loss equals the oracle's at theta0
+        l0 = orc.loss_grad(p0s[k], hdesc[k], meas[k].cpu().numpy())[0]
+        assert abs(histb[k][0] - l0) <= 1e-5 * l0
+
+
+def test_batched_recovery_within_3pct(wmb, orc):
+    sets, sizes, descs, hdesc, meas, p0s, masks = _batched_problem(orc, wmb, 1)
+    say("batched sizes", sizes)
+    opts = [wmb.calib_opts(steps=500, free_mask=mk) for mk in masks]
+    rc, thb, histb = wmb.calibrate_batched(descs, meas, p0s, opts)
+    assert rc == wmb.WM_OK
+    for k, pk in enumerate(sets):
+        e = _rec_err(thb[k], pk, masks[k])
+        say("set", k, "recovery error", e)
+        assert e <= 0.03
