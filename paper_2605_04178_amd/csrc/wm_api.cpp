@@ -189,15 +189,31 @@ CalibState init_state(const wm_params_t* p, uint32_t mask)
 }
 
 // calibration workspace layout
+// gradient-sweep workspace: partial rows, then redo-flag words
+struct GradWs {
+    GradLayout g;
+    size_t partials, flags, total;
+};
+
+GradWs grad_ws(int64_t n)
+{
+    GradWs W;
+    W.g = grad_layout(n);
+    W.partials = 0;
+    W.flags = up256(sizeof(double) * kAcc * (size_t)(W.g.nb + W.g.nb2));
+    W.total = W.flags + up256(sizeof(uint64_t) * (size_t)(W.g.nwords > 0 ? W.g.nwords : 1));
+    return W;
+}
+
 struct CalibLayout {
-    size_t set, state, hist, partials, total;
-    int nb;
+    size_t set, state, hist, grad, total;
+    GradWs g;
 };
 
 CalibLayout calib_layout(int64_t n, int32_t steps)
 {
     CalibLayout L;
-    L.nb = grad_blocks(n);
+    L.g = grad_ws(n);
     size_t off = 0;
     L.set = off;
     off += up256(sizeof(Set));
@@ -205,18 +221,19 @@ CalibLayout calib_layout(int64_t n, int32_t steps)
     off += up256(sizeof(CalibState));
     L.hist = off;
     off += up256(sizeof(double) * (size_t)(steps > 0 ? steps : 1));
-    L.partials = off;
-    off += up256(sizeof(double) * kAcc * (size_t)L.nb);
+    L.grad = off;
+    off += L.g.total;
     L.total = off;
     return L;
 }
 
 constexpr int64_t kBatchChunk = 16384;
-constexpr int kBatchMaxBlocks = 1024;
+constexpr int kBatchMaxBlocks = kGradMaxBlocks;
 
 struct BatchLayout {
-    size_t sets, states, opts, descs, meas, items, hist, partials, total;
-    int nb, max_items;
+    size_t sets, states, opts, descs, meas, items, setn, flagoff, hist, partials, flags, total;
+    int nb, nb2, max_items;
+    int64_t max_words;
 };
 
 BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
@@ -224,6 +241,8 @@ BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
     BatchLayout L;
     L.max_items = (int)(n_total / kBatchChunk + n_sets + 1);
     L.nb = L.max_items < kBatchMaxBlocks ? L.max_items : kBatchMaxBlocks;
+    L.nb2 = grad_layout(n_total).nb2;
+    L.max_words = n_total / 64 + n_sets + 1;
     size_t off = 0;
     L.sets = off;
     off += up256(sizeof(Set) * n_sets);
@@ -237,10 +256,16 @@ BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
     off += up256(sizeof(float*) * n_sets);
     L.items = off;
     off += up256(sizeof(WorkItem) * (size_t)L.max_items);
+    L.setn = off;
+    off += up256(sizeof(int64_t) * n_sets);
+    L.flagoff = off;
+    off += up256(sizeof(int64_t) * n_sets);
     L.hist = off;
     off += up256(sizeof(double) * (size_t)n_sets * (size_t)(steps > 0 ? steps : 1));
     L.partials = off;
-    off += up256(sizeof(double) * kAcc * (size_t)n_sets * (size_t)L.nb);
+    off += up256(sizeof(double) * kAcc * (size_t)n_sets * (size_t)(L.nb + L.nb2));
+    L.flags = off;
+    off += up256(sizeof(uint64_t) * (size_t)L.max_words);
     L.total = off;
     return L;
 }
@@ -348,7 +373,7 @@ size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps)
     switch (op) {
     case WM_OP_VJP:
     case WM_OP_LOSS_GRAD:
-        return up256(sizeof(double) * kAcc * (size_t)grad_blocks(n));
+        return grad_ws(n).total;
     case WM_OP_CALIBRATE:
         if (steps < 1) return 0;
         return calib_layout(n, steps).total;
@@ -390,10 +415,11 @@ static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, cons
     const size_t need = wm_workspace_bytes(mode == 1 ? WM_OP_LOSS_GRAD : WM_OP_VJP, desc->n, 1, 0);
     if (!ws_ok(ws, ws_bytes, need)) return WM_EWORKSPACE;
     const Set S = make_set(params);
-    const int nb = grad_blocks(desc->n);
+    const GradWs W = grad_ws(desc->n);
+    char* base = (char*)ws;
     // n == 0 still writes zeros through the (empty) sweep and reduction
-    WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)ws, nb, out,
-                       (hipStream_t)stream));
+    WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)(base + W.partials),
+                       (uint64_t*)(base + W.flags), W.g, out, (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -447,7 +473,8 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
     Set* S_dev = (Set*)(base + L.set);
     CalibState* st_dev = (CalibState*)(base + L.state);
     double* hist_dev = (double*)(base + L.hist);
-    double* part_dev = (double*)(base + L.partials);
+    double* part_dev = (double*)(base + L.grad + L.g.partials);
+    uint64_t* flags_dev = (uint64_t*)(base + L.grad + L.g.flags);
     const Set S = make_set(p0);
     const CalibState st0 = init_state(p0, opts->free_mask);
     const AdamOpts ao = adam_of(opts);
@@ -457,11 +484,12 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
 
     const DescPtrs dp = ptrs_of(desc);
     const int64_t n = desc->n;
-    const int nb = L.nb;
+    const GradLayout G = L.g.g;
+    const int rows = grad_grid(1, true, n) + G.nb2;
     auto step = [&]() -> hipError_t {
-        hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, nb, nullptr, s);
+        hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, flags_dev, G, nullptr, s);
         if (e != hipSuccess) return e;
-        return launch_adam(part_dev, nb, st_dev, ao, S_dev, hist_dev, s);
+        return launch_adam(part_dev, rows, st_dev, ao, S_dev, hist_dev, s);
     };
     rc = run_steps(s, opts->steps, step);
     if (rc != WM_OK) return rc;
@@ -503,8 +531,13 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float*
     std::vector<AdamOpts> oh((size_t)n_sets);
     std::vector<DescPtrs> dh((size_t)n_sets);
     std::vector<const float*> mh((size_t)n_sets);
+    std::vector<int64_t> nh((size_t)n_sets), foh((size_t)n_sets);
     std::vector<WorkItem> items;
+    int64_t words = 0;
     for (int s = 0; s < n_sets; ++s) {
+        nh[s] = sets[s].n;
+        foh[s] = words;
+        words += (sets[s].n + 63) / 64;
         Sh[s] = make_set(&p0[s]);
         sth[s] = init_state(&p0[s], opts[s].free_mask);
         oh[s] = adam_of(&opts[s]);
@@ -520,7 +553,7 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float*
         }
     }
     const int n_items = (int)items.size();
-    const int nb = n_items < 1 ? 1 : (n_items < L.nb ? n_items : L.nb);
+    const int nb = batched_grid(n_items);
 
     hipStream_t s = nullptr;
     int32_t rc = capture_stream(stream, &s);
@@ -532,23 +565,30 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float*
     DescPtrs* d_dev = (DescPtrs*)(base + L.descs);
     const float** m_dev = (const float**)(base + L.meas);
     WorkItem* it_dev = (WorkItem*)(base + L.items);
+    int64_t* n_dev = (int64_t*)(base + L.setn);
+    int64_t* fo_dev = (int64_t*)(base + L.flagoff);
     double* hist_dev = (double*)(base + L.hist);
     double* part_dev = (double*)(base + L.partials);
+    uint64_t* flags_dev = (uint64_t*)(base + L.flags);
     WM_HIP(hipMemcpyAsync(S_dev, Sh.data(), sizeof(Set) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(st_dev, sth.data(), sizeof(CalibState) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(o_dev, oh.data(), sizeof(AdamOpts) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(d_dev, dh.data(), sizeof(DescPtrs) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(m_dev, mh.data(), sizeof(float*) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(n_dev, nh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(fo_dev, foh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
     if (n_items > 0)
         WM_HIP(hipMemcpyAsync(it_dev, items.data(), sizeof(WorkItem) * n_items,
                               hipMemcpyHostToDevice, s));
     WM_HIP(hipStreamSynchronize(s));
 
+    const int nb2 = L.nb2;
     auto step = [&]() -> hipError_t {
-        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, part_dev,
-                                           nb, s);
+        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, n_dev,
+                                           fo_dev, flags_dev, words, part_dev, nb, nb2, s);
         if (e != hipSuccess) return e;
-        return launch_adam_batched(part_dev, nb, n_sets, st_dev, o_dev, S_dev, steps, hist_dev, s);
+        return launch_adam_batched(part_dev, nb + nb2, n_sets, st_dev, o_dev, S_dev, steps,
+                                   hist_dev, s);
     };
     rc = run_steps(s, steps, step);
     if (rc != WM_OK) return rc;

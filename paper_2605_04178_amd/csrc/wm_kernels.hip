@@ -11,6 +11,10 @@
 // and across blocks by a second single-block kernel in a fixed order.
 #include "wm_launch.hpp"
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 namespace wm {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -165,91 +169,159 @@ __device__ inline void block_reduce_acc(double* acc, double* lds /* [4][26] */, 
     __syncthreads();
 }
 
-// one descriptor's contribution: mode 0 weight = dL/dT, mode 1 mean relative error
+// Weight of one descriptor's Jacobian row in the sum, and its loss term.
+// mode 0: dL/dT supplied; mode 1: mean relative error against measured m.
+// Returns false if the descriptor does not contribute.
+template <int MODE, typename R>
+__device__ inline bool weight_of(R T, float wi, double& w, double& loss_term)
+{
+    if (MODE == 1) {
+        if (!(wi > 0.0f && wi < __builtin_huge_valf())) return false;
+        // 1/m: float32 reciprocal refined by one float64 Newton step (~1e-14)
+        const double m = wi, r0 = (double)__builtin_amdgcn_rcpf(wi);
+        const double im = r0 * (2.0 - m * r0), Td = (double)T;
+        loss_term = __builtin_fabs(Td - m) * im;
+        w = Td > m ? im : (Td < m ? -im : 0.0);
+    } else {
+        w = wi;
+        loss_term = 0.0;
+    }
+    return true;
+}
+
+// Phase 1, float32: accumulate the descriptor's contribution unless it lies
+// within 1e-5 of a max/min switch or (mode 1) of T = m; those return true and
+// are left to the float64 pass.
 template <int MODE>
-__device__ inline void grad_one(const Set& S, const Desc<float>& x, float wi, double* acc)
+__device__ inline bool grad_fast(const Set& S, const Desc<float>& x, float wi, double* acc)
 {
     Eval<float> E;
     evaluate<float, true>(S.st, S.cf, x, E);
-    if (!(E.T < __builtin_huge_valf())) return;  // invalid (NaN) or infeasible (+inf)
+    if (!(E.T < __builtin_huge_valf())) return false;  // invalid (NaN) or infeasible (+inf)
     bool redo = E.near_kink;
-    double w;
-    if (MODE == 1) {
-        if (!(wi > 0.0f && wi < __builtin_huge_valf())) return;
+    if (MODE == 1 && wi > 0.0f && wi < __builtin_huge_valf()) {
         const float rho = E.T * __builtin_amdgcn_rcpf(wi) - 1.0f;
         redo = redo || (__builtin_fabsf(rho) <= 1e-5f);
     }
-    if (!redo) {
-        if (MODE == 1) {
-            const double m = wi, im = 1.0 / m, Td = E.T;
-            acc[0] += __builtin_fabs(Td - m) * im;
-            acc[1] += 1.0;
-            w = Td > m ? im : (Td < m ? -im : 0.0);
-        } else {
-            w = wi;
-        }
-        accumulate_partials<float, double>(S.st, S.cf, E, w, acc);
-    } else {
-        // float64 re-evaluation decides the loss sign and the active branch
-        Eval<double> D;
-        evaluate<double, true>(S.st, S.cd, widen(x), D);
-        if (MODE == 1) {
-            const double m = wi, im = 1.0 / m;
-            acc[0] += __builtin_fabs(D.T - m) * im;
-            acc[1] += 1.0;
-            w = D.T > m ? im : (D.T < m ? -im : 0.0);
-        } else {
-            w = wi;
-        }
-        accumulate_partials<double, double>(S.st, S.cd, D, w, acc);
+    if (redo) return true;
+    double w, lt;
+    if (!weight_of<MODE>(E.T, wi, w, lt)) return false;
+    if (MODE == 1) {
+        acc[0] += lt;
+        acc[1] += 1.0;
     }
+    accumulate_partials<float, double>(S.st, S.cf, E, w, acc);
+    return false;
 }
 
+// Phase 2, float64: the full contribution of a flagged descriptor.
+template <int MODE>
+__device__ inline void grad_exact(const Set& S, const Desc<float>& x, float wi, double* acc)
+{
+    Eval<double> D;
+    evaluate<double, true>(S.st, S.cd, widen(x), D);
+    if (!(D.T < __builtin_huge_val())) return;
+    double w, lt;
+    if (!weight_of<MODE>(D.T, wi, w, lt)) return;
+    if (MODE == 1) {
+        acc[0] += lt;
+        acc[1] += 1.0;
+    }
+    accumulate_partials<double, double>(S.st, S.cd, D, w, acc);
+}
+
+// Phase 1 sweep.  The loop runs over wave-aligned groups of 64 consecutive
+// descriptors so that every group's redo flags leave as one 64-bit ballot
+// word, written exactly once (no clearing needed, order fixed).
 template <int MODE, bool PTR>
 __global__ __launch_bounds__(256) void k_grad(DescPtrs d, int64_t n, const float* __restrict__ wv,
                                                Set sv, const Set* __restrict__ sp,
-                                               double* __restrict__ partials)
+                                               double* __restrict__ partials,
+                                               uint64_t* __restrict__ flags)
 {
     __shared__ double red[4 * kAcc];
     const Set& S = PTR ? *sp : sv;
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        Desc<float> x = load_desc(d, i);
-        const float wi = ntload(wv + i);
-        grad_one<MODE>(S, x, wi, acc);
+    // software pipeline: the next group's loads are in flight while this
+    // group is evaluated
+    int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    Desc<float> xn;
+    float wn = 0.0f;
+    if (base + lane < n) {
+        xn = load_desc(d, base + lane);
+        wn = ntload(wv + base + lane);
+    }
+    for (; base < n; base += stride) {
+        const int64_t i = base + lane;
+        const Desc<float> x = xn;
+        const float w = wn;
+        const int64_t inext = i + stride;
+        if (inext < n) {
+            xn = load_desc(d, inext);
+            wn = ntload(wv + inext);
+        }
+        bool redo = false;
+        if (i < n) redo = grad_fast<MODE>(S, x, w, acc);
+        const uint64_t m = __ballot(redo);
+        if (lane == 0) flags[base >> 6] = m;
     }
     block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
 }
 
-// Fixed-order sum of the per-block partials: thread t adds blocks t, t+256,
-// ...; then a tree over the 256 threads.  mode 1 divides by the count.
-__device__ inline void reduce_partials(const double* __restrict__ partials, int nb, int stride,
-                                       double* sh /* [256] */, double* tot /* [26] */)
+// Phase 2 sweep over the flag words (fixed order).
+template <int MODE, bool PTR>
+__global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
+                                                    const float* __restrict__ wv, Set sv,
+                                                    const Set* __restrict__ sp,
+                                                    const uint64_t* __restrict__ flags,
+                                                    double* __restrict__ partials)
 {
-    for (int j = 0; j < kAcc; ++j) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(int64_t)b * stride + j];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int m = blockDim.x >> 1; m >= 1; m >>= 1) {
-            if ((int)threadIdx.x < m) sh[threadIdx.x] += sh[threadIdx.x + m];
-            __syncthreads();
+    __shared__ double red[4 * kAcc];
+    const Set& S = PTR ? *sp : sv;
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    const int64_t nwords = (n + 63) >> 6;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
+        uint64_t m = flags[wi];
+        while (m) {
+            const int bit = __builtin_ctzll(m);
+            m &= m - 1;
+            const int64_t i = (wi << 6) + bit;
+            grad_exact<MODE>(S, load_desc(d, i), wv[i], acc);
         }
-        if (threadIdx.x == 0) tot[j] = sh[0];
-        __syncthreads();
     }
+    block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
+}
+
+// Fixed-order sum of partial rows: thread t adds rows t, t+256, ... of all 26
+// columns, then the block tree of block_reduce_acc.
+__device__ inline void reduce_partials(const double* __restrict__ partials, int rows, int stride,
+                                       double* red /* [4][26] */, double* tot /* [26] */)
+{
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        const double* row = partials + (int64_t)r * stride;
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
+    }
+    block_reduce_acc(acc, red, tot);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int nb,
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int rows,
                                                  double* __restrict__ out)
 {
-    __shared__ double sh[256];
+    __shared__ double red[4 * kAcc];
     __shared__ double tot[kAcc];
-    reduce_partials(partials, nb, kAcc, sh, tot);
+    reduce_partials(partials, rows, kAcc, red, tot);
     if (threadIdx.x < kAcc) {
         if (MODE == 1) {
             const double c = tot[1];
@@ -261,41 +333,88 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ parti
     }
 }
 
-int grad_blocks(int64_t n)
+GradLayout grad_layout(int64_t n)
 {
-    int64_t b = (n + 1023) / 1024;
-    if (b > kGradMaxBlocks) b = kGradMaxBlocks;
-    if (b < 1) b = 1;
-    return (int)b;
+    GradLayout L;
+    int64_t b = (n + 255) / 256;
+    L.nb = (int)(b < 1 ? 1 : (b > kGradMaxBlocks ? kGradMaxBlocks : b));
+    L.nwords = (n + 63) / 64;
+    int64_t b2 = (L.nwords + 255) / 256;
+    L.nb2 = (int)(b2 < 1 ? 1 : (b2 > kRedoMaxBlocks ? kRedoMaxBlocks : b2));
+    return L;
+}
+
+// Blocks of 256 threads that are resident at once on the current device for
+// a kernel (occupancy x compute units), cached per device and kernel.  A
+// persistent grid of exactly this size has no second, half-empty round.
+static int resident_blocks(const void* kernel)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair(dev, kernel);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1;
+    int r = per_cu * cus;
+    r = r < 1 ? 1 : r;
+    cache[key] = r;
+    return r;
+}
+
+template <int MODE, bool PTR>
+static int grad_grid_t(int64_t n)
+{
+    const GradLayout L = grad_layout(n);
+    const int r = resident_blocks(reinterpret_cast<const void*>(&k_grad<MODE, PTR>));
+    return r < L.nb ? r : L.nb;
+}
+
+int grad_grid(int mode, bool ptr, int64_t n)
+{
+    if (mode == 1) return ptr ? grad_grid_t<1, true>(n) : grad_grid_t<1, false>(n);
+    return ptr ? grad_grid_t<0, true>(n) : grad_grid_t<0, false>(n);
+}
+
+template <int MODE, bool PTR>
+static void launch_grad_t(const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                          const Set* S_dev, double* partials, uint64_t* flags, int nb,
+                          const GradLayout& L, hipStream_t stream)
+{
+    k_grad<MODE, PTR><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials, flags);
+    k_grad_redo<MODE, PTR><<<L.nb2, 256, 0, stream>>>(d, n, w, S, S_dev, flags,
+                                                       partials + (int64_t)nb * kAcc);
 }
 
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
-                       const Set* S_dev, double* partials, int nb, double* out, hipStream_t stream)
+                       const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
+                       double* out, hipStream_t stream)
 {
+    const int nb = grad_grid(mode, S_dev != nullptr, n);
     if (mode == 1) {
-        if (S_dev)
-            k_grad<1, true><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
-        else
-            k_grad<1, false><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+        if (S_dev) launch_grad_t<1, true>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
+        else launch_grad_t<1, false>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
     } else {
-        if (S_dev)
-            k_grad<0, true><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
-        else
-            k_grad<0, false><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials);
+        if (S_dev) launch_grad_t<0, true>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
+        else launch_grad_t<0, false>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !out) return e;
     if (mode == 1)
-        k_reduce<1><<<1, 256, 0, stream>>>(partials, nb, out);
+        k_reduce<1><<<1, 256, 0, stream>>>(partials, nb + L.nb2, out);
     else
-        k_reduce<0><<<1, 256, 0, stream>>>(partials, nb, out);
+        k_reduce<0><<<1, 256, 0, stream>>>(partials, nb + L.nb2, out);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // device Adam on log(theta)
 // ---------------------------------------------------------------------------
-// state: theta, phi, m, v (24 each), theta_last_finite (24), flags
 __device__ inline void adam_update(CalibState* st, const double* tot, const AdamOpts& o, Set* S,
                                    double* loss_hist)
 {
@@ -349,32 +468,34 @@ __device__ inline void adam_update(CalibState* st, const double* tot, const Adam
     make_const<double>(st->theta, S->st, S->cd);
 }
 
-__global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partials, int nb,
+__global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partials, int rows,
                                                CalibState* st, AdamOpts o, Set* S,
                                                double* loss_hist)
 {
-    __shared__ double sh[256];
+    __shared__ double red[4 * kAcc];
     __shared__ double tot[kAcc];
-    reduce_partials(partials, nb, kAcc, sh, tot);
+    reduce_partials(partials, rows, kAcc, red, tot);
     adam_update(st, tot, o, S, loss_hist);
 }
 
-hipError_t launch_adam(const double* partials, int nb, CalibState* st, const AdamOpts& o, Set* S,
+hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream)
 {
-    k_adam<<<1, 256, 0, stream>>>(partials, nb, st, o, S, loss_hist);
+    k_adam<<<1, 256, 0, stream>>>(partials, rows, st, o, S, loss_hist);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // multi-set calibration sweep: one persistent launch over a (set, chunk)
-// work list; per-block, per-set accumulators staged in LDS
+// work list; per-block, per-set sums staged in LDS
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict__ sets,
                                                        const float* const* __restrict__ meas,
                                                        const Set* __restrict__ S_all,
                                                        const WorkItem* __restrict__ items,
                                                        int n_items, int n_sets,
+                                                       const int64_t* __restrict__ flag_off,
+                                                       uint64_t* __restrict__ flags,
                                                        double* __restrict__ partials)
 {
     __shared__ double red[4 * kAcc];
@@ -385,6 +506,7 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
     const int b = blockIdx.x, nb = gridDim.x;
     const int it0 = (int)((int64_t)n_items * b / nb);
     const int it1 = (int)((int64_t)n_items * (b + 1) / nb);
+    const int lane = threadIdx.x & 63;
     int cur = -1;
     double acc[kAcc];
 #pragma unroll
@@ -404,9 +526,14 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
         const DescPtrs d = sets[w.set];
         const float* m = meas[w.set];
         const Set& S = S_all[w.set];
-        for (int64_t i = w.begin + threadIdx.x; i < w.end; i += blockDim.x) {
-            Desc<float> x = load_desc(d, i);
-            grad_one<1>(S, x, ntload(m + i), acc);
+        uint64_t* fl = flags + flag_off[w.set];
+        // items start at multiples of 64, so each wave covers whole flag words
+        for (int64_t base = w.begin + (threadIdx.x & ~63); base < w.end; base += blockDim.x) {
+            const int64_t i = base + lane;
+            bool redo = false;
+            if (i < w.end) redo = grad_fast<1>(S, load_desc(d, i), ntload(m + i), acc);
+            const uint64_t msk = __ballot(redo);
+            if (lane == 0) fl[base >> 6] = msk;
         }
     }
     if (cur >= 0) {
@@ -418,32 +545,83 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
         partials[(int64_t)b * n_sets * kAcc + j] = per_set[j];
 }
 
-__global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__ partials, int nb,
+// Phase 2 for every set in turn (set loop uniform; fixed order).
+__global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __restrict__ sets,
+                                                            const float* const* __restrict__ meas,
+                                                            const Set* __restrict__ S_all,
+                                                            const int64_t* __restrict__ set_n,
+                                                            const int64_t* __restrict__ flag_off,
+                                                            const uint64_t* __restrict__ flags,
+                                                            int n_sets,
+                                                            double* __restrict__ partials)
+{
+    __shared__ double red[4 * kAcc];
+    __shared__ double tot[kAcc];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int s = 0; s < n_sets; ++s) {
+        double acc[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        const DescPtrs d = sets[s];
+        const float* m = meas[s];
+        const Set& S = S_all[s];
+        const uint64_t* fl = flags + flag_off[s];
+        const int64_t nwords = (set_n[s] + 63) >> 6;
+        for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
+            uint64_t mk = fl[wi];
+            while (mk) {
+                const int bit = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                const int64_t i = (wi << 6) + bit;
+                grad_exact<1>(S, load_desc(d, i), m[i], acc);
+            }
+        }
+        block_reduce_acc(acc, red, tot);
+        if (threadIdx.x < kAcc)
+            partials[((int64_t)blockIdx.x * n_sets + s) * kAcc + threadIdx.x] = tot[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__ partials, int rows,
                                                        int n_sets, CalibState* st,
                                                        const AdamOpts* __restrict__ opts,
                                                        Set* S_all, int steps, double* loss_hist)
 {
-    __shared__ double sh[256];
+    __shared__ double red[4 * kAcc];
     __shared__ double tot[kAcc];
     const int s = blockIdx.x;
-    reduce_partials(partials + s * kAcc, nb, n_sets * kAcc, sh, tot);
+    reduce_partials(partials + s * kAcc, rows, n_sets * kAcc, red, tot);
     adam_update(st + s, tot, opts[s], S_all + s,
                 loss_hist ? loss_hist + (int64_t)s * steps : nullptr);
 }
 
-hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
-                               const WorkItem* items, int n_items, int n_sets, double* partials,
-                               int nb, hipStream_t stream)
+int batched_grid(int n_items)
 {
-    k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, items, n_items, n_sets, partials);
+    const int r = resident_blocks(reinterpret_cast<const void*>(&k_grad_batched));
+    const int m = n_items < kGradMaxBlocks ? n_items : kGradMaxBlocks;
+    return m < 1 ? 1 : (r < m ? r : m);
+}
+
+hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
+                               const WorkItem* items, int n_items, int n_sets,
+                               const int64_t* set_n, const int64_t* flag_off, uint64_t* flags,
+                               int64_t total_words, double* partials, int nb, int nb2,
+                               hipStream_t stream)
+{
+    k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, items, n_items, n_sets, flag_off,
+                                           flags, partials);
+    (void)total_words;
+    k_grad_redo_batched<<<nb2, 256, 0, stream>>>(sets, meas, S_all, set_n, flag_off, flags, n_sets,
+                                                 partials + (int64_t)nb * n_sets * kAcc);
     return hipGetLastError();
 }
 
-hipError_t launch_adam_batched(const double* partials, int nb, int n_sets, CalibState* st,
+hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, CalibState* st,
                                const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
                                hipStream_t stream)
 {
-    k_adam_batched<<<n_sets, 256, 0, stream>>>(partials, nb, n_sets, st, opts, S_all, steps,
+    k_adam_batched<<<n_sets, 256, 0, stream>>>(partials, rows, n_sets, st, opts, S_all, steps,
                                                 loss_hist);
     return hipGetLastError();
 }

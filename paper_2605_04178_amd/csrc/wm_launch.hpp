@@ -10,7 +10,8 @@
 
 namespace wm {
 
-constexpr int kGradMaxBlocks = 1024;   // persistent gradient grid cap
+constexpr int kGradMaxBlocks = 2048;   // persistent gradient grid cap
+constexpr int kRedoMaxBlocks = 256;    // float64 re-evaluation grid cap
 constexpr int kTileMaxBlocks = 2048;   // persistent tile-selection grid cap
 constexpr int kMaxSets = 16;           // parameter sets per batched calibration
 constexpr float kTileWindow = 3e-5f;   // float32 window re-evaluated in float64
@@ -46,7 +47,18 @@ struct WorkItem {
     int64_t begin, end;
 };
 
-int grad_blocks(int64_t n);
+// Gradient sweep geometry for n descriptors: nb phase-1 blocks, nb2 phase-2
+// blocks (partial rows nb + nb2), nwords 64-bit redo-flag words.
+struct GradLayout {
+    int nb, nb2;
+    int64_t nwords;
+};
+GradLayout grad_layout(int64_t n);
+// phase-1 blocks actually launched (<= grad_layout(n).nb): the number of
+// blocks resident at once on the current device, so partial rows = that + nb2
+int grad_grid(int mode, bool from_device_set, int64_t n);
+// blocks for the multi-set sweep over n_items work items
+int batched_grid(int n_items);
 
 hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
                           bool vec4, hipStream_t stream);
@@ -57,14 +69,16 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
 // device memory (graph replay with a changing theta).  out == nullptr skips
 // the final reduction.
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
-                       const Set* S_dev, double* partials, int nb, double* out,
-                       hipStream_t stream);
-hipError_t launch_adam(const double* partials, int nb, CalibState* st, const AdamOpts& o, Set* S,
+                       const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
+                       double* out, hipStream_t stream);
+hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream);
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
-                               const WorkItem* items, int n_items, int n_sets, double* partials,
-                               int nb, hipStream_t stream);
-hipError_t launch_adam_batched(const double* partials, int nb, int n_sets, CalibState* st,
+                               const WorkItem* items, int n_items, int n_sets,
+                               const int64_t* set_n, const int64_t* flag_off, uint64_t* flags,
+                               int64_t total_words, double* partials, int nb, int nb2,
+                               hipStream_t stream);
+hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, CalibState* st,
                                const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
                                hipStream_t stream);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,

@@ -44,6 +44,7 @@ struct Const {
     R ov[7];     // T_launch, tau_wg, tau_bar, tau_interf, tau_gpu, tau_fusion, tau_sync
     R alpha, beta;
     R inv_w0;    // 1 / w0 when the Eq. (16) blend is on, else 0
+    R blend_k;   // -log2(e) / w0: exp(-W/w0) = exp2(W * blend_k)
     R bp_minus_bw;
     R inv_lw;    // 1 / bytes in flight per wave
     R inv_f;     // 1 / f_clk
@@ -71,6 +72,7 @@ WM_HD void make_const(const double* th, const Struct& s, Const<R>& c)
     c.beta = (R)th[21];
     c.blend_on = th[22] > 0.0 ? 1 : 0;
     c.inv_w0 = c.blend_on ? (R)(1.0 / th[22]) : (R)0;
+    c.blend_k = c.blend_on ? (R)(-1.4426950408889634 / th[22]) : (R)0;
     c.bp_minus_bw = (R)(th[23] - th[3]);
     c.inv_lw = (R)(1.0 / (double)s.bytes_inflight_wave);
     c.inv_f = (R)(1.0 / s.f_clk);
@@ -86,16 +88,26 @@ WM_HD void make_const(const double* th, const Struct& s, Const<R>& c)
 template <typename R> struct Ar;
 template <> struct Ar<float> {
     static __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ inline float pw(float x, float y) { return powf(x, y); }
-    static __device__ inline float ex(float x) { return expf(x); }
-    static __device__ inline float lg(float x) { return logf(x); }
+    // hardware base-2 logarithm / exponential (v_log_f32, v_exp_f32)
+    static __device__ inline float lg2(float x) { return __builtin_amdgcn_logf(x); }
+    static __device__ inline float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 };
 template <> struct Ar<double> {
     static __device__ inline double rcp(double x) { return 1.0 / x; }
-    static __device__ inline double pw(double x, double y) { return pow(x, y); }
-    static __device__ inline double ex(double x) { return exp(x); }
-    static __device__ inline double lg(double x) { return log(x); }
+    static __device__ inline double lg2(double x) { return log2(x); }
+    static __device__ inline double ex2(double x) { return exp2(x); }
 };
+
+// floor(a / b) for a < 2^24, 1 <= b < 2^24 and a quotient below 2^21: the
+// float estimate a * rcp(b) is within 0.37 of a / b (rcp 1 ulp, product
+// 0.5 ulp), so truncation is off by at most one, which the remainder fixes.
+__device__ inline uint32_t udiv_small(uint32_t a, uint32_t b)
+{
+    uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+    const int32_t r = (int32_t)(a - q * b);
+    q = r < 0 ? q - 1u : (r >= (int32_t)b ? q + 1u : q);
+    return q;
+}
 
 template <typename R>
 struct Desc {
@@ -112,20 +124,23 @@ struct Occ {
 
 __device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t g)
 {
+    // all quotients below are < 2^21 by the parameter limits (VGPR_SIMD <=
+    // 65536, N_SIMD * waves <= 1024), so udiv_small is exact
     Occ r;
     r.k = (g + (1 << st.wave_shift) - 1) >> st.wave_shift;
     int32_t w = 0;
     if (v <= st.vgpr_simd) {
         int32_t va = (v + st.vgpr_gran_mask) & ~st.vgpr_gran_mask;
-        w = (uint32_t)st.vgpr_simd / (uint32_t)va;
+        w = (int32_t)udiv_small((uint32_t)st.vgpr_simd, (uint32_t)va);
         w = w < st.waves_simd ? w : st.waves_simd;
     }
-    int32_t o = (uint32_t)(st.n_simd * w) / (uint32_t)r.k;
+    int32_t o = (int32_t)udiv_small((uint32_t)(st.n_simd * w), (uint32_t)r.k);
     if (s > 0) {
         int32_t ol = 0;
         if (s <= st.lds_cu) {
             int32_t sa = (s + st.lds_gran_mask) & ~st.lds_gran_mask;
-            ol = (uint32_t)st.lds_cu / (uint32_t)sa;
+            // o_l only matters below o_w <= 1024: cap it there so the quotient stays small
+            ol = (sa <= (st.lds_cu >> 10)) ? 1024 : (int32_t)udiv_small((uint32_t)st.lds_cu, (uint32_t)sa);
         }
         o = o < ol ? o : ol;
     }
@@ -189,30 +204,28 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         return;
     }
     const uint32_t per_round = (uint32_t)st.n_cu * (uint32_t)oc.o;
-    const int32_t nr = (int32_t)(((uint32_t)d.G + per_round - 1u) / per_round);
+    const uint32_t num = (uint32_t)d.G + per_round - 1u;
+    const int32_t nr = (int32_t)(num < (1u << 21) ? udiv_small(num, per_round) : num / per_round);
     E.nr = nr;
 
-    // traffic split
+    // traffic split: with W > 0 and an LLC, h_LLC(W) replaces r3
+    // (Table "hlcc-piecewise"): 1 below W_lo, base^alpha in the transition
+    // zone, (C/W)^beta above C -- one log2/exp2 pair for every regime
     R h3 = d.r3;
     E.llc_regime = 0;
     E.base_log = (R)0;
     if (st.n_levels == 4 && d.W > (R)0) {
         const R Wm = d.W * (R)(1.0 / 1048576.0);
-        if (Wm < c.w_lo) {
-            h3 = (R)1;
-        } else if (Wm <= c.c_llc) {
-            // (1 - (W - W_lo)/(C - W_lo)) written as (C - W)/(C - W_lo): same
-            // value, no cancellation near C
-            const R base = (c.c_llc - Wm) * c.inv_span;
-            h3 = A::pw(base, c.alpha);
-            E.llc_regime = 1;
-            if (FULL) E.base_log = base > (R)0 ? A::lg(base) : (R)0;
-        } else {
-            const R ratio = c.c_llc * A::rcp(Wm);
-            h3 = A::pw(ratio, c.beta);
-            E.llc_regime = 2;
-            if (FULL) E.base_log = A::lg(ratio);
-        }
+        const int reg = Wm < c.w_lo ? 0 : (Wm <= c.c_llc ? 1 : 2);
+        // (1 - (W - W_lo)/(C - W_lo)) written as (C - W)/(C - W_lo): same
+        // value, no cancellation near C
+        R x = reg == 1 ? (c.c_llc - Wm) * c.inv_span : c.c_llc * A::rcp(Wm);
+        x = reg == 0 ? (R)1 : x;
+        const R y = reg == 1 ? c.alpha : c.beta;
+        const R l2 = A::lg2(x);
+        h3 = x > (R)0 ? A::ex2(y * l2) : (R)0;
+        E.llc_regime = reg;
+        if (FULL) E.base_log = x > (R)0 ? l2 * (R)0.69314718055994531 : (R)0;
     }
     const R m1 = (R)1 - d.r1;
     const R s1 = d.r1;
@@ -223,9 +236,10 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         s3 = a12 * h3;
         sh = a12 * ((R)1 - h3);
     }
+    // Eq. (16) blend of the HBM bandwidth
     R e = (R)0, bwh = c.bw[3];
     if (c.blend_on && d.W > (R)0) {
-        e = A::ex(-d.W * c.inv_w0);
+        e = A::ex2(d.W * c.blend_k);
         bwh = c.bw[3] + c.bp_minus_bw * e;
     }
     const R S = s1 * c.bw[0] + s2 * c.bw[1] + s3 * c.bw[2] + sh * bwh;
