@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="forward sweep only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-steps", type=int, default=500)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the default launch configurations instead of autotuned ones")
     ap.add_argument("--profile", action="store_true",
                     help="run each hot kernel a few times, then a plain 1 GiB device copy whose "
                          "known traffic scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -159,6 +161,11 @@ def main():
         profile_run(wm, synth, dd, p, n, dev)
         return
 
+    tuned = {}
+    if not args.no_tune:
+        tuned["predict"] = wm.autotune_predict(dd, p)
+        log(f"autotuned predict: {tuned['predict']}")
+
     # ---- forward sweep (the step) ----
     fwd = lambda: wm.predict(dd, p, out_T=T, out_occ=occ)
     wall_ms, ev_ms = timed(fwd, args.steps, args.warmup)
@@ -175,8 +182,9 @@ def main():
                    "n_descriptors": n, "param_set": "seed 0, 4 levels, HK_MAX"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic("k_predict<4>"),
-                     "kernel": "wm::k_predict<4>", "bytes_per_eval": FWD_BYTES,
+                     "kernel": "wm::k_predict", "bytes_per_eval": FWD_BYTES,
                      "avg_launch_us": ev_ms * 1e3},
+        "launch": {"predict": wm.get_launch(wm.OP_PREDICT, n)},
     }
 
     if not args.quick:
@@ -189,6 +197,10 @@ def main():
         p0 = synth.perturb_theta(ps, 3)
         ws = wm._workspace(wm.workspace_bytes(wm.OP_LOSS_GRAD, n), dev)
         out = torch.empty(26, dtype=torch.float64, device=dev)
+        if not args.no_tune:
+            tuned["loss_grad"] = wm.autotune_grad(wm.OP_LOSS_GRAD, dd, meas, p0)
+            log(f"autotuned loss_grad: {tuned['loss_grad']}")
+        res["launch"]["loss_grad"] = wm.get_launch(wm.OP_LOSS_GRAD, n)
         lg = lambda: wm.loss_grad(dd, meas, p0, ws=ws, out=out)
         wall_a, ev_a = timed(lg, max(args.steps // 2, 3), 2)
         ach_a = ADJ_BYTES * n / (ev_a * 1e-3) / 1e9
@@ -202,6 +214,10 @@ def main():
         # ---- tile selection ----
         sh = synth.shapes(1 << 16, 102)
         dsh = wm.DeviceShapes.from_host(sh, dev)
+        if not args.no_tune:
+            tuned["select_tile"] = wm.autotune_select_tile(dsh, p)
+            log(f"autotuned select_tile: {tuned['select_tile']}")
+        res["launch"]["select_tile"] = wm.get_launch(wm.OP_SELECT_TILE, sh.n)
         outs = (torch.empty(sh.n, dtype=torch.int32, device=dev),
                 torch.empty(sh.n, dtype=torch.float64, device=dev),
                 torch.empty(sh.n, dtype=torch.uint8, device=dev))
@@ -232,6 +248,9 @@ def main():
         mc = (Tc * torch.from_numpy(synth.lognormal_noise(nc, 2, 0.02).astype(np.float32)).to(dev)).contiguous()
         mask = 0x3FFFFF
         p0c = synth.perturb_theta(ps, 3, mask=mask)
+        if not args.no_tune:
+            tuned["loss_grad_2^20"] = wm.autotune_grad(wm.OP_LOSS_GRAD, ddc, mc, p0c)
+        res["launch"]["calibrate"] = wm.get_launch(wm.OP_CALIBRATE, nc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, th, hist = wm.calibrate(ddc, mc, p0c, steps=args.calib_steps, free_mask=mask)
@@ -259,6 +278,10 @@ def main():
             meas_l.append(mk)
             p0s.append(synth.perturb_theta(pk, 140 + k, mask=mk_mask))
             opts.append(wm.calib_opts(steps=args.calib_steps, free_mask=mk_mask))
+        if not args.no_tune:
+            tuned["batched"] = wm.autotune_batched(descs, meas_l, p0s, opts)
+            log(f"autotuned batched: {tuned['batched']}")
+        res["launch"]["batched"] = wm.get_launch(wm.OP_CALIBRATE_BATCHED, sum(sizes))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rcb, thb, histb = wm.calibrate_batched(descs, meas_l, p0s, opts)
@@ -278,6 +301,8 @@ def main():
                           "speedup": el_p / el_b, "per_set_recovery_err": rec, "status": rcb}
         log(f"batched: {el_b:.3f} s persistent vs {el_p:.3f} s per-set")
 
+    if tuned:
+        res["autotune_us"] = {k: v["us"] for k, v in tuned.items()}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(p, d)

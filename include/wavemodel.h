@@ -14,7 +14,7 @@
  *    sized by wm_workspace_bytes(), 256-byte aligned.
  *  - Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
  *    stream).  Calls enqueue work and return without synchronising, except
- *    wm_calibrate / wm_calibrate_batched / wm_autotune, which synchronise
+ *    wm_calibrate, wm_calibrate_batched and the wm_autotune_* calls, which synchronise
  *    `stream` once before returning (they write host results).
  *  - Errors.  Return value 0 (WM_OK) or a negative status.  Arguments are
  *    validated on the host before any HIP call, so a bad call never launches
@@ -240,6 +240,56 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t *sets, const float 
                              const wm_params_t *p0, const wm_calib_opts_t *opts,
                              wm_params_t *p_out, double *loss_hist, void *ws, size_t ws_bytes,
                              void *stream);
+
+/* ---- launch configurations and autotuning ----
+ *
+ * Every call above launches its kernels with a configuration looked up by
+ * (GPU architecture, compute-unit count, op, floor(log2 n)); without an entry
+ * it uses the default.  Fields: block = threads per block (64, 128, 256,
+ * 512); per_thread = descriptors per thread of the forward sweep (1, 2, 4,
+ * 8; other ops ignore it); grid_mult = persistent grid as a multiple of the
+ * blocks resident at once (1..8; gradient, tile and batched sweeps); chunk =
+ * descriptors per work item of the batched sweep (power of two, 4096..65536;
+ * that op requires block 256).  Results do not depend on the configuration
+ * except through the order of FP64 additions in gradient sums (differences
+ * of order 1e-15 relative).  Entries live in process memory; if the
+ * environment variable WAVEMODEL_TUNE_CACHE names a file, tuning results are
+ * appended to it as JSON lines and read back at the first lookup.
+ */
+typedef struct {
+    int32_t block, per_thread, grid_mult, chunk;
+} wm_launch_t;
+
+/* Configuration the next call of `op` on n items would use (host; queries the
+ * current device).  WM_EINVAL for an unknown op or a NULL cfg. */
+int32_t wm_get_launch(int32_t op, int64_t n, wm_launch_t *cfg);
+
+/* Install a configuration for (current device, op, floor(log2 n)).
+ * WM_EINVAL if it is not valid for the op (checked before any HIP call). */
+int32_t wm_set_launch(int32_t op, int64_t n, const wm_launch_t *cfg);
+
+/* Autotuners: time every candidate configuration on the caller's inputs
+ * (one warm-up, median of 10 runs by HIP events on `stream`), install the
+ * fastest for this size bucket, and return it with its median time in
+ * microseconds (best / best_us, host, may be NULL).  They write the op's
+ * outputs as a side effect and synchronise `stream`.  Arguments as for the
+ * corresponding call; wm_autotune_grad takes op = WM_OP_VJP or
+ * WM_OP_LOSS_GRAD and `w` = dL/dT or the measured times.  The batched tuner
+ * times one calibration step per candidate in the workspace without
+ * touching the caller's parameter sets. */
+int32_t wm_autotune_predict(const wm_desc_t *desc, const wm_params_t *params, float *T,
+                            int32_t *occ, void *stream, wm_launch_t *best, double *best_us);
+int32_t wm_autotune_grad(int32_t op, const wm_desc_t *desc, const float *w,
+                         const wm_params_t *params, double *out, void *ws, size_t ws_bytes,
+                         void *stream, wm_launch_t *best, double *best_us);
+int32_t wm_autotune_select_tile(const wm_shapes_t *shapes, const int32_t *cand_off,
+                                const uint32_t *cand_code, int64_t n_cand,
+                                const wm_params_t *params, int32_t *best_idx, double *best_cost,
+                                uint8_t *near_tie, void *stream, wm_launch_t *best,
+                                double *best_us);
+int32_t wm_autotune_batched(int32_t n_sets, const wm_desc_t *sets, const float *const *measured,
+                            const wm_params_t *p0, const wm_calib_opts_t *opts, void *ws,
+                            size_t ws_bytes, void *stream, wm_launch_t *best, double *best_us);
 
 #ifdef __cplusplus
 }

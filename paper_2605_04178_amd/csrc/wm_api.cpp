@@ -3,6 +3,7 @@
 // HIP-graph capture of the calibration loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -227,7 +228,6 @@ CalibLayout calib_layout(int64_t n, int32_t steps)
     return L;
 }
 
-constexpr int64_t kBatchChunk = 16384;
 constexpr int kBatchMaxBlocks = kGradMaxBlocks;
 
 struct BatchLayout {
@@ -239,7 +239,7 @@ struct BatchLayout {
 BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
 {
     BatchLayout L;
-    L.max_items = (int)(n_total / kBatchChunk + n_sets + 1);
+    L.max_items = (int)(n_total / kMinChunk + n_sets + 1);
     L.nb = L.max_items < kBatchMaxBlocks ? L.max_items : kBatchMaxBlocks;
     L.nb2 = grad_layout(n_total).nb2;
     L.max_words = n_total / 64 + n_sets + 1;
@@ -346,6 +346,230 @@ int32_t capture_stream(void* user, hipStream_t* out)
     return WM_OK;
 }
 
+
+// Device images of a multi-set calibration in a workspace: the per-set
+// parameter images, Adam states, options, descriptor and measurement pointer
+// tables, and the (set, begin, end) work list in items of `chunk`
+// descriptors.  step() enqueues one sweep plus one reduce-and-Adam launch.
+struct BatchRun {
+    int n_sets = 0, steps = 0, n_items = 0, nb = 0, nb2 = 0;
+    int64_t words = 0;
+    Set* S_dev = nullptr;
+    CalibState* st_dev = nullptr;
+    AdamOpts* o_dev = nullptr;
+    DescPtrs* d_dev = nullptr;
+    const float** m_dev = nullptr;
+    WorkItem* it_dev = nullptr;
+    int64_t* n_dev = nullptr;
+    int64_t* fo_dev = nullptr;
+    double* hist_dev = nullptr;
+    double* part_dev = nullptr;
+    uint64_t* flags_dev = nullptr;
+    hipStream_t s = nullptr;
+
+    hipError_t step() const
+    {
+        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, n_dev,
+                                           fo_dev, flags_dev, words, part_dev, nb, nb2, s);
+        if (e != hipSuccess) return e;
+        return launch_adam_batched(part_dev, nb + nb2, n_sets, st_dev, o_dev, S_dev, steps,
+                                   hist_dev, s);
+    }
+};
+
+int32_t batch_prepare(int32_t n_sets, const wm_desc_t* sets, const float* const* measured,
+                      const wm_params_t* p0, const wm_calib_opts_t* opts, const BatchLayout& L,
+                      const LaunchCfg& cfg, void* ws, hipStream_t s, BatchRun* run)
+{
+    std::vector<Set> Sh((size_t)n_sets);
+    std::vector<CalibState> sth((size_t)n_sets);
+    std::vector<AdamOpts> oh((size_t)n_sets);
+    std::vector<DescPtrs> dh((size_t)n_sets);
+    std::vector<const float*> mh((size_t)n_sets);
+    std::vector<int64_t> nh((size_t)n_sets), foh((size_t)n_sets);
+    std::vector<WorkItem> items;
+    int64_t words = 0;
+    const int64_t chunk = cfg.chunk;
+    for (int k = 0; k < n_sets; ++k) {
+        nh[k] = sets[k].n;
+        foh[k] = words;
+        words += (sets[k].n + 63) / 64;
+        Sh[k] = make_set(&p0[k]);
+        sth[k] = init_state(&p0[k], opts[k].free_mask);
+        oh[k] = adam_of(&opts[k]);
+        dh[k] = ptrs_of(&sets[k]);
+        mh[k] = measured[k];
+        for (int64_t b = 0; b < sets[k].n; b += chunk) {
+            WorkItem w;
+            w.set = k;
+            w.pad_ = 0;
+            w.begin = b;
+            w.end = b + chunk < sets[k].n ? b + chunk : sets[k].n;
+            items.push_back(w);
+        }
+    }
+    if ((int)items.size() > L.max_items) return WM_EINVAL;
+    char* base = (char*)ws;
+    run->n_sets = n_sets;
+    run->steps = opts[0].steps;
+    run->n_items = (int)items.size();
+    run->nb = batched_grid(run->n_items, cfg.grid_mult);
+    run->nb2 = L.nb2;
+    run->words = words;
+    run->S_dev = (Set*)(base + L.sets);
+    run->st_dev = (CalibState*)(base + L.states);
+    run->o_dev = (AdamOpts*)(base + L.opts);
+    run->d_dev = (DescPtrs*)(base + L.descs);
+    run->m_dev = (const float**)(base + L.meas);
+    run->it_dev = (WorkItem*)(base + L.items);
+    run->n_dev = (int64_t*)(base + L.setn);
+    run->fo_dev = (int64_t*)(base + L.flagoff);
+    run->hist_dev = (double*)(base + L.hist);
+    run->part_dev = (double*)(base + L.partials);
+    run->flags_dev = (uint64_t*)(base + L.flags);
+    run->s = s;
+    WM_HIP(hipMemcpyAsync(run->S_dev, Sh.data(), sizeof(Set) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->st_dev, sth.data(), sizeof(CalibState) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->o_dev, oh.data(), sizeof(AdamOpts) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->d_dev, dh.data(), sizeof(DescPtrs) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->m_dev, mh.data(), sizeof(float*) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->n_dev, nh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->fo_dev, foh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        WM_HIP(hipMemcpyAsync(run->it_dev, items.data(), sizeof(WorkItem) * items.size(),
+                              hipMemcpyHostToDevice, s));
+    WM_HIP(hipStreamSynchronize(s));  // the host images above go out of scope
+    return WM_OK;
+}
+
+bool batch_args_ok(int32_t n_sets, const wm_desc_t* sets, const float* const* measured,
+                   const wm_params_t* p0, const wm_calib_opts_t* opts, int64_t* n_total)
+{
+    if (n_sets < 1 || n_sets > kMaxSets || !sets || !measured || !p0 || !opts) return false;
+    int64_t t = 0;
+    for (int k = 0; k < n_sets; ++k) {
+        if (!desc_ok(&sets[k]) || !measured[k] || !params_ok(&p0[k]) || !opts_ok(&opts[k]))
+            return false;
+        if (!free_slots_ok(&p0[k], opts[k].free_mask)) return false;
+        if (opts[k].steps != opts[0].steps) return false;
+        t += sets[k].n;
+    }
+    *n_total = t;
+    return true;
+}
+
+// median of `reps` event-timed runs (after one warm-up), microseconds
+template <typename F>
+int32_t time_median(hipStream_t s, int reps, F run, double* us)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    WM_HIP(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e);
+    }
+    std::vector<float> t;
+    e = run();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = run();
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e);
+    std::sort(t.begin(), t.end());
+    *us = 1e3 * (double)t[t.size() / 2];
+    return WM_OK;
+}
+
+wm_launch_t to_pub(const LaunchCfg& c)
+{
+    wm_launch_t o;
+    o.block = c.block;
+    o.per_thread = c.vec;
+    o.grid_mult = c.grid_mult;
+    o.chunk = c.chunk;
+    return o;
+}
+
+LaunchCfg from_pub(const wm_launch_t& o)
+{
+    LaunchCfg c;
+    c.block = o.block;
+    c.vec = o.per_thread;
+    c.grid_mult = o.grid_mult;
+    c.chunk = o.chunk;
+    return c;
+}
+
+// try every candidate, keep the fastest (ties: first), record it
+template <typename F>
+int32_t tune_over(int op, int64_t n, const std::vector<LaunchCfg>& cands, hipStream_t s, int reps,
+                  F run_with, wm_launch_t* best, double* best_us)
+{
+    double bu = 1e300;
+    LaunchCfg bc = cands.front();
+    for (const LaunchCfg& c : cands) {
+        double us = 0.0;
+        int32_t rc = time_median(s, reps, [&]() { return run_with(c); }, &us);
+        if (rc != WM_OK) return rc;
+        if (us < bu) {
+            bu = us;
+            bc = c;
+        }
+    }
+    store_cfg(op, n, bc, bu, true);
+    if (best) *best = to_pub(bc);
+    if (best_us) *best_us = bu;
+    return WM_OK;
+}
+
+std::vector<LaunchCfg> candidates(int op)
+{
+    std::vector<LaunchCfg> v;
+    const int blocks[4] = {64, 128, 256, 512};
+    LaunchCfg c = default_cfg(op);
+    if (op == kOpPredict) {
+        const int vecs[4] = {1, 2, 4, 8};
+        for (int b : blocks)
+            for (int vv : vecs) {
+                c.block = b;
+                c.vec = vv;
+                v.push_back(c);
+            }
+    } else if (op == kOpCalibrateBatched) {
+        for (int ch = (int)kMinChunk; ch <= 65536; ch *= 2)
+            for (int gm = 1; gm <= 2; ++gm) {
+                c.chunk = ch;
+                c.grid_mult = gm;
+                v.push_back(c);
+            }
+    } else {
+        for (int b : blocks)
+            for (int gm = 1; gm <= 4; gm *= 2) {
+                c.block = b;
+                c.grid_mult = gm;
+                v.push_back(c);
+            }
+    }
+    // the default first, so it wins ties
+    const LaunchCfg d = default_cfg(op);
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].block == d.block && v[i].vec == d.vec && v[i].grid_mult == d.grid_mult &&
+            v[i].chunk == d.chunk) {
+            std::swap(v[0], v[i]);
+            break;
+        }
+    return v;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -393,7 +617,8 @@ int32_t wm_predict(const wm_desc_t* desc, const wm_params_t* params, float* T, i
     if (!T) return WM_EINVAL;
     const bool vec = aligned16(desc) && ((uintptr_t)T & 15u) == 0 && ((uintptr_t)occ & 15u) == 0;
     const Set S = make_set(params);
-    WM_HIP(launch_predict(ptrs_of(desc), desc->n, S, T, occ, vec, (hipStream_t)stream));
+    WM_HIP(launch_predict(ptrs_of(desc), desc->n, S, T, occ, vec, launch_cfg(kOpPredict, desc->n),
+                          (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -418,8 +643,9 @@ static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, cons
     const GradWs W = grad_ws(desc->n);
     char* base = (char*)ws;
     // n == 0 still writes zeros through the (empty) sweep and reduction
+    const LaunchCfg cfg = launch_cfg(mode == 1 ? kOpLossGrad : kOpVjp, desc->n);
     WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)(base + W.partials),
-                       (uint64_t*)(base + W.flags), W.g, out, (hipStream_t)stream));
+                       (uint64_t*)(base + W.flags), W.g, cfg, out, (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -453,7 +679,7 @@ int32_t wm_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
     sp.dtype = shapes->dtype;
     const Set S = make_set(params);
     WM_HIP(launch_select_tile(sp, cand_off, cand_code, shapes->n, n_cand, S, best, best_cost,
-                              near_tie, 0, (hipStream_t)stream));
+                              near_tie, launch_cfg(kOpSelectTile, shapes->n), (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -485,9 +711,11 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
     const DescPtrs dp = ptrs_of(desc);
     const int64_t n = desc->n;
     const GradLayout G = L.g.g;
-    const int rows = grad_grid(1, true, n) + G.nb2;
+    const LaunchCfg cfg = launch_cfg(kOpLossGrad, n);
+    const int rows = grad_grid(1, true, n, cfg) + G.nb2;
     auto step = [&]() -> hipError_t {
-        hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, flags_dev, G, nullptr, s);
+        hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, flags_dev, G, cfg,
+                                   nullptr, s);
         if (e != hipSuccess) return e;
         return launch_adam(part_dev, rows, st_dev, ao, S_dev, hist_dev, s);
     };
@@ -511,91 +739,25 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float*
                              wm_params_t* p_out, double* loss_hist, void* ws, size_t ws_bytes,
                              void* stream)
 {
-    if (n_sets < 1 || n_sets > kMaxSets || !sets || !measured || !p0 || !opts || !p_out)
-        return WM_EINVAL;
     int64_t n_total = 0;
-    for (int s = 0; s < n_sets; ++s) {
-        if (!desc_ok(&sets[s]) || !measured[s] || !params_ok(&p0[s]) || !opts_ok(&opts[s]))
-            return WM_EINVAL;
-        if (!free_slots_ok(&p0[s], opts[s].free_mask)) return WM_EINVAL;
-        if (opts[s].steps != opts[0].steps) return WM_EINVAL;
-        n_total += sets[s].n;
-    }
+    if (!batch_args_ok(n_sets, sets, measured, p0, opts, &n_total) || !p_out) return WM_EINVAL;
     const int steps = opts[0].steps;
     const BatchLayout L = batch_layout(n_total, n_sets, steps);
     if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
-
-    // host images
-    std::vector<Set> Sh((size_t)n_sets);
-    std::vector<CalibState> sth((size_t)n_sets);
-    std::vector<AdamOpts> oh((size_t)n_sets);
-    std::vector<DescPtrs> dh((size_t)n_sets);
-    std::vector<const float*> mh((size_t)n_sets);
-    std::vector<int64_t> nh((size_t)n_sets), foh((size_t)n_sets);
-    std::vector<WorkItem> items;
-    int64_t words = 0;
-    for (int s = 0; s < n_sets; ++s) {
-        nh[s] = sets[s].n;
-        foh[s] = words;
-        words += (sets[s].n + 63) / 64;
-        Sh[s] = make_set(&p0[s]);
-        sth[s] = init_state(&p0[s], opts[s].free_mask);
-        oh[s] = adam_of(&opts[s]);
-        dh[s] = ptrs_of(&sets[s]);
-        mh[s] = measured[s];
-        for (int64_t b = 0; b < sets[s].n; b += kBatchChunk) {
-            WorkItem w;
-            w.set = s;
-            w.pad_ = 0;
-            w.begin = b;
-            w.end = b + kBatchChunk < sets[s].n ? b + kBatchChunk : sets[s].n;
-            items.push_back(w);
-        }
-    }
-    const int n_items = (int)items.size();
-    const int nb = batched_grid(n_items);
-
     hipStream_t s = nullptr;
     int32_t rc = capture_stream(stream, &s);
     if (rc != WM_OK) return rc;
-    char* base = (char*)ws;
-    Set* S_dev = (Set*)(base + L.sets);
-    CalibState* st_dev = (CalibState*)(base + L.states);
-    AdamOpts* o_dev = (AdamOpts*)(base + L.opts);
-    DescPtrs* d_dev = (DescPtrs*)(base + L.descs);
-    const float** m_dev = (const float**)(base + L.meas);
-    WorkItem* it_dev = (WorkItem*)(base + L.items);
-    int64_t* n_dev = (int64_t*)(base + L.setn);
-    int64_t* fo_dev = (int64_t*)(base + L.flagoff);
-    double* hist_dev = (double*)(base + L.hist);
-    double* part_dev = (double*)(base + L.partials);
-    uint64_t* flags_dev = (uint64_t*)(base + L.flags);
-    WM_HIP(hipMemcpyAsync(S_dev, Sh.data(), sizeof(Set) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(st_dev, sth.data(), sizeof(CalibState) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(o_dev, oh.data(), sizeof(AdamOpts) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(d_dev, dh.data(), sizeof(DescPtrs) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(m_dev, mh.data(), sizeof(float*) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(n_dev, nh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
-    WM_HIP(hipMemcpyAsync(fo_dev, foh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
-    if (n_items > 0)
-        WM_HIP(hipMemcpyAsync(it_dev, items.data(), sizeof(WorkItem) * n_items,
-                              hipMemcpyHostToDevice, s));
-    WM_HIP(hipStreamSynchronize(s));
-
-    const int nb2 = L.nb2;
-    auto step = [&]() -> hipError_t {
-        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, n_dev,
-                                           fo_dev, flags_dev, words, part_dev, nb, nb2, s);
-        if (e != hipSuccess) return e;
-        return launch_adam_batched(part_dev, nb + nb2, n_sets, st_dev, o_dev, S_dev, steps,
-                                   hist_dev, s);
-    };
-    rc = run_steps(s, steps, step);
+    BatchRun run;
+    rc = batch_prepare(n_sets, sets, measured, p0, opts, L, launch_cfg(kOpCalibrateBatched, n_total),
+                       ws, s, &run);
+    if (rc != WM_OK) return rc;
+    rc = run_steps(s, steps, [&]() { return run.step(); });
     if (rc != WM_OK) return rc;
 
-    WM_HIP(hipMemcpyAsync(sth.data(), st_dev, sizeof(CalibState) * n_sets, hipMemcpyDeviceToHost, s));
+    std::vector<CalibState> sth((size_t)n_sets);
+    WM_HIP(hipMemcpyAsync(sth.data(), run.st_dev, sizeof(CalibState) * n_sets, hipMemcpyDeviceToHost, s));
     std::vector<double> hist((size_t)n_sets * steps);
-    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev, sizeof(double) * hist.size(),
+    WM_HIP(hipMemcpyAsync(hist.data(), run.hist_dev, sizeof(double) * hist.size(),
                           hipMemcpyDeviceToHost, s));
     WM_HIP(hipStreamSynchronize(s));
     bool div = false;
@@ -607,6 +769,129 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float*
     }
     if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * hist.size());
     return div ? WM_EDIVERGED : WM_OK;
+}
+
+// ---- launch configurations and autotuning ----
+
+int32_t wm_get_launch(int32_t op, int64_t n, wm_launch_t* cfg)
+{
+    if (!cfg || n < 0 || !cfg_valid(op, default_cfg(op))) return WM_EINVAL;
+    *cfg = to_pub(launch_cfg(op, n));
+    return WM_OK;
+}
+
+int32_t wm_set_launch(int32_t op, int64_t n, const wm_launch_t* cfg)
+{
+    if (!cfg || n < 0) return WM_EINVAL;
+    const LaunchCfg c = from_pub(*cfg);
+    if (!cfg_valid(op, c)) return WM_EINVAL;
+    store_cfg(op, n, c, 0.0, false);
+    return WM_OK;
+}
+
+int32_t wm_autotune_predict(const wm_desc_t* desc, const wm_params_t* params, float* T,
+                            int32_t* occ, void* stream, wm_launch_t* best, double* best_us)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !T || desc->n < 1) return WM_EINVAL;
+    const bool vec = aligned16(desc) && ((uintptr_t)T & 15u) == 0 && ((uintptr_t)occ & 15u) == 0;
+    const Set S = make_set(params);
+    const DescPtrs dp = ptrs_of(desc);
+    const int64_t n = desc->n;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<LaunchCfg> cands = candidates(kOpPredict);
+    if (!vec) {
+        std::vector<LaunchCfg> scal;
+        for (const LaunchCfg& c : cands)
+            if (c.vec == 1) scal.push_back(c);
+        cands = scal;
+    }
+    return tune_over(kOpPredict, n, cands, s, 10,
+                     [&](const LaunchCfg& c) { return launch_predict(dp, n, S, T, occ, vec, c, s); },
+                     best, best_us);
+}
+
+int32_t wm_autotune_grad(int32_t op, const wm_desc_t* desc, const float* w,
+                         const wm_params_t* params, double* out, void* ws, size_t ws_bytes,
+                         void* stream, wm_launch_t* best, double* best_us)
+{
+    if (op != WM_OP_VJP && op != WM_OP_LOSS_GRAD) return WM_EINVAL;
+    if (!desc_ok(desc) || !params_ok(params) || !out || !w || desc->n < 1) return WM_EINVAL;
+    const int mode = op == WM_OP_LOSS_GRAD ? 1 : 0;
+    const GradWs W = grad_ws(desc->n);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    const Set S = make_set(params);
+    const DescPtrs dp = ptrs_of(desc);
+    const int64_t n = desc->n;
+    char* base = (char*)ws;
+    hipStream_t s = (hipStream_t)stream;
+    return tune_over(op, n, candidates(op), s, 10,
+                     [&](const LaunchCfg& c) {
+                         return launch_grad(mode, dp, n, w, S, nullptr, (double*)(base + W.partials),
+                                            (uint64_t*)(base + W.flags), W.g, c, out, s);
+                     },
+                     best, best_us);
+}
+
+int32_t wm_autotune_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
+                                const uint32_t* cand_code, int64_t n_cand,
+                                const wm_params_t* params, int32_t* best_idx, double* best_cost,
+                                uint8_t* near_tie, void* stream, wm_launch_t* best,
+                                double* best_us)
+{
+    if (!shapes || shapes->n < 1 || !params_ok(params) || n_cand < 0 || n_cand > 0x7fffffffll)
+        return WM_EINVAL;
+    if (!shapes->M || !shapes->N || !shapes->K || !shapes->dtype || !cand_off || !best_idx ||
+        !best_cost || !near_tie || (n_cand > 0 && !cand_code))
+        return WM_EINVAL;
+    ShapePtrs sp;
+    sp.M = shapes->M;
+    sp.N = shapes->N;
+    sp.K = shapes->K;
+    sp.dtype = shapes->dtype;
+    const Set S = make_set(params);
+    const int64_t n = shapes->n;
+    hipStream_t s = (hipStream_t)stream;
+    return tune_over(kOpSelectTile, n, candidates(kOpSelectTile), s, 10,
+                     [&](const LaunchCfg& c) {
+                         return launch_select_tile(sp, cand_off, cand_code, n, n_cand, S, best_idx,
+                                                   best_cost, near_tie, c, s);
+                     },
+                     best, best_us);
+}
+
+int32_t wm_autotune_batched(int32_t n_sets, const wm_desc_t* sets, const float* const* measured,
+                            const wm_params_t* p0, const wm_calib_opts_t* opts, void* ws,
+                            size_t ws_bytes, void* stream, wm_launch_t* best, double* best_us)
+{
+    int64_t n_total = 0;
+    if (!batch_args_ok(n_sets, sets, measured, p0, opts, &n_total)) return WM_EINVAL;
+    const BatchLayout L = batch_layout(n_total, n_sets, opts[0].steps);
+    if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
+    hipStream_t s = nullptr;
+    int32_t rc = capture_stream(stream, &s);
+    if (rc != WM_OK) return rc;
+    // every candidate times one calibration step (sweep + reduce-and-Adam)
+    // from freshly uploaded images, so the Adam state it perturbs is private
+    // to the workspace
+    std::vector<LaunchCfg> cands = candidates(kOpCalibrateBatched);
+    double bu = 1e300;
+    LaunchCfg bc = cands.front();
+    for (const LaunchCfg& c : cands) {
+        BatchRun run;
+        rc = batch_prepare(n_sets, sets, measured, p0, opts, L, c, ws, s, &run);
+        if (rc != WM_OK) return rc;
+        double us = 0.0;
+        rc = time_median(s, 10, [&]() { return run.step(); }, &us);
+        if (rc != WM_OK) return rc;
+        if (us < bu) {
+            bu = us;
+            bc = c;
+        }
+    }
+    store_cfg(kOpCalibrateBatched, n_total, bc, bu, true);
+    if (best) *best = to_pub(bc);
+    if (best_us) *best_us = bu;
+    return WM_OK;
 }
 
 }  // extern "C"

@@ -52,49 +52,60 @@ __device__ inline Desc<double> widen(const Desc<float>& x)
 // ---------------------------------------------------------------------------
 // forward sweep
 // ---------------------------------------------------------------------------
-template <int VEC>
-__global__ __launch_bounds__(256) void k_predict(DescPtrs d, int64_t n, Set S,
-                                                  float* __restrict__ T, int32_t* __restrict__ occ)
+template <int V> struct VecT {
+    typedef float f __attribute__((ext_vector_type(V)));
+    typedef int i __attribute__((ext_vector_type(V)));
+};
+
+// VEC consecutive descriptors per thread: one VEC-wide nontemporal load per
+// array (16 B at VEC = 4), the evaluations, one VEC-wide store of T and occ.
+template <int VEC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_predict(DescPtrs d, int64_t n, Set S,
+                                                    float* __restrict__ T, int32_t* __restrict__ occ)
 {
-    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    const int64_t i0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * VEC;
     if (i0 >= n) return;
-    if (VEC == 4 && i0 + 4 <= n) {
-        const f4 F = ntload((const f4*)(d.F + i0));
-        const f4 B = ntload((const f4*)(d.B + i0));
-        const f4 r1 = ntload((const f4*)(d.r1 + i0));
-        const f4 r2 = ntload((const f4*)(d.r2 + i0));
-        const f4 r3 = ntload((const f4*)(d.r3 + i0));
-        const f4 K = ntload((const f4*)(d.K + i0));
-        const f4 u = ntload((const f4*)(d.u + i0));
-        const f4 W = ntload((const f4*)(d.W + i0));
-        const i4 v = ntload((const i4*)(d.vgpr + i0));
-        const i4 s = ntload((const i4*)(d.lds + i0));
-        const i4 gp = ntload((const i4*)(d.gpack + i0));
-        const i4 G = ntload((const i4*)(d.grid + i0));
-        f4 t;
-        i4 o;
+    if constexpr (VEC > 1) {
+        if (i0 + VEC <= n) {
+            typedef typename VecT<VEC>::f fv;
+            typedef typename VecT<VEC>::i iv;
+            const fv F = ntload((const fv*)(d.F + i0));
+            const fv B = ntload((const fv*)(d.B + i0));
+            const fv r1 = ntload((const fv*)(d.r1 + i0));
+            const fv r2 = ntload((const fv*)(d.r2 + i0));
+            const fv r3 = ntload((const fv*)(d.r3 + i0));
+            const fv K = ntload((const fv*)(d.K + i0));
+            const fv u = ntload((const fv*)(d.u + i0));
+            const fv W = ntload((const fv*)(d.W + i0));
+            const iv v = ntload((const iv*)(d.vgpr + i0));
+            const iv s = ntload((const iv*)(d.lds + i0));
+            const iv gp = ntload((const iv*)(d.gpack + i0));
+            const iv G = ntload((const iv*)(d.grid + i0));
+            fv t;
+            iv o;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            Desc<float> x;
-            x.F = F[j]; x.B = B[j]; x.r1 = r1[j]; x.r2 = r2[j]; x.r3 = r3[j];
-            x.K = K[j]; x.u = u[j]; x.W = W[j]; x.v = v[j]; x.s = s[j]; x.gp = gp[j]; x.G = G[j];
-            Eval<float> E;
-            evaluate<float, false>(S.st, S.cf, x, E);
-            t[j] = E.T;
-            o[j] = E.occ;
+            for (int j = 0; j < VEC; ++j) {
+                Desc<float> x;
+                x.F = F[j]; x.B = B[j]; x.r1 = r1[j]; x.r2 = r2[j]; x.r3 = r3[j];
+                x.K = K[j]; x.u = u[j]; x.W = W[j]; x.v = v[j]; x.s = s[j]; x.gp = gp[j]; x.G = G[j];
+                Eval<float> E;
+                evaluate<float, false>(S.st, S.cf, x, E);
+                t[j] = E.T;
+                o[j] = E.occ;
+            }
+            __builtin_nontemporal_store(t, (fv*)(T + i0));
+            if (occ) __builtin_nontemporal_store(o, (iv*)(occ + i0));
+            return;
         }
-        __builtin_nontemporal_store(t, (f4*)(T + i0));
-        if (occ) __builtin_nontemporal_store(o, (i4*)(occ + i0));
-    } else {
-        for (int j = 0; j < VEC; ++j) {
-            const int64_t i = i0 + j;
-            if (i >= n) break;
-            Desc<float> x = load_desc(d, i);
-            Eval<float> E;
-            evaluate<float, false>(S.st, S.cf, x, E);
-            __builtin_nontemporal_store(E.T, T + i);
-            if (occ) __builtin_nontemporal_store(E.occ, occ + i);
-        }
+    }
+    for (int j = 0; j < VEC; ++j) {
+        const int64_t i = i0 + j;
+        if (i >= n) break;
+        Desc<float> x = load_desc(d, i);
+        Eval<float> E;
+        evaluate<float, false>(S.st, S.cf, x, E);
+        __builtin_nontemporal_store(E.T, T + i);
+        if (occ) __builtin_nontemporal_store(E.occ, occ + i);
     }
 }
 
@@ -119,17 +130,41 @@ __global__ __launch_bounds__(256) void k_roofline(DescPtrs d, int64_t n, Set S,
     T[i] = r;
 }
 
+template <int VEC, int BLOCK>
+static void predict_t(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
+                      hipStream_t stream)
+{
+    const int64_t threads = (n + VEC - 1) / VEC;
+    const int64_t blocks = (threads + BLOCK - 1) / BLOCK;
+    k_predict<VEC, BLOCK><<<dim3((unsigned)blocks), dim3(BLOCK), 0, stream>>>(d, n, S, T, occ);
+}
+
+template <int VEC>
+static bool predict_v(int block, const DescPtrs& d, int64_t n, const Set& S, float* T,
+                      int32_t* occ, hipStream_t stream)
+{
+    switch (block) {
+    case 64: predict_t<VEC, 64>(d, n, S, T, occ, stream); return true;
+    case 128: predict_t<VEC, 128>(d, n, S, T, occ, stream); return true;
+    case 256: predict_t<VEC, 256>(d, n, S, T, occ, stream); return true;
+    case 512: predict_t<VEC, 512>(d, n, S, T, occ, stream); return true;
+    default: return false;
+    }
+}
+
 hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
-                          bool vec4, hipStream_t stream)
+                          bool vec_ok, const LaunchCfg& cfg, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const int per = vec4 ? 4 : 1;
-    const int64_t threads = (n + per - 1) / per;
-    const int64_t blocks = (threads + 255) / 256;
-    if (vec4)
-        k_predict<4><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(d, n, S, T, occ);
-    else
-        k_predict<1><<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(d, n, S, T, occ);
+    const int vec = vec_ok ? cfg.vec : 1;
+    bool ok = false;
+    switch (vec) {
+    case 1: ok = predict_v<1>(cfg.block, d, n, S, T, occ, stream); break;
+    case 2: ok = predict_v<2>(cfg.block, d, n, S, T, occ, stream); break;
+    case 4: ok = predict_v<4>(cfg.block, d, n, S, T, occ, stream); break;
+    case 8: ok = predict_v<8>(cfg.block, d, n, S, T, occ, stream); break;
+    }
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -144,7 +179,7 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
 // ---------------------------------------------------------------------------
 // block reduction of the 26 FP64 accumulators (fixed order)
 // ---------------------------------------------------------------------------
-__device__ inline void block_reduce_acc(double* acc, double* lds /* [4][26] */, double* out)
+__device__ inline void block_reduce_acc(double* acc, double* lds /* [waves][26] */, double* out)
 {
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -233,22 +268,22 @@ __device__ inline void grad_exact(const Set& S, const Desc<float>& x, float wi, 
 // Phase 1 sweep.  The loop runs over wave-aligned groups of 64 consecutive
 // descriptors so that every group's redo flags leave as one 64-bit ballot
 // word, written exactly once (no clearing needed, order fixed).
-template <int MODE, bool PTR>
-__global__ __launch_bounds__(256) void k_grad(DescPtrs d, int64_t n, const float* __restrict__ wv,
+template <int MODE, bool PTR, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const float* __restrict__ wv,
                                                Set sv, const Set* __restrict__ sp,
                                                double* __restrict__ partials,
                                                uint64_t* __restrict__ flags)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     const Set& S = PTR ? *sp : sv;
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
     // software pipeline: the next group's loads are in flight while this
     // group is evaluated
-    int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63);
     Desc<float> xn;
     float wn = 0.0f;
     if (base + lane < n) {
@@ -280,7 +315,7 @@ __global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
                                                     const uint64_t* __restrict__ flags,
                                                     double* __restrict__ partials)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     const Set& S = PTR ? *sp : sv;
     double acc[kAcc];
 #pragma unroll
@@ -302,7 +337,7 @@ __global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
 // Fixed-order sum of partial rows: thread t adds rows t, t+256, ... of all 26
 // columns, then the block tree of block_reduce_acc.
 __device__ inline void reduce_partials(const double* __restrict__ partials, int rows, int stride,
-                                       double* red /* [4][26] */, double* tot /* [26] */)
+                                       double* red /* [waves][26] */, double* tot /* [26] */)
 {
     double acc[kAcc];
 #pragma unroll
@@ -319,7 +354,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int rows,
                                                  double* __restrict__ out)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     reduce_partials(partials, rows, kAcc, red, tot);
     if (threadIdx.x < kAcc) {
@@ -336,7 +371,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ parti
 GradLayout grad_layout(int64_t n)
 {
     GradLayout L;
-    int64_t b = (n + 255) / 256;
+    int64_t b = (n + 63) / 64;
     L.nb = (int)(b < 1 ? 1 : (b > kGradMaxBlocks ? kGradMaxBlocks : b));
     L.nwords = (n + 63) / 64;
     int64_t b2 = (L.nwords + 255) / 256;
@@ -347,7 +382,7 @@ GradLayout grad_layout(int64_t n)
 // Blocks of 256 threads that are resident at once on the current device for
 // a kernel (occupancy x compute units), cached per device and kernel.  A
 // persistent grid of exactly this size has no second, half-empty round.
-static int resident_blocks(const void* kernel)
+static int resident_blocks(const void* kernel, int block)
 {
     static std::mutex mu;
     static std::map<std::pair<int, const void*>, int> cache;
@@ -358,7 +393,7 @@ static int resident_blocks(const void* kernel)
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 1;
     int r = per_cu * cus;
@@ -367,42 +402,65 @@ static int resident_blocks(const void* kernel)
     return r;
 }
 
-template <int MODE, bool PTR>
-static int grad_grid_t(int64_t n)
+template <int MODE, bool PTR, int BLOCK>
+static int grad_grid_t(int64_t n, int grid_mult)
 {
     const GradLayout L = grad_layout(n);
-    const int r = resident_blocks(reinterpret_cast<const void*>(&k_grad<MODE, PTR>));
-    return r < L.nb ? r : L.nb;
-}
-
-int grad_grid(int mode, bool ptr, int64_t n)
-{
-    if (mode == 1) return ptr ? grad_grid_t<1, true>(n) : grad_grid_t<1, false>(n);
-    return ptr ? grad_grid_t<0, true>(n) : grad_grid_t<0, false>(n);
+    const int64_t want = (n + BLOCK - 1) / BLOCK;
+    int64_t r = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_grad<MODE, PTR, BLOCK>), BLOCK) *
+                (grid_mult < 1 ? 1 : grid_mult);
+    r = r < want ? r : want;
+    r = r < L.nb ? r : L.nb;
+    return (int)(r < 1 ? 1 : r);
 }
 
 template <int MODE, bool PTR>
-static void launch_grad_t(const DescPtrs& d, int64_t n, const float* w, const Set& S,
-                          const Set* S_dev, double* partials, uint64_t* flags, int nb,
-                          const GradLayout& L, hipStream_t stream)
+static int grad_grid_b(int64_t n, const LaunchCfg& c)
 {
-    k_grad<MODE, PTR><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials, flags);
+    switch (c.block) {
+    case 64: return grad_grid_t<MODE, PTR, 64>(n, c.grid_mult);
+    case 128: return grad_grid_t<MODE, PTR, 128>(n, c.grid_mult);
+    case 512: return grad_grid_t<MODE, PTR, 512>(n, c.grid_mult);
+    default: return grad_grid_t<MODE, PTR, 256>(n, c.grid_mult);
+    }
+}
+
+int grad_grid(int mode, bool ptr, int64_t n, const LaunchCfg& c)
+{
+    if (mode == 1) return ptr ? grad_grid_b<1, true>(n, c) : grad_grid_b<1, false>(n, c);
+    return ptr ? grad_grid_b<0, true>(n, c) : grad_grid_b<0, false>(n, c);
+}
+
+template <int MODE, bool PTR>
+static bool launch_grad_t(const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                          const Set* S_dev, double* partials, uint64_t* flags, int nb,
+                          const GradLayout& L, const LaunchCfg& c, hipStream_t stream)
+{
+    switch (c.block) {
+    case 64: k_grad<MODE, PTR, 64><<<nb, 64, 0, stream>>>(d, n, w, S, S_dev, partials, flags); break;
+    case 128: k_grad<MODE, PTR, 128><<<nb, 128, 0, stream>>>(d, n, w, S, S_dev, partials, flags); break;
+    case 256: k_grad<MODE, PTR, 256><<<nb, 256, 0, stream>>>(d, n, w, S, S_dev, partials, flags); break;
+    case 512: k_grad<MODE, PTR, 512><<<nb, 512, 0, stream>>>(d, n, w, S, S_dev, partials, flags); break;
+    default: return false;
+    }
     k_grad_redo<MODE, PTR><<<L.nb2, 256, 0, stream>>>(d, n, w, S, S_dev, flags,
                                                        partials + (int64_t)nb * kAcc);
+    return true;
 }
 
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
                        const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
-                       double* out, hipStream_t stream)
+                       const LaunchCfg& c, double* out, hipStream_t stream)
 {
-    const int nb = grad_grid(mode, S_dev != nullptr, n);
-    if (mode == 1) {
-        if (S_dev) launch_grad_t<1, true>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
-        else launch_grad_t<1, false>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
-    } else {
-        if (S_dev) launch_grad_t<0, true>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
-        else launch_grad_t<0, false>(d, n, w, S, S_dev, partials, flags, nb, L, stream);
-    }
+    const int nb = grad_grid(mode, S_dev != nullptr, n, c);
+    bool ok;
+    if (mode == 1)
+        ok = S_dev ? launch_grad_t<1, true>(d, n, w, S, S_dev, partials, flags, nb, L, c, stream)
+                   : launch_grad_t<1, false>(d, n, w, S, S_dev, partials, flags, nb, L, c, stream);
+    else
+        ok = S_dev ? launch_grad_t<0, true>(d, n, w, S, S_dev, partials, flags, nb, L, c, stream)
+                   : launch_grad_t<0, false>(d, n, w, S, S_dev, partials, flags, nb, L, c, stream);
+    if (!ok) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !out) return e;
     if (mode == 1)
@@ -472,7 +530,7 @@ __global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partial
                                                CalibState* st, AdamOpts o, Set* S,
                                                double* loss_hist)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     reduce_partials(partials, rows, kAcc, red, tot);
     adam_update(st, tot, o, S, loss_hist);
@@ -498,7 +556,7 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
                                                        uint64_t* __restrict__ flags,
                                                        double* __restrict__ partials)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     __shared__ double per_set[kMaxSets * kAcc];
     for (int j = threadIdx.x; j < n_sets * kAcc; j += blockDim.x) per_set[j] = 0.0;
@@ -555,7 +613,7 @@ __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __res
                                                             int n_sets,
                                                             double* __restrict__ partials)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int s = 0; s < n_sets; ++s) {
@@ -588,7 +646,7 @@ __global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__
                                                        const AdamOpts* __restrict__ opts,
                                                        Set* S_all, int steps, double* loss_hist)
 {
-    __shared__ double red[4 * kAcc];
+    __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     const int s = blockIdx.x;
     reduce_partials(partials + s * kAcc, rows, n_sets * kAcc, red, tot);
@@ -596,9 +654,10 @@ __global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__
                 loss_hist ? loss_hist + (int64_t)s * steps : nullptr);
 }
 
-int batched_grid(int n_items)
+int batched_grid(int n_items, int grid_mult)
 {
-    const int r = resident_blocks(reinterpret_cast<const void*>(&k_grad_batched));
+    const int r = resident_blocks(reinterpret_cast<const void*>(&k_grad_batched), 256) *
+                  (grid_mult < 1 ? 1 : grid_mult);
     const int m = n_items < kGradMaxBlocks ? n_items : kGradMaxBlocks;
     return m < 1 ? 1 : (r < m ? r : m);
 }
@@ -692,7 +751,8 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
 // float64 every candidate whose float32 cost is within kTileWindow of that
 // minimum and keeps the smallest and second-smallest float64 costs, the
 // lowest index winning exact ties.
-__global__ __launch_bounds__(256) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
                                                       const uint32_t* __restrict__ code, int64_t n,
                                                       int64_t n_cand,
                                                       Set S, int32_t* __restrict__ best,
@@ -700,8 +760,8 @@ __global__ __launch_bounds__(256) void k_select_tile(ShapePtrs sh, const int32_t
                                                       uint8_t* __restrict__ near_tie)
 {
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * BLOCK + threadIdx.x) >> 6));
+    const int nwaves = (int)((gridDim.x * BLOCK) >> 6);
     const double dinf = __builtin_huge_val();
     for (int64_t i = wave; i < n; i += nwaves) {
         const int32_t M = sh.M[i], N = sh.N[i], K = sh.K[i], t = sh.dtype[i];
@@ -767,18 +827,33 @@ __global__ __launch_bounds__(256) void k_select_tile(ShapePtrs sh, const int32_t
     }
 }
 
+template <int BLOCK>
+static void select_t(const ShapePtrs& sh, const int32_t* off, const uint32_t* code, int64_t n,
+                     int64_t n_cand, const Set& S, int32_t* best, double* best_cost,
+                     uint8_t* near_tie, int grid_mult, hipStream_t stream)
+{
+    const int64_t waves_per_block = BLOCK / 64;
+    const int64_t want = (n + waves_per_block - 1) / waves_per_block;
+    int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_select_tile<BLOCK>), BLOCK) *
+                (grid_mult < 1 ? 1 : grid_mult);
+    b = b < want ? b : want;
+    k_select_tile<BLOCK><<<(int)(b < 1 ? 1 : b), BLOCK, 0, stream>>>(sh, off, code, n, n_cand, S, best,
+                                                                     best_cost, near_tie);
+}
+
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
-                              double* best_cost, uint8_t* near_tie, int blocks,
+                              double* best_cost, uint8_t* near_tie, const LaunchCfg& c,
                               hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    if (blocks <= 0) {
-        int64_t b = (n + 3) / 4;
-        blocks = (int)(b < kTileMaxBlocks ? b : kTileMaxBlocks);
+    switch (c.block) {
+    case 64: select_t<64>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
+    case 128: select_t<128>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
+    case 256: select_t<256>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
+    case 512: select_t<512>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
+    default: return hipErrorInvalidValue;
     }
-    k_select_tile<<<blocks, 256, 0, stream>>>(sh, off, code, n, n_cand, S, best, best_cost,
-                                               near_tie);
     return hipGetLastError();
 }
 

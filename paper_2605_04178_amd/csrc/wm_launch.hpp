@@ -10,11 +10,29 @@
 
 namespace wm {
 
-constexpr int kGradMaxBlocks = 2048;   // persistent gradient grid cap
+constexpr int kGradMaxBlocks = 8192;   // partial-row cap of the persistent gradient grids
 constexpr int kRedoMaxBlocks = 256;    // float64 re-evaluation grid cap
-constexpr int kTileMaxBlocks = 2048;   // persistent tile-selection grid cap
 constexpr int kMaxSets = 16;           // parameter sets per batched calibration
 constexpr float kTileWindow = 3e-5f;   // float32 window re-evaluated in float64
+
+// A kernel launch shape: threads per block, descriptors per thread (forward
+// sweep), persistent grid as a multiple of the resident blocks, and the work
+// item size of the multi-set sweep.
+struct LaunchCfg {
+    int32_t block, vec, grid_mult, chunk;
+};
+
+// op codes as in the public header
+constexpr int kOpPredict = 0, kOpVjp = 2, kOpLossGrad = 3, kOpSelectTile = 4,
+              kOpCalibrate = 5, kOpCalibrateBatched = 6;
+constexpr int64_t kMinChunk = 4096;
+
+LaunchCfg default_cfg(int op);
+bool cfg_valid(int op, const LaunchCfg& c);
+// tuned configuration for (current device, op, floor(log2 n)) or the default
+LaunchCfg launch_cfg(int op, int64_t n);
+// record a configuration (and append it to the cache file, if one is set)
+void store_cfg(int op, int64_t n, const LaunchCfg& c, double us, bool persist);
 
 struct DescPtrs {
     const float *F, *B, *r1, *r2, *r3, *K, *u, *W;
@@ -54,14 +72,15 @@ struct GradLayout {
     int64_t nwords;
 };
 GradLayout grad_layout(int64_t n);
-// phase-1 blocks actually launched (<= grad_layout(n).nb): the number of
-// blocks resident at once on the current device, so partial rows = that + nb2
-int grad_grid(int mode, bool from_device_set, int64_t n);
+// phase-1 blocks actually launched (<= grad_layout(n).nb): the blocks
+// resident at once on the current device times cfg.grid_mult, so partial
+// rows = that + nb2
+int grad_grid(int mode, bool from_device_set, int64_t n, const LaunchCfg& cfg);
 // blocks for the multi-set sweep over n_items work items
-int batched_grid(int n_items);
+int batched_grid(int n_items, int grid_mult);
 
 hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
-                          bool vec4, hipStream_t stream);
+                          bool vec_ok, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
                            hipStream_t stream);
 // mode 0: weights are dL/dT, out = dL/dtheta[24]; mode 1: weights are measured
@@ -70,7 +89,7 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
 // the final reduction.
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
                        const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
-                       double* out, hipStream_t stream);
+                       const LaunchCfg& cfg, double* out, hipStream_t stream);
 hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream);
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
@@ -83,7 +102,7 @@ hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, Cal
                                hipStream_t stream);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
-                              double* best_cost, uint8_t* near_tie, int blocks,
+                              double* best_cost, uint8_t* near_tie, const LaunchCfg& cfg,
                               hipStream_t stream);
 
 }  // namespace wm

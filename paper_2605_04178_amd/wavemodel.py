@@ -24,7 +24,9 @@ OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_
 
 EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_workspace_bytes",
             "wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
-            "wm_calibrate", "wm_calibrate_batched")
+            "wm_calibrate", "wm_calibrate_batched", "wm_get_launch", "wm_set_launch",
+            "wm_autotune_predict", "wm_autotune_grad", "wm_autotune_select_tile",
+            "wm_autotune_batched")
 
 
 class WmError(RuntimeError):
@@ -51,6 +53,13 @@ class WmDesc(C.Structure):
 
 class WmShapes(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("M", "N", "K", "dtype")] + [("n", C.c_int64)]
+
+
+class WmLaunch(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("block", "per_thread", "grid_mult", "chunk")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class WmCalibOpts(C.Structure):
@@ -94,6 +103,20 @@ def lib():
         L.wm_calibrate.restype = i32
         L.wm_calibrate_batched.argtypes = [i32, D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
         L.wm_calibrate_batched.restype = i32
+        LP = C.POINTER(WmLaunch)
+        dp = C.POINTER(C.c_double)
+        L.wm_get_launch.argtypes = [i32, i64, LP]
+        L.wm_get_launch.restype = i32
+        L.wm_set_launch.argtypes = [i32, i64, LP]
+        L.wm_set_launch.restype = i32
+        L.wm_autotune_predict.argtypes = [D, P, vp, vp, vp, LP, dp]
+        L.wm_autotune_predict.restype = i32
+        L.wm_autotune_grad.argtypes = [i32, D, vp, P, vp, vp, sz, vp, LP, dp]
+        L.wm_autotune_grad.restype = i32
+        L.wm_autotune_select_tile.argtypes = [C.POINTER(WmShapes), vp, vp, i64, P, vp, vp, vp, vp, LP, dp]
+        L.wm_autotune_select_tile.restype = i32
+        L.wm_autotune_batched.argtypes = [i32, D, vp, P, C.POINTER(WmCalibOpts), vp, sz, vp, LP, dp]
+        L.wm_autotune_batched.restype = i32
         _lib = L
     return _lib
 
@@ -316,6 +339,74 @@ def calibrate_batched(descs: List[DeviceDescriptors], measured: List[torch.Tenso
     if rc not in (WM_OK, WM_EDIVERGED):
         raise WmError(rc, "wm_calibrate_batched")
     return rc, np.stack([theta_of(POUT[i]) for i in range(k)]), hist
+
+
+# ---------------------------------------------------------------------------
+# launch configurations and autotuning
+# ---------------------------------------------------------------------------
+def get_launch(op: int, n: int) -> dict:
+    c = WmLaunch()
+    _check(lib().wm_get_launch(op, n, C.byref(c)), "wm_get_launch")
+    return c.as_dict()
+
+
+def set_launch(op: int, n: int, block=256, per_thread=1, grid_mult=1, chunk=0):
+    c = WmLaunch(block, per_thread, grid_mult, chunk)
+    _check(lib().wm_set_launch(op, n, C.byref(c)), "wm_set_launch")
+
+
+def _tuned(rc, what, best, us):
+    _check(rc, what)
+    return {**best.as_dict(), "us": us.value}
+
+
+def autotune_predict(desc: DeviceDescriptors, params, stream=None) -> dict:
+    T = torch.empty(desc.n, dtype=torch.float32, device=desc.device)
+    occ = torch.empty(desc.n, dtype=torch.int32, device=desc.device)
+    best, us = WmLaunch(), C.c_double()
+    rc = lib().wm_autotune_predict(C.byref(desc.struct()), C.byref(params_struct(params)), _ptr(T),
+                                   _ptr(occ), _stream(stream), C.byref(best), C.byref(us))
+    return _tuned(rc, "wm_autotune_predict", best, us)
+
+
+def autotune_grad(op: int, desc: DeviceDescriptors, w: torch.Tensor, params, stream=None) -> dict:
+    out = torch.empty(26, dtype=torch.float64, device=desc.device)
+    ws = _workspace(workspace_bytes(op, desc.n), desc.device)
+    best, us = WmLaunch(), C.c_double()
+    rc = lib().wm_autotune_grad(op, C.byref(desc.struct()), _ptr(w), C.byref(params_struct(params)),
+                                _ptr(out), _ptr(ws), ws.numel(), _stream(stream), C.byref(best),
+                                C.byref(us))
+    return _tuned(rc, "wm_autotune_grad", best, us)
+
+
+def autotune_select_tile(shapes: DeviceShapes, params, stream=None) -> dict:
+    dev = shapes.device
+    best_i = torch.empty(shapes.n, dtype=torch.int32, device=dev)
+    cost = torch.empty(shapes.n, dtype=torch.float64, device=dev)
+    tie = torch.empty(shapes.n, dtype=torch.uint8, device=dev)
+    s = WmShapes(shapes.M.data_ptr(), shapes.N.data_ptr(), shapes.K.data_ptr(),
+                 shapes.dtype.data_ptr(), shapes.n)
+    best, us = WmLaunch(), C.c_double()
+    rc = lib().wm_autotune_select_tile(C.byref(s), _ptr(shapes.cand_off), _ptr(shapes.cand_code),
+                                       int(shapes.cand_code.numel()), C.byref(params_struct(params)),
+                                       _ptr(best_i), _ptr(cost), _ptr(tie), _stream(stream),
+                                       C.byref(best), C.byref(us))
+    return _tuned(rc, "wm_autotune_select_tile", best, us)
+
+
+def autotune_batched(descs, measured, p0s, opts_list, stream=None) -> dict:
+    k = len(descs)
+    steps = int(opts_list[0].steps)
+    D = (WmDesc * k)(*[d.struct() for d in descs])
+    M = (C.c_void_p * k)(*[m.data_ptr() for m in measured])
+    P0 = (WmParams * k)(*[params_struct(p) for p in p0s])
+    O = (WmCalibOpts * k)(*opts_list)
+    n_total = sum(d.n for d in descs)
+    ws = _workspace(workspace_bytes(OP_CALIBRATE_BATCHED, n_total, k, steps), descs[0].device)
+    best, us = WmLaunch(), C.c_double()
+    rc = lib().wm_autotune_batched(k, D, M, P0, O, _ptr(ws), ws.numel(), _stream(stream),
+                                   C.byref(best), C.byref(us))
+    return _tuned(rc, "wm_autotune_batched", best, us)
 
 
 # ---------------------------------------------------------------------------

@@ -202,3 +202,24 @@ def test_product_package_does_not_reference_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import|from)\s+oracle|liboracle|wm_oracle", src), f
+
+
+def test_set_launch_rejects_invalid_configs_without_a_gpu(wmb):
+    L = wmb.lib()
+    bad = [(wmb.OP_PREDICT, (96, 4, 1, 0)), (wmb.OP_PREDICT, (256, 3, 1, 0)),
+           (wmb.OP_LOSS_GRAD, (256, 1, 0, 0)), (wmb.OP_LOSS_GRAD, (256, 1, 9, 0)),
+           (wmb.OP_SELECT_TILE, (1024, 1, 1, 0)), (wmb.OP_CALIBRATE_BATCHED, (128, 1, 1, 16384)),
+           (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 3000)), (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 1 << 17)),
+           (wmb.OP_ROOFLINE, (256, 1, 1, 0)), (99, (256, 1, 1, 0))]
+    for op, cfg in bad:
+        c = wmb.WmLaunch(*cfg)
+        assert L.wm_set_launch(op, 1000, C.byref(c)) == wmb.WM_EINVAL, (op, cfg)
+    assert L.wm_set_launch(wmb.OP_PREDICT, -1, C.byref(wmb.WmLaunch(256, 4, 1, 0))) == wmb.WM_EINVAL
+    assert L.wm_set_launch(wmb.OP_PREDICT, 10, None) == wmb.WM_EINVAL
+    assert L.wm_get_launch(wmb.OP_PREDICT, 10, None) == wmb.WM_EINVAL
+    assert L.wm_get_launch(99, 10, C.byref(wmb.WmLaunch())) == wmb.WM_EINVAL
+    # tuners validate their arguments first
+    p = wmb.params_struct(synth.param_set(0))
+    assert L.wm_autotune_predict(None, C.byref(p), None, None, None, None, None) == wmb.WM_EINVAL
+    assert L.wm_autotune_grad(wmb.OP_PREDICT, None, None, C.byref(p), None, None, 0, None, None,
+                              None) == wmb.WM_EINVAL

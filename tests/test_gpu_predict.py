@@ -168,6 +168,15 @@ def test_predict_full_size_sampled(wmb, orc):
     To, occo = orc.predict(p, sub)
     assert np.array_equal(occ[idx], occo)
     assert rel_err(T[idx], To).max() <= TOL
+    # the autotuned launch configuration (what the benchmark times) gives the
+    # same bytes
+    best = wmb.autotune_predict(dd, p)
+    say("tuned", best)
+    T2, occ2 = wmb.predict(dd, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(occ2.cpu().numpy(), occ)
+    assert np.array_equal(np.nan_to_num(T2.cpu().numpy(), nan=-1.0), np.nan_to_num(T, nan=-1.0))
+    wmb.set_launch(wmb.OP_PREDICT, n, 256, 4)
     # properties over every output
     assert np.all((occ >= -1) & (occ <= p.n_simd * p.waves_simd))
     assert np.all(np.isinf(T[occ == 0])) and np.all(np.isfinite(T[occ > 0]))
