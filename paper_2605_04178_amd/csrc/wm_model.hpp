@@ -349,17 +349,17 @@ __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, 
     acc[2 + 10] += E.dt == 2 ? gP : (Acc)0;
     acc[2 + 11] += E.dt == 3 ? gP : (Acc)0;
     acc[2 + 12] += E.dt == 4 ? gP : (Acc)0;
-    // bandwidth: dT_b/dX = -(T_b / S) dS/dX
+    // bandwidth: dT_b/dX = -(T_b / S) dS/dX.  Without the working-set blend
+    // e = 0, which zeroes the B_peak and w0 terms; outside the h_LLC regimes
+    // base_log = 0 -- so every slot is updated unconditionally.
     const R cb = -E.wb * E.Tb * A::rcp(E.S);
-    const bool blend = c.blend_on && E.W > (R)0;
+    const R cbh = cb * E.sh;
     acc[2 + 0] += w * (Acc)(cb * E.s1);
     acc[2 + 1] += w * (Acc)(cb * E.s2);
     acc[2 + 2] += w * (Acc)(cb * E.s3);
-    acc[2 + 3] += w * (Acc)(cb * E.sh * (blend ? (R)1 - E.e : (R)1));
-    if (blend) {
-        acc[2 + 23] += w * (Acc)(cb * E.sh * E.e);
-        acc[2 + 22] += w * (Acc)(cb * E.sh * c.bp_minus_bw * E.e * E.W * c.inv_w0 * c.inv_w0);
-    }
+    acc[2 + 3] += w * (Acc)(cbh * ((R)1 - E.e));
+    acc[2 + 23] += w * (Acc)(cbh * E.e);
+    acc[2 + 22] += w * (Acc)(cbh * c.bp_minus_bw * E.e * E.W * c.inv_w0 * c.inv_w0);
     // latency: T_lat = q * sum s_l Lat_l / f
     const R cl = E.wl * E.q * c.inv_f;
     acc[2 + 4] += w * (Acc)(cl * E.s1);
@@ -367,12 +367,10 @@ __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, 
     acc[2 + 6] += w * (Acc)(cl * E.s3);
     acc[2 + 7] += w * (Acc)(cl * E.sh);
     // h_LLC(W) exponents through s3 and s_hbm
-    if (E.llc_regime != 0) {
-        const R dTdh = cb * E.a12 * (c.bw[2] - E.bwh) + E.wl * E.q * E.a12 * (c.latf[2] - c.latf[3]);
-        const Acc gh = w * (Acc)(dTdh * E.h3 * E.base_log);
-        acc[2 + 20] += E.llc_regime == 1 ? gh : (Acc)0;
-        acc[2 + 21] += E.llc_regime == 2 ? gh : (Acc)0;
-    }
+    const R dTdh = cb * E.a12 * (c.bw[2] - E.bwh) + E.wl * E.q * E.a12 * (c.latf[2] - c.latf[3]);
+    const Acc gh = w * (Acc)(dTdh * E.h3 * E.base_log);
+    acc[2 + 20] += E.llc_regime == 1 ? gh : (Acc)0;
+    acc[2 + 21] += E.llc_regime == 2 ? gh : (Acc)0;
 }
 
 }  // namespace wm
