@@ -51,6 +51,15 @@ def timed(fn, steps, warmup):
     return wall, e0.elapsed_time(e1) / steps
 
 
+def kernel_name(kind, cfg):
+    """Demangled name of the kernel instance a launch configuration selects."""
+    if kind == "predict":
+        return f"void wm::k_predict<{cfg['per_thread']}, {cfg['block']}>"
+    if kind == "loss_grad":
+        return f"void wm::k_grad<1, false, {cfg['block']}>"
+    return kind
+
+
 def counted_traffic(kernel_prefix):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (profiles/traffic.json), or None when the kernel sources changed
@@ -66,7 +75,7 @@ def counted_traffic(kernel_prefix):
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
     for name, v in rec["kernels"].items():
-        if kernel_prefix in name:
+        if name.startswith(kernel_prefix):
             return v["read_bytes"] + v["write_bytes"]
     return None
 
@@ -91,21 +100,26 @@ def cpu_baseline(p, d, seconds=10.0):
 
 
 def profile_run(wm, synth, dd, p, n, dev):
+    """Autotune as the benchmark does, then run each hot kernel a few times in
+    its tuned configuration, then the reference copy."""
     import torch
     T = torch.empty(n, dtype=torch.float32, device=dev)
     occ = torch.empty(n, dtype=torch.int32, device=dev)
+    log("profile: tuned", wm.autotune_predict(dd, p))
     for _ in range(5):
         wm.predict(dd, p, out_T=T, out_occ=occ)
     torch.cuda.synchronize()
     log("profile: predict x5 done")
     meas = (T.clamp(min=1e-6, max=1.0) * 1.01).contiguous()
     ws = wm._workspace(wm.workspace_bytes(wm.OP_LOSS_GRAD, n), dev)
+    log("profile: tuned", wm.autotune_grad(wm.OP_LOSS_GRAD, dd, meas, p))
     for _ in range(3):
         wm.loss_grad(dd, meas, p, ws=ws)
     torch.cuda.synchronize()
     log("profile: loss_grad x3 done")
     sh = synth.shapes(1 << 16, 102)
     dsh = wm.DeviceShapes.from_host(sh, dev)
+    log("profile: tuned", wm.autotune_select_tile(dsh, p))
     for _ in range(3):
         wm.select_tile(dsh, p)
     torch.cuda.synchronize()
@@ -181,9 +195,10 @@ def main():
                                "(8 f32 + 4 i32 each), one CDNA-style parameter set",
                    "n_descriptors": n, "param_set": "seed 0, 4 levels, HK_MAX"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic("k_predict<4>"),
-                     "kernel": "wm::k_predict", "bytes_per_eval": FWD_BYTES,
-                     "avg_launch_us": ev_ms * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counted_traffic(kernel_name("predict", wm.get_launch(wm.OP_PREDICT, n))),
+                     "kernel": kernel_name("predict", wm.get_launch(wm.OP_PREDICT, n)),
+                     "bytes_per_eval": FWD_BYTES, "avg_launch_us": ev_ms * 1e3},
         "launch": {"predict": wm.get_launch(wm.OP_PREDICT, n)},
     }
 
@@ -207,7 +222,7 @@ def main():
         res["fwd_adjoint"] = {"value": n / (wall_a * 1e-3), "unit": "evals/s", "ms_per_step": wall_a,
                               "achieved_GBs": ach_a, "hbm_frac": ach_a / HBM_PEAK_GBS,
                               "bytes_per_eval": ADJ_BYTES, "dtype": "f32 + f64 reductions",
-                              "traffic": counted_traffic("k_grad<1")}
+                              "traffic": counted_traffic(kernel_name("loss_grad", res["launch"]["loss_grad"]))}
         log(f"fwd+adjoint: {wall_a:.4f} ms/step, {ach_a:.0f} GB/s")
         del meas, ws
 
