@@ -372,8 +372,8 @@ struct BatchRun {
         hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, n_dev,
                                            fo_dev, flags_dev, words, part_dev, nb, nb2, s);
         if (e != hipSuccess) return e;
-        return launch_adam_batched(part_dev, nb + nb2, n_sets, st_dev, o_dev, S_dev, steps,
-                                   hist_dev, s);
+        return launch_adam_batched(part_dev + (int64_t)nb * n_sets * kAcc, nb2, n_sets, st_dev,
+                                   o_dev, S_dev, steps, hist_dev, s);
     }
 };
 
@@ -712,12 +712,13 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
     const int64_t n = desc->n;
     const GradLayout G = L.g.g;
     const LaunchCfg cfg = launch_cfg(kOpLossGrad, n);
-    const int rows = grad_grid(1, true, n, cfg) + G.nb2;
+    // the float64 pass folds the sweep's rows: Adam reduces its nb2 rows
+    double* rows2_dev = part_dev + (int64_t)grad_grid(1, true, n, cfg) * kAcc;
     auto step = [&]() -> hipError_t {
         hipError_t e = launch_grad(1, dp, n, measured, S, S_dev, part_dev, flags_dev, G, cfg,
                                    nullptr, s);
         if (e != hipSuccess) return e;
-        return launch_adam(part_dev, rows, st_dev, ao, S_dev, hist_dev, s);
+        return launch_adam(rows2_dev, G.nb2, st_dev, ao, S_dev, hist_dev, s);
     };
     rc = run_steps(s, opts->steps, step);
     if (rc != WM_OK) return rc;

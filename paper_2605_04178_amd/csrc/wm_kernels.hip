@@ -307,19 +307,26 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
     block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
 }
 
-// Phase 2 sweep over the flag words (fixed order).
+// Phase 2: (a) block b first folds the phase-1 partial rows b, b + nb2, ...
+// (fixed order), so the final single-block reduction only sees nb2 rows;
+// (b) it re-evaluates in float64 every descriptor flagged in its flag words.
 template <int MODE, bool PTR>
 __global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
                                                     const float* __restrict__ wv, Set sv,
                                                     const Set* __restrict__ sp,
                                                     const uint64_t* __restrict__ flags,
-                                                    double* __restrict__ partials)
+                                                    const double* __restrict__ rows1, int nrows1,
+                                                    double* __restrict__ rows2)
 {
     __shared__ double red[16 * kAcc];
     const Set& S = PTR ? *sp : sv;
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] += rows1[(int64_t)r * kAcc + j];
+    }
     const int64_t nwords = (n + 63) >> 6;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
             grad_exact<MODE>(S, load_desc(d, i), wv[i], acc);
         }
     }
-    block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
+    block_reduce_acc(acc, red, rows2 + (int64_t)blockIdx.x * kAcc);
 }
 
 // Fixed-order sum of partial rows: thread t adds rows t, t+256, ... of all 26
@@ -443,7 +450,7 @@ static bool launch_grad_t(const DescPtrs& d, int64_t n, const float* w, const Se
     case 512: k_grad<MODE, PTR, 512><<<nb, 512, 0, stream>>>(d, n, w, S, S_dev, partials, flags); break;
     default: return false;
     }
-    k_grad_redo<MODE, PTR><<<L.nb2, 256, 0, stream>>>(d, n, w, S, S_dev, flags,
+    k_grad_redo<MODE, PTR><<<L.nb2, 256, 0, stream>>>(d, n, w, S, S_dev, flags, partials, nb,
                                                        partials + (int64_t)nb * kAcc);
     return true;
 }
@@ -464,9 +471,9 @@ hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, c
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !out) return e;
     if (mode == 1)
-        k_reduce<1><<<1, 256, 0, stream>>>(partials, nb + L.nb2, out);
+        k_reduce<1><<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, out);
     else
-        k_reduce<0><<<1, 256, 0, stream>>>(partials, nb + L.nb2, out);
+        k_reduce<0><<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, out);
     return hipGetLastError();
 }
 
@@ -603,7 +610,9 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
         partials[(int64_t)b * n_sets * kAcc + j] = per_set[j];
 }
 
-// Phase 2 for every set in turn (set loop uniform; fixed order).
+// Phase 2 for every set in turn (set loop uniform; fixed order): fold the
+// phase-1 rows b, b + nb2, ... of the set, then re-evaluate its flagged
+// descriptors in float64.
 __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __restrict__ sets,
                                                             const float* const* __restrict__ meas,
                                                             const Set* __restrict__ S_all,
@@ -611,6 +620,8 @@ __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __res
                                                             const int64_t* __restrict__ flag_off,
                                                             const uint64_t* __restrict__ flags,
                                                             int n_sets,
+                                                            const double* __restrict__ rows1,
+                                                            int nrows1,
                                                             double* __restrict__ partials)
 {
     __shared__ double red[16 * kAcc];
@@ -620,6 +631,11 @@ __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __res
         double acc[kAcc];
 #pragma unroll
         for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
+            const double* row = rows1 + ((int64_t)r * n_sets + s) * kAcc;
+#pragma unroll
+            for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
+        }
         const DescPtrs d = sets[s];
         const float* m = meas[s];
         const Set& S = S_all[s];
@@ -672,6 +688,7 @@ hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, c
                                            flags, partials);
     (void)total_words;
     k_grad_redo_batched<<<nb2, 256, 0, stream>>>(sets, meas, S_all, set_n, flag_off, flags, n_sets,
+                                                 partials, nb,
                                                  partials + (int64_t)nb * n_sets * kAcc);
     return hipGetLastError();
 }
