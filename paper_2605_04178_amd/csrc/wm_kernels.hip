@@ -786,9 +786,15 @@ __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32
         int64_t a = off[i], b = off[i + 1];
         a = a < 0 ? 0 : (a > n_cand ? n_cand : a);
         b = b < a ? a : (b > n_cand ? n_cand : b);
+        // float32 costs of the lane's first two candidates stay in registers
+        // for the second pass (covers lists of up to 128 candidates)
+        const float finf = __builtin_huge_valf();
+        float cc0 = finf, cc1 = finf;
         uint64_t key = ~0ull;
-        for (int64_t j = a + lane; j < b; j += 64) {
+        for (int64_t j = a + lane, r = 0; j < b; j += 64, ++r) {
             const float c = tile_cost<float>(S, M, N, K, t, code[j]);
+            cc0 = r == 0 ? c : cc0;
+            cc1 = r == 1 ? c : cc1;
             const uint64_t k = ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)(j - a);
             key = k < key ? k : key;
         }
@@ -809,8 +815,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32
         const float thr = c32 * (1.0f + kTileWindow);
         double c1 = dinf, c2 = dinf;
         int32_t j1 = 0x7fffffff;
-        for (int64_t j = a + lane; j < b; j += 64) {
-            const float c = tile_cost<float>(S, M, N, K, t, code[j]);
+        for (int64_t j = a + lane, r = 0; j < b; j += 64, ++r) {
+            const float c = r == 0 ? cc0 : (r == 1 ? cc1 : tile_cost<float>(S, M, N, K, t, code[j]));
             if (!(c <= thr)) continue;
             const double cd = tile_cost<double>(S, M, N, K, t, code[j]);
             const int32_t jl = (int32_t)(j - a);
