@@ -242,3 +242,69 @@ def select_tile(p, sh):
     lib().orc_select_tile(C.byref(params(p)), n, *[x.ctypes.data for x in a], best.ctypes.data,
                           cost.ctypes.data, nt.ctypes.data)
     return best, cost, nt
+
+
+# ----------------------------------------------------------------------------
+# workload segments
+# ----------------------------------------------------------------------------
+class OrcSegs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("app_off", "n_exec", "n_kern", "cls", "h2d", "d2h")] + [
+        ("n_apps", C.c_int64)]
+
+
+class OrcSegp(C.Structure):
+    _fields_ = [("kappa", C.c_double * 4), ("bw_h2d", C.c_double), ("bw_d2h", C.c_double),
+                ("tau_memcpy", C.c_double)]
+
+
+N_SEGP = 7
+
+
+def _segs(sg):
+    keep = [np.ascontiguousarray(sg.app_off, np.int32), np.ascontiguousarray(sg.n_exec, np.float32),
+            np.ascontiguousarray(sg.n_kern, np.int32), np.ascontiguousarray(sg.cls, np.int32),
+            np.ascontiguousarray(sg.h2d, np.float32), np.ascontiguousarray(sg.d2h, np.float32)]
+    o = OrcSegs(*[k.ctypes.data for k in keep], int(keep[0].shape[0] - 1))
+    return o, keep
+
+
+def segp(q) -> OrcSegp:
+    o = OrcSegp()
+    for c in range(4):
+        o.kappa[c] = float(q.kappa[c])
+    o.bw_h2d, o.bw_d2h, o.tau_memcpy = float(q.bw_h2d), float(q.bw_d2h), float(q.tau_memcpy)
+    return o
+
+
+def _seg_lib():
+    L = lib()
+    if not hasattr(L, "_seg_ready"):
+        P, D = C.POINTER(OrcParams), C.POINTER(OrcDesc)
+        L.orc_predict_apps.argtypes = [P, C.POINTER(OrcSegp), D, C.POINTER(OrcSegs), C.c_void_p, C.c_void_p]
+        L.orc_apps_loss_grad.argtypes = [P, C.POINTER(OrcSegp), D, C.POINTER(OrcSegs), C.c_void_p, C.c_void_p]
+        L.orc_segment.argtypes = [P, C.POINTER(OrcSegp), D, C.POINTER(OrcSegs), C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_segment.restype = C.c_double
+        L._seg_ready = True
+    return L
+
+
+def predict_apps(p, q, d, sg):
+    """(T_app float64 [n_apps], T_seg float64 [n_segments])."""
+    o, keep = _desc(d)
+    so, skeep = _segs(sg)
+    Ta = np.empty(so.n_apps, np.float64)
+    Ts = np.empty(o.n, np.float64)
+    _seg_lib().orc_predict_apps(C.byref(params(p)), C.byref(segp(q)), C.byref(o), C.byref(so),
+                                Ta.ctypes.data, Ts.ctypes.data)
+    return Ta, Ts
+
+
+def apps_loss_grad(p, q, d, sg, measured):
+    """(loss, count, dL/dtheta[24], dL/dsegparam[7])."""
+    o, keep = _desc(d)
+    so, skeep = _segs(sg)
+    m = np.ascontiguousarray(measured, np.float64)
+    out = np.zeros(2 + N_THETA + N_SEGP)
+    _seg_lib().orc_apps_loss_grad(C.byref(params(p)), C.byref(segp(q)), C.byref(o), C.byref(so),
+                                  m.ctypes.data, out.ctypes.data)
+    return float(out[0]), int(out[1]), out[2:2 + N_THETA].copy(), out[2 + N_THETA:].copy()

@@ -613,3 +613,122 @@ void orc_select_tile(const orc_params_t *p, int64_t n, const int32_t *M, const i
         near_tie[i] = (bi >= 0 && isfinite(c2) && (c2 - c1) <= 1e-6 * c1) ? 1 : 0;
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* workload segments (Sections IV-E, IV-F and the multi-segment model   */
+/* of Section V-B): an application is a list of segments, each a kernel */
+/* executed n_exec times                                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const int32_t *app_off;   /* [n_apps + 1] CSR offsets into the segment rows */
+    const float *n_exec;      /* executions of the segment                      */
+    const int32_t *n_kern;    /* kernels launched per execution (>= 1)          */
+    const int32_t *cls;       /* class 0 memory, 1 compute, 2 balanced, 3 stencil */
+    const float *h2d, *d2h;   /* host-to-device / device-to-host bytes per execution */
+    int64_t n_apps;
+} orc_segs_t;
+
+typedef struct {
+    double kappa[4];          /* per-class scale of the kernel time              */
+    double bw_h2d, bw_d2h;    /* effective transfer bandwidth per direction, B/s */
+    double tau_memcpy;        /* fixed cost per transfer episode, s (Eq. (15))   */
+} orc_segp_t;
+
+#define ORC_NSEG 7            /* kappa[4], bw_h2d, bw_d2h, tau_memcpy */
+
+static int seg_valid(double ne, int64_t nk, int64_t c, double h, double d)
+{
+    return isfinite(ne) && ne >= 0.0 && nk >= 1 && c >= 0 && c <= 3 &&
+           isfinite(h) && h >= 0.0 && isfinite(d) && d >= 0.0;
+}
+
+/*
+ * One segment: T_seg = n_exec * (kappa_cls * T_kernel          (kernel model)
+ *                                + (n_kern - 1) * T_launch     (extra launches, Section IV-F)
+ *                                + [h2d > 0] (h2d / B_h2d + tau_memcpy)   (Eq. (15))
+ *                                + [d2h > 0] (d2h / B_d2h + tau_memcpy)).
+ * Writes dT/dtheta (24) and dT/dsegparam (7) when the pointers are set.
+ */
+double orc_segment(const orc_params_t *p, const orc_segp_t *q, const orc_desc_t *d, const orc_segs_t *s,
+                   int64_t i, double *dth, double *dsp)
+{
+    orc_trace_t tr;
+    double J[N_THETA];
+    orc_eval(p, DESC_ARGS(d, i), &tr, dth ? J : NULL);
+    double ne = s->n_exec[i], h = s->h2d[i], dd = s->d2h[i];
+    int64_t nk = s->n_kern[i], c = s->cls[i];
+    if (dth) memset(dth, 0, sizeof(double) * N_THETA);
+    if (dsp) memset(dsp, 0, sizeof(double) * ORC_NSEG);
+    if (!seg_valid(ne, nk, c, h, dd)) return NAN;
+    if (!tr.valid) return NAN;
+    if (!isfinite(tr.T)) return INFINITY;
+    double T = q->kappa[c] * tr.T + (double)(nk - 1) * p->theta[S_T_LAUNCH];
+    if (h > 0.0) T += h / q->bw_h2d + q->tau_memcpy;
+    if (dd > 0.0) T += dd / q->bw_d2h + q->tau_memcpy;
+    if (dth) {
+        for (int j = 0; j < N_THETA; ++j) dth[j] = ne * q->kappa[c] * J[j];
+        dth[S_T_LAUNCH] += ne * (double)(nk - 1);
+    }
+    if (dsp) {
+        dsp[c] = ne * tr.T;
+        if (h > 0.0) { dsp[4] = -ne * h / (q->bw_h2d * q->bw_h2d); dsp[6] += ne; }
+        if (dd > 0.0) { dsp[5] = -ne * dd / (q->bw_d2h * q->bw_d2h); dsp[6] += ne; }
+    }
+    return ne * T;
+}
+
+/* Application totals T_app[a] = sum of its segments' times (NaN if any
+ * segment is invalid, else +inf if any is infeasible). */
+void orc_predict_apps(const orc_params_t *p, const orc_segp_t *q, const orc_desc_t *d,
+                      const orc_segs_t *s, double *T_app, double *T_seg)
+{
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < s->n_apps; ++a) {
+        double tot = 0.0;
+        for (int64_t i = s->app_off[a]; i < s->app_off[a + 1]; ++i) {
+            double t = orc_segment(p, q, d, s, i, NULL, NULL);
+            if (T_seg) T_seg[i] = t;
+            tot += t;
+        }
+        T_app[a] = tot;
+    }
+}
+
+/*
+ * Mean relative error over applications with finite total and finite
+ * measured m > 0, and its gradient: out[0] loss, out[1] count,
+ * out[2..25] dL/dtheta, out[26..32] dL/dsegparam.  Fixed-order sums.
+ */
+void orc_apps_loss_grad(const orc_params_t *p, const orc_segp_t *q, const orc_desc_t *d,
+                        const orc_segs_t *s, const double *measured, double *out)
+{
+    const int NO = 2 + N_THETA + ORC_NSEG;
+    int64_t na = s->n_apps;
+    double *part = (double *)calloc((size_t)(na > 0 ? na : 1) * NO, sizeof(double));
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < na; ++a) {
+        double *row = part + a * NO;
+        double tot = 0.0;
+        for (int64_t i = s->app_off[a]; i < s->app_off[a + 1]; ++i)
+            tot += orc_segment(p, q, d, s, i, NULL, NULL);
+        double m = measured[a];
+        if (!isfinite(tot) || !isfinite(m) || !(m > 0.0)) continue;
+        row[0] = fabs((tot - m) / m);
+        row[1] = 1.0;
+        double w = tot > m ? 1.0 / m : (tot < m ? -1.0 / m : 0.0);
+        double dth[N_THETA], dsp[ORC_NSEG];
+        for (int64_t i = s->app_off[a]; i < s->app_off[a + 1]; ++i) {
+            orc_segment(p, q, d, s, i, dth, dsp);
+            for (int j = 0; j < N_THETA; ++j) row[2 + j] += w * dth[j];
+            for (int j = 0; j < ORC_NSEG; ++j) row[2 + N_THETA + j] += w * dsp[j];
+        }
+    }
+    memset(out, 0, sizeof(double) * NO);
+    for (int64_t a = 0; a < na; ++a)
+        for (int j = 0; j < NO; ++j) out[j] += part[a * NO + j];
+    free(part);
+    if (out[1] > 0.0) {
+        out[0] /= out[1];
+        for (int j = 2; j < NO; ++j) out[j] /= out[1];
+    }
+}

@@ -332,3 +332,66 @@ def shapes(n: int, seed: int = 102, cmin: int = 8, cmax: int = 96,
     for i in range(n):
         codes[off[i]:off[i + 1]] = tiles[rng.permutation(N_TILES)[:cnt[i]]]
     return Shapes(M, N, K, dt, off.astype(np.int32), codes)
+
+
+# ---------------------------------------------------------------------------
+# workload segments: applications as lists of (kernel, executions) segments
+# ---------------------------------------------------------------------------
+SEG_CLASSES = ("memory", "compute", "balanced", "stencil")
+
+
+@dataclasses.dataclass
+class SegParams:
+    """Per-class kernel-time scales, host<->device bandwidths (B/s) and the
+    fixed cost per transfer episode (s).  Defaults: scales 1, 45 GB/s each
+    way and 2 us per transfer (the defaults printed in Table "parameters")."""
+    kappa: List[float] = dataclasses.field(default_factory=lambda: [1.0, 1.0, 1.0, 1.0])
+    bw_h2d: float = 45e9
+    bw_d2h: float = 45e9
+    tau_memcpy: float = 2e-6
+
+
+@dataclasses.dataclass
+class Segments:
+    app_off: np.ndarray   # int32 [n_apps + 1], CSR offsets into the segment rows
+    n_exec: np.ndarray    # float32
+    n_kern: np.ndarray    # int32 >= 1
+    cls: np.ndarray       # int32 0..3
+    h2d: np.ndarray       # float32 bytes per execution
+    d2h: np.ndarray
+
+    @property
+    def n_apps(self) -> int:
+        return int(self.app_off.shape[0] - 1)
+
+
+def seg_params(seed: int = 7) -> SegParams:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return SegParams(kappa=[float(x) for x in rng.uniform(0.7, 1.5, 4)],
+                     bw_h2d=float(_logu(rng, 20e9, 64e9)), bw_d2h=float(_logu(rng, 20e9, 64e9)),
+                     tau_memcpy=float(_logu(rng, 1e-6, 10e-6)))
+
+
+def segments(n_apps: int, seed: int = 120, smin: int = 1, smax: int = 12):
+    """Applications with U-int[1, 12] segments each (multi-segment benchmarks
+    of a few dominant kernels); per segment n_exec round(log-U[1, 1e4]),
+    1-4 kernels per execution, class U{0..3}, host-to-device and
+    device-to-host bytes 0 with p = 1/2 else log-U[1 KB, 1 GB].  Returns the
+    segment table and a matching descriptor sweep (one kernel per segment,
+    drawn as in descriptors() but with VGPRs/thread U-int[16, 128] so that
+    every kernel fits on a CU)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cnt = rng.integers(smin, smax + 1, n_apps)
+    off = np.zeros(n_apps + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    n = int(off[-1])
+    n_exec = np.round(_logu(rng, 1.0, 1e4, n)).astype(np.float32)
+    n_kern = rng.integers(1, 5, n).astype(np.int32)
+    cls = rng.integers(0, 4, n).astype(np.int32)
+    h2d = np.where(rng.random(n) < 0.5, 0.0, _logu(rng, 1e3, 1e9, n)).astype(np.float32)
+    d2h = np.where(rng.random(n) < 0.5, 0.0, _logu(rng, 1e3, 1e9, n)).astype(np.float32)
+    sg = Segments(off.astype(np.int32), n_exec, n_kern, cls, h2d, d2h)
+    d = descriptors(n, seed + 1)
+    # kernels of a running application launch: VGPRs/thread U-int[16, 128]
+    d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
+    return sg, d
