@@ -115,6 +115,46 @@ typedef struct {
     uint32_t reserved2;
 } wm_calib_opts_t;
 
+/*
+ * Workload segments (Sections IV-E, IV-F and V-B).  An application is a run
+ * of consecutive segment rows; segment row i pairs descriptor row i of a
+ * wm_desc_t with:
+ *   n_exec [n] float32  executions of the segment (finite, >= 0)
+ *   n_kern [n] int32    kernels launched per execution (>= 1); each beyond
+ *                       the first adds T_launch (theta slot 13)
+ *   cls    [n] int32    class 0 memory, 1 compute, 2 balanced, 3 stencil:
+ *                       selects the scale kappa_cls of the kernel time
+ *   h2d, d2h [n] float32  host-to-device / device-to-host bytes per
+ *                       execution (finite, >= 0; 0 = no transfer)
+ *   app_off [n_apps + 1] int32  application a owns rows
+ *                       [app_off[a], app_off[a + 1]); non-decreasing,
+ *                       app_off[0] = 0, app_off[n_apps] = n.  Offsets are
+ *                       read on the device and clamped into [0, n]: offsets
+ *                       that break these rules give unspecified results but
+ *                       never an out-of-range access.
+ * A row with a field outside these ranges makes its application's time NaN.
+ */
+typedef struct {
+    const int32_t *app_off;
+    const float *n_exec;
+    const int32_t *n_kern, *cls;
+    const float *h2d, *d2h;
+    int64_t n_apps;
+} wm_segs_t;
+
+/* Segment parameters (host struct): kappa[4] per-class scales of the kernel
+ * time (finite, >= 0; Section IV-F's separately calibrated class scales),
+ * bw_h2d / bw_d2h effective transfer bandwidths in B/s (> 0) and tau_memcpy
+ * the fixed cost per transfer episode in s (>= 0), Eq. (15).  Table
+ * "parameters" defaults: 45e9, 45e9, 2e-6. */
+typedef struct {
+    double kappa[4];
+    double bw_h2d, bw_d2h;
+    double tau_memcpy;
+} wm_segparams_t;
+
+#define WM_N_SEGPARAMS 7
+
 /* ---- host-only helpers (no HIP call) ---- */
 
 /* Text for a status code; never NULL. */
@@ -134,7 +174,10 @@ int32_t wm_validate_params(const wm_params_t *params);
  *  WM_OP_CALIBRATE: device parameter set, Adam state, a `steps`-entry loss
  *      history and the partial sums for n descriptors.
  *  WM_OP_CALIBRATE_BATCHED: the same for n_sets sets holding n descriptors
- *      in total, plus the work list. */
+ *      in total, plus the work list.
+ *  WM_OP_PREDICT_APPS: 0.
+ *  WM_OP_APPS_LOSS_GRAD: 0 here; its size depends on the application count
+ *      too: use wm_apps_workspace_bytes(). */
 #define WM_OP_PREDICT 0
 #define WM_OP_ROOFLINE 1
 #define WM_OP_VJP 2
@@ -142,7 +185,14 @@ int32_t wm_validate_params(const wm_params_t *params);
 #define WM_OP_SELECT_TILE 4
 #define WM_OP_CALIBRATE 5
 #define WM_OP_CALIBRATE_BATCHED 6
+#define WM_OP_PREDICT_APPS 7
+#define WM_OP_APPS_LOSS_GRAD 8
 size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps);
+
+/* Workspace bytes of wm_apps_loss_grad for n segment rows in n_apps
+ * applications: per-row adjoint weights, per-application flags and partial
+ * sums (0 for negative arguments). */
+size_t wm_apps_workspace_bytes(int64_t n, int64_t n_apps);
 
 /* ---- device calls ---- */
 
@@ -240,6 +290,39 @@ int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t *sets, const float 
                              const wm_params_t *p0, const wm_calib_opts_t *opts,
                              wm_params_t *p_out, double *loss_hist, void *ws, size_t ws_bytes,
                              void *stream);
+
+/*
+ * Application times: T_app[a] = sum over the application's rows of
+ *   n_exec (kappa_cls T_kernel + (n_kern - 1) T_launch
+ *           + [h2d > 0] (h2d / bw_h2d + tau_memcpy)
+ *           + [d2h > 0] (d2h / bw_d2h + tau_memcpy)),
+ * T_kernel the wm_predict time of the row's descriptor (segment times
+ * multiply by n_exec, Section IV-E; extra launches of multi-kernel segments,
+ * Section IV-F; transfers by Eq. (15); no overlap of copies and kernels).
+ * NaN if any row is invalid, else +inf if any kernel is infeasible; 0 for an
+ * application without rows.  T_app [n_apps] float32 (required); T_seg [n]
+ * float32 segment times or NULL.  Segment times are float32; application
+ * sums are float64 in row order, then rounded to float32.  One launch.
+ */
+int32_t wm_predict_apps(const wm_desc_t *desc, const wm_segs_t *segs, const wm_params_t *params,
+                        const wm_segparams_t *segp, float *T_app, float *T_seg, void *stream);
+
+/*
+ * Application-level mean relative error and its gradient (Section V-B: an
+ * application's prediction is the sum of its segments, compared with its
+ * measured time): over applications with finite T_app and finite measured
+ * m > 0, loss = mean |T_app - m| / m, with the gradient with respect to theta
+ * and the segment parameters (sign(0) = 0; subgradients of the kernel model
+ * as in wm_predict_vjp).  Applications with |T_app/m - 1| <= 1e-5 are summed
+ * again in float64 to take the sign.  measured [n_apps] float32.  out [33]
+ * float64 device: loss, count, dL/dtheta[24], dL/d(kappa[4], bw_h2d, bw_d2h,
+ * tau_memcpy).  Workspace: wm_apps_workspace_bytes(n, n_apps).  An
+ * application sweep, a float64 pass over the flagged applications, the
+ * gradient sweep of wm_predict_vjp over the rows, and a final reduction.
+ */
+int32_t wm_apps_loss_grad(const wm_desc_t *desc, const wm_segs_t *segs, const float *measured,
+                          const wm_params_t *params, const wm_segparams_t *segp, double *out,
+                          void *ws, size_t ws_bytes, void *stream);
 
 /* ---- launch configurations and autotuning ----
  *

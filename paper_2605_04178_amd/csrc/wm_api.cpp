@@ -189,6 +189,58 @@ CalibState init_state(const wm_params_t* p, uint32_t mask)
     return s;
 }
 
+bool segp_ok(const wm_segparams_t* q)
+{
+    if (!q) return false;
+    for (int c = 0; c < 4; ++c)
+        if (!(fin(q->kappa[c]) && q->kappa[c] >= 0.0 && f32_ok(q->kappa[c]))) return false;
+    if (!(fin(q->bw_h2d) && q->bw_h2d > 0.0 && f32_pos(1.0 / q->bw_h2d))) return false;
+    if (!(fin(q->bw_d2h) && q->bw_d2h > 0.0 && f32_pos(1.0 / q->bw_d2h))) return false;
+    if (!(fin(q->tau_memcpy) && q->tau_memcpy >= 0.0 && f32_ok(q->tau_memcpy))) return false;
+    return true;
+}
+
+// segment rows parallel to n descriptor rows
+bool segs_ok(const wm_segs_t* s, int64_t n)
+{
+    if (!s || s->n_apps < 0 || n > 0x7fffffffll) return false;
+    if (s->n_apps == 0) return n == 0;
+    if (!s->app_off) return false;
+    if (n > 0 && (!s->n_exec || !s->n_kern || !s->cls || !s->h2d || !s->d2h)) return false;
+    return true;
+}
+
+SegSet make_segset(const wm_segparams_t* q)
+{
+    SegSet Q;
+    std::memset(&Q, 0, sizeof(Q));
+    for (int c = 0; c < 4; ++c) {
+        Q.f.kappa[c] = (float)q->kappa[c];
+        Q.d.kappa[c] = q->kappa[c];
+    }
+    Q.d.inv_bw_h2d = 1.0 / q->bw_h2d;
+    Q.d.inv_bw_d2h = 1.0 / q->bw_d2h;
+    Q.d.tau = q->tau_memcpy;
+    Q.f.inv_bw_h2d = (float)Q.d.inv_bw_h2d;
+    Q.f.inv_bw_d2h = (float)Q.d.inv_bw_d2h;
+    Q.f.tau = (float)q->tau_memcpy;
+    Q.inv_bw2_h2d = Q.d.inv_bw_h2d * Q.d.inv_bw_h2d;
+    Q.inv_bw2_d2h = Q.d.inv_bw_d2h * Q.d.inv_bw_d2h;
+    return Q;
+}
+
+SegPtrs segptrs_of(const wm_segs_t* s)
+{
+    SegPtrs p;
+    p.off = s->app_off;
+    p.n_exec = s->n_exec;
+    p.n_kern = s->n_kern;
+    p.cls = s->cls;
+    p.h2d = s->h2d;
+    p.d2h = s->d2h;
+    return p;
+}
+
 // calibration workspace layout
 // gradient-sweep workspace: partial rows, then redo-flag words
 struct GradWs {
@@ -203,6 +255,30 @@ GradWs grad_ws(int64_t n)
     W.partials = 0;
     W.flags = up256(sizeof(double) * kAcc * (size_t)(W.g.nb + W.g.nb2));
     W.total = W.flags + up256(sizeof(uint64_t) * (size_t)(W.g.nwords > 0 ? W.g.nwords : 1));
+    return W;
+}
+
+// application loss-gradient workspace: row weights, application rows,
+// application flag words, then the gradient sweep's partials and flags
+struct AppsWs {
+    size_t wseg, rows, aflags, grad, total;
+    GradWs g;
+};
+
+AppsWs apps_ws(int64_t n, int64_t n_apps)
+{
+    AppsWs W;
+    W.g = grad_ws(n);
+    size_t off = 0;
+    W.wseg = off;
+    off += up256(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    W.rows = off;
+    off += up256(sizeof(double) * kAppAcc * (size_t)(kAppsMaxBlocks + kRedoMaxBlocks));
+    W.aflags = off;
+    off += up256(sizeof(uint64_t) * (size_t)((n_apps + 63) / 64 > 0 ? (n_apps + 63) / 64 : 1));
+    W.grad = off;
+    off += W.g.total;
+    W.total = off;
     return W;
 }
 
@@ -609,6 +685,12 @@ size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps)
     }
 }
 
+size_t wm_apps_workspace_bytes(int64_t n, int64_t n_apps)
+{
+    if (n < 0 || n_apps < 0) return 0;
+    return apps_ws(n, n_apps).total;
+}
+
 int32_t wm_predict(const wm_desc_t* desc, const wm_params_t* params, float* T, int32_t* occ,
                    void* stream)
 {
@@ -659,6 +741,42 @@ int32_t wm_loss_grad(const wm_desc_t* desc, const float* measured, const wm_para
                      double* out, void* ws, size_t ws_bytes, void* stream)
 {
     return grad_common(1, desc, measured, params, out, ws, ws_bytes, stream);
+}
+
+int32_t wm_predict_apps(const wm_desc_t* desc, const wm_segs_t* segs, const wm_params_t* params,
+                        const wm_segparams_t* segp, float* T_app, float* T_seg, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !segp_ok(segp) || !segs_ok(segs, desc->n))
+        return WM_EINVAL;
+    if (segs->n_apps == 0) return WM_OK;
+    if (!T_app) return WM_EINVAL;
+    const Set S = make_set(params);
+    WM_HIP(launch_predict_apps(ptrs_of(desc), segptrs_of(segs), desc->n, segs->n_apps, S,
+                               make_segset(segp), T_app, T_seg,
+                               launch_cfg(kOpPredictApps, segs->n_apps), (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_apps_loss_grad(const wm_desc_t* desc, const wm_segs_t* segs, const float* measured,
+                          const wm_params_t* params, const wm_segparams_t* segp, double* out,
+                          void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !segp_ok(segp) || !segs_ok(segs, desc->n) || !out)
+        return WM_EINVAL;
+    if (segs->n_apps > 0 && !measured) return WM_EINVAL;
+    const AppsWs W = apps_ws(desc->n, segs->n_apps);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    char* base = (char*)ws;
+    const Set S = make_set(params);
+    // no applications: the sweeps write zero rows, so out is still written
+    WM_HIP(launch_apps_loss_grad(ptrs_of(desc), segptrs_of(segs), desc->n, segs->n_apps, measured,
+                                 S, make_segset(segp), (float*)(base + W.wseg),
+                                 (double*)(base + W.rows), (uint64_t*)(base + W.aflags),
+                                 (double*)(base + W.grad + W.g.partials),
+                                 (uint64_t*)(base + W.grad + W.g.flags), W.g.g,
+                                 launch_cfg(kOpAppsLossGrad, segs->n_apps),
+                                 launch_cfg(kOpVjp, desc->n), out, (hipStream_t)stream));
+    return WM_OK;
 }
 
 int32_t wm_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,

@@ -9,7 +9,7 @@
 // kernels are persistent (grid-stride) and keep 26 FP64 accumulators per
 // thread, reduced across the wave with shuffles, across the block through LDS
 // and across blocks by a second single-block kernel in a fixed order.
-#include "wm_launch.hpp"
+#include "wm_device.hpp"
 
 #include <map>
 #include <mutex>
@@ -19,35 +19,6 @@ namespace wm {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-__device__ inline T ntload(const T* p) { return __builtin_nontemporal_load(p); }
-
-__device__ inline Desc<float> load_desc(const DescPtrs& d, int64_t i)
-{
-    Desc<float> x;
-    x.F = ntload(d.F + i);
-    x.B = ntload(d.B + i);
-    x.r1 = ntload(d.r1 + i);
-    x.r2 = ntload(d.r2 + i);
-    x.r3 = ntload(d.r3 + i);
-    x.K = ntload(d.K + i);
-    x.u = ntload(d.u + i);
-    x.W = ntload(d.W + i);
-    x.v = ntload(d.vgpr + i);
-    x.s = ntload(d.lds + i);
-    x.gp = ntload(d.gpack + i);
-    x.G = ntload(d.grid + i);
-    return x;
-}
-
-__device__ inline Desc<double> widen(const Desc<float>& x)
-{
-    Desc<double> y;
-    y.F = x.F; y.B = x.B; y.r1 = x.r1; y.r2 = x.r2; y.r3 = x.r3; y.K = x.K; y.u = x.u; y.W = x.W;
-    y.v = x.v; y.s = x.s; y.gp = x.gp; y.G = x.G;
-    return y;
-}
 
 // ---------------------------------------------------------------------------
 // forward sweep
@@ -389,7 +360,7 @@ GradLayout grad_layout(int64_t n)
 // Blocks of 256 threads that are resident at once on the current device for
 // a kernel (occupancy x compute units), cached per device and kernel.  A
 // persistent grid of exactly this size has no second, half-empty round.
-static int resident_blocks(const void* kernel, int block)
+int resident_blocks(const void* kernel, int block)
 {
     static std::mutex mu;
     static std::map<std::pair<int, const void*>, int> cache;

@@ -24,7 +24,7 @@ struct LaunchCfg {
 
 // op codes as in the public header
 constexpr int kOpPredict = 0, kOpVjp = 2, kOpLossGrad = 3, kOpSelectTile = 4,
-              kOpCalibrate = 5, kOpCalibrateBatched = 6;
+              kOpCalibrate = 5, kOpCalibrateBatched = 6, kOpPredictApps = 7, kOpAppsLossGrad = 8;
 constexpr int64_t kMinChunk = 4096;
 
 LaunchCfg default_cfg(int op);
@@ -38,6 +38,32 @@ struct DescPtrs {
     const float *F, *B, *r1, *r2, *r3, *K, *u, *W;
     const int32_t *vgpr, *lds, *gpack, *grid;
 };
+
+// Segment rows (parallel to the descriptor rows) and the application CSR
+// offsets over them.
+struct SegPtrs {
+    const int32_t* off;
+    const float* n_exec;
+    const int32_t *n_kern, *cls;
+    const float *h2d, *d2h;
+};
+
+// Segment parameters: class scales of the kernel time, reciprocal transfer
+// bandwidths, fixed cost per transfer episode.
+template <typename R>
+struct SegConst {
+    R kappa[4];
+    R inv_bw_h2d, inv_bw_d2h, tau;
+};
+struct SegSet {
+    SegConst<float> f;
+    SegConst<double> d;
+    double inv_bw2_h2d, inv_bw2_d2h;  // 1 / B^2, for the bandwidth gradients
+};
+constexpr int kSegParams = 7;                 // kappa[4], bw_h2d, bw_d2h, tau_memcpy
+constexpr int kAppAcc = 10;                   // loss, count, T_launch, kappa[4], h2d, d2h, tau sums
+constexpr int kAppsOut = kAcc + kSegParams;   // loss, count, grad theta[24], grad seg params[7]
+constexpr int kAppsMaxBlocks = 4096;          // partial-row cap of the application sweep
 
 struct ShapePtrs {
     const int32_t *M, *N, *K, *dtype;
@@ -76,6 +102,8 @@ GradLayout grad_layout(int64_t n);
 // resident at once on the current device times cfg.grid_mult, so partial
 // rows = that + nb2
 int grad_grid(int mode, bool from_device_set, int64_t n, const LaunchCfg& cfg);
+// blocks of `block` threads of `kernel` resident at once on the current device
+int resident_blocks(const void* kernel, int block);
 // blocks for the multi-set sweep over n_items work items
 int batched_grid(int n_items, int grid_mult);
 
@@ -100,6 +128,20 @@ hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, c
 hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, CalibState* st,
                                const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
                                hipStream_t stream);
+// Application totals (and, if T_seg != nullptr, segment times) in float32.
+hipError_t launch_predict_apps(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                               const Set& S, const SegSet& Q, float* T_app, float* T_seg,
+                               const LaunchCfg& cfg, hipStream_t stream);
+// Application mean relative error and its gradient [kAppsOut] (float64).
+// Workspace: wseg (n_seg floats), app_rows ((kAppsMaxBlocks + kRedoMaxBlocks)
+// x kAppAcc), aflags ((n_apps + 63) / 64 words), the gradient sweep's
+// partials / flags for n_seg descriptors.
+hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg,
+                                 int64_t n_apps, const float* measured, const Set& S,
+                                 const SegSet& Q, float* wseg, double* app_rows, uint64_t* aflags,
+                                 double* partials, uint64_t* flags, const GradLayout& L,
+                                 const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
+                                 hipStream_t stream);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
                               double* best_cost, uint8_t* near_tie, const LaunchCfg& cfg,

@@ -136,6 +136,8 @@ bool cfg_valid(int op, const LaunchCfg& c)
     case kOpVjp:
     case kOpLossGrad:
     case kOpSelectTile:
+    case kOpPredictApps:
+    case kOpAppsLossGrad:
         return blk && c.grid_mult >= 1 && c.grid_mult <= 8;
     case kOpCalibrateBatched:
         return c.block == 256 && c.grid_mult >= 1 && c.grid_mult <= 8 &&

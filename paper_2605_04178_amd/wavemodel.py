@@ -20,13 +20,15 @@ LIB_PATH = os.path.join(HERE, "libwavemodel.so")
 N_THETA = 24
 
 WM_OK, WM_EINVAL, WM_EWORKSPACE, WM_EHIP, WM_EDIVERGED = 0, -1, -2, -3, -4
-OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_CALIBRATE_BATCHED = range(7)
+(OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_CALIBRATE_BATCHED,
+ OP_PREDICT_APPS, OP_APPS_LOSS_GRAD) = range(9)
+N_SEGPARAMS = 7
 
 EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_workspace_bytes",
             "wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
             "wm_calibrate", "wm_calibrate_batched", "wm_get_launch", "wm_set_launch",
             "wm_autotune_predict", "wm_autotune_grad", "wm_autotune_select_tile",
-            "wm_autotune_batched")
+            "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad")
 
 
 class WmError(RuntimeError):
@@ -60,6 +62,16 @@ class WmLaunch(C.Structure):
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class WmSegs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("app_off", "n_exec", "n_kern", "cls", "h2d", "d2h")] + [
+        ("n_apps", C.c_int64)]
+
+
+class WmSegParams(C.Structure):
+    _fields_ = [("kappa", C.c_double * 4), ("bw_h2d", C.c_double), ("bw_d2h", C.c_double),
+                ("tau_memcpy", C.c_double)]
 
 
 class WmCalibOpts(C.Structure):
@@ -117,6 +129,13 @@ def lib():
         L.wm_autotune_select_tile.restype = i32
         L.wm_autotune_batched.argtypes = [i32, D, vp, P, C.POINTER(WmCalibOpts), vp, sz, vp, LP, dp]
         L.wm_autotune_batched.restype = i32
+        SG, SP = C.POINTER(WmSegs), C.POINTER(WmSegParams)
+        L.wm_apps_workspace_bytes.argtypes = [i64, i64]
+        L.wm_apps_workspace_bytes.restype = sz
+        L.wm_predict_apps.argtypes = [D, SG, P, SP, vp, vp, vp]
+        L.wm_predict_apps.restype = i32
+        L.wm_apps_loss_grad.argtypes = [D, SG, vp, P, SP, vp, vp, sz, vp]
+        L.wm_apps_loss_grad.restype = i32
         _lib = L
     return _lib
 
@@ -217,6 +236,52 @@ class DeviceDescriptors:
         return o
 
 
+class DeviceSegments:
+    """Segment rows (parallel to a DeviceDescriptors) and application offsets
+    as device tensors."""
+    FIELDS = (("app_off", torch.int32), ("n_exec", torch.float32), ("n_kern", torch.int32),
+              ("cls", torch.int32), ("h2d", torch.float32), ("d2h", torch.float32))
+
+    def __init__(self, tensors: dict):
+        for f, dt in self.FIELDS:
+            t = tensors[f]
+            if t.dtype != dt or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError(f"segment field {f} must be a contiguous 1-D {dt} tensor")
+            setattr(self, f, t)
+        self.n = int(self.n_exec.shape[0])
+        for f, _ in self.FIELDS[1:]:
+            if getattr(self, f).shape[0] != self.n:
+                raise ValueError("segment fields differ in length")
+        self.n_apps = int(self.app_off.shape[0]) - 1
+        if self.n_apps < 0:
+            raise ValueError("app_off needs n_apps + 1 entries")
+        self.device = self.n_exec.device
+
+    @classmethod
+    def from_host(cls, sg, device="cuda") -> "DeviceSegments":
+        out = {}
+        for f, dt in cls.FIELDS:
+            npdt = np.int32 if dt == torch.int32 else np.float32
+            out[f] = torch.from_numpy(np.ascontiguousarray(getattr(sg, f), dtype=npdt)).to(device)
+        return cls(out)
+
+    def struct(self) -> WmSegs:
+        o = WmSegs()
+        for f, _ in self.FIELDS:
+            setattr(o, f, getattr(self, f).data_ptr())
+        o.n_apps = self.n_apps
+        return o
+
+
+def segparams_struct(q) -> WmSegParams:
+    """Marshal segment parameters (kappa[4], bw_h2d, bw_d2h, tau_memcpy)."""
+    o = WmSegParams()
+    for c in range(4):
+        o.kappa[c] = float(q.kappa[c])
+    o.bw_h2d, o.bw_d2h, o.tau_memcpy = float(q.bw_h2d), float(q.bw_d2h), float(q.tau_memcpy)
+    return o
+
+
 class DeviceShapes:
     def __init__(self, M, N, K, dtype, cand_off, cand_code):
         self.M, self.N, self.K, self.dtype = M, N, K, dtype
@@ -294,6 +359,45 @@ def select_tile(shapes: DeviceShapes, params, out=None, stream=None):
                               _ptr(best), _ptr(cost), _ptr(tie), _stream(stream))
     _check(rc, "wm_select_tile")
     return best, cost, tie
+
+
+def apps_workspace_bytes(n: int, n_apps: int) -> int:
+    return int(lib().wm_apps_workspace_bytes(n, n_apps))
+
+
+def _check_rows(desc: DeviceDescriptors, segs: DeviceSegments):
+    if desc.n != segs.n:
+        raise ValueError(f"{desc.n} descriptor rows but {segs.n} segment rows")
+
+
+def predict_apps(desc: DeviceDescriptors, segs: DeviceSegments, params, segp, want_seg=False,
+                 out=None, stream=None):
+    """Application times (float32 [n_apps]) and, if want_seg, segment times."""
+    _check_rows(desc, segs)
+    T_app = out if out is not None else torch.empty(segs.n_apps, dtype=torch.float32, device=desc.device)
+    T_seg = torch.empty(segs.n, dtype=torch.float32, device=desc.device) if want_seg else None
+    rc = lib().wm_predict_apps(C.byref(desc.struct()), C.byref(segs.struct()),
+                               C.byref(params_struct(params)), C.byref(segparams_struct(segp)),
+                               _ptr(T_app), _ptr(T_seg), _stream(stream))
+    _check(rc, "wm_predict_apps")
+    return T_app, T_seg
+
+
+def apps_loss_grad(desc: DeviceDescriptors, segs: DeviceSegments, measured: torch.Tensor, params,
+                   segp, ws=None, out=None, stream=None):
+    """[loss, count, grad theta[24], grad (kappa[4], bw_h2d, bw_d2h, tau_memcpy)]
+    float64 on the device (application mean relative error)."""
+    _check_rows(desc, segs)
+    if out is None:
+        out = torch.empty(2 + N_THETA + N_SEGPARAMS, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(apps_workspace_bytes(desc.n, segs.n_apps), desc.device)
+    nb = 0 if ws is None else ws.numel()
+    rc = lib().wm_apps_loss_grad(C.byref(desc.struct()), C.byref(segs.struct()), _ptr(measured),
+                                 C.byref(params_struct(params)), C.byref(segparams_struct(segp)),
+                                 _ptr(out), _ptr(ws), nb, _stream(stream))
+    _check(rc, "wm_apps_loss_grad")
+    return out
 
 
 def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,

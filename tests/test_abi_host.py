@@ -32,7 +32,8 @@ def test_header_declares_the_calls():
     names = _declared()
     for n in ("wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
               "wm_calibrate", "wm_calibrate_batched", "wm_workspace_bytes", "wm_strerror",
-              "wm_last_hip_error", "wm_validate_params"):
+              "wm_last_hip_error", "wm_validate_params", "wm_predict_apps", "wm_apps_loss_grad",
+              "wm_apps_workspace_bytes"):
         assert n in names
 
 
@@ -184,6 +185,58 @@ def test_argument_errors_before_any_hip_call(wmb):
     assert L.wm_calibrate_batched(2, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_calibrate_batched(0, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_calibrate_batched(17, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_last_hip_error() == 0
+
+
+def _fake_segs(wmb, n_apps):
+    s = wmb.WmSegs()
+    for i, f in enumerate(("app_off", "n_exec", "n_kern", "cls", "h2d", "d2h")):
+        setattr(s, f, 0x20000 * (i + 1))
+    s.n_apps = n_apps
+    return s
+
+
+def test_segment_calls_validate_before_any_hip_call(wmb):
+    L = wmb.lib()
+    p = wmb.params_struct(synth.param_set(0))
+    q = wmb.segparams_struct(synth.SegParams())
+    d = _fake_desc(wmb, 16)
+    sg = _fake_segs(wmb, 4)
+    T = C.c_void_p(0x2000)
+    out = C.c_void_p(0x3000)
+    m = C.c_void_p(0x4000)
+    assert C.sizeof(wmb.WmSegs) == 6 * 8 + 8 and C.sizeof(wmb.WmSegParams) == 7 * 8
+    assert L.wm_predict_apps(C.byref(d), None, C.byref(p), C.byref(q), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict_apps(C.byref(d), C.byref(sg), C.byref(p), None, T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict_apps(C.byref(d), C.byref(sg), C.byref(p), C.byref(q), None, None, None) == wmb.WM_EINVAL
+    for kw in (dict(kappa=[1, 1, -1, 1]), dict(kappa=[1, float("nan"), 1, 1]), dict(bw_h2d=0.0),
+               dict(bw_d2h=-5.0), dict(tau_memcpy=-1e-6), dict(bw_h2d=float("inf"))):
+        bad = wmb.segparams_struct(synth.SegParams(**kw))
+        assert L.wm_predict_apps(C.byref(d), C.byref(sg), C.byref(p), C.byref(bad), T, None, None) == wmb.WM_EINVAL, kw
+    # rows without applications, a missing row field, negative count
+    assert L.wm_predict_apps(C.byref(d), C.byref(_fake_segs(wmb, 0)), C.byref(p), C.byref(q), T, None,
+                             None) == wmb.WM_EINVAL
+    s2 = _fake_segs(wmb, 4)
+    s2.cls = None
+    assert L.wm_predict_apps(C.byref(d), C.byref(s2), C.byref(p), C.byref(q), T, None, None) == wmb.WM_EINVAL
+    assert L.wm_predict_apps(C.byref(d), C.byref(_fake_segs(wmb, -1)), C.byref(p), C.byref(q), T, None,
+                             None) == wmb.WM_EINVAL
+    # nothing to do
+    d0 = _fake_desc(wmb, 0)
+    assert L.wm_predict_apps(C.byref(d0), C.byref(_fake_segs(wmb, 0)), C.byref(p), C.byref(q), None, None,
+                             None) == wmb.WM_OK
+    # loss gradient: workspace and measured
+    need = wmb.apps_workspace_bytes(16, 4)
+    assert need > 0 and need % 256 == 0
+    assert wmb.apps_workspace_bytes(16, 1 << 20) > need and wmb.apps_workspace_bytes(-1, 4) == 0
+    assert L.wm_apps_loss_grad(C.byref(d), C.byref(sg), m, C.byref(p), C.byref(q), out, None, 0,
+                               None) == wmb.WM_EWORKSPACE
+    assert L.wm_apps_loss_grad(C.byref(d), C.byref(sg), m, C.byref(p), C.byref(q), out,
+                               C.c_void_p(0x10000), need - 256, None) == wmb.WM_EWORKSPACE
+    assert L.wm_apps_loss_grad(C.byref(d), C.byref(sg), None, C.byref(p), C.byref(q), out,
+                               C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    assert L.wm_apps_loss_grad(C.byref(d), C.byref(sg), m, C.byref(p), C.byref(q), None,
+                               C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
     assert L.wm_last_hip_error() == 0
 
 
