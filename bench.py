@@ -27,6 +27,8 @@ METRIC = "model evals/sec (fwd; fwd+adjoint) and % HBM peak at ≤1e-5 rel err v
 HBM_PEAK_GBS = 8000.0
 FWD_BYTES = 56      # 8 f32 + 4 i32 read, T f32 + occ i32 written
 ADJ_BYTES = 52      # 8 f32 + 4 i32 + measured f32 read
+SEG_ROW_BYTES = 68  # descriptor (48) + segment row (n_exec, n_kern, cls, h2d, d2h: 20)
+APP_BYTES = 8       # offset int32 + T_app (or measured) f32 per application
 
 
 def log(*a):
@@ -57,7 +59,19 @@ def kernel_name(kind, cfg):
         return f"void wm::k_predict<{cfg['per_thread']}, {cfg['block']}>"
     if kind == "loss_grad":
         return f"void wm::k_grad<1, false, {cfg['block']}>"
+    if kind == "predict_apps":
+        return f"void wm::k_apps<{cfg['block']}, false>"
+    if kind == "apps_loss_grad":
+        return f"void wm::k_apps<{cfg['block']}, true>"
     return kind
+
+
+def kernel_sources():
+    """Bytes of every device-code source file, in name order (the fingerprint
+    that ties a counter summary to the kernels it measured)."""
+    csrc = os.path.join(ROOT, "paper_2605_04178_amd", "csrc")
+    names = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    return b"".join(open(os.path.join(csrc, f), "rb").read() for f in names)
 
 
 def counted_traffic(kernel_prefix):
@@ -69,9 +83,7 @@ def counted_traffic(kernel_prefix):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    csrc = os.path.join(ROOT, "paper_2605_04178_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                   for f in ("wm_kernels.hip", "wm_model.hpp", "wm_launch.hpp"))
+    src = kernel_sources()
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
     for name, v in rec["kernels"].items():
@@ -125,12 +137,73 @@ def profile_run(wm, synth, dd, p, n, dev):
     torch.cuda.synchronize()
     log("profile: select_tile x3 done")
     del T, occ, meas, ws
+    na = 1 << 20
+    q = synth.seg_params(7)
+    sg, d = synth.segments(na, 150)
+    dd2 = wm.DeviceDescriptors.from_host(d, dev)
+    ds = wm.DeviceSegments.from_host(sg, dev)
+    log("profile: tuned", wm.autotune_apps(wm.OP_PREDICT_APPS, dd2, ds, None, p, q))
+    for _ in range(3):
+        Ta, _ = wm.predict_apps(dd2, ds, p, q)
+    meas = (Ta * 1.05).contiguous()
+    log("profile: tuned", wm.autotune_apps(wm.OP_APPS_LOSS_GRAD, dd2, ds, meas, p, q))
+    for _ in range(3):
+        wm.apps_loss_grad(dd2, ds, meas, p, q)
+    torch.cuda.synchronize()
+    log("profile: predict_apps x3, apps_loss_grad x3 done")
+    del dd2, ds, Ta, meas
     a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)           # 1 GiB read + 1 GiB written per launch
     torch.cuda.synchronize()
     log("profile: reference copy x3 done (1073741824 bytes each way)")
+
+
+def segments_leg(wm, synth, args, dev, tuned):
+    """Workload segments: 2^20 applications of 1-12 segment rows (about 6.8
+    million rows): application totals, and the application-level loss with
+    its gradient."""
+    import torch
+    na = 1 << 20
+    p = synth.param_set(0)
+    q = synth.seg_params(7)
+    sg, d = synth.segments(na, 150)
+    rows = int(sg.app_off[-1])
+    dd = wm.DeviceDescriptors.from_host(d, dev)
+    ds = wm.DeviceSegments.from_host(sg, dev)
+    Ta = torch.empty(na, dtype=torch.float32, device=dev)
+    if not args.no_tune:
+        tuned["predict_apps"] = wm.autotune_apps(wm.OP_PREDICT_APPS, dd, ds, None, p, q)
+        log(f"autotuned predict_apps: {tuned['predict_apps']}")
+    fa = lambda: wm.predict_apps(dd, ds, p, q, out=Ta)
+    wall_f, ev_f = timed(fa, args.steps, args.warmup)
+    meas = (Ta * torch.from_numpy(synth.lognormal_noise(na, 151, 0.05).astype(np.float32)).to(dev)).contiguous()
+    p0 = synth.perturb_theta(p, 152, factor=1.2)
+    ws = wm._workspace(wm.apps_workspace_bytes(rows, na), dev)
+    out = torch.empty(33, dtype=torch.float64, device=dev)
+    if not args.no_tune:
+        tuned["apps_loss_grad"] = wm.autotune_apps(wm.OP_APPS_LOSS_GRAD, dd, ds, meas, p0, q)
+        log(f"autotuned apps_loss_grad: {tuned['apps_loss_grad']}")
+    fg = lambda: wm.apps_loss_grad(dd, ds, meas, p0, q, ws=ws, out=out)
+    wall_g, ev_g = timed(fg, max(args.steps // 2, 3), 2)
+    alg = SEG_ROW_BYTES * rows + APP_BYTES * na
+    fa_gbs = alg / (ev_f * 1e-3) / 1e9
+    fg_gbs = alg / (ev_g * 1e-3) / 1e9
+    cf = wm.get_launch(wm.OP_PREDICT_APPS, na)
+    cg = wm.get_launch(wm.OP_APPS_LOSS_GRAD, na)
+    log(f"segments: predict_apps {ev_f:.4f} ms ({fa_gbs:.0f} GB/s), apps_loss_grad {ev_g:.4f} ms")
+    return {"applications": na, "rows": rows,
+            "predict_apps": {"ms_per_call": wall_f, "event_ms": ev_f, "rows_per_s": rows / (ev_f * 1e-3),
+                             "apps_per_s": na / (ev_f * 1e-3), "achieved_GBs": fa_gbs,
+                             "hbm_frac": fa_gbs / HBM_PEAK_GBS, "launch": cf,
+                             "kernel": kernel_name("predict_apps", cf),
+                             "traffic": counted_traffic(kernel_name("predict_apps", cf))},
+            "apps_loss_grad": {"ms_per_call": wall_g, "event_ms": ev_g, "rows_per_s": rows / (ev_g * 1e-3),
+                               "achieved_GBs_vs_one_pass": fg_gbs, "hbm_frac_vs_one_pass": fg_gbs / HBM_PEAK_GBS,
+                               "launch": cg, "sweep_kernel": kernel_name("apps_loss_grad", cg),
+                               "sweep_traffic": counted_traffic(kernel_name("apps_loss_grad", cg))},
+            "bytes_per_row": SEG_ROW_BYTES, "bytes_per_app": APP_BYTES}
 
 
 def main():
@@ -315,6 +388,9 @@ def main():
                           "persistent_evals_per_s": tot / el_b, "per_set_evals_per_s": tot / el_p,
                           "speedup": el_p / el_b, "per_set_recovery_err": rec, "status": rcb}
         log(f"batched: {el_b:.3f} s persistent vs {el_p:.3f} s per-set")
+        del descs, meas_l
+
+        res["segments"] = segments_leg(wm, synth, args, dev, tuned)
 
     if tuned:
         res["autotune_us"] = {k: v["us"] for k, v in tuned.items()}

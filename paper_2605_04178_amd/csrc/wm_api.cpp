@@ -951,6 +951,45 @@ int32_t wm_autotune_grad(int32_t op, const wm_desc_t* desc, const float* w,
                      best, best_us);
 }
 
+int32_t wm_autotune_apps(int32_t op, const wm_desc_t* desc, const wm_segs_t* segs,
+                         const float* measured, const wm_params_t* params,
+                         const wm_segparams_t* segp, float* T_app, double* out, void* ws,
+                         size_t ws_bytes, void* stream, wm_launch_t* best, double* best_us)
+{
+    if (op != WM_OP_PREDICT_APPS && op != WM_OP_APPS_LOSS_GRAD) return WM_EINVAL;
+    if (!desc_ok(desc) || !params_ok(params) || !segp_ok(segp) || !segs_ok(segs, desc->n) ||
+        segs->n_apps < 1)
+        return WM_EINVAL;
+    const Set S = make_set(params);
+    const SegSet Q = make_segset(segp);
+    const DescPtrs dp = ptrs_of(desc);
+    const SegPtrs sp = segptrs_of(segs);
+    const int64_t n = desc->n, na = segs->n_apps;
+    hipStream_t s = (hipStream_t)stream;
+    if (op == WM_OP_PREDICT_APPS) {
+        if (!T_app) return WM_EINVAL;
+        return tune_over(op, na, candidates(op), s, 10,
+                         [&](const LaunchCfg& c) {
+                             return launch_predict_apps(dp, sp, n, na, S, Q, T_app, nullptr, c, s);
+                         },
+                         best, best_us);
+    }
+    if (!measured || !out) return WM_EINVAL;
+    const AppsWs W = apps_ws(n, na);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    char* base = (char*)ws;
+    const LaunchCfg vc = launch_cfg(kOpVjp, n);
+    return tune_over(op, na, candidates(op), s, 10,
+                     [&](const LaunchCfg& c) {
+                         return launch_apps_loss_grad(
+                             dp, sp, n, na, measured, S, Q, (float*)(base + W.wseg),
+                             (double*)(base + W.rows), (uint64_t*)(base + W.aflags),
+                             (double*)(base + W.grad + W.g.partials),
+                             (uint64_t*)(base + W.grad + W.g.flags), W.g.g, c, vc, out, s);
+                     },
+                     best, best_us);
+}
+
 int32_t wm_autotune_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
                                 const uint32_t* cand_code, int64_t n_cand,
                                 const wm_params_t* params, int32_t* best_idx, double* best_cost,

@@ -8,27 +8,37 @@
 // Layout: applications are CSR offsets over the segment rows, which run
 // parallel to the descriptor rows.  A block takes `BLOCK` consecutive
 // applications; their rows are contiguous, so it streams them with coalesced
-// loads in pieces of kSegCap rows staged in LDS, then each thread adds its own
+// loads in pieces of 8 x BLOCK rows staged in LDS, then each thread adds its own
 // application's rows in float64, in row order.
 #include "wm_device.hpp"
 
 namespace wm {
 
-constexpr int kSegCap = 1024;  // segment rows per LDS piece
 
 struct SegRow {
     float ne, h, dd;
     int32_t nk, c;
 };
 
+// KEEP = true: ordinary loads, so that a second pass over the same rows
+// finds them in the caches; false: streaming (nontemporal) loads.
+template <bool KEEP = false>
 __device__ inline SegRow load_seg(const SegPtrs& sg, int64_t i)
 {
     SegRow r;
-    r.ne = ntload(sg.n_exec + i);
-    r.nk = ntload(sg.n_kern + i);
-    r.c = ntload(sg.cls + i);
-    r.h = ntload(sg.h2d + i);
-    r.dd = ntload(sg.d2h + i);
+    if (KEEP) {
+        r.ne = sg.n_exec[i];
+        r.nk = sg.n_kern[i];
+        r.c = sg.cls[i];
+        r.h = sg.h2d[i];
+        r.dd = sg.d2h[i];
+    } else {
+        r.ne = ntload(sg.n_exec + i);
+        r.nk = ntload(sg.n_kern + i);
+        r.c = ntload(sg.cls + i);
+        r.h = ntload(sg.h2d + i);
+        r.dd = ntload(sg.d2h + i);
+    }
     return r;
 }
 
@@ -91,15 +101,20 @@ __device__ inline void block_sum(double* acc, double* lds /* [waves][NA] */, dou
     __syncthreads();
 }
 
-// Application sweep.  LOSS = false: T_app[a] (float32) and optionally the
-// segment times.  LOSS = true: per block one row of kAppAcc float64 sums
-// (loss, count, then sign(T - m)/m times the application's sums of
-// n_exec (n_kern - 1), n_exec Tk per class, n_exec h2d, n_exec d2h and
-// n_exec x transfers), and the per-row adjoint weights
-// wseg[j] = sign(T_a - m_a) / m_a * n_exec_j * kappa_cls(j) for the kernel
-// model's vector-Jacobian product.  Offsets are caller data: they are clamped
-// into [0, n_seg], so malformed offsets give unspecified values but no
-// out-of-range access.
+// Application sweep.  A block takes BLOCK consecutive applications (one per
+// thread); their rows are staged in LDS in pieces of 8 x BLOCK rows (one
+// piece unless the chunk averages more than 8 rows per application).
+// LOSS = false: T_app[a] (float32) and optionally the segment times.
+// LOSS = true: after the application totals, a second row-parallel pass
+// writes the adjoint weights wseg[j] = sign(T_a - m_a) / m_a * n_exec_j *
+// kappa_cls(j) for the kernel model's vector-Jacobian product and adds
+// sign/m times each row's n_exec (n_kern - 1), n_exec Tk (per class),
+// n_exec h2d, n_exec d2h and n_exec x transfers; per block one row of
+// kAppAcc float64 sums (loss, count, those seven).  An application with
+// |T_a/m_a - 1| <= 1e-5 in this float32 sweep gets zero weights and is
+// flagged in aflags (one 64-bit ballot word per 64 applications) for
+// k_apps_redo.  Offsets are caller data: they are clamped into [0, n_seg],
+// so malformed offsets give unspecified values but no out-of-range access.
 template <int BLOCK, bool LOSS>
 __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t n_seg,
                                                int64_t n_apps, Set S, SegSet Q,
@@ -108,13 +123,15 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
                                                float* __restrict__ wseg, double* __restrict__ rows,
                                                uint64_t* __restrict__ aflags)
 {
-    constexpr int LC = LOSS ? kSegCap : 1;
-    __shared__ float ts[kSegCap];
-    __shared__ float ek[LC], el[LC], eh[LC], ed[LC], en[LC];
-    __shared__ uint8_t ecls[LC];
+    constexpr int CAP = 8 * BLOCK;
+    constexpr int LC = LOSS ? CAP : 1;
+    __shared__ float ts[CAP];
+    __shared__ float ekn[LC];       // n_exec * T_kernel
+    __shared__ uint8_t ecl[LC];     // class
+    __shared__ uint16_t own[LC];    // application (index in the chunk) of the row
     __shared__ int32_t lo_s[BLOCK], hi_s[BLOCK];
     __shared__ float wa_s[LOSS ? BLOCK : 1];
-    __shared__ double red[16 * kAppAcc];
+    __shared__ double red[LOSS ? 8 * kAppAcc : 1];
 
     double acc[kAppAcc];
 #pragma unroll
@@ -137,46 +154,32 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
         hi_s[tid] = hi;
         __syncthreads();
         const int32_t sb = lo_s[0], se = hi_s[na - 1];
-        double tot = 0.0, sk0 = 0.0, sk1 = 0.0, sk2 = 0.0, sk3 = 0.0, sl = 0.0, sh = 0.0,
-               sd = 0.0, sn = 0.0;
-        for (int32_t pb = sb; pb < se; pb += kSegCap) {
-            const int32_t pe = se - pb < kSegCap ? se : pb + kSegCap;
-            for (int32_t j = pb + tid; j < pe; j += BLOCK) {
+        const bool one_piece = se - sb <= CAP;
+        double tot = 0.0;
+        for (int32_t pb = sb; pb < se; pb += CAP) {
+            const int32_t pe = se - pb < CAP ? se : pb + CAP;
+            // rows are visited from a 64-row boundary so that every wave's
+            // loads cover whole cache lines (the rows before pb are skipped)
+            for (int32_t j = (pb & ~63) + tid; j < pe; j += BLOCK) {
+                if (j < pb) continue;
                 const Desc<float> x = load_desc(d, j);
-                const SegRow r = load_seg(sg, j);
+                const SegRow r = load_seg<LOSS>(sg, j);
                 Eval<float> E;
                 evaluate<float, false>(S.st, S.cf, x, E);
                 const float t = seg_time<float>(E.T, r, Q.f, S.cf.ov[0]);
                 ts[j - pb] = t;
                 if (T_seg) __builtin_nontemporal_store(t, T_seg + j);
                 if (LOSS) {
-                    const int k = j - pb;
-                    ek[k] = r.ne * E.T;
-                    el[k] = r.ne * (float)(r.nk - 1);
-                    eh[k] = r.h > 0.0f ? r.ne * r.h : 0.0f;
-                    ed[k] = r.dd > 0.0f ? r.ne * r.dd : 0.0f;
-                    en[k] = r.ne * (float)((int)(r.h > 0.0f) + (int)(r.dd > 0.0f));
-                    ecls[k] = (uint8_t)(r.c & 3);
+                    ekn[j - pb] = r.ne * E.T;
+                    ecl[j - pb] = (uint8_t)(r.c & 3);
                 }
             }
             __syncthreads();
             if (tid < na) {
                 const int32_t jb = lo > pb ? lo : pb, je = hi < pe ? hi : pe;
                 for (int32_t j = jb; j < je; ++j) {
-                    const int k = j - pb;
-                    tot += (double)ts[k];
-                    if (LOSS) {
-                        const int c = ecls[k];
-                        const double v = (double)ek[k];
-                        sk0 += c == 0 ? v : 0.0;
-                        sk1 += c == 1 ? v : 0.0;
-                        sk2 += c == 2 ? v : 0.0;
-                        sk3 += c == 3 ? v : 0.0;
-                        sl += (double)el[k];
-                        sh += (double)eh[k];
-                        sd += (double)ed[k];
-                        sn += (double)en[k];
-                    }
+                    tot += (double)ts[j - pb];
+                    if (LOSS) own[j - pb] = (uint16_t)tid;
                 }
             }
             __syncthreads();
@@ -198,14 +201,6 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
                     const double w = T > m ? im : (T < m ? -im : 0.0);
                     acc[0] += __builtin_fabs(T - m) * im;
                     acc[1] += 1.0;
-                    acc[2] += w * sl;
-                    acc[3] += w * sk0;
-                    acc[4] += w * sk1;
-                    acc[5] += w * sk2;
-                    acc[6] += w * sk3;
-                    acc[7] += w * sh;
-                    acc[8] += w * sd;
-                    acc[9] += w * sn;
                     wa = (float)w;
                 }
             }
@@ -214,19 +209,59 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
         if ((tid & 63) == 0 && a < n_apps) aflags[a >> 6] = fw;
         wa_s[tid] = wa;
         __syncthreads();
-        // adjoint weights of the chunk's rows, coalesced: the owning
-        // application is the last one whose first row is <= j
-        for (int32_t j = sb + tid; j < se; j += BLOCK) {
-            int t0 = 0, t1 = na - 1;
-            while (t0 < t1) {
-                const int mid = (t0 + t1 + 1) >> 1;
-                if (lo_s[mid] <= j) t0 = mid;
-                else t1 = mid - 1;
+        // row-parallel pass: weights and the segment-parameter sums.  With one
+        // piece the owner, class and n_exec Tk are still in LDS; otherwise the
+        // owner is found by binary search and Tk is evaluated again.
+        for (int32_t j = (sb & ~63) + tid; j < se; j += BLOCK) {
+            if (j < sb) continue;
+            int t0;
+            float ek;
+            int32_t c;
+            bool mine = true;
+            if (one_piece) {
+                t0 = own[j - sb];
+                t0 = t0 < na ? t0 : na - 1;  // rows no application owns (bad offsets)
+                mine = j >= lo_s[t0] && j < hi_s[t0];
+                ek = ekn[j - sb];
+                c = ecl[j - sb];
+            } else {
+                int t1 = na - 1;
+                t0 = 0;
+                while (t0 < t1) {
+                    const int mid = (t0 + t1 + 1) >> 1;
+                    if (lo_s[mid] <= j) t0 = mid;
+                    else t1 = mid - 1;
+                }
+                mine = j >= lo_s[t0] && j < hi_s[t0];
+                ek = 0.0f;
+                c = 0;
             }
+            const float wt = mine ? wa_s[t0] : 0.0f;
             float w = 0.0f;
-            if (j >= lo_s[t0] && j < hi_s[t0] && wa_s[t0] != 0.0f) {
-                const int32_t c = sg.cls[j];
-                w = wa_s[t0] * sg.n_exec[j] * kappa_of(Q.f, c);
+            if (wt != 0.0f) {
+                const SegRow r = load_seg<true>(sg, j);
+                if (!one_piece) {
+                    Eval<float> E;
+                    evaluate<float, false>(S.st, S.cf, load_desc(d, j), E);
+                    ek = r.ne * E.T;
+                    c = r.c;
+                }
+                w = wt * r.ne * kappa_of(Q.f, c);
+                const double wd = wt;
+                acc[2] += wd * (double)(r.ne * (float)(r.nk - 1));
+                const double v = wd * (double)ek;
+                acc[3] += c == 0 ? v : 0.0;
+                acc[4] += c == 1 ? v : 0.0;
+                acc[5] += c == 2 ? v : 0.0;
+                acc[6] += c == 3 ? v : 0.0;
+                if (r.h > 0.0f) {
+                    acc[7] += wd * (double)(r.ne * r.h);
+                    acc[9] += wd * (double)r.ne;
+                }
+                if (r.dd > 0.0f) {
+                    acc[8] += wd * (double)(r.ne * r.dd);
+                    acc[9] += wd * (double)r.ne;
+                }
             }
             wseg[j] = w;
         }
