@@ -370,6 +370,14 @@ int32_t wm_autotune_select_tile(const wm_shapes_t *shapes, const int32_t *cand_o
                                 const wm_params_t *params, int32_t *best_idx, double *best_cost,
                                 uint8_t *near_tie, void *stream, wm_launch_t *best,
                                 double *best_us);
+/* op = WM_OP_PREDICT_APPS (writes T_app [n_apps]; measured, out, ws
+ * unused) or WM_OP_APPS_LOSS_GRAD (writes out [33]; needs measured and a
+ * wm_apps_workspace_bytes() workspace; T_app unused).  Tunes the application
+ * sweep; the row gradient sweep keeps the WM_OP_VJP configuration. */
+int32_t wm_autotune_apps(int32_t op, const wm_desc_t *desc, const wm_segs_t *segs,
+                         const float *measured, const wm_params_t *params,
+                         const wm_segparams_t *segp, float *T_app, double *out, void *ws,
+                         size_t ws_bytes, void *stream, wm_launch_t *best, double *best_us);
 int32_t wm_autotune_batched(int32_t n_sets, const wm_desc_t *sets, const float *const *measured,
                             const wm_params_t *p0, const wm_calib_opts_t *opts, void *ws,
                             size_t ws_bytes, void *stream, wm_launch_t *best, double *best_us);

@@ -28,7 +28,8 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_predict", "wm_roofline", "wm_predict_vjp", "wm_loss_grad", "wm_select_tile",
             "wm_calibrate", "wm_calibrate_batched", "wm_get_launch", "wm_set_launch",
             "wm_autotune_predict", "wm_autotune_grad", "wm_autotune_select_tile",
-            "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad")
+            "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad",
+            "wm_autotune_apps")
 
 
 class WmError(RuntimeError):
@@ -136,6 +137,8 @@ def lib():
         L.wm_predict_apps.restype = i32
         L.wm_apps_loss_grad.argtypes = [D, SG, vp, P, SP, vp, vp, sz, vp]
         L.wm_apps_loss_grad.restype = i32
+        L.wm_autotune_apps.argtypes = [i32, D, SG, vp, P, SP, vp, vp, vp, sz, vp, LP, dp]
+        L.wm_autotune_apps.restype = i32
         _lib = L
     return _lib
 
@@ -496,6 +499,26 @@ def autotune_select_tile(shapes: DeviceShapes, params, stream=None) -> dict:
                                        _ptr(best_i), _ptr(cost), _ptr(tie), _stream(stream),
                                        C.byref(best), C.byref(us))
     return _tuned(rc, "wm_autotune_select_tile", best, us)
+
+
+def autotune_apps(op: int, desc: DeviceDescriptors, segs: DeviceSegments, measured, params, segp,
+                  stream=None) -> dict:
+    """Tune the application sweep of predict_apps (op OP_PREDICT_APPS) or
+    apps_loss_grad (OP_APPS_LOSS_GRAD, needs measured)."""
+    _check_rows(desc, segs)
+    best, us = WmLaunch(), C.c_double()
+    dev = desc.device
+    T = ws = out = None
+    if op == OP_PREDICT_APPS:
+        T = torch.empty(max(segs.n_apps, 1), dtype=torch.float32, device=dev)
+    else:
+        out = torch.empty(2 + N_THETA + N_SEGPARAMS, dtype=torch.float64, device=dev)
+        ws = _workspace(apps_workspace_bytes(desc.n, segs.n_apps), dev)
+    rc = lib().wm_autotune_apps(op, C.byref(desc.struct()), C.byref(segs.struct()), _ptr(measured),
+                                C.byref(params_struct(params)), C.byref(segparams_struct(segp)),
+                                _ptr(T), _ptr(out), _ptr(ws), 0 if ws is None else ws.numel(),
+                                _stream(stream), C.byref(best), C.byref(us))
+    return _tuned(rc, "wm_autotune_apps", best, us)
 
 
 def autotune_batched(descs, measured, p0s, opts_list, stream=None) -> dict:
