@@ -206,6 +206,28 @@ def segments_leg(wm, synth, args, dev, tuned):
             "bytes_per_row": SEG_ROW_BYTES, "bytes_per_app": APP_BYTES}
 
 
+def hardware_model_leg(wm, log):
+    """Re-times the held-out validation kernels of the shipped MI355X
+    parameter file on this GPU and scores the model with that file's
+    microbenchmark and calibrated parameters, and the naive roofline."""
+    from paper_2605_04178_amd import microbench as mb, recalibrate as rc
+    path = os.path.join(ROOT, "paper_2605_04178_amd", "params", "mi355x.json")
+    rec = json.load(open(path))
+    names = {c["name"] for c in rec["cases"] if c["split"] == "hold"}
+    cases = [c for c in mb.case_list() if c.name in names]
+    mb.run_cases(cases, launches=5, log=lambda *a: None)
+    meas = np.array([c.seconds for c in cases])
+    out = {"cases": len(cases), "params": "paper_2605_04178_amd/params/mi355x.json"}
+    for which in ("microbench", "calibrated"):
+        T, _ = rc.predict(wm, rc.load_params(path, which), cases)
+        out[f"mae_{which}"] = mb.mae(T, meas)
+    out["mae_roofline"] = mb.mae(mb.roofline_naive(cases), meas)
+    out["mae_recorded"] = rec["mae"]["calibrated_holdout"]
+    log(f"hardware model on held-out kernels: MAE calibrated {out['mae_calibrated']:.3f}, "
+        f"microbench {out['mae_microbench']:.3f}, roofline {out['mae_roofline']:.3f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +413,7 @@ def main():
         del descs, meas_l
 
         res["segments"] = segments_leg(wm, synth, args, dev, tuned)
+        res["mi355x_model"] = hardware_model_leg(wm, log)
 
     if tuned:
         res["autotune_us"] = {k: v["us"] for k, v in tuned.items()}

@@ -1,4 +1,4 @@
-"""Build libwavemodel.so (HIP for gfx950) in-tree with hipcc.
+"""Build libwavemodel.so and libwmbench.so (HIP for gfx950) in-tree with hipcc.
 
 Usage: python -m paper_2605_04178_amd.build  (or build() from Python).
 """
@@ -20,10 +20,14 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=None) -> str:
+BENCH_OUT = os.path.join(HERE, "libwmbench.so")
+BENCH_SOURCES = ["wm_microbench.hip"]
+
+
+def _hipcc(out, sources, verbose, extra):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc] + FLAGS + list(extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = out + ".tmp"
+    cmd = [hipcc] + FLAGS + list(extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -33,7 +37,14 @@ def build(verbose: bool = False, extra=None) -> str:
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out)
-    os.replace(tmp, OUT)
+    return tmp
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    """Compile libwavemodel.so (the model) and libwmbench.so (microbenchmarks
+    and validation kernels)."""
+    os.replace(_hipcc(OUT, SOURCES, verbose, extra), OUT)
+    os.replace(_hipcc(BENCH_OUT, BENCH_SOURCES, verbose, extra), BENCH_OUT)
     return OUT
 
 

@@ -1,0 +1,145 @@
+"""Recalibrate the wavefront-centric model on this GPU and score it.
+
+    python -m paper_2605_04178_amd.recalibrate --out results.json [--quick]
+
+Steps (Section IV-D workflow, Section V-A scoring):
+ 1. microbenchmarks -> first-principles parameter set (microbench.derive_params);
+ 2. validation kernels with known flops and bytes, timed;
+ 3. predictions of the model (wm_predict on the GPU) with those parameters,
+    and of the naive roofline with datasheet peaks; mean absolute relative
+    error (MAE) of each against the measured times;
+ 4. calibration (wm_calibrate: Adam on log theta over the mean relative
+    error) on a training split of the validation kernels, MAE on the
+    held-out split, before and after.
+Writes every raw number to --out as JSON and prints a summary.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import microbench as mb
+from . import synth
+
+# slots the validation kernels inform: L1-HBM bandwidths and latencies, the
+# FP32 and BF16 peaks, launch, dispatch and barrier costs, h_LLC exponents
+FIT_SLOTS = (0, 1, 2, 3, 4, 5, 6, 7, 9, 10, 13, 14, 15, 20, 21)
+FIT_MASK = sum(1 << j for j in FIT_SLOTS)
+
+
+def predict(wm, p, cases):
+    import torch
+    d = mb.descriptors_of(cases)
+    dd = wm.DeviceDescriptors.from_host(d)
+    T, occ = wm.predict(dd, p)
+    torch.cuda.synchronize()
+    return T.cpu().numpy().astype(np.float64), occ.cpu().numpy()
+
+
+def calibrate(wm, p0, cases, steps=2000, lr=0.02):
+    import torch
+    d = mb.descriptors_of(cases)
+    dd = wm.DeviceDescriptors.from_host(d)
+    m = torch.tensor([c.seconds for c in cases], dtype=torch.float32, device="cuda")
+    mask = FIT_MASK & ~sum(1 << j for j in range(24) if not p0.theta[j] > 0.0)
+    rc, th, hist = wm.calibrate(dd, m, p0, steps=steps, lr=lr, lr_final=1e-3, free_mask=mask)
+    return rc, p0.copy(theta=[float(x) for x in th]), hist, mask
+
+
+def params_record(res: dict) -> dict:
+    """The shipped parameter file: structure, both theta vectors, the
+    transfer model, the scores and the per-kernel table of a run."""
+    keep = ("name", "kind", "n", "iters", "F", "B", "r1", "r2", "K", "W", "dtype", "grid", "vgpr",
+            "lds", "block", "seconds", "pred_microbench", "pred_calibrated", "pred_roofline", "split")
+    return {
+        "device": res["device"],
+        "struct": res["struct"],
+        "theta_microbench": res["theta_microbench"],
+        "theta_calibrated": res["theta_calibrated"],
+        "calibration": res["calibration"],
+        "copy_model": {k: {"bw": v[0], "tau": v[1]} for k, v in res["copy_model"].items()},
+        "peaks_measured": res["microbench"]["peak"],
+        "mae": res["mae"],
+        "cases": [{k: c[k] for k in keep} for c in res["cases"]],
+        "command": "python -m paper_2605_04178_amd.recalibrate --out <raw.json> --params-out <this file>",
+    }
+
+
+def load_params(path: str, which: str = "calibrated") -> "synth.ParamSet":
+    """Parameter set from a file written by params_record (which =
+    'calibrated' or 'microbench')."""
+    rec = json.load(open(path))
+    return synth.ParamSet(**rec["struct"], theta=list(rec["theta_" + which]))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True, help="raw results (JSON)")
+    ap.add_argument("--params-out", default=None, help="parameter file to write (JSON)")
+    ap.add_argument("--from-raw", default=None,
+                    help="write --params-out from an earlier raw results file; no GPU work")
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--steps", type=int, default=2000)
+    args = ap.parse_args(argv)
+    if args.from_raw:
+        res = json.load(open(args.from_raw))
+        with open(args.params_out, "w") as f:
+            json.dump(params_record(res), f, indent=1)
+        return 0
+    from . import wavemodel as wm
+    wm.lib()
+    log = lambda *a: print(*a, flush=True)
+    t0 = time.time()
+    meas = mb.measure(quick=args.quick, log=log)
+    p_mb = mb.derive_params(meas)
+    log("derived theta:", [f"{x:.4g}" for x in p_mb.theta])
+    cases = mb.run_cases(mb.case_list(args.quick), log=log)
+    meas_t = np.array([c.seconds for c in cases])
+    T_mb, occ = predict(wm, p_mb, cases)
+    T_roof = mb.roofline_naive(cases)
+    train, hold = mb.split(cases)
+    idx_t = [cases.index(c) for c in train]
+    idx_h = [cases.index(c) for c in hold]
+    rc, p_cal, hist, mask = calibrate(wm, p_mb, train, steps=args.steps)
+    T_cal, _ = predict(wm, p_cal, cases)
+    res = {
+        "device": meas["device"],
+        "microbench": meas,
+        "copy_model": mb.copy_model(meas),
+        "theta_microbench": list(p_mb.theta),
+        "theta_calibrated": list(p_cal.theta),
+        "calibration": {"status": rc, "free_mask": mask, "steps": args.steps,
+                        "loss_first_last": [float(hist[0]), float(hist[-1])]},
+        "struct": {k: getattr(p_mb, k) for k in mb.MI355X_STRUCT},
+        "cases": [dict(dataclasses.asdict(c), pred_microbench=float(T_mb[i]), pred_calibrated=float(T_cal[i]),
+                       pred_roofline=float(T_roof[i]), occ=int(occ[i]), split="hold" if i in idx_h else "train")
+                  for i, c in enumerate(cases)],
+        "mae": {
+            "roofline_all": mb.mae(T_roof, meas_t),
+            "microbench_all": mb.mae(T_mb, meas_t),
+            "roofline_holdout": mb.mae(T_roof[idx_h], meas_t[idx_h]),
+            "microbench_holdout": mb.mae(T_mb[idx_h], meas_t[idx_h]),
+            "calibrated_train": mb.mae(T_cal[idx_t], meas_t[idx_t]),
+            "calibrated_holdout": mb.mae(T_cal[idx_h], meas_t[idx_h]),
+        },
+        "seconds": time.time() - t0,
+    }
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1, default=float)
+    if args.params_out:
+        with open(args.params_out, "w") as f:
+            json.dump(params_record(json.loads(json.dumps(res, default=float))), f, indent=1)
+    log("MAE:", json.dumps(res["mae"]))
+    for i, c in enumerate(cases):
+        log(f"{c.name:24s} meas {c.seconds * 1e6:10.1f} us  model {T_mb[i] * 1e6:10.1f}  "
+            f"cal {T_cal[i] * 1e6:10.1f}  roof {T_roof[i] * 1e6:10.1f}  [{'hold' if i in idx_h else 'train'}]")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
