@@ -186,3 +186,17 @@ def test_wmbench_argument_checks_without_a_gpu():
     assert L.wmb_val_run(mb.VAL["triad"], C.c_void_p(0x1000), 4096, None, 0, C.c_void_p(0x2000), 4096,
                          1024, 0, 1, None, C.byref(d), C.byref(g)) == -1
     assert L.wmb_last_hip_error() == 0
+
+
+def test_wmbench_exports_every_declared_symbol():
+    import os
+    import re
+    import subprocess
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                       "wm_microbench.h")
+    src = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+    declared = set(re.findall(r"\b(wmb_[a-z_]+)\s*\(", src))
+    assert {"wmb_read_bw", "wmb_chase", "wmb_peak", "wmb_empty", "wmb_val_run"} <= declared
+    out = subprocess.run(["nm", "-D", "--defined-only", mb.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    assert declared <= set(re.findall(r"\s[TW]\s+(wmb_\w+)", out))
