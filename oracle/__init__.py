@@ -308,3 +308,71 @@ def apps_loss_grad(p, q, d, sg, measured):
     _seg_lib().orc_apps_loss_grad(C.byref(params(p)), C.byref(segp(q)), C.byref(o), C.byref(so),
                                   m.ctypes.data, out.ctypes.data)
     return float(out[0]), int(out[1]), out[2:2 + N_THETA].copy(), out[2 + N_THETA:].copy()
+
+
+# ----------------------------------------------------------------------------
+# calibration multipliers and fusion planning
+# ----------------------------------------------------------------------------
+class OrcFDesc(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("F", "B", "r1", "r2", "r3", "K", "u", "W")] + [
+        (n, C.c_int64) for n in ("v", "s", "gpack", "G")]
+
+
+def _plan_lib():
+    L = lib()
+    if not hasattr(L, "_plan_ready"):
+        P, D = C.POINTER(OrcParams), C.POINTER(OrcDesc)
+        vp = C.c_void_p
+        L.orc_fit_multipliers.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp, vp]
+        L.orc_fuse.argtypes = [P, D, vp, C.c_int64, C.c_int64, C.POINTER(OrcFDesc)]
+        L.orc_fuse.restype = C.c_int
+        L.orc_fused_cost.argtypes = [P, D, vp, C.c_int64, C.c_int64]
+        L.orc_fused_cost.restype = C.c_double
+        L.orc_plan_fusion.argtypes = [P, D, vp, vp, C.c_int64, C.c_int32, vp, vp, vp]
+        L._plan_ready = True
+    return L
+
+
+def fit_multipliers(T, m, off, train):
+    """(mult [n_groups], T_scaled [n], (train loss sum, train count, holdout
+    loss sum, holdout count))."""
+    T = np.ascontiguousarray(T, np.float64)
+    m = np.ascontiguousarray(m, np.float64)
+    off = np.ascontiguousarray(off, np.int32)
+    tr = np.ascontiguousarray(train, np.uint8)
+    ng = off.shape[0] - 1
+    mult = np.empty(max(ng, 1), np.float64)
+    Ts = np.empty(max(T.shape[0], 1), np.float64)
+    st = np.zeros(4)
+    _plan_lib().orc_fit_multipliers(T.ctypes.data, m.ctypes.data, off.ctypes.data, ng, tr.ctypes.data,
+                                    mult.ctypes.data, Ts.ctypes.data, st.ctypes.data)
+    return mult[:ng], Ts[:T.shape[0]], tuple(st)
+
+
+def fuse(p, d, edge, a, length):
+    """(ok, dict of the fused descriptor's fields)."""
+    o, keep = _desc(d)
+    e = np.ascontiguousarray(edge, np.float32)
+    f = OrcFDesc()
+    ok = _plan_lib().orc_fuse(C.byref(params(p)), C.byref(o), e.ctypes.data, int(a), int(length), C.byref(f))
+    return bool(ok), {n: getattr(f, n) for n, _ in OrcFDesc._fields_}
+
+
+def fused_cost(p, d, edge, a, length):
+    o, keep = _desc(d)
+    e = np.ascontiguousarray(edge, np.float32)
+    return _plan_lib().orc_fused_cost(C.byref(params(p)), C.byref(o), e.ctypes.data, int(a), int(length))
+
+
+def plan_fusion(p, d, edge, off, R):
+    """(total [n_chains], unfused [n_chains], start uint8 [n])."""
+    o, keep = _desc(d)
+    e = np.ascontiguousarray(edge, np.float32)
+    off = np.ascontiguousarray(off, np.int32)
+    nc = off.shape[0] - 1
+    tot = np.empty(max(nc, 1))
+    unf = np.empty(max(nc, 1))
+    st = np.zeros(max(o.n, 1), np.uint8)
+    _plan_lib().orc_plan_fusion(C.byref(params(p)), C.byref(o), e.ctypes.data, off.ctypes.data, nc, int(R),
+                                tot.ctypes.data, unf.ctypes.data, st.ctypes.data)
+    return tot[:nc], unf[:nc], st[:o.n]

@@ -732,3 +732,207 @@ void orc_apps_loss_grad(const orc_params_t *p, const orc_segp_t *q, const orc_de
         for (int j = 2; j < NO; ++j) out[j] /= out[1];
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* per-group calibration multipliers (Section IV-D optional per-case    */
+/* multipliers with train/holdout separation; Section V-B m_case)       */
+/* ------------------------------------------------------------------ */
+typedef struct { double x, w; int64_t i; } orc_xw_t;
+
+static int cmp_xw(const void *a, const void *b)
+{
+    const orc_xw_t *p = (const orc_xw_t *)a, *q = (const orc_xw_t *)b;
+    if (p->x < q->x) return -1;
+    if (p->x > q->x) return 1;
+    return p->i < q->i ? -1 : (p->i > q->i ? 1 : 0);
+}
+
+static int mult_row_ok(double T, double m)
+{
+    return isfinite(T) && T > 0.0 && isfinite(m) && m > 0.0;
+}
+
+/*
+ * Group g owns rows [off[g], off[g+1]).  Its multiplier minimises the
+ * training mean relative error sum_i |mult * T_i - m_i| / m_i over its
+ * valid training rows (T_i, m_i finite and > 0, train_i != 0): writing
+ * x_i = m_i / T_i and w_i = T_i / m_i the objective is sum_i w_i |mult - x_i|,
+ * minimised by a weighted median of the x_i -- the smallest x_k (ascending
+ * x, then row index) whose cumulative weight reaches half the total.
+ * Groups without a valid training row keep mult = 1.  T_scaled[i] =
+ * mult[g] * T_i for every row; stats: training loss sum, training count,
+ * held-out loss sum, held-out count over valid rows.
+ */
+void orc_fit_multipliers(const double *T, const double *m, const int32_t *off, int64_t n_groups,
+                         const uint8_t *train, double *mult, double *T_scaled, double *stats)
+{
+    stats[0] = stats[1] = stats[2] = stats[3] = 0.0;
+    for (int64_t g = 0; g < n_groups; ++g) {
+        int64_t a = off[g], b = off[g + 1];
+        orc_xw_t *buf = (orc_xw_t *)malloc(sizeof(orc_xw_t) * (size_t)(b > a ? b - a : 1));
+        int64_t k = 0;
+        double W = 0.0;
+        for (int64_t i = a; i < b; ++i) {
+            if (!train[i] || !mult_row_ok(T[i], m[i])) continue;
+            buf[k].x = m[i] / T[i];
+            buf[k].w = T[i] / m[i];
+            buf[k].i = i;
+            ++k;
+        }
+        double mu = 1.0;
+        if (k > 0) {
+            qsort(buf, (size_t)k, sizeof(orc_xw_t), cmp_xw);
+            for (int64_t j = 0; j < k; ++j) W += buf[j].w;
+            double c = 0.0;
+            for (int64_t j = 0; j < k; ++j) {
+                c += buf[j].w;
+                if (c >= 0.5 * W) { mu = buf[j].x; break; }
+            }
+        }
+        free(buf);
+        mult[g] = mu;
+        for (int64_t i = a; i < b; ++i) {
+            T_scaled[i] = mu * T[i];
+            if (!mult_row_ok(T[i], m[i])) continue;
+            double e = fabs(mu * T[i] - m[i]) / m[i];
+            if (train[i]) { stats[0] += e; stats[1] += 1.0; }
+            else { stats[2] += e; stats[3] += 1.0; }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* kernel-fusion planning (Section IV-B: a fused kernel is modelled with */
+/* the combined flops and bytes plus tau_fusion)                         */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double F, B, r1, r2, r3, K, u, W;
+    int64_t v, s, gpack, G;
+} orc_fdesc_t;
+
+/*
+ * The descriptor of rows a .. a+len-1 of one chain run as one kernel
+ * (len = 1: the row itself).  edge[k] = bytes row k hands to row k+1 (written
+ * by k, read by k+1), which a fused kernel keeps on chip:
+ *   F = sum F_k;  B = max(sum B_k - 2 sum edges, 0);
+ *   r_l = sum r_l,k B_k / sum B_k (0 when sum B_k = 0);
+ *   K = sum K_k;  W = max(sum W_k - sum edges, 0);
+ *   dtype of the first row with the largest F_k;  u such that the fused
+ *   compute time F / (u P_dtype) equals the sum of the rows' F_k / (u_k
+ *   P_dtype_k), capped at 1 (1 when F = 0);
+ *   VGPRs, LDS, workgroup size, grid, concurrent kernels and devices: the
+ *   largest;  host syncs: the sum (at most 15);  fused flag set.
+ * Returns 0 if a row or an edge is invalid.
+ */
+int orc_fuse(const orc_params_t *p, const orc_desc_t *d, const float *edge, int64_t a,
+             int64_t len, orc_fdesc_t *o)
+{
+    memset(o, 0, sizeof(*o));
+    for (int64_t k = a; k < a + len; ++k) {
+        if (!desc_valid(DESC_ARGS(d, k))) return 0;
+        if (k < a + len - 1 && !(isfinite((double)edge[k]) && edge[k] >= 0.0f)) return 0;
+    }
+    if (len == 1) {
+        o->F = d->F[a]; o->B = d->B[a]; o->r1 = d->r1[a]; o->r2 = d->r2[a]; o->r3 = d->r3[a];
+        o->K = d->K[a]; o->u = d->u[a]; o->W = d->W[a];
+        o->v = d->vgpr[a]; o->s = d->lds[a]; o->gpack = d->gpack[a]; o->G = d->grid[a];
+        return 1;
+    }
+    double F = 0, Bs = 0, E = 0, r1 = 0, r2 = 0, r3 = 0, K = 0, Ws = 0, tc = 0, Fmax = -1.0;
+    int64_t v = 0, s = 0, g = 0, G = 0, nc = 0, nd = 0, ns = 0, dt = 0;
+    for (int64_t k = a; k < a + len; ++k) {
+        const double Fk = d->F[k], Bk = d->B[k];
+        const int64_t gp = d->gpack[k];
+        const int64_t dtk = (gp >> 11) & 7;
+        F += Fk;
+        Bs += Bk;
+        r1 += (double)d->r1[k] * Bk;
+        r2 += (double)d->r2[k] * Bk;
+        r3 += (double)d->r3[k] * Bk;
+        K += d->K[k];
+        Ws += d->W[k];
+        if (Fk > 0.0) tc += Fk / ((double)d->u[k] * p->theta[8 + dtk]);
+        if (Fk > Fmax) { Fmax = Fk; dt = dtk; }
+        if (k < a + len - 1) E += edge[k];
+        v = d->vgpr[k] > v ? d->vgpr[k] : v;
+        s = d->lds[k] > s ? d->lds[k] : s;
+        g = (gp & 2047) > g ? (gp & 2047) : g;
+        G = d->grid[k] > G ? d->grid[k] : G;
+        nc = ((gp >> 14) & 7) > nc ? ((gp >> 14) & 7) : nc;
+        nd = ((gp >> 17) & 7) > nd ? ((gp >> 17) & 7) : nd;
+        ns += (gp >> 21) & 15;
+    }
+    o->F = F;
+    o->B = Bs - 2.0 * E > 0.0 ? Bs - 2.0 * E : 0.0;
+    o->r1 = Bs > 0.0 ? r1 / Bs : 0.0;
+    o->r2 = Bs > 0.0 ? r2 / Bs : 0.0;
+    o->r3 = Bs > 0.0 ? r3 / Bs : 0.0;
+    o->K = K;
+    o->W = Ws - E > 0.0 ? Ws - E : 0.0;
+    if (F > 0.0) {
+        double u = F / (p->theta[8 + dt] * tc);
+        o->u = u < 1.0 ? u : 1.0;
+    } else {
+        o->u = 1.0;
+    }
+    o->v = v; o->s = s; o->G = G;
+    ns = ns < 15 ? ns : 15;
+    o->gpack = g | (dt << 11) | (nc << 14) | (nd << 17) | ((int64_t)1 << 20) | (ns << 21);
+    return 1;
+}
+
+/* Modelled time of rows a .. a+len-1 run as one kernel; NaN if invalid. */
+double orc_fused_cost(const orc_params_t *p, const orc_desc_t *d, const float *edge, int64_t a,
+                      int64_t len)
+{
+    orc_fdesc_t f;
+    if (!orc_fuse(p, d, edge, a, len, &f)) return NAN;
+    orc_trace_t tr;
+    orc_eval(p, f.F, f.B, f.r1, f.r2, f.r3, f.K, f.u, f.W, f.v, f.s, f.gpack, f.G, &tr, NULL);
+    return tr.T;
+}
+
+/*
+ * Chain c owns rows [off[c], off[c+1]) in execution order.  A plan cuts the
+ * chain into runs of 1 .. R consecutive rows, each run one kernel; its cost
+ * is the sum of the runs' modelled times (NaN counts as +inf).  Dynamic
+ * programming over the prefix: best[j] = min over run lengths L (1 .. R,
+ * shortest first, strict improvement) of best[j - L] + cost(run of the L
+ * rows ending at j).  total[c] = best over the whole chain (+inf if no plan
+ * is finite), unfused[c] = the all-singles plan, start[i] = 1 where a run of
+ * the chosen plan begins.
+ */
+void orc_plan_fusion(const orc_params_t *p, const orc_desc_t *d, const float *edge,
+                     const int32_t *off, int64_t n_chains, int32_t R, double *total,
+                     double *unfused, uint8_t *start)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < n_chains; ++c) {
+        int64_t a = off[c], n = off[c + 1] - off[c];
+        double *best = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+        int64_t *cut = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        best[0] = 0.0;
+        double single = 0.0;
+        for (int64_t j = 1; j <= n; ++j) {
+            best[j] = INFINITY;
+            cut[j] = 1;
+            for (int64_t L = 1; L <= R && L <= j; ++L) {
+                double t = orc_fused_cost(p, d, edge, a + j - L, L);
+                if (!(t == t)) t = INFINITY;
+                if (L == 1) single += t;
+                double v = best[j - L] + t;
+                if (v < best[j]) { best[j] = v; cut[j] = L; }
+            }
+        }
+        total[c] = best[n];
+        unfused[c] = single;
+        for (int64_t i = a; i < a + n; ++i) start[i] = 0;
+        int64_t j = n;
+        while (j > 0) {
+            start[a + j - cut[j]] = 1;
+            j -= cut[j];
+        }
+        free(best);
+        free(cut);
+    }
+}

@@ -395,3 +395,47 @@ def segments(n_apps: int, seed: int = 120, smin: int = 1, smax: int = 12):
     # kernels of a running application launch: VGPRs/thread U-int[16, 128]
     d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
     return sg, d
+
+
+# ---------------------------------------------------------------------------
+# kernel chains for fusion planning; grouped measurements for multipliers
+# ---------------------------------------------------------------------------
+def chains(n_chains: int, seed: int = 160, lmin: int = 2, lmax: int = 16):
+    """Chains of U-int[lmin, lmax] kernels executed in order (the operator
+    sequences a fusion pass looks at).  Returns (offsets int32 [n_chains + 1],
+    descriptors, edge float32 [n]): each row's descriptor is drawn as in
+    descriptors() with VGPRs U-int[16, 128]; edge[i] = bytes row i hands to
+    row i + 1, U(0.05, 0.45) x min(B_i, B_i+1) (0 on a chain's last row)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cnt = rng.integers(lmin, lmax + 1, n_chains)
+    off = np.zeros(n_chains + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    n = int(off[-1])
+    d = descriptors(n, seed + 1)
+    d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
+    nxtB = np.concatenate([d.B[1:], np.zeros(1, np.float32)]).astype(np.float64)
+    edge = rng.uniform(0.05, 0.45, n) * np.minimum(d.B.astype(np.float64), nxtB)
+    last = np.zeros(n, bool)
+    last[off[1:] - 1] = True
+    edge[last] = 0.0
+    return off.astype(np.int32), d, edge.astype(np.float32)
+
+
+def grouped_measurements(n_groups: int, seed: int = 170, gmin: int = 1, gmax: int = 40,
+                         sigma: float = 0.05, holdout: float = 1.0 / 3.0):
+    """Cases grouped for per-case multipliers: U-int[gmin, gmax] rows per
+    group; each group's true factor log-U[0.5, 2]; returns (offsets int32
+    [n_groups + 1], factor [n_groups], noise [n] (exp(sigma z)), train uint8 [n]
+    with each row held out with probability `holdout`), plus descriptors for
+    the rows.  Measured times are factor x T x noise for the caller's T."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cnt = rng.integers(gmin, gmax + 1, n_groups)
+    off = np.zeros(n_groups + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    n = int(off[-1])
+    factor = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_groups))
+    noise = np.exp(sigma * rng.standard_normal(n))
+    train = (rng.random(n) >= holdout).astype(np.uint8)
+    d = descriptors(n, seed + 1)
+    d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
+    return off.astype(np.int32), factor, noise, train, d
