@@ -177,7 +177,9 @@ int32_t wm_validate_params(const wm_params_t *params);
  *      in total, plus the work list.
  *  WM_OP_PREDICT_APPS: 0.
  *  WM_OP_APPS_LOSS_GRAD: 0 here; its size depends on the application count
- *      too: use wm_apps_workspace_bytes(). */
+ *      too: use wm_apps_workspace_bytes().
+ *  WM_OP_FIT_MULTIPLIERS: a fixed block of per-wave partial sums (any n).
+ *  Fusion planning: use wm_plan_workspace_bytes(). */
 #define WM_OP_PREDICT 0
 #define WM_OP_ROOFLINE 1
 #define WM_OP_VJP 2
@@ -187,6 +189,7 @@ int32_t wm_validate_params(const wm_params_t *params);
 #define WM_OP_CALIBRATE_BATCHED 6
 #define WM_OP_PREDICT_APPS 7
 #define WM_OP_APPS_LOSS_GRAD 8
+#define WM_OP_FIT_MULTIPLIERS 9
 size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps);
 
 /* Workspace bytes of wm_apps_loss_grad for n segment rows in n_apps
@@ -323,6 +326,50 @@ int32_t wm_predict_apps(const wm_desc_t *desc, const wm_segs_t *segs, const wm_p
 int32_t wm_apps_loss_grad(const wm_desc_t *desc, const wm_segs_t *segs, const float *measured,
                           const wm_params_t *params, const wm_segparams_t *segp, double *out,
                           void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Per-group calibration multipliers (Section IV-D: optional per-case
+ * multipliers, fitted with train / holdout separation; Section V-B: m_case).
+ * Group g owns rows [group_off[g], group_off[g+1]) of n rows (CSR,
+ * non-decreasing, group_off[n_groups] = n; offsets are clamped into [0, n]).
+ * Over the group's valid training rows (T and measured finite and > 0,
+ * train != 0) the multiplier minimises sum |mult * T - m| / m: a weighted
+ * median of m/T with weights T/m -- the smallest ratio (ties: lowest row)
+ * whose cumulative weight reaches half the total.  Groups without a valid
+ * training row get 1.  Outputs (device): mult [n_groups] float64, T_scaled
+ * [n] float32 = mult * T, stats [4] float64 = training error sum, training
+ * rows, held-out error sum, held-out rows.  Ratios and weights are float64;
+ * cumulative weights are summed in row order, so a multiplier can differ from
+ * a sort-based one only where two candidates' objectives tie to rounding.
+ * Cost O(s^2 / 64) per group of s rows (one wave per group).
+ * Workspace: wm_workspace_bytes(WM_OP_FIT_MULTIPLIERS, n, 1, 0).
+ */
+int32_t wm_fit_multipliers(const float *T, const float *measured, const int32_t *group_off,
+                           int64_t n_groups, int64_t n, const uint8_t *train, double *mult,
+                           float *T_scaled, double *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Kernel-fusion planning (Section IV-B: a fused kernel is modelled with the
+ * combined flops and bytes plus tau_fusion).  Chain c owns descriptor rows
+ * [chain_off[c], chain_off[c+1]) in execution order (CSR, clamped like the
+ * other offsets); edge [n] float32: bytes row i hands to row i + 1 (read only
+ * inside a chain).  A plan cuts each chain into runs of 1 .. R (<= 32)
+ * consecutive kernels, each run modelled as one kernel whose descriptor
+ * combines the rows: flops, steps and host syncs add; bytes add minus twice
+ * the edges inside the run (intermediates stay on chip); working set adds
+ * minus the edges; hit rates are byte-weighted; u keeps the summed compute
+ * time at the dtype of the largest-flop row (capped at 1); VGPRs, LDS,
+ * workgroup size, grid and concurrency take the maximum; the fused flag adds
+ * tau_fusion.  Costs are float64 (+inf for invalid runs); the optimal plan
+ * comes from the prefix dynamic programme (shortest run first on ties).
+ * Outputs (device): total [n_chains] and unfused [n_chains] float64 (the
+ * optimal and the all-singles sums), start [n] uint8 = 1 where a run of the
+ * optimal plan begins.  Workspace: wm_plan_workspace_bytes(n, R).
+ */
+size_t wm_plan_workspace_bytes(int64_t n, int32_t R);
+int32_t wm_plan_fusion(const wm_desc_t *desc, const float *edge, const int32_t *chain_off,
+                       int64_t n_chains, int32_t R, const wm_params_t *params, double *total,
+                       double *unfused, uint8_t *start, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- launch configurations and autotuning ----
  *

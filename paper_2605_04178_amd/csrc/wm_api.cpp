@@ -241,6 +241,28 @@ SegPtrs segptrs_of(const wm_segs_t* s)
     return p;
 }
 
+// fusion-planning workspace: candidate costs, prefix optima, run lengths
+struct PlanWs {
+    size_t cost, best, cut, total;
+};
+
+PlanWs plan_ws(int64_t n, int32_t R)
+{
+    PlanWs W;
+    size_t off = 0;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    W.cost = off;
+    off += up256(sizeof(double) * nn * (size_t)R);
+    W.best = off;
+    off += up256(sizeof(double) * nn);
+    W.cut = off;
+    off += up256(nn);
+    W.total = off;
+    return W;
+}
+
+constexpr size_t kFitMultWs = sizeof(double) * 4 * 4 * (size_t)kFitMultMaxBlocks;
+
 // calibration workspace layout
 // gradient-sweep workspace: partial rows, then redo-flag words
 struct GradWs {
@@ -680,9 +702,49 @@ size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps)
     case WM_OP_CALIBRATE_BATCHED:
         if (steps < 1 || n_sets < 1 || n_sets > kMaxSets) return 0;
         return batch_layout(n, n_sets, steps).total;
+    case WM_OP_FIT_MULTIPLIERS:
+        return kFitMultWs;
     default:
         return 0;
     }
+}
+
+size_t wm_plan_workspace_bytes(int64_t n, int32_t R)
+{
+    if (n < 0 || R < 1 || R > kPlanMaxRun) return 0;
+    return plan_ws(n, R).total;
+}
+
+int32_t wm_fit_multipliers(const float* T, const float* measured, const int32_t* group_off,
+                           int64_t n_groups, int64_t n, const uint8_t* train, double* mult,
+                           float* T_scaled, double* stats, void* ws, size_t ws_bytes, void* stream)
+{
+    if (n < 0 || n_groups < 0 || !stats) return WM_EINVAL;
+    if (n > 0 && (!T || !measured || !train || !T_scaled)) return WM_EINVAL;
+    if (n_groups > 0 && (!group_off || !mult)) return WM_EINVAL;
+    if (!ws_ok(ws, ws_bytes, kFitMultWs)) return WM_EWORKSPACE;
+    WM_HIP(launch_fit_multipliers(T, measured, group_off, n_groups, n, train, mult, T_scaled,
+                                  (double*)ws, stats, (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_plan_fusion(const wm_desc_t* desc, const float* edge, const int32_t* chain_off,
+                       int64_t n_chains, int32_t R, const wm_params_t* params, double* total,
+                       double* unfused, uint8_t* start, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params) || n_chains < 0 || R < 1 || R > kPlanMaxRun)
+        return WM_EINVAL;
+    if (n_chains == 0) return WM_OK;
+    if (!chain_off || !total || !unfused) return WM_EINVAL;
+    if (desc->n > 0 && (!edge || !start)) return WM_EINVAL;
+    const PlanWs W = plan_ws(desc->n, R);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    char* base = (char*)ws;
+    const Set S = make_set(params);
+    WM_HIP(launch_plan_fusion(ptrs_of(desc), edge, chain_off, n_chains, desc->n, R, S,
+                              params->theta + 8, (double*)(base + W.cost), (double*)(base + W.best),
+                              (uint8_t*)(base + W.cut), total, unfused, start, (hipStream_t)stream));
+    return WM_OK;
 }
 
 size_t wm_apps_workspace_bytes(int64_t n, int64_t n_apps)

@@ -64,6 +64,8 @@ constexpr int kSegParams = 7;                 // kappa[4], bw_h2d, bw_d2h, tau_m
 constexpr int kAppAcc = 10;                   // loss, count, T_launch, kappa[4], h2d, d2h, tau sums
 constexpr int kAppsOut = kAcc + kSegParams;   // loss, count, grad theta[24], grad seg params[7]
 constexpr int kAppsMaxBlocks = 4096;          // partial-row cap of the application sweep
+constexpr int kFitMultMaxBlocks = 1024;       // multiplier sweep: rows = 4 x blocks
+constexpr int kPlanMaxRun = 32;               // longest fused run
 
 struct ShapePtrs {
     const int32_t *M, *N, *K, *dtype;
@@ -142,6 +144,17 @@ hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n
                                  double* partials, uint64_t* flags, const GradLayout& L,
                                  const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
                                  hipStream_t stream);
+// Per-group weighted-median multipliers; rows: 4 x kFitMultMaxBlocks x 4
+// doubles of workspace; stats [4] float64 device.
+hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32_t* off,
+                                  int64_t n_groups, int64_t n, const uint8_t* train, double* mult,
+                                  float* T_scaled, double* rows, double* stats, hipStream_t s);
+// Fusion plans of chains over n descriptor rows; cost (n x R doubles),
+// best (n doubles) and cut (n bytes) are workspace.
+hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_t* off,
+                              int64_t n_chains, int64_t n, int32_t R, const Set& S,
+                              const double* peaks, double* cost, double* best, uint8_t* cut,
+                              double* total, double* unfused, uint8_t* start, hipStream_t s);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
                               double* best_cost, uint8_t* near_tie, const LaunchCfg& cfg,

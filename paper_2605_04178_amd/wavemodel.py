@@ -21,7 +21,7 @@ N_THETA = 24
 
 WM_OK, WM_EINVAL, WM_EWORKSPACE, WM_EHIP, WM_EDIVERGED = 0, -1, -2, -3, -4
 (OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_CALIBRATE_BATCHED,
- OP_PREDICT_APPS, OP_APPS_LOSS_GRAD) = range(9)
+ OP_PREDICT_APPS, OP_APPS_LOSS_GRAD, OP_FIT_MULTIPLIERS) = range(10)
 N_SEGPARAMS = 7
 
 EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_workspace_bytes",
@@ -29,7 +29,7 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_calibrate", "wm_calibrate_batched", "wm_get_launch", "wm_set_launch",
             "wm_autotune_predict", "wm_autotune_grad", "wm_autotune_select_tile",
             "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad",
-            "wm_autotune_apps")
+            "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion")
 
 
 class WmError(RuntimeError):
@@ -139,6 +139,12 @@ def lib():
         L.wm_apps_loss_grad.restype = i32
         L.wm_autotune_apps.argtypes = [i32, D, SG, vp, P, SP, vp, vp, vp, sz, vp, LP, dp]
         L.wm_autotune_apps.restype = i32
+        L.wm_fit_multipliers.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]
+        L.wm_fit_multipliers.restype = i32
+        L.wm_plan_workspace_bytes.argtypes = [i64, i32]
+        L.wm_plan_workspace_bytes.restype = sz
+        L.wm_plan_fusion.argtypes = [D, vp, vp, i64, i32, P, vp, vp, vp, vp, sz, vp]
+        L.wm_plan_fusion.restype = i32
         _lib = L
     return _lib
 
@@ -401,6 +407,51 @@ def apps_loss_grad(desc: DeviceDescriptors, segs: DeviceSegments, measured: torc
                                  _ptr(out), _ptr(ws), nb, _stream(stream))
     _check(rc, "wm_apps_loss_grad")
     return out
+
+
+def fit_multipliers(T: torch.Tensor, measured: torch.Tensor, group_off: torch.Tensor,
+                    train: torch.Tensor, ws=None, stream=None):
+    """Per-group weighted-median multipliers on the training rows.  Returns
+    (mult float64 [n_groups], T_scaled float32 [n], stats float64 [4]: training
+    error sum, training rows, held-out error sum, held-out rows) on the device."""
+    dev = T.device
+    n = int(T.numel())
+    ng = int(group_off.numel()) - 1
+    if measured.numel() != n or train.numel() != n or ng < 0:
+        raise ValueError("T, measured and train must have one entry per row; group_off n_groups + 1")
+    mult = torch.empty(max(ng, 1), dtype=torch.float64, device=dev)
+    Ts = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    stats = torch.empty(4, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_FIT_MULTIPLIERS, n), dev)
+    rc = lib().wm_fit_multipliers(_ptr(T), _ptr(measured), _ptr(group_off), ng, n, _ptr(train), _ptr(mult),
+                                  _ptr(Ts), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "wm_fit_multipliers")
+    return mult[:ng], Ts[:n], stats
+
+
+def plan_workspace_bytes(n: int, R: int) -> int:
+    return int(lib().wm_plan_workspace_bytes(n, R))
+
+
+def plan_fusion(desc: DeviceDescriptors, edge: torch.Tensor, chain_off: torch.Tensor, params, R: int = 8,
+                ws=None, stream=None):
+    """Optimal fusion plans: (total float64 [n_chains], unfused float64
+    [n_chains], start uint8 [n]) on the device."""
+    dev = desc.device
+    nc = int(chain_off.numel()) - 1
+    if edge.numel() != desc.n:
+        raise ValueError("edge needs one entry per descriptor row")
+    total = torch.empty(max(nc, 1), dtype=torch.float64, device=dev)
+    unf = torch.empty(max(nc, 1), dtype=torch.float64, device=dev)
+    start = torch.empty(max(desc.n, 1), dtype=torch.uint8, device=dev)
+    if ws is None:
+        ws = _workspace(plan_workspace_bytes(desc.n, R), dev)
+    rc = lib().wm_plan_fusion(C.byref(desc.struct()), _ptr(edge), _ptr(chain_off), nc, int(R),
+                              C.byref(params_struct(params)), _ptr(total), _ptr(unf), _ptr(start), _ptr(ws),
+                              0 if ws is None else ws.numel(), _stream(stream))
+    _check(rc, "wm_plan_fusion")
+    return total[:nc], unf[:nc], start[:desc.n]
 
 
 def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,

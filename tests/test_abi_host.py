@@ -240,6 +240,31 @@ def test_segment_calls_validate_before_any_hip_call(wmb):
     assert L.wm_last_hip_error() == 0
 
 
+def test_planning_calls_validate_before_any_hip_call(wmb):
+    L = wmb.lib()
+    p = wmb.params_struct(synth.param_set(0))
+    d = _fake_desc(wmb, 16)
+    x = C.c_void_p(0x7000)
+    ws = C.c_void_p(0x10000)
+    need = wmb.workspace_bytes(wmb.OP_FIT_MULTIPLIERS, 16)
+    assert need > 0 and need % 256 == 0 and wmb.workspace_bytes(wmb.OP_FIT_MULTIPLIERS, 1 << 30) == need
+    assert L.wm_fit_multipliers(x, x, x, 2, -1, x, x, x, x, ws, need, None) == wmb.WM_EINVAL
+    assert L.wm_fit_multipliers(x, x, x, -1, 16, x, x, x, x, ws, need, None) == wmb.WM_EINVAL
+    assert L.wm_fit_multipliers(None, x, x, 2, 16, x, x, x, x, ws, need, None) == wmb.WM_EINVAL
+    assert L.wm_fit_multipliers(x, x, None, 2, 16, x, x, x, x, ws, need, None) == wmb.WM_EINVAL
+    assert L.wm_fit_multipliers(x, x, x, 2, 16, x, x, x, None, ws, need, None) == wmb.WM_EINVAL
+    assert L.wm_fit_multipliers(x, x, x, 2, 16, x, x, x, x, ws, need - 1, None) == wmb.WM_EWORKSPACE
+    assert wmb.plan_workspace_bytes(16, 0) == 0 and wmb.plan_workspace_bytes(16, 33) == 0
+    pw = wmb.plan_workspace_bytes(16, 8)
+    assert pw > 0 and wmb.plan_workspace_bytes(1 << 20, 8) > pw
+    for R in (0, 33):
+        assert L.wm_plan_fusion(C.byref(d), x, x, 2, R, C.byref(p), x, x, x, ws, 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_plan_fusion(C.byref(d), x, x, 0, 8, C.byref(p), None, None, None, None, 0, None) == wmb.WM_OK
+    assert L.wm_plan_fusion(C.byref(d), None, x, 2, 8, C.byref(p), x, x, x, ws, 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_plan_fusion(C.byref(d), x, x, 2, 8, C.byref(p), x, x, x, ws, pw - 1, None) == wmb.WM_EWORKSPACE
+    assert L.wm_last_hip_error() == 0
+
+
 def test_product_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_2605_04178_amd import wavemodel
     monkeypatch.setattr(wavemodel, "_lib", None)
