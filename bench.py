@@ -152,6 +152,19 @@ def profile_run(wm, synth, dd, p, n, dev):
     torch.cuda.synchronize()
     log("profile: predict_apps x3, apps_loss_grad x3 done")
     del dd2, ds, Ta, meas
+    off, d3, e = synth.chains(1 << 16, 164)
+    dd3 = wm.DeviceDescriptors.from_host(d3, dev)
+    de, doff = torch.from_numpy(e).to(dev), torch.from_numpy(off).to(dev)
+    for _ in range(3):
+        wm.plan_fusion(dd3, de, doff, p, 8)
+    goff, fac, noise, train, d4 = synth.grouped_measurements(1 << 16, 172)
+    T4, _ = wm.predict(wm.DeviceDescriptors.from_host(d4, dev), p, want_occ=False)
+    m4 = (T4 * 1.1).contiguous()
+    for _ in range(3):
+        wm.fit_multipliers(T4, m4, torch.from_numpy(goff).to(dev), torch.from_numpy(train).to(dev))
+    torch.cuda.synchronize()
+    log("profile: plan_fusion x3, fit_multipliers x3 done")
+    del dd3, de, doff, T4, m4
     a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(3):
@@ -206,6 +219,48 @@ def segments_leg(wm, synth, args, dev, tuned):
             "bytes_per_row": SEG_ROW_BYTES, "bytes_per_app": APP_BYTES}
 
 
+def planning_leg(wm, synth, args, dev, log):
+    """Fusion planning over 2^16 synthetic kernel chains (2-16 kernels, runs up
+    to 8) and per-group multipliers over 2^16 groups (1-40 rows)."""
+    import torch
+    p = synth.param_set(0)
+    off, d, e = synth.chains(1 << 16, 164)
+    dd = wm.DeviceDescriptors.from_host(d, dev)
+    de = torch.from_numpy(e).to(dev)
+    doff = torch.from_numpy(off).to(dev)
+    R = 8
+    ws = wm._workspace(wm.plan_workspace_bytes(d.n, R), dev)
+    fp = lambda: wm.plan_fusion(dd, de, doff, p, R, ws=ws)
+    wall_p, ev_p = timed(fp, args.steps, args.warmup)
+    lens = np.diff(off).astype(np.int64)
+    cands = int(sum(min(R, j + 1) for L in lens for j in range(L)))
+    tot, unf, st = fp()
+    gain = float((unf / tot).double().mean().item())
+    goff, fac, noise, train, d2 = synth.grouped_measurements(1 << 16, 172)
+    dd2 = wm.DeviceDescriptors.from_host(d2, dev)
+    T, _ = wm.predict(dd2, p, want_occ=False)
+    g = torch.from_numpy(np.repeat(np.arange(1 << 16), np.diff(goff))).to(dev)
+    meas = (T * torch.from_numpy(fac.astype(np.float32)).to(dev)[g] *
+            torch.from_numpy(noise.astype(np.float32)).to(dev)).contiguous()
+    dgoff = torch.from_numpy(goff).to(dev)
+    dtrain = torch.from_numpy(train).to(dev)
+    ws2 = wm._workspace(wm.workspace_bytes(wm.OP_FIT_MULTIPLIERS, d2.n), dev)
+    fm = lambda: wm.fit_multipliers(T, meas, dgoff, dtrain, ws=ws2)
+    wall_m, ev_m = timed(fm, args.steps, args.warmup)
+    _, _, stt = fm()
+    stt = stt.cpu().numpy()
+    log(f"planning: fusion {ev_p:.3f} ms ({cands / (ev_p * 1e-3):.3g} FP64 candidate runs/s), "
+        f"multipliers {ev_m:.3f} ms")
+    return {"fusion": {"chains": len(lens), "rows": int(d.n), "max_run": R, "candidate_runs": cands,
+                       "ms_per_call": wall_p, "event_ms": ev_p,
+                       "candidate_runs_per_s": cands / (ev_p * 1e-3), "chains_per_s": len(lens) / (ev_p * 1e-3),
+                       "mean_unfused_over_planned": gain, "fused_share": float(1.0 - st.float().mean().item())},
+            "multipliers": {"groups": 1 << 16, "rows": int(d2.n), "ms_per_call": wall_m, "event_ms": ev_m,
+                            "rows_per_s": d2.n / (ev_m * 1e-3),
+                            "train_mre": float(stt[0] / max(stt[1], 1)),
+                            "holdout_mre": float(stt[2] / max(stt[3], 1))}}
+
+
 def hardware_model_leg(wm, log):
     """Re-times the held-out validation kernels of the shipped MI355X
     parameter file on this GPU and scores the model with that file's
@@ -221,8 +276,12 @@ def hardware_model_leg(wm, log):
     for which in ("microbench", "calibrated"):
         T, _ = rc.predict(wm, rc.load_params(path, which), cases)
         out[f"mae_{which}"] = mb.mae(T, meas)
+    fm = rec.get("family_multipliers", {})
+    if fm:
+        out["mae_calibrated_multiplied"] = mb.mae(np.array([fm[c.kind] for c in cases]) * T, meas)
     out["mae_roofline"] = mb.mae(mb.roofline_naive(cases), meas)
-    out["mae_recorded"] = rec["mae"]["calibrated_holdout"]
+    out["mae_recorded"] = {k: rec["mae"][k] for k in ("calibrated_holdout", "multipliers_holdout",
+                                                       "roofline_holdout") if k in rec["mae"]}
     log(f"hardware model on held-out kernels: MAE calibrated {out['mae_calibrated']:.3f}, "
         f"microbench {out['mae_microbench']:.3f}, roofline {out['mae_roofline']:.3f}")
     return out
@@ -413,6 +472,7 @@ def main():
         del descs, meas_l
 
         res["segments"] = segments_leg(wm, synth, args, dev, tuned)
+        res["planning"] = planning_leg(wm, synth, args, dev, log)
         res["mi355x_model"] = hardware_model_leg(wm, log)
 
     if tuned:

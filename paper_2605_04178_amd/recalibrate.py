@@ -10,7 +10,9 @@ Steps (Section IV-D workflow, Section V-A scoring):
     error (MAE) of each against the measured times;
  4. calibration (wm_calibrate: Adam on log theta over the mean relative
     error) on a training split of the validation kernels, MAE on the
-    held-out split, before and after.
+    held-out split, before and after;
+ 5. per-family multipliers on top of the calibrated model
+    (wm_fit_multipliers on the training split), MAE on the held-out split.
 Writes every raw number to --out as JSON and prints a summary.
 """
 from __future__ import annotations
@@ -51,17 +53,39 @@ def calibrate(wm, p0, cases, steps=2000, lr=0.02):
     return rc, p0.copy(theta=[float(x) for x in th]), hist, mask
 
 
+def family_multipliers(wm, cases, T_pred, train_idx):
+    """Per-family multipliers (Section IV-D per-case multipliers; one group per
+    validation-kernel family) fitted on the training split with
+    wm_fit_multipliers; returns (multiplier per family, scaled predictions)."""
+    import torch
+    fams = sorted({c.kind for c in cases})
+    order = sorted(range(len(cases)), key=lambda i: (fams.index(cases[i].kind), i))
+    off = np.zeros(len(fams) + 1, np.int32)
+    for i in order:
+        off[fams.index(cases[i].kind) + 1] += 1
+    off = np.cumsum(off).astype(np.int32)
+    T = torch.tensor([T_pred[i] for i in order], dtype=torch.float32, device="cuda")
+    m = torch.tensor([cases[i].seconds for i in order], dtype=torch.float32, device="cuda")
+    tr = torch.tensor([1 if i in train_idx else 0 for i in order], dtype=torch.uint8, device="cuda")
+    mult, Ts, _ = wm.fit_multipliers(T, m, torch.from_numpy(off).cuda(), tr)
+    scaled = np.empty(len(cases))
+    scaled[order] = Ts.cpu().numpy()
+    return dict(zip(fams, mult.cpu().numpy().tolist())), scaled
+
+
 def params_record(res: dict) -> dict:
     """The shipped parameter file: structure, both theta vectors, the
     transfer model, the scores and the per-kernel table of a run."""
     keep = ("name", "kind", "n", "iters", "F", "B", "r1", "r2", "K", "W", "dtype", "grid", "vgpr",
-            "lds", "block", "seconds", "pred_microbench", "pred_calibrated", "pred_roofline", "split")
+            "lds", "block", "seconds", "pred_microbench", "pred_calibrated", "pred_multiplied",
+            "pred_roofline", "split")
     return {
         "device": res["device"],
         "struct": res["struct"],
         "theta_microbench": res["theta_microbench"],
         "theta_calibrated": res["theta_calibrated"],
         "calibration": res["calibration"],
+        "family_multipliers": res.get("family_multipliers", {}),
         "copy_model": {k: {"bw": v[0], "tau": v[1]} for k, v in res["copy_model"].items()},
         "peaks_measured": res["microbench"]["peak"],
         "mae": res["mae"],
@@ -107,6 +131,7 @@ def main(argv=None):
     idx_h = [cases.index(c) for c in hold]
     rc, p_cal, hist, mask = calibrate(wm, p_mb, train, steps=args.steps)
     T_cal, _ = predict(wm, p_cal, cases)
+    fam_mult, T_mult = family_multipliers(wm, cases, T_cal, set(idx_t))
     res = {
         "device": meas["device"],
         "microbench": meas,
@@ -115,9 +140,11 @@ def main(argv=None):
         "theta_calibrated": list(p_cal.theta),
         "calibration": {"status": rc, "free_mask": mask, "steps": args.steps,
                         "loss_first_last": [float(hist[0]), float(hist[-1])]},
+        "family_multipliers": fam_mult,
         "struct": {k: getattr(p_mb, k) for k in mb.MI355X_STRUCT},
         "cases": [dict(dataclasses.asdict(c), pred_microbench=float(T_mb[i]), pred_calibrated=float(T_cal[i]),
-                       pred_roofline=float(T_roof[i]), occ=int(occ[i]), split="hold" if i in idx_h else "train")
+                       pred_multiplied=float(T_mult[i]), pred_roofline=float(T_roof[i]), occ=int(occ[i]),
+                       split="hold" if i in idx_h else "train")
                   for i, c in enumerate(cases)],
         "mae": {
             "roofline_all": mb.mae(T_roof, meas_t),
@@ -126,6 +153,8 @@ def main(argv=None):
             "microbench_holdout": mb.mae(T_mb[idx_h], meas_t[idx_h]),
             "calibrated_train": mb.mae(T_cal[idx_t], meas_t[idx_t]),
             "calibrated_holdout": mb.mae(T_cal[idx_h], meas_t[idx_h]),
+            "multipliers_train": mb.mae(T_mult[idx_t], meas_t[idx_t]),
+            "multipliers_holdout": mb.mae(T_mult[idx_h], meas_t[idx_h]),
         },
         "seconds": time.time() - t0,
     }
@@ -137,7 +166,8 @@ def main(argv=None):
     log("MAE:", json.dumps(res["mae"]))
     for i, c in enumerate(cases):
         log(f"{c.name:24s} meas {c.seconds * 1e6:10.1f} us  model {T_mb[i] * 1e6:10.1f}  "
-            f"cal {T_cal[i] * 1e6:10.1f}  roof {T_roof[i] * 1e6:10.1f}  [{'hold' if i in idx_h else 'train'}]")
+            f"cal {T_cal[i] * 1e6:10.1f}  mult {T_mult[i] * 1e6:10.1f}  roof {T_roof[i] * 1e6:10.1f}  "
+            f"[{'hold' if i in idx_h else 'train'}]")
     return 0
 
 
