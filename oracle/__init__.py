@@ -376,3 +376,128 @@ def plan_fusion(p, d, edge, off, R):
     _plan_lib().orc_plan_fusion(C.byref(params(p)), C.byref(o), e.ctypes.data, off.ctypes.data, nc, int(R),
                                 tot.ctypes.data, unf.ctypes.data, st.ctypes.data)
     return tot[:nc], unf[:nc], st[:o.n]
+
+
+# ----------------------------------------------------------------------------
+# Blackwell stage-centric family (bw_oracle.c)
+# ----------------------------------------------------------------------------
+BW_NTHETA = 24
+
+
+class BwParams(C.Structure):
+    _fields_ = [("n_sm", C.c_int32), ("max_cta", C.c_int32), ("tmem_bytes", C.c_int64),
+                ("f_clk", C.c_double), ("theta", C.c_double * BW_NTHETA)]
+
+
+class BwDesc(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("bM", "bN", "bK", "G", "flags", "Kt", "CR", "ob")] + [
+        ("n", C.c_int64)]
+
+
+class BwTrace(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("compute_bound", C.c_int32), ("c", C.c_int32), ("pad_", C.c_int32),
+                ("n_r", C.c_int64)] + [(n, C.c_double) for n in (
+                    "MA", "MB", "D_acc", "T_tmem", "T_mgmt", "T_compute", "T_tma", "T_decomp", "T_dsm",
+                    "T_sync", "T_io", "T_step", "T_store", "T")]
+
+
+def _bw_lib():
+    L = lib()
+    if not hasattr(L, "_bw_ready"):
+        P, D = C.POINTER(BwParams), C.POINTER(BwDesc)
+        vp = C.c_void_p
+        L.bw_eval.argtypes = [P] + [C.c_int64] * 5 + [C.c_double] * 3 + [C.POINTER(BwTrace), vp]
+        L.bw_predict.argtypes = [P, D, vp, vp]
+        L.bw_trace.argtypes = [P, D, vp]
+        L.bw_jacobian.argtypes = [P, D, vp]
+        L.bw_weighted_grad.argtypes = [P, D, vp, C.c_int, vp]
+        L.bw_calibrate.argtypes = [P, D, vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_uint32, P, vp]
+        L.bw_calibrate.restype = C.c_int
+        L._bw_ready = True
+    return L
+
+
+def bw_params(p) -> BwParams:
+    o = BwParams()
+    o.n_sm, o.max_cta, o.tmem_bytes, o.f_clk = int(p.n_sm), int(p.max_cta), int(p.tmem_bytes), float(p.f_clk)
+    for j in range(BW_NTHETA):
+        o.theta[j] = float(p.theta[j])
+    return o
+
+
+_BW_INT = ("bM", "bN", "bK", "G", "flags")
+_BW_FLT = ("Kt", "CR", "ob")
+
+
+def _bw_desc(d):
+    keep = []
+    o = BwDesc()
+    for f in _BW_INT:
+        a = np.ascontiguousarray(getattr(d, f), np.int32)
+        keep.append(a)
+        setattr(o, f, a.ctypes.data)
+    for f in _BW_FLT:
+        a = np.ascontiguousarray(getattr(d, f), np.float32)
+        keep.append(a)
+        setattr(o, f, a.ctypes.data)
+    o.n = int(keep[0].shape[0])
+    return o, keep
+
+
+def bw_eval_one(p, bM, bN, bK, G, flags, Kt, CR, ob, with_grad=False):
+    tr = BwTrace()
+    J = np.zeros(BW_NTHETA) if with_grad else None
+    _bw_lib().bw_eval(C.byref(bw_params(p)), int(bM), int(bN), int(bK), int(G), int(flags), float(Kt),
+                      float(CR), float(ob), C.byref(tr), J.ctypes.data if with_grad else None)
+    return (tr, J) if with_grad else tr
+
+
+def bw_predict(p, d):
+    o, keep = _bw_desc(d)
+    T = np.empty(max(o.n, 1))
+    c = np.empty(max(o.n, 1), np.int32)
+    _bw_lib().bw_predict(C.byref(bw_params(p)), C.byref(o), T.ctypes.data, c.ctypes.data)
+    return T[:o.n], c[:o.n]
+
+
+def bw_trace(p, d):
+    o, keep = _bw_desc(d)
+    buf = (BwTrace * max(o.n, 1))()
+    _bw_lib().bw_trace(C.byref(bw_params(p)), C.byref(o), C.addressof(buf))
+    arr = np.ctypeslib.as_array(buf)[: o.n]
+    return {name: np.array(arr[name]) for name in arr.dtype.names if not name.startswith("pad")}
+
+
+def bw_jacobian(p, d):
+    o, keep = _bw_desc(d)
+    J = np.empty((max(o.n, 1), BW_NTHETA))
+    _bw_lib().bw_jacobian(C.byref(bw_params(p)), C.byref(o), J.ctypes.data)
+    return J[:o.n]
+
+
+def bw_vjp(p, d, w):
+    o, keep = _bw_desc(d)
+    wv = np.ascontiguousarray(w, np.float32)
+    out = np.zeros(26)
+    _bw_lib().bw_weighted_grad(C.byref(bw_params(p)), C.byref(o), wv.ctypes.data, 0, out.ctypes.data)
+    return out[2:]
+
+
+def bw_loss_grad(p, d, measured):
+    o, keep = _bw_desc(d)
+    m = np.ascontiguousarray(measured, np.float32)
+    out = np.zeros(26)
+    _bw_lib().bw_weighted_grad(C.byref(bw_params(p)), C.byref(o), m.ctypes.data, 1, out.ctypes.data)
+    return float(out[0]), int(out[1]), out[2:].copy()
+
+
+def bw_calibrate(p0, d, measured, steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 free_mask=0xFFFFFF):
+    o, keep = _bw_desc(d)
+    m = np.ascontiguousarray(measured, np.float32)
+    pout = BwParams()
+    hist = np.zeros(steps)
+    rc = _bw_lib().bw_calibrate(C.byref(bw_params(p0)), C.byref(o), m.ctypes.data, int(steps), lr, lr_final,
+                                beta1, beta2, eps, int(free_mask), C.byref(pout), hist.ctypes.data)
+    return rc, np.array([pout.theta[j] for j in range(BW_NTHETA)]), hist

@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "wm_oracle.c")
+SRCS = [os.path.join(HERE, "wm_oracle.c"), os.path.join(HERE, "bw_oracle.c")]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
@@ -15,7 +15,7 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", tmp, SRC, "-lm"]
+           "-o", tmp] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

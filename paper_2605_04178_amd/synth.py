@@ -439,3 +439,115 @@ def grouped_measurements(n_groups: int, seed: int = 170, gmin: int = 1, gmax: in
     d = descriptors(n, seed + 1)
     d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
     return off.astype(np.int32), factor, noise, train, d
+
+
+# ---------------------------------------------------------------------------
+# Blackwell stage-centric family: parameter sets and tile-kernel descriptors
+# ---------------------------------------------------------------------------
+BW_THETA_NAMES = ("BW_TMEM_read", "BW_TMEM_write", "L_mma", "R_TC_fp64", "R_TC_tf32", "R_TC_fp16",
+                  "R_TC_fp8", "R_TC_fp4", "S_2SM", "L_TMA", "B_TMA", "L_mbar", "L_commit", "BW_link",
+                  "eta_DE", "R_decomp", "L_decomp_setup", "eps_exposed", "B_gmem", "L_store_setup",
+                  "L_tmem_mgmt", "O_misc", "T_launch", "BW_dsmem")
+
+
+@dataclasses.dataclass
+class BwParamSet:
+    """Structure plus the 24-slot Blackwell parameter vector (rates per SM,
+    latencies in cycles, times in seconds)."""
+    n_sm: int = 148
+    max_cta: int = 1
+    tmem_bytes: int = 256 * 1024
+    f_clk: float = 1.965e9
+    theta: List[float] = dataclasses.field(default_factory=lambda: [0.0] * N_THETA)
+
+    def copy(self, **kw) -> "BwParamSet":
+        d = dataclasses.asdict(self)
+        d["theta"] = list(self.theta)
+        d.update(kw)
+        return BwParamSet(**d)
+
+
+def b200_like() -> BwParamSet:
+    """Values the paper prints for B200 (Table "parameters" and Section IV-A):
+    TMEM 16 / 8 TB/s, L_TMA 420 cycles, tcgen05.mma latency 11-14 cycles
+    (12), tensor throughput 44.8 (FP64) to 7702 (FP4) TFLOP/s over 148 SMs,
+    L_mbar and L_commit 40-50 cycles (45), alpha 0.85-0.95 (exposed 0.1),
+    2-SM speedup 1.30.  TF32/FP16/FP8 throughput, the TMA, link, store and
+    DSMEM rates and the remaining latencies are not printed: placeholders."""
+    sm = 148.0
+    th = [0.0] * N_THETA
+    th[0], th[1], th[2] = 16e12, 8e12, 12.0
+    th[3:8] = [44.8e12 / sm, 1100e12 / sm, 2250e12 / sm, 4500e12 / sm, 7702e12 / sm]
+    th[8], th[9], th[10] = 1.30, 420.0, 64e9
+    th[11], th[12] = 45.0, 45.0
+    th[13], th[14], th[15], th[16] = 64e9, 0.9, 256e9, 200.0
+    th[17] = 0.1
+    th[18], th[19] = 48e9, 500.0
+    th[20], th[21], th[22], th[23] = 2000.0, 5e-9, 4e-6, 128e9
+    return BwParamSet(theta=th)
+
+
+def bw_param_set(seed: int = 0) -> BwParamSet:
+    """Seeded synthetic Blackwell-style set around the b200_like values:
+    each positive slot scaled by exp(U(+-ln 1.6)); the exposed fraction
+    U[0.05, 0.3], the 2-SM speedup U[1.1, 1.6], eta_DE U[0.6, 0.95]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = b200_like()
+    th = [float(t * np.exp(rng.uniform(-np.log(1.6), np.log(1.6)))) for t in base.theta]
+    th[8] = float(rng.uniform(1.1, 1.6))
+    th[14] = float(rng.uniform(0.6, 0.95))
+    th[17] = float(rng.uniform(0.05, 0.3))
+    return base.copy(theta=th, max_cta=int(rng.integers(1, 3)))
+
+
+@dataclasses.dataclass
+class BwDescriptors:
+    bM: np.ndarray
+    bN: np.ndarray
+    bK: np.ndarray
+    G: np.ndarray
+    flags: np.ndarray
+    Kt: np.ndarray
+    CR: np.ndarray
+    ob: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.bM.shape[0])
+
+    def slice(self, a: int, b: int) -> "BwDescriptors":
+        return BwDescriptors(*[getattr(self, f.name)[a:b] for f in dataclasses.fields(self)])
+
+
+def pack_bw_flags(dtype, pair, stratB, PA, PB, nbar, comp):
+    """Blackwell descriptor flags: [0,3) dtype, [3] 2-SM pair, [4] TMEM
+    strategy B, [5,9) P_A - 1, [9,13) P_B - 1, [13,16) barriers, [16] compressed."""
+    return (np.asarray(dtype) | (np.asarray(pair) << 3) | (np.asarray(stratB) << 4)
+            | ((np.asarray(PA) - 1) << 5) | ((np.asarray(PB) - 1) << 9) | (np.asarray(nbar) << 13)
+            | (np.asarray(comp) << 16)).astype(np.int32)
+
+
+def bw_descriptors(n: int, seed: int = 200) -> BwDescriptors:
+    """Tile-kernel sweep: bM, bN in {64, 128, 256}, bK in {16, 32, 64, 128},
+    Kt round(log-U[1, 1024]), CTAs round(log-U[1, 2^16]), dtype U{0..4},
+    2-SM pair and TMEM strategy B Bernoulli(1/2), P_A and P_B in {1, 2, 4}
+    (1 with p = 1/2), barriers U{1, 2}, compressed Bernoulli(1/4) with
+    CR U[1, 4], output element bytes in {2, 4}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tiles = np.array([64, 128, 256])
+    bM = tiles[rng.integers(0, 3, n)].astype(np.int32)
+    bN = tiles[rng.integers(0, 3, n)].astype(np.int32)
+    bK = np.array([16, 32, 64, 128])[rng.integers(0, 4, n)].astype(np.int32)
+    Kt = np.round(_logu(rng, 1.0, 1024.0, n)).astype(np.float32)
+    G = np.round(_logu(rng, 1.0, 65536.0, n)).astype(np.int32)
+    dt = rng.integers(0, 5, n)
+    pair = (rng.random(n) < 0.5).astype(np.int64)
+    sb = (rng.random(n) < 0.5).astype(np.int64)
+    pp = np.array([1, 2, 4])
+    PA = np.where(rng.random(n) < 0.5, 1, pp[rng.integers(0, 3, n)])
+    PB = np.where(rng.random(n) < 0.5, 1, pp[rng.integers(0, 3, n)])
+    nbar = rng.integers(1, 3, n)
+    comp = (rng.random(n) < 0.25).astype(np.int64)
+    CR = np.where(comp == 1, rng.uniform(1.0, 4.0, n), 1.0).astype(np.float32)
+    ob = np.array([2.0, 4.0], np.float32)[rng.integers(0, 2, n)]
+    return BwDescriptors(bM, bN, bK, G, pack_bw_flags(dt, pair, sb, PA, PB, nbar, comp), Kt, CR, ob)

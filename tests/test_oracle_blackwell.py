@@ -1,0 +1,170 @@
+"""Pins of the oracle's Blackwell stage-centric model (Section IV-A, Eq. (2)
+to Eq. (8)): terms worked by hand, the multicast and 2-CTA traffic ratios the
+paper states, the overlap limits, TMEM capacity, rounds, invalid inputs,
+finite differences of the analytic gradient and calibration recovery.
+CPU only.  Absolute times for the paper's GEMM example are parity unpinned
+(most B200 rates are not printed)."""
+import numpy as np
+import pytest
+
+from paper_2605_04178_amd import synth
+
+F = synth.pack_bw_flags
+
+
+def _p(**over):
+    p = synth.b200_like()
+    th = list(p.theta)
+    for k, v in over.items():
+        th[synth.BW_THETA_NAMES.index(k)] = v
+    return p.copy(theta=th)
+
+
+def test_tmem_compute_and_store_terms_by_hand(orc):
+    p = _p()
+    f = p.f_clk
+    th = p.theta
+    for sb in (0, 1):
+        t = orc.bw_eval_one(p, 128, 256, 64, 10, int(F(2, 0, sb, 1, 1, 1, 0)), 8, 1.0, 4.0)
+        D = 128 * 256 * 4.0
+        MA = 128 * 64 * 2.0
+        want = (D + sb * MA) / th[0] + th[2] / f + D / th[1]
+        assert abs(t.T_tmem - want) <= 1e-15 * want
+        assert abs(t.T_compute - (2.0 * 128 * 256 * 64 / th[5] + want + th[20] / f / 8)) <= 1e-14 * t.T_compute
+        assert abs(t.T_store - (128 * 256 * 4.0 / th[18] + th[19] / f)) <= 1e-15 * t.T_store
+    # FP64 accumulates in 8 bytes
+    t = orc.bw_eval_one(p, 64, 64, 16, 1, int(F(0, 0, 0, 1, 1, 1, 0)), 1, 1.0, 8.0)
+    assert t.D_acc == 64 * 64 * 8.0
+
+
+def test_multicast_and_pair_traffic_ratios(orc):
+    p = _p()
+    f = p.f_clk
+    B = p.theta[10]
+    base = orc.bw_eval_one(p, 128, 128, 64, 1, int(F(2, 0, 0, 1, 1, 1, 0)), 4, 1.0, 2.0)
+    MA = MB = 128 * 64 * 2.0
+    assert abs((base.T_tma - 420 / f) - (MA + MB) / B) <= 1e-15 * base.T_tma
+    mc = orc.bw_eval_one(p, 128, 128, 64, 1, int(F(2, 0, 0, 2, 4, 1, 0)), 4, 1.0, 2.0)
+    assert abs((mc.T_tma - 420 / f) - (MA / 2 + MB / 4) / B) <= 1e-15 * mc.T_tma
+    # 2-SM pair: the two CTAs load 2 M_A + M_B instead of 2 (M_A + M_B):
+    # a 4/3 traffic reduction for square tiles (Eq. (6))
+    pr = orc.bw_eval_one(p, 128, 128, 64, 1, int(F(2, 1, 0, 1, 1, 1, 0)), 4, 1.0, 2.0)
+    pair_bytes = 2 * (pr.T_tma - 420 / f) * B
+    single_bytes = 2 * (base.T_tma - 420 / f) * B
+    assert abs(single_bytes / pair_bytes - 4.0 / 3.0) < 1e-12
+    assert abs(pr.T_dsm - MB / 2 / p.theta[23]) <= 1e-15 * pr.T_dsm
+    assert abs(pr.T_sync - (45 + 45) / f) < 1e-20 and abs(base.T_sync - 45 / f) < 1e-20
+    # the compute term divides by the 2-SM speedup
+    mma = 2.0 * 128 * 128 * 64 / p.theta[5]
+    assert abs((base.T_compute - pr.T_compute) - (mma - mma / p.theta[8])) <= 1e-12 * mma
+
+
+def test_decompression_and_subbyte_unpack(orc):
+    p = _p()
+    f = p.f_clk
+    th = p.theta
+    t = orc.bw_eval_one(p, 128, 128, 128, 1, int(F(3, 0, 0, 1, 1, 1, 1)), 4, 2.5, 2.0)
+    D = (128 * 128 + 128 * 128) * 1.0
+    assert abs(t.T_decomp - D / (2.5 * th[13] * th[14])) <= 1e-15 * t.T_decomp
+    t = orc.bw_eval_one(p, 128, 128, 128, 1, int(F(4, 0, 0, 1, 1, 1, 0)), 4, 1.0, 2.0)
+    D = 2 * 128 * 128 * 0.5
+    assert abs(t.T_decomp - (D / th[15] + th[16] / f)) <= 1e-15 * t.T_decomp
+
+
+def test_overlap_limits_and_step(orc):
+    # all I/O hidden (eps -> 0): T_io is the sync alone; fully exposed: eps = 1
+    for eps in (1e-12, 1.0):
+        p = _p(eps_exposed=eps)
+        t = orc.bw_eval_one(p, 64, 64, 128, 1, int(F(3, 0, 0, 1, 1, 2, 0)), 16, 1.0, 2.0)
+        raw = t.T_tma + t.T_decomp + t.T_dsm
+        assert abs(t.T_io - (eps * raw + t.T_sync)) <= 1e-15 * t.T_io
+        Tm = max(t.T_compute, t.T_io)
+        assert abs(t.T_step - (Tm + t.T_sync + p.theta[21])) <= 1e-15 * t.T_step
+        assert bool(t.compute_bound) == (t.T_compute >= t.T_io)
+    assert orc.bw_eval_one(_p(eps_exposed=1e-12), 64, 64, 128, 1, int(F(3, 0, 0, 1, 1, 2, 0)), 16, 1.0, 2.0).compute_bound
+
+
+def test_capacity_rounds_and_total(orc):
+    p = _p()
+    th = p.theta
+    fl = int(F(2, 0, 0, 1, 1, 1, 0))
+    # 256 x 256 FP32 accumulators fill the 256 KB of TMEM exactly; FP64 overflows it
+    assert orc.bw_eval_one(p, 256, 256, 32, 1, fl, 1, 1.0, 2.0).c == 1
+    t = orc.bw_eval_one(p, 256, 256, 32, 1, int(F(0, 0, 0, 1, 1, 1, 0)), 1, 1.0, 2.0)
+    assert t.c == 0 and np.isinf(t.T) and t.T > 0
+    p2 = p.copy(max_cta=4)
+    assert orc.bw_eval_one(p2, 128, 128, 32, 1, fl, 1, 1.0, 2.0).c == 4
+    assert orc.bw_eval_one(p2, 128, 256, 32, 1, fl, 1, 1.0, 2.0).c == 2
+    for G, nr in ((148, 1), (149, 2), (296, 2), (297, 3)):
+        t = orc.bw_eval_one(p, 128, 128, 32, G, fl, 7, 1.0, 2.0)
+        assert t.n_r == nr
+        assert abs(t.T - (th[22] + nr * (7 * t.T_step + t.T_store))) <= 1e-15 * t.T
+
+
+@pytest.mark.parametrize("args", [
+    (0, 128, 32, 1, F(2, 0, 0, 1, 1, 1, 0), 4, 1.0, 2.0),
+    (128, 128, 32, 0, F(2, 0, 0, 1, 1, 1, 0), 4, 1.0, 2.0),
+    (128, 128, 32, 1, F(5, 0, 0, 1, 1, 1, 0), 4, 1.0, 2.0),
+    (128, 128, 32, 1, int(F(2, 0, 0, 1, 1, 1, 0)) | (1 << 20), 4, 1.0, 2.0),
+    (128, 128, 32, 1, F(2, 0, 0, 1, 1, 1, 0), 0.5, 1.0, 2.0),
+    (128, 128, 32, 1, F(2, 0, 0, 1, 1, 1, 1), 4, 0.9, 2.0),
+    (128, 128, 32, 1, F(2, 0, 0, 1, 1, 1, 0), 4, 1.0, 0.0),
+    (128, 128, 32, 1, F(2, 0, 0, 1, 1, 1, 0), float("nan"), 1.0, 2.0),
+])
+def test_invalid_inputs_are_nan(orc, args):
+    t = orc.bw_eval_one(_p(), *[int(a) if i < 5 else a for i, a in enumerate(args)])
+    assert t.valid == 0 and np.isnan(t.T)
+
+
+def test_jacobian_matches_central_differences(orc):
+    rng = np.random.default_rng(0)
+    d = synth.bw_descriptors(400, 201)
+    checked = 0
+    for seed in range(3):
+        p = synth.bw_param_set(seed)
+        tr = orc.bw_trace(p, d)
+        J = orc.bw_jacobian(p, d)
+        th0 = np.array(p.theta)
+        for i in rng.choice(d.n, 60, replace=False):
+            if not np.isfinite(tr["T"][i]):
+                continue
+            gap = abs(tr["T_compute"][i] - tr["T_io"][i]) / max(tr["T_compute"][i], tr["T_io"][i])
+            if gap < 1e-3:
+                continue
+            args = [int(d.bM[i]), int(d.bN[i]), int(d.bK[i]), int(d.G[i]), int(d.flags[i]),
+                    float(d.Kt[i]), float(d.CR[i]), float(d.ob[i])]
+            for j in range(24):
+                h = 1e-6
+                tp, tm = th0.copy(), th0.copy()
+                tp[j] *= 1 + h
+                tm[j] *= 1 - h
+                fp = orc.bw_eval_one(p.copy(theta=list(tp)), *args).T
+                fm = orc.bw_eval_one(p.copy(theta=list(tm)), *args).T
+                fd = (fp - fm) / (2 * h * th0[j])
+                assert abs(fd - J[i, j]) <= 1e-5 * abs(J[i, j]) + 1e-9 * tr["T"][i] / th0[j], (i, j, fd, J[i, j])
+            checked += 1
+    assert checked > 100
+
+
+def test_loss_gradient_and_calibration_recovery(orc):
+    p_true = synth.bw_param_set(7)
+    d = synth.bw_descriptors(1 << 14, 202)
+    T, _ = orc.bw_predict(p_true, d)
+    m = T.astype(np.float32)
+    loss, cnt, g = orc.bw_loss_grad(p_true, d, m)
+    assert cnt == np.isfinite(T).sum() and loss < 1e-6
+    # well-determined slots: tensor throughputs, TMEM rates, TMA rate and
+    # latency, exposed fraction, launch, store rate, O_misc
+    free = [0, 1, 3, 4, 5, 6, 7, 9, 10, 17, 18, 21, 22]
+    mask = sum(1 << j for j in free)
+    rng = np.random.default_rng(3)
+    th0 = list(p_true.theta)
+    for j in free:
+        th0[j] *= float(np.exp(rng.uniform(-np.log(1.3), np.log(1.3))))
+    p0 = p_true.copy(theta=th0)
+    rc, th, hist = orc.bw_calibrate(p0, d, m, steps=800, lr=0.02, lr_final=1e-4, free_mask=mask)
+    assert rc == 0 and hist[-1] < 0.1 * hist[0]
+    err = max(abs(th[j] / p_true.theta[j] - 1) for j in free)
+    assert err < 0.03, (err, [(j, th[j] / p_true.theta[j]) for j in free])
+    # fixed slots did not move
+    assert all(th[j] == p0.theta[j] for j in range(24) if j not in free)
