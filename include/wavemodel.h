@@ -371,6 +371,72 @@ int32_t wm_plan_fusion(const wm_desc_t *desc, const float *edge, const int32_t *
                        int64_t n_chains, int32_t R, const wm_params_t *params, double *total,
                        double *unfused, uint8_t *start, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * ---- Blackwell stage-centric family (Section IV-A) ----
+ * A second per-descriptor model on the same batched machinery.  Parameter
+ * vector (24 slots; rates per SM in B/s or flop/s, latencies in cycles at
+ * f_clk, times in s):
+ *   0 BW_TMEM_read   1 BW_TMEM_write   2 L_mma           (Eq. (2))
+ *   3-7 R_TC per dtype: fp64, tf32, fp16/bf16, fp8, fp4  (Eq. (3))
+ *   8 S_2SM (2-SM speedup)             (Eq. (6))
+ *   9 L_TMA   10 B_TMA                 (Eq. (4))
+ *   11 L_mbar   12 L_commit            (sync per K-step)
+ *   13 BW_link  14 eta_DE  15 R_decomp  16 L_decomp_setup   (Eq. (5))
+ *   17 eps = 1 - alpha, the exposed I/O fraction            (Eq. (7))
+ *   18 B_gmem  19 L_store_setup  (C-tile writeback)
+ *   20 L_alloc + L_dealloc (TMEM management, amortised over K-steps)
+ *   21 O_misc (per step)  22 T_launch  23 BW_dsmem (2-SM B-tile exchange)
+ * All slots > 0 except 2, 9, 11, 12, 16, 19, 20, 21, 22 (>= 0) and
+ * 17 (>= 0).  Structure: n_sm, max_cta (CTAs per SM cap), tmem_bytes per
+ * SM, f_clk.
+ * Descriptors (structure of arrays, 32 B each): bM, bN, bK tile sizes
+ * (>= 1), G CTAs (>= 1), flags ([0,3) dtype 0..4, [3] 2-SM pair, [4] TMEM
+ * strategy B (A tile through TMEM), [5,9) P_A - 1, [9,13) P_B - 1 multicast
+ * participants, [13,16) barriers per K-step, [16] compressed operands; other
+ * bits zero) as int32; Kt K-steps per tile (>= 1), CR compression ratio
+ * (>= 1), ob output element bytes (> 0) as float32.  Invalid rows give NaN
+ * and cta = -1; an accumulator larger than TMEM gives +inf and cta = 0.
+ * The model, term by term: see the paper's Eq. (2)-(8); per K-step
+ * T_step = max(T_compute, eps (T_tma + T_decomp + T_dsm) + T_sync) + T_sync +
+ * O_misc; kernel T = T_launch + n_r (Kt T_step + T_store), n_r =
+ * ceil(G / (n_sm cta)).
+ */
+typedef struct {
+    int32_t n_sm, max_cta;
+    int64_t tmem_bytes;
+    double f_clk;
+    double theta[WM_N_THETA];
+} wm_bw_params_t;
+
+typedef struct {
+    const int32_t *bM, *bN, *bK, *G, *flags;
+    const float *Kt, *CR, *ob;
+    int64_t n;
+} wm_bw_desc_t;
+
+#define WM_BW_OP_GRAD 0       /* wm_bw_predict_vjp, wm_bw_loss_grad */
+#define WM_BW_OP_CALIBRATE 1  /* wm_bw_calibrate */
+
+int32_t wm_bw_validate_params(const wm_bw_params_t *params);
+/* Workspace bytes of a Blackwell call for n descriptors (steps: calibration
+ * steps, ignored for WM_BW_OP_GRAD); 0 for bad arguments. */
+size_t wm_bw_workspace_bytes(int32_t op, int64_t n, int32_t steps);
+/* Predicted time T [n] float32 s (required) and CTAs per SM cta [n] int32
+ * (or NULL); float32, error against the FP64 definition below 1e-5. */
+int32_t wm_bw_predict(const wm_bw_desc_t *desc, const wm_bw_params_t *params, float *T, int32_t *cta,
+                      void *stream);
+/* As wm_predict_vjp / wm_loss_grad for the Blackwell model (subgradient at
+ * the compute / I-O switch: compute on ties; descriptors within 1e-5 of the
+ * switch or of T = m are re-evaluated in float64). */
+int32_t wm_bw_predict_vjp(const wm_bw_desc_t *desc, const wm_bw_params_t *params, const float *dL_dT,
+                          double *dL_dtheta, void *ws, size_t ws_bytes, void *stream);
+int32_t wm_bw_loss_grad(const wm_bw_desc_t *desc, const float *measured, const wm_bw_params_t *params,
+                        double *out, void *ws, size_t ws_bytes, void *stream);
+/* As wm_calibrate (Adam on log theta in captured HIP graphs). */
+int32_t wm_bw_calibrate(const wm_bw_desc_t *desc, const float *measured, const wm_bw_params_t *p0,
+                        const wm_calib_opts_t *opts, wm_bw_params_t *p_out, double *loss_hist,
+                        void *ws, size_t ws_bytes, void *stream);
+
 /* ---- launch configurations and autotuning ----
  *
  * Every call above launches its kernels with a configuration looked up by

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/wavemodel.h"
+#include "bw_launch.hpp"
 #include "wm_launch.hpp"
 
 using namespace wm;
@@ -263,6 +264,53 @@ PlanWs plan_ws(int64_t n, int32_t R)
 
 constexpr size_t kFitMultWs = sizeof(double) * 4 * 4 * (size_t)kFitMultMaxBlocks;
 
+// ---- Blackwell family helpers ----
+bool bw_params_ok(const wm_bw_params_t* p)
+{
+    if (!p) return false;
+    if (p->n_sm < 1 || p->n_sm > 65536 || p->max_cta < 1 || p->max_cta > 64) return false;
+    if (p->tmem_bytes < 1 || p->tmem_bytes > (1ll << 40)) return false;
+    if (!(fin(p->f_clk) && p->f_clk > 0.0 && f32_pos(1.0 / p->f_clk))) return false;
+    const double* th = p->theta;
+    for (int j = 0; j < WM_N_THETA; ++j)
+        if (!fin(th[j])) return false;
+    const int pos[] = {0, 1, 3, 4, 5, 6, 7, 8, 10, 13, 14, 15, 18, 23};
+    for (int j : pos)
+        if (!(th[j] > 0.0 && f32_pos(th[j]) && f32_pos(1.0 / th[j]))) return false;
+    const int nonneg[] = {2, 9, 11, 12, 16, 17, 19, 20, 21, 22};
+    for (int j : nonneg)
+        if (!(th[j] >= 0.0 && f32_ok(th[j]) && f32_ok(th[j] / p->f_clk))) return false;
+    return true;
+}
+
+BwSet make_bw_set(const wm_bw_params_t* p)
+{
+    BwSet S;
+    std::memset(&S, 0, sizeof(S));
+    S.st.n_sm = p->n_sm;
+    S.st.max_cta = p->max_cta;
+    S.st.tmem_bytes = p->tmem_bytes;
+    S.st.f_clk = p->f_clk;
+    make_bw_const<float>(p->theta, S.st, S.cf);
+    make_bw_const<double>(p->theta, S.st, S.cd);
+    return S;
+}
+
+bool bw_desc_ok(const wm_bw_desc_t* d)
+{
+    if (!d || d->n < 0) return false;
+    if (d->n == 0) return true;
+    return d->bM && d->bN && d->bK && d->G && d->flags && d->Kt && d->CR && d->ob;
+}
+
+BwDescPtrs bw_ptrs_of(const wm_bw_desc_t* d)
+{
+    BwDescPtrs p;
+    p.bM = d->bM; p.bN = d->bN; p.bK = d->bK; p.G = d->G; p.flags = d->flags;
+    p.Kt = d->Kt; p.CR = d->CR; p.ob = d->ob;
+    return p;
+}
+
 // calibration workspace layout
 // gradient-sweep workspace: partial rows, then redo-flag words
 struct GradWs {
@@ -309,13 +357,13 @@ struct CalibLayout {
     GradWs g;
 };
 
-CalibLayout calib_layout(int64_t n, int32_t steps)
+CalibLayout calib_layout(int64_t n, int32_t steps, size_t set_bytes = sizeof(Set))
 {
     CalibLayout L;
     L.g = grad_ws(n);
     size_t off = 0;
     L.set = off;
-    off += up256(sizeof(Set));
+    off += up256(set_bytes);
     L.state = off;
     off += up256(sizeof(CalibState));
     L.hist = off;
@@ -707,6 +755,112 @@ size_t wm_workspace_bytes(int32_t op, int64_t n, int32_t n_sets, int32_t steps)
     default:
         return 0;
     }
+}
+
+int32_t wm_bw_validate_params(const wm_bw_params_t* p) { return bw_params_ok(p) ? WM_OK : WM_EINVAL; }
+
+size_t wm_bw_workspace_bytes(int32_t op, int64_t n, int32_t steps)
+{
+    if (n < 0) return 0;
+    if (op == WM_BW_OP_GRAD) return grad_ws(n).total;
+    if (op == WM_BW_OP_CALIBRATE && steps >= 1) return calib_layout(n, steps, sizeof(BwSet)).total;
+    return 0;
+}
+
+int32_t wm_bw_predict(const wm_bw_desc_t* desc, const wm_bw_params_t* params, float* T, int32_t* cta,
+                      void* stream)
+{
+    if (!bw_desc_ok(desc) || !bw_params_ok(params)) return WM_EINVAL;
+    if (desc->n == 0) return WM_OK;
+    if (!T) return WM_EINVAL;
+    const BwSet S = make_bw_set(params);
+    WM_HIP(launch_bw_predict(bw_ptrs_of(desc), desc->n, S, T, cta, default_cfg(kOpPredict),
+                             (hipStream_t)stream));
+    return WM_OK;
+}
+
+static int32_t bw_grad_common(int mode, const wm_bw_desc_t* desc, const float* w,
+                              const wm_bw_params_t* params, double* out, void* ws, size_t ws_bytes,
+                              void* stream)
+{
+    if (!bw_desc_ok(desc) || !bw_params_ok(params) || !out) return WM_EINVAL;
+    if (desc->n > 0 && !w) return WM_EINVAL;
+    const GradWs W = grad_ws(desc->n);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    const BwSet S = make_bw_set(params);
+    char* base = (char*)ws;
+    const LaunchCfg cfg = launch_cfg(mode == 1 ? kOpLossGrad : kOpVjp, desc->n);
+    WM_HIP(launch_bw_grad(mode, bw_ptrs_of(desc), desc->n, w, S, nullptr, (double*)(base + W.partials),
+                          (uint64_t*)(base + W.flags), W.g, cfg, out, (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_bw_predict_vjp(const wm_bw_desc_t* desc, const wm_bw_params_t* params, const float* dL_dT,
+                          double* dL_dtheta, void* ws, size_t ws_bytes, void* stream)
+{
+    return bw_grad_common(0, desc, dL_dT, params, dL_dtheta, ws, ws_bytes, stream);
+}
+
+int32_t wm_bw_loss_grad(const wm_bw_desc_t* desc, const float* measured, const wm_bw_params_t* params,
+                        double* out, void* ws, size_t ws_bytes, void* stream)
+{
+    return bw_grad_common(1, desc, measured, params, out, ws, ws_bytes, stream);
+}
+
+int32_t wm_bw_calibrate(const wm_bw_desc_t* desc, const float* measured, const wm_bw_params_t* p0,
+                        const wm_calib_opts_t* opts, wm_bw_params_t* p_out, double* loss_hist,
+                        void* ws, size_t ws_bytes, void* stream)
+{
+    if (!bw_desc_ok(desc) || !measured || !bw_params_ok(p0) || !opts_ok(opts) || !p_out)
+        return WM_EINVAL;
+    for (int j = 0; j < WM_N_THETA; ++j)
+        if (((opts->free_mask >> j) & 1u) && !(p0->theta[j] > 0.0)) return WM_EINVAL;
+    const CalibLayout L = calib_layout(desc->n, opts->steps, sizeof(BwSet));
+    if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
+    hipStream_t s = nullptr;
+    int32_t rc = capture_stream(stream, &s);
+    if (rc != WM_OK) return rc;
+    char* base = (char*)ws;
+    BwSet* S_dev = (BwSet*)(base + L.set);
+    CalibState* st_dev = (CalibState*)(base + L.state);
+    double* hist_dev = (double*)(base + L.hist);
+    double* part_dev = (double*)(base + L.grad + L.g.partials);
+    uint64_t* flags_dev = (uint64_t*)(base + L.grad + L.g.flags);
+    const BwSet S = make_bw_set(p0);
+    CalibState st0;
+    std::memset(&st0, 0, sizeof(st0));
+    for (int j = 0; j < WM_N_THETA; ++j) {
+        st0.theta[j] = p0->theta[j];
+        st0.theta_ok[j] = p0->theta[j];
+        st0.phi[j] = ((opts->free_mask >> j) & 1u) ? std::log(p0->theta[j]) : 0.0;
+    }
+    const AdamOpts ao = adam_of(opts);
+    WM_HIP(hipMemcpyAsync(S_dev, &S, sizeof(S), hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(st_dev, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    WM_HIP(hipStreamSynchronize(s));
+    const BwDescPtrs dp = bw_ptrs_of(desc);
+    const int64_t n = desc->n;
+    const GradLayout G = L.g.g;
+    const LaunchCfg cfg = launch_cfg(kOpLossGrad, n);
+    double* rows2_dev = part_dev + (int64_t)bw_grad_grid(1, true, n, cfg) * kAcc;
+    auto step = [&]() -> hipError_t {
+        hipError_t e = launch_bw_grad(1, dp, n, measured, S, S_dev, part_dev, flags_dev, G, cfg,
+                                      nullptr, s);
+        if (e != hipSuccess) return e;
+        return launch_bw_adam(rows2_dev, G.nb2, st_dev, ao, S_dev, hist_dev, s);
+    };
+    rc = run_steps(s, opts->steps, step);
+    if (rc != WM_OK) return rc;
+    CalibState fin_st;
+    WM_HIP(hipMemcpyAsync(&fin_st, st_dev, sizeof(fin_st), hipMemcpyDeviceToHost, s));
+    std::vector<double> hist((size_t)opts->steps);
+    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev, sizeof(double) * opts->steps, hipMemcpyDeviceToHost, s));
+    WM_HIP(hipStreamSynchronize(s));
+    *p_out = *p0;
+    const double* th = fin_st.diverged ? fin_st.theta_ok : fin_st.theta;
+    for (int j = 0; j < WM_N_THETA; ++j) p_out->theta[j] = th[j];
+    if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * opts->steps);
+    return fin_st.diverged ? WM_EDIVERGED : WM_OK;
 }
 
 size_t wm_plan_workspace_bytes(int64_t n, int32_t R)

@@ -1,5 +1,6 @@
 // wm_device.hpp -- device-side helpers shared by the kernel files: streaming
-// loads of one descriptor row and its float64 image.
+// loads of one descriptor row and its float64 image, the fixed-order FP64
+// block reductions, and the Adam step on log(theta).
 #pragma once
 
 #include "wm_launch.hpp"
@@ -34,5 +35,104 @@ __device__ inline Desc<double> widen(const Desc<float>& x)
     y.v = x.v; y.s = x.s; y.gp = x.gp; y.G = x.G;
     return y;
 }
+
+// ---------------------------------------------------------------------------
+// block reduction of the 26 FP64 accumulators (fixed order)
+// ---------------------------------------------------------------------------
+__device__ inline void block_reduce_acc(double* acc, double* lds /* [waves][26] */, double* out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        acc[j] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) lds[wid * kAcc + j] = acc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < kAcc) {
+        const int nw = blockDim.x >> 6;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * kAcc + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Fixed-order sum of partial rows: thread t adds rows t, t+256, ... of all 26
+// columns, then the block tree of block_reduce_acc.
+__device__ inline void reduce_partials(const double* __restrict__ partials, int rows, int stride,
+                                       double* red /* [waves][26] */, double* tot /* [26] */)
+{
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        const double* row = partials + (int64_t)r * stride;
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
+    }
+    block_reduce_acc(acc, red, tot);
+}
+
+// ---------------------------------------------------------------------------
+// device Adam on log(theta)
+// ---------------------------------------------------------------------------
+__device__ inline bool adam_theta_step(CalibState* st, const double* tot, const AdamOpts& o,
+                                       double* loss_hist)
+{
+    // one thread does the update (24 values); the step index lives in device
+    // memory so one captured graph serves every chunk of steps.  Returns true
+    // when theta changed (the caller rebuilds its constants).
+    const int step_index = st->t;
+    st->t = step_index + 1;
+    const double cnt = tot[1];
+    const double loss = cnt > 0.0 ? tot[0] / cnt : 0.0;
+    if (loss_hist && step_index < o.steps)
+        loss_hist[step_index] = st->diverged ? __builtin_nan("") : loss;
+    if (st->diverged) return false;
+    bool finite = __builtin_isfinite(loss);
+    double g[kTheta];
+    for (int j = 0; j < kTheta; ++j) {
+        g[j] = cnt > 0.0 ? tot[2 + j] / cnt : 0.0;
+        finite = finite && __builtin_isfinite(g[j]);
+    }
+    if (!finite) {
+        st->diverged = 1;
+        return false;
+    }
+    for (int j = 0; j < kTheta; ++j) st->theta_ok[j] = st->theta[j];
+    const double t = (double)(step_index + 1);
+    double lr = o.lr;
+    if (o.lr_final > 0.0 && o.steps > 1)
+        lr = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
+    const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
+    double th_new[kTheta];
+    bool ok = true;
+    for (int j = 0; j < kTheta; ++j) {
+        th_new[j] = st->theta[j];
+        if (!((o.free_mask >> j) & 1u)) continue;
+        const double gp = st->theta[j] * g[j];
+        st->m[j] = o.beta1 * st->m[j] + (1.0 - o.beta1) * gp;
+        st->v[j] = o.beta2 * st->v[j] + (1.0 - o.beta2) * gp * gp;
+        const double mh = st->m[j] / (1.0 - b1t);
+        const double vh = st->v[j] / (1.0 - b2t);
+        st->phi[j] -= lr * mh / (sqrt(vh) + o.eps);
+        th_new[j] = exp(st->phi[j]);
+        ok = ok && __builtin_isfinite(th_new[j]) && th_new[j] > 0.0;
+    }
+    if (!ok) {
+        st->diverged = 1;
+        return false;
+    }
+    for (int j = 0; j < kTheta; ++j) st->theta[j] = th_new[j];
+    return true;
+}
+
 
 }  // namespace wm

@@ -147,34 +147,6 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// block reduction of the 26 FP64 accumulators (fixed order)
-// ---------------------------------------------------------------------------
-__device__ inline void block_reduce_acc(double* acc, double* lds /* [waves][26] */, double* out)
-{
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < kAcc; ++j) {
-        double v = acc[j];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-        acc[j] = v;
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < kAcc; ++j) lds[wid * kAcc + j] = acc[j];
-    }
-    __syncthreads();
-    if (threadIdx.x < kAcc) {
-        const int nw = blockDim.x >> 6;
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += lds[w * kAcc + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
-}
-
 // Weight of one descriptor's Jacobian row in the sum, and its loss term.
 // mode 0: dL/dT supplied; mode 1: mean relative error against measured m.
 // Returns false if the descriptor does not contribute.
@@ -312,22 +284,6 @@ __global__ __launch_bounds__(256) void k_grad_redo(DescPtrs d, int64_t n,
     block_reduce_acc(acc, red, rows2 + (int64_t)blockIdx.x * kAcc);
 }
 
-// Fixed-order sum of partial rows: thread t adds rows t, t+256, ... of all 26
-// columns, then the block tree of block_reduce_acc.
-__device__ inline void reduce_partials(const double* __restrict__ partials, int rows, int stride,
-                                       double* red /* [waves][26] */, double* tot /* [26] */)
-{
-    double acc[kAcc];
-#pragma unroll
-    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        const double* row = partials + (int64_t)r * stride;
-#pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
-    }
-    block_reduce_acc(acc, red, tot);
-}
-
 template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int rows,
                                                  double* __restrict__ out)
@@ -344,6 +300,13 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ parti
             out[threadIdx.x - 2] = tot[threadIdx.x];
         }
     }
+}
+
+hipError_t launch_reduce(int mode, const double* partials, int rows, double* out, hipStream_t stream)
+{
+    if (mode == 1) k_reduce<1><<<1, 256, 0, stream>>>(partials, rows, out);
+    else k_reduce<0><<<1, 256, 0, stream>>>(partials, rows, out);
+    return hipGetLastError();
 }
 
 GradLayout grad_layout(int64_t n)
@@ -454,54 +417,11 @@ hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, c
 __device__ inline void adam_update(CalibState* st, const double* tot, const AdamOpts& o, Set* S,
                                    double* loss_hist)
 {
-    // thread 0 of the calling block does the update (24 values); the step
-    // index lives in device memory so one captured graph serves every chunk
-    // of steps
     if (threadIdx.x != 0) return;
-    const int step_index = st->t;
-    st->t = step_index + 1;
-    const double cnt = tot[1];
-    const double loss = cnt > 0.0 ? tot[0] / cnt : 0.0;
-    if (loss_hist && step_index < o.steps)
-        loss_hist[step_index] = st->diverged ? __builtin_nan("") : loss;
-    if (st->diverged) return;
-    bool finite = __builtin_isfinite(loss);
-    double g[kTheta];
-    for (int j = 0; j < kTheta; ++j) {
-        g[j] = cnt > 0.0 ? tot[2 + j] / cnt : 0.0;
-        finite = finite && __builtin_isfinite(g[j]);
+    if (adam_theta_step(st, tot, o, loss_hist)) {
+        make_const<float>(st->theta, S->st, S->cf);
+        make_const<double>(st->theta, S->st, S->cd);
     }
-    if (!finite) {
-        st->diverged = 1;
-        return;
-    }
-    for (int j = 0; j < kTheta; ++j) st->theta_ok[j] = st->theta[j];
-    const double t = (double)(step_index + 1);
-    double lr = o.lr;
-    if (o.lr_final > 0.0 && o.steps > 1)
-        lr = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
-    const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
-    double th_new[kTheta];
-    bool ok = true;
-    for (int j = 0; j < kTheta; ++j) {
-        th_new[j] = st->theta[j];
-        if (!((o.free_mask >> j) & 1u)) continue;
-        const double gp = st->theta[j] * g[j];
-        st->m[j] = o.beta1 * st->m[j] + (1.0 - o.beta1) * gp;
-        st->v[j] = o.beta2 * st->v[j] + (1.0 - o.beta2) * gp * gp;
-        const double mh = st->m[j] / (1.0 - b1t);
-        const double vh = st->v[j] / (1.0 - b2t);
-        st->phi[j] -= lr * mh / (sqrt(vh) + o.eps);
-        th_new[j] = exp(st->phi[j]);
-        ok = ok && __builtin_isfinite(th_new[j]) && th_new[j] > 0.0;
-    }
-    if (!ok) {
-        st->diverged = 1;
-        return;
-    }
-    for (int j = 0; j < kTheta; ++j) st->theta[j] = th_new[j];
-    make_const<float>(st->theta, S->st, S->cf);
-    make_const<double>(st->theta, S->st, S->cd);
 }
 
 __global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partials, int rows,

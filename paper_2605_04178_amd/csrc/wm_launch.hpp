@@ -120,6 +120,9 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
                        const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
                        const LaunchCfg& cfg, double* out, hipStream_t stream);
+// Fixed-order reduction of `rows` partial rows of 26 doubles: mode 0 writes
+// the 24 gradient sums, mode 1 [loss, count, grad[24]] divided by the count.
+hipError_t launch_reduce(int mode, const double* partials, int rows, double* out, hipStream_t stream);
 hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream);
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,

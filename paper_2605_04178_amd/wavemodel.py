@@ -29,7 +29,10 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_calibrate", "wm_calibrate_batched", "wm_get_launch", "wm_set_launch",
             "wm_autotune_predict", "wm_autotune_grad", "wm_autotune_select_tile",
             "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad",
-            "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion")
+            "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion",
+            "wm_bw_validate_params", "wm_bw_workspace_bytes", "wm_bw_predict", "wm_bw_predict_vjp",
+            "wm_bw_loss_grad", "wm_bw_calibrate")
+BW_OP_GRAD, BW_OP_CALIBRATE = 0, 1
 
 
 class WmError(RuntimeError):
@@ -73,6 +76,16 @@ class WmSegs(C.Structure):
 class WmSegParams(C.Structure):
     _fields_ = [("kappa", C.c_double * 4), ("bw_h2d", C.c_double), ("bw_d2h", C.c_double),
                 ("tau_memcpy", C.c_double)]
+
+
+class WmBwParams(C.Structure):
+    _fields_ = [("n_sm", C.c_int32), ("max_cta", C.c_int32), ("tmem_bytes", C.c_int64),
+                ("f_clk", C.c_double), ("theta", C.c_double * N_THETA)]
+
+
+class WmBwDesc(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("bM", "bN", "bK", "G", "flags", "Kt", "CR", "ob")] + [
+        ("n", C.c_int64)]
 
 
 class WmCalibOpts(C.Structure):
@@ -145,6 +158,19 @@ def lib():
         L.wm_plan_workspace_bytes.restype = sz
         L.wm_plan_fusion.argtypes = [D, vp, vp, i64, i32, P, vp, vp, vp, vp, sz, vp]
         L.wm_plan_fusion.restype = i32
+        BP, BD = C.POINTER(WmBwParams), C.POINTER(WmBwDesc)
+        L.wm_bw_validate_params.argtypes = [BP]
+        L.wm_bw_validate_params.restype = i32
+        L.wm_bw_workspace_bytes.argtypes = [i32, i64, i32]
+        L.wm_bw_workspace_bytes.restype = sz
+        L.wm_bw_predict.argtypes = [BD, BP, vp, vp, vp]
+        L.wm_bw_predict.restype = i32
+        L.wm_bw_predict_vjp.argtypes = [BD, BP, vp, vp, vp, sz, vp]
+        L.wm_bw_predict_vjp.restype = i32
+        L.wm_bw_loss_grad.argtypes = [BD, vp, BP, vp, vp, sz, vp]
+        L.wm_bw_loss_grad.restype = i32
+        L.wm_bw_calibrate.argtypes = [BD, vp, BP, C.POINTER(WmCalibOpts), BP, vp, vp, sz, vp]
+        L.wm_bw_calibrate.restype = i32
         _lib = L
     return _lib
 
@@ -452,6 +478,104 @@ def plan_fusion(desc: DeviceDescriptors, edge: torch.Tensor, chain_off: torch.Te
                               0 if ws is None else ws.numel(), _stream(stream))
     _check(rc, "wm_plan_fusion")
     return total[:nc], unf[:nc], start[:desc.n]
+
+
+# ---------------------------------------------------------------------------
+# Blackwell stage-centric family
+# ---------------------------------------------------------------------------
+def bw_params_struct(p, theta: Optional[Sequence[float]] = None) -> WmBwParams:
+    """Marshal a Blackwell parameter set (n_sm, max_cta, tmem_bytes, f_clk, theta)."""
+    o = WmBwParams()
+    o.n_sm, o.max_cta, o.tmem_bytes, o.f_clk = int(p.n_sm), int(p.max_cta), int(p.tmem_bytes), float(p.f_clk)
+    th = p.theta if theta is None else theta
+    for j in range(N_THETA):
+        o.theta[j] = float(th[j])
+    return o
+
+
+def bw_validate_params(p) -> bool:
+    return lib().wm_bw_validate_params(C.byref(bw_params_struct(p))) == WM_OK
+
+
+class DeviceBwDescriptors:
+    """Blackwell tile-kernel descriptors: 5 int32 + 3 float32 device arrays."""
+    INTS = ("bM", "bN", "bK", "G", "flags")
+    FLOATS = ("Kt", "CR", "ob")
+
+    def __init__(self, tensors: dict):
+        n = None
+        for f in self.INTS + self.FLOATS:
+            t = tensors[f]
+            want = torch.int32 if f in self.INTS else torch.float32
+            if t.dtype != want or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError(f"descriptor field {f} must be a contiguous 1-D {want} tensor")
+            n = t.shape[0] if n is None else n
+            if t.shape[0] != n:
+                raise ValueError("descriptor fields differ in length")
+            setattr(self, f, t)
+        self.n = int(n)
+        self.device = tensors["bM"].device
+
+    @classmethod
+    def from_host(cls, d, device="cuda") -> "DeviceBwDescriptors":
+        return cls({f: torch.from_numpy(np.ascontiguousarray(getattr(d, f))).to(device)
+                    for f in cls.INTS + cls.FLOATS})
+
+    def struct(self) -> WmBwDesc:
+        o = WmBwDesc()
+        for f in self.INTS + self.FLOATS:
+            setattr(o, f, getattr(self, f).data_ptr())
+        o.n = self.n
+        return o
+
+
+def bw_workspace_bytes(op: int, n: int, steps: int = 0) -> int:
+    return int(lib().wm_bw_workspace_bytes(op, n, steps))
+
+
+def bw_predict(desc: DeviceBwDescriptors, params, out_T=None, want_cta=True, stream=None):
+    T = out_T if out_T is not None else torch.empty(desc.n, dtype=torch.float32, device=desc.device)
+    cta = torch.empty(desc.n, dtype=torch.int32, device=desc.device) if want_cta else None
+    _check(lib().wm_bw_predict(C.byref(desc.struct()), C.byref(bw_params_struct(params)), _ptr(T), _ptr(cta),
+                               _stream(stream)), "wm_bw_predict")
+    return T, cta
+
+
+def bw_vjp(desc: DeviceBwDescriptors, params, dL_dT: torch.Tensor, ws=None, stream=None):
+    out = torch.empty(N_THETA, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(bw_workspace_bytes(BW_OP_GRAD, desc.n), desc.device)
+    _check(lib().wm_bw_predict_vjp(C.byref(desc.struct()), C.byref(bw_params_struct(params)),
+                                   _ptr(dL_dT.contiguous()), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "wm_bw_predict_vjp")
+    return out
+
+
+def bw_loss_grad(desc: DeviceBwDescriptors, measured: torch.Tensor, params, ws=None, out=None, stream=None):
+    if out is None:
+        out = torch.empty(26, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(bw_workspace_bytes(BW_OP_GRAD, desc.n), desc.device)
+    _check(lib().wm_bw_loss_grad(C.byref(desc.struct()), _ptr(measured), C.byref(bw_params_struct(params)),
+                                 _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "wm_bw_loss_grad")
+    return out
+
+
+def bw_calibrate(desc: DeviceBwDescriptors, measured: torch.Tensor, p0, steps=500, lr=0.05, lr_final=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None, stream=None):
+    """Device Adam on log(theta) for the Blackwell model.  Returns (status,
+    theta float64 [24], loss history)."""
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+    if ws is None:
+        ws = _workspace(bw_workspace_bytes(BW_OP_CALIBRATE, desc.n, steps), desc.device)
+    pout = WmBwParams()
+    hist = np.zeros(steps)
+    rc = lib().wm_bw_calibrate(C.byref(desc.struct()), _ptr(measured), C.byref(bw_params_struct(p0)),
+                               C.byref(opts), C.byref(pout), hist.ctypes.data, _ptr(ws), ws.numel(),
+                               _stream(stream))
+    if rc not in (WM_OK, WM_EDIVERGED):
+        raise WmError(rc, "wm_bw_calibrate")
+    return rc, np.array([pout.theta[j] for j in range(N_THETA)]), hist
 
 
 def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,

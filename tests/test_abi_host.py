@@ -265,6 +265,41 @@ def test_planning_calls_validate_before_any_hip_call(wmb):
     assert L.wm_last_hip_error() == 0
 
 
+def test_blackwell_calls_validate_before_any_hip_call(wmb):
+    L = wmb.lib()
+    assert C.sizeof(wmb.WmBwParams) == 4 + 4 + 8 + 8 + 24 * 8 and C.sizeof(wmb.WmBwDesc) == 8 * 8 + 8
+    p = synth.b200_like()
+    assert wmb.bw_validate_params(p)
+    for s in range(5):
+        assert wmb.bw_validate_params(synth.bw_param_set(s))
+    for kw in (dict(n_sm=0), dict(max_cta=0), dict(tmem_bytes=0), dict(f_clk=0.0)):
+        assert not wmb.bw_validate_params(p.copy(**kw)), kw
+    for j, v in ((0, 0.0), (5, -1.0), (8, 0.0), (14, 0.0), (17, -0.1), (22, -1e-6), (9, float("nan"))):
+        th = list(p.theta)
+        th[j] = v
+        assert not wmb.bw_validate_params(p.copy(theta=th)), (j, v)
+    ps = wmb.bw_params_struct(p)
+    d = wmb.WmBwDesc()
+    for i, f in enumerate(wmb.DeviceBwDescriptors.INTS + wmb.DeviceBwDescriptors.FLOATS):
+        setattr(d, f, 0x1000 * (i + 1))
+    d.n = 16
+    x = C.c_void_p(0x9000)
+    assert L.wm_bw_predict(C.byref(d), C.byref(ps), None, None, None) == wmb.WM_EINVAL
+    d0 = wmb.WmBwDesc()
+    assert L.wm_bw_predict(C.byref(d0), C.byref(ps), None, None, None) == wmb.WM_OK
+    need = wmb.bw_workspace_bytes(wmb.BW_OP_GRAD, 16)
+    assert need > 0 and wmb.bw_workspace_bytes(wmb.BW_OP_CALIBRATE, 16, 0) == 0
+    assert wmb.bw_workspace_bytes(wmb.BW_OP_CALIBRATE, 16, 10) > need
+    assert L.wm_bw_loss_grad(C.byref(d), x, C.byref(ps), x, None, 0, None) == wmb.WM_EWORKSPACE
+    assert L.wm_bw_loss_grad(C.byref(d), None, C.byref(ps), x, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    o = wmb.calib_opts(steps=5, free_mask=1 << 17)
+    th = list(p.theta)
+    th[17] = 0.0
+    assert L.wm_bw_calibrate(C.byref(d), x, C.byref(wmb.bw_params_struct(p.copy(theta=th))), C.byref(o),
+                             C.byref(wmb.WmBwParams()), None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    assert L.wm_last_hip_error() == 0
+
+
 def test_product_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_2605_04178_amd import wavemodel
     monkeypatch.setattr(wavemodel, "_lib", None)
