@@ -165,6 +165,16 @@ def profile_run(wm, synth, dd, p, n, dev):
     torch.cuda.synchronize()
     log("profile: plan_fusion x3, fit_multipliers x3 done")
     del dd3, de, doff, T4, m4
+    pb = synth.bw_param_set(0)
+    db = wm.DeviceBwDescriptors.from_host(synth.bw_descriptors(n, 230), dev)
+    for _ in range(5):
+        Tb, _ = wm.bw_predict(db, pb)
+    mb_ = (Tb * 1.02).contiguous()
+    for _ in range(3):
+        wm.bw_loss_grad(db, mb_, synth.bw_param_set(1))
+    torch.cuda.synchronize()
+    log("profile: bw_predict x5, bw_loss_grad x3 done")
+    del db, Tb, mb_
     a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(3):
@@ -259,6 +269,39 @@ def planning_leg(wm, synth, args, dev, log):
                             "rows_per_s": d2.n / (ev_m * 1e-3),
                             "train_mre": float(stt[0] / max(stt[1], 1)),
                             "holdout_mre": float(stt[2] / max(stt[3], 1))}}
+
+
+BW_FWD_BYTES = 40    # 5 int32 + 3 float32 read, T f32 + cta i32 written
+BW_ADJ_BYTES = 36    # 32 read + measured f32
+
+
+def blackwell_leg(wm, synth, args, dev, log):
+    """The Blackwell stage-centric family over 2^24 tile-kernel descriptors:
+    forward sweep and forward + adjoint (loss and gradient)."""
+    import torch
+    n = 1 << 24
+    p = synth.bw_param_set(0)
+    d = synth.bw_descriptors(n, 230)
+    dd = wm.DeviceBwDescriptors.from_host(d, dev)
+    T = torch.empty(n, dtype=torch.float32, device=dev)
+    fw = lambda: wm.bw_predict(dd, p, out_T=T)
+    wall_f, ev_f = timed(fw, args.steps, args.warmup)
+    Tm, _ = wm.bw_predict(dd, synth.bw_param_set(1), want_cta=False)
+    meas = (Tm * torch.from_numpy(synth.lognormal_noise(n, 231, 0.02).astype(np.float32)).to(dev)).contiguous()
+    del Tm
+    ws = wm._workspace(wm.bw_workspace_bytes(wm.BW_OP_GRAD, n), dev)
+    out = torch.empty(26, dtype=torch.float64, device=dev)
+    lg = lambda: wm.bw_loss_grad(dd, meas, p, ws=ws, out=out)
+    wall_g, ev_g = timed(lg, max(args.steps // 2, 3), 2)
+    gf = BW_FWD_BYTES * n / (ev_f * 1e-3) / 1e9
+    gg = BW_ADJ_BYTES * n / (ev_g * 1e-3) / 1e9
+    log(f"blackwell: forward {ev_f:.4f} ms ({gf:.0f} GB/s), fwd+adjoint {ev_g:.4f} ms ({gg:.0f} GB/s)")
+    return {"descriptors": n, "param_set": "Blackwell-style seed 0",
+            "forward": {"evals_per_s": n / (ev_f * 1e-3), "event_ms": ev_f, "ms_per_call": wall_f,
+                        "achieved_GBs": gf, "hbm_frac": gf / HBM_PEAK_GBS, "bytes_per_eval": BW_FWD_BYTES,
+                        "traffic": counted_traffic("void wm::k_bw_predict<256>")},
+            "fwd_adjoint": {"evals_per_s": n / (ev_g * 1e-3), "event_ms": ev_g, "ms_per_call": wall_g,
+                            "achieved_GBs": gg, "hbm_frac": gg / HBM_PEAK_GBS, "bytes_per_eval": BW_ADJ_BYTES}}
 
 
 def hardware_model_leg(wm, log):
@@ -473,6 +516,7 @@ def main():
 
         res["segments"] = segments_leg(wm, synth, args, dev, tuned)
         res["planning"] = planning_leg(wm, synth, args, dev, log)
+        res["blackwell"] = blackwell_leg(wm, synth, args, dev, log)
         res["mi355x_model"] = hardware_model_leg(wm, log)
 
     if tuned:

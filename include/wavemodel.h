@@ -387,8 +387,8 @@ int32_t wm_plan_fusion(const wm_desc_t *desc, const float *edge, const int32_t *
  *   20 L_alloc + L_dealloc (TMEM management, amortised over K-steps)
  *   21 O_misc (per step)  22 T_launch  23 BW_dsmem (2-SM B-tile exchange)
  * All slots > 0 except 2, 9, 11, 12, 16, 19, 20, 21, 22 (>= 0) and
- * 17 (>= 0).  Structure: n_sm, max_cta (CTAs per SM cap), tmem_bytes per
- * SM, f_clk.
+ * 17 (>= 0).  Structure: n_sm (1..65536), max_cta (CTAs per SM cap,
+ * 1..64), tmem_bytes per SM (1 .. 2^30 - 1), f_clk.
  * Descriptors (structure of arrays, 32 B each): bM, bN, bK tile sizes
  * (>= 1), G CTAs (>= 1), flags ([0,3) dtype 0..4, [3] 2-SM pair, [4] TMEM
  * strategy B (A tile through TMEM), [5,9) P_A - 1, [9,13) P_B - 1 multicast

@@ -130,17 +130,19 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
     E.comp = comp;
     E.nbar = nbar;
 
-    // residency: accumulator bytes (8 per element for FP64, else 4)
+    // residency: accumulator bytes (8 per element for FP64, else 4); TMEM is
+    // below 2^30 bytes, so once the accumulator fits every quotient is a
+    // 32-bit one (n_sm * cta <= 2^22, G < 2^31)
     const int64_t acc = (int64_t)d.bM * (int64_t)d.bN * (dt == 0 ? 8 : 4);
-    int64_t cta = st.tmem_bytes / acc;
-    cta = cta < st.max_cta ? cta : st.max_cta;
+    uint32_t cta = acc > st.tmem_bytes ? 0u : (uint32_t)st.tmem_bytes / (uint32_t)acc;
+    cta = cta < (uint32_t)st.max_cta ? cta : (uint32_t)st.max_cta;
     E.cta = (int32_t)cta;
     if (cta < 1) {
         E.T = (R)__builtin_huge_val();
         return;
     }
-    const int64_t per_round = (int64_t)st.n_sm * cta;
-    const int64_t nr = ((int64_t)d.G + per_round - 1) / per_round;
+    const uint32_t per_round = (uint32_t)st.n_sm * cta;
+    const uint32_t nr = ((uint32_t)d.G + per_round - 1u) / per_round;
     E.nr = (int32_t)nr;
 
     const R e = dt == 0 ? (R)8 : (dt == 1 ? (R)4 : (dt == 2 ? (R)2 : (dt == 3 ? (R)1 : (R)0.5)));

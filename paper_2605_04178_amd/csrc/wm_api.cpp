@@ -269,7 +269,7 @@ bool bw_params_ok(const wm_bw_params_t* p)
 {
     if (!p) return false;
     if (p->n_sm < 1 || p->n_sm > 65536 || p->max_cta < 1 || p->max_cta > 64) return false;
-    if (p->tmem_bytes < 1 || p->tmem_bytes > (1ll << 40)) return false;
+    if (p->tmem_bytes < 1 || p->tmem_bytes >= (1ll << 30)) return false;
     if (!(fin(p->f_clk) && p->f_clk > 0.0 && f32_pos(1.0 / p->f_clk))) return false;
     const double* th = p->theta;
     for (int j = 0; j < WM_N_THETA; ++j)

@@ -104,10 +104,25 @@ __global__ __launch_bounds__(BLOCK) void k_bw_grad(BwDescPtrs d, int64_t n, cons
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63); base < n; base += stride) {
+    // software pipeline: the next group's loads are in flight while this
+    // group is evaluated
+    int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63);
+    BwDesc xn;
+    float wn = 0.0f;
+    if (base + lane < n) {
+        xn = load_bw_desc(d, base + lane);
+        wn = ntload(wv + base + lane);
+    }
+    for (; base < n; base += stride) {
         const int64_t i = base + lane;
+        const BwDesc x = xn;
+        const float w = wn;
+        if (i + stride < n) {
+            xn = load_bw_desc(d, i + stride);
+            wn = ntload(wv + i + stride);
+        }
         bool redo = false;
-        if (i < n) redo = bw_grad_fast<MODE>(S, load_bw_desc(d, i), ntload(wv + i), acc);
+        if (i < n) redo = bw_grad_fast<MODE>(S, x, w, acc);
         const uint64_t m = __ballot(redo);
         if (lane == 0) flags[base >> 6] = m;
     }
