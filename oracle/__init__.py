@@ -501,3 +501,19 @@ def bw_calibrate(p0, d, measured, steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, 
     rc = _bw_lib().bw_calibrate(C.byref(bw_params(p0)), C.byref(o), m.ctypes.data, int(steps), lr, lr_final,
                                 beta1, beta2, eps, int(free_mask), C.byref(pout), hist.ctypes.data)
     return rc, np.array([pout.theta[j] for j in range(BW_NTHETA)]), hist
+
+
+def apps_vjp(p, q, d, sg, w_app):
+    """(sum_a w_a dT_a/dtheta [24], sum_a w_a dT_a/dsegparam [7])."""
+    L = _seg_lib()
+    if not hasattr(L, "_vjp_ready"):
+        L.orc_apps_vjp.argtypes = [C.POINTER(OrcParams), C.POINTER(OrcSegp), C.POINTER(OrcDesc),
+                                   C.POINTER(OrcSegs), C.c_void_p, C.c_void_p]
+        L._vjp_ready = True
+    o, keep = _desc(d)
+    so, skeep = _segs(sg)
+    w = np.ascontiguousarray(w_app, np.float64)
+    out = np.zeros(N_THETA + N_SEGP)
+    L.orc_apps_vjp(C.byref(params(p)), C.byref(segp(q)), C.byref(o), C.byref(so), w.ctypes.data,
+                   out.ctypes.data)
+    return out[:N_THETA].copy(), out[N_THETA:].copy()

@@ -936,3 +936,35 @@ void orc_plan_fusion(const orc_params_t *p, const orc_desc_t *d, const float *ed
         free(cut);
     }
 }
+
+/*
+ * Vector-Jacobian product of the application totals: out[0..23] =
+ * sum_a w_a dT_a/dtheta, out[24..30] = sum_a w_a dT_a/d(segment parameters),
+ * over applications with finite T_a.  Fixed-order sums.
+ */
+void orc_apps_vjp(const orc_params_t *p, const orc_segp_t *q, const orc_desc_t *d,
+                  const orc_segs_t *s, const double *w_app, double *out)
+{
+    const int NO = N_THETA + ORC_NSEG;
+    int64_t na = s->n_apps;
+    double *part = (double *)calloc((size_t)(na > 0 ? na : 1) * NO, sizeof(double));
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < na; ++a) {
+        double *row = part + a * NO;
+        double tot = 0.0;
+        for (int64_t i = s->app_off[a]; i < s->app_off[a + 1]; ++i)
+            tot += orc_segment(p, q, d, s, i, NULL, NULL);
+        if (!isfinite(tot)) continue;
+        const double w = w_app[a];
+        double dth[N_THETA], dsp[ORC_NSEG];
+        for (int64_t i = s->app_off[a]; i < s->app_off[a + 1]; ++i) {
+            orc_segment(p, q, d, s, i, dth, dsp);
+            for (int j = 0; j < N_THETA; ++j) row[j] += w * dth[j];
+            for (int j = 0; j < ORC_NSEG; ++j) row[N_THETA + j] += w * dsp[j];
+        }
+    }
+    memset(out, 0, sizeof(double) * NO);
+    for (int64_t a = 0; a < na; ++a)
+        for (int j = 0; j < NO; ++j) out[j] += part[a * NO + j];
+    free(part);
+}

@@ -214,3 +214,39 @@ def test_app_loss_skips_nonfinite_and_bad_measurements(orc, case):
     loss, cnt, _, _ = orc.apps_loss_grad(p, q, d, sg, m)
     assert cnt == sg.n_apps - 4
     assert abs(loss - 0.1 / 1.1) <= 1e-12
+
+
+def test_app_vjp_matches_finite_differences(orc):
+    p = synth.param_set(3)
+    q = synth.seg_params(10)
+    sg, d = synth.segments(200, 132)
+    Ta, _ = orc.predict_apps(p, q, d, sg)
+    w = np.random.default_rng(4).standard_normal(sg.n_apps)
+    gth, gsp = orc.apps_vjp(p, q, d, sg, w)
+    ok = np.isfinite(Ta)
+
+    def F(pp=None, qq=None):
+        T, _ = orc.predict_apps(pp or p, qq or q, d, sg)
+        return float(np.sum(w[ok] * T[ok]))
+    h = 1e-6
+    th0 = np.array(p.theta)
+    tr = orc.trace(p, d)
+    for j in range(24):
+        if gth[j] == 0.0:
+            continue
+        tp, tm = th0.copy(), th0.copy()
+        tp[j] *= 1 + h
+        tm[j] *= 1 - h
+        fd = (F(pp=p.copy(theta=list(tp))) - F(pp=p.copy(theta=list(tm)))) / (2 * h * th0[j])
+        scale = np.sum(np.abs(w[ok] * Ta[ok])) / th0[j]
+        assert abs(fd - gth[j]) <= 1e-4 * abs(gth[j]) + 1e-7 * scale, (j, fd, gth[j])
+    vals = list(q.kappa) + [q.bw_h2d, q.bw_d2h, q.tau_memcpy]
+    for j in range(7):
+        def qq(v):
+            x = list(vals)
+            x[j] = v
+            return synth.SegParams(kappa=x[:4], bw_h2d=x[4], bw_d2h=x[5], tau_memcpy=x[6])
+        # T is linear in kappa and tau (large steps are exact), smooth in 1/B
+        hs = 1e-4 if j in (4, 5) else 1e-2
+        fd = (F(qq=qq(vals[j] * (1 + hs))) - F(qq=qq(vals[j] * (1 - hs)))) / (2 * hs * vals[j])
+        assert abs(fd - gsp[j]) <= 1e-6 * abs(gsp[j]) + 1e-12, (j, fd, gsp[j])
