@@ -328,6 +328,17 @@ int32_t wm_apps_loss_grad(const wm_desc_t *desc, const wm_segs_t *segs, const fl
                           void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Vector-Jacobian product of the application times: given dL/dT_app
+ * [n_apps] float32, out [31] float64 device = sum over applications with
+ * finite T_app of dL/dT_app * dT_app/d(theta[24], kappa[4], bw_h2d, bw_d2h,
+ * tau_memcpy) (subgradients of the kernel model as in wm_predict_vjp).
+ * Workspace: wm_apps_workspace_bytes(n, n_apps).
+ */
+int32_t wm_predict_apps_vjp(const wm_desc_t *desc, const wm_segs_t *segs, const float *dL_dTapp,
+                            const wm_params_t *params, const wm_segparams_t *segp, double *out,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Per-group calibration multipliers (Section IV-D: optional per-case
  * multipliers, fitted with train / holdout separation; Section V-B: m_case).
  * Group g owns rows [group_off[g], group_off[g+1]) of n rows (CSR,

@@ -995,6 +995,26 @@ int32_t wm_apps_loss_grad(const wm_desc_t* desc, const wm_segs_t* segs, const fl
     return WM_OK;
 }
 
+int32_t wm_predict_apps_vjp(const wm_desc_t* desc, const wm_segs_t* segs, const float* dL_dTapp,
+                            const wm_params_t* params, const wm_segparams_t* segp, double* out,
+                            void* ws, size_t ws_bytes, void* stream)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !segp_ok(segp) || !segs_ok(segs, desc->n) || !out)
+        return WM_EINVAL;
+    if (segs->n_apps > 0 && !dL_dTapp) return WM_EINVAL;
+    const AppsWs W = apps_ws(desc->n, segs->n_apps);
+    if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
+    char* base = (char*)ws;
+    const Set S = make_set(params);
+    WM_HIP(launch_apps_vjp(ptrs_of(desc), segptrs_of(segs), desc->n, segs->n_apps, dL_dTapp, S,
+                           make_segset(segp), (float*)(base + W.wseg), (double*)(base + W.rows),
+                           (double*)(base + W.grad + W.g.partials),
+                           (uint64_t*)(base + W.grad + W.g.flags), W.g.g,
+                           launch_cfg(kOpAppsLossGrad, segs->n_apps), launch_cfg(kOpVjp, desc->n),
+                           out, (hipStream_t)stream));
+    return WM_OK;
+}
+
 int32_t wm_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
                        const uint32_t* cand_code, int64_t n_cand, const wm_params_t* params,
                        int32_t* best, double* best_cost, uint8_t* near_tie, void* stream)

@@ -158,6 +158,13 @@ hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_
                               int64_t n_chains, int64_t n, int32_t R, const Set& S,
                               const double* peaks, double* cost, double* best, uint8_t* cut,
                               double* total, double* unfused, uint8_t* start, hipStream_t s);
+// Vector-Jacobian product of the application totals: out [31] = sum_a
+// w_app[a] dT_a/d(theta[24], seg params[7]); workspace as the loss gradient.
+hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                           const float* w_app, const Set& S, const SegSet& Q, float* wseg,
+                           double* app_rows, double* partials, uint64_t* flags, const GradLayout& L,
+                           const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
+                           hipStream_t stream);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
                               double* best_cost, uint8_t* near_tie, const LaunchCfg& cfg,

@@ -104,18 +104,19 @@ __device__ inline void block_sum(double* acc, double* lds /* [waves][NA] */, dou
 // Application sweep.  A block takes BLOCK consecutive applications (one per
 // thread); their rows are staged in LDS in pieces of 8 x BLOCK rows (one
 // piece unless the chunk averages more than 8 rows per application).
-// LOSS = false: T_app[a] (float32) and optionally the segment times.
-// LOSS = true: after the application totals, a second row-parallel pass
-// writes the adjoint weights wseg[j] = sign(T_a - m_a) / m_a * n_exec_j *
-// kappa_cls(j) for the kernel model's vector-Jacobian product and adds
-// sign/m times each row's n_exec (n_kern - 1), n_exec Tk (per class),
+// MODE 0: T_app[a] (float32) and optionally the segment times.
+// MODE 1 (loss) and MODE 2 (vector-Jacobian product, weights dL/dT_app read
+// from `meas`): after the application totals, a second row-parallel pass
+// writes the adjoint weights wseg[j] = w_a * n_exec_j * kappa_cls(j) for the
+// kernel model's vector-Jacobian product, with w_a = sign(T_a - m_a) / m_a
+// (MODE 1) or dL/dT_app[a] (MODE 2), and adds w_a times each row's n_exec (n_kern - 1), n_exec Tk (per class),
 // n_exec h2d, n_exec d2h and n_exec x transfers; per block one row of
-// kAppAcc float64 sums (loss, count, those seven).  An application with
-// |T_a/m_a - 1| <= 1e-5 in this float32 sweep gets zero weights and is
+// kAppAcc float64 sums (loss, count, those seven).  In MODE 1 an application
+// with |T_a/m_a - 1| <= 1e-5 in this float32 sweep gets zero weights and is
 // flagged in aflags (one 64-bit ballot word per 64 applications) for
 // k_apps_redo.  Offsets are caller data: they are clamped into [0, n_seg],
 // so malformed offsets give unspecified values but no out-of-range access.
-template <int BLOCK, bool LOSS>
+template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t n_seg,
                                                int64_t n_apps, Set S, SegSet Q,
                                                const float* __restrict__ meas,
@@ -123,6 +124,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
                                                float* __restrict__ wseg, double* __restrict__ rows,
                                                uint64_t* __restrict__ aflags)
 {
+    constexpr bool LOSS = MODE != 0;  // loss (1) and vector-Jacobian product (2) share the weights pass
     constexpr int CAP = 8 * BLOCK;
     constexpr int LC = LOSS ? CAP : 1;
     __shared__ float ts[CAP];
@@ -191,7 +193,9 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
         }
         float wa = 0.0f;
         bool near = false;
-        if (tid < na) {
+        if (MODE == 2 && tid < na && tot - tot == 0.0) {
+            wa = meas[a];  // dL/dT_app
+        } else if (MODE == 1 && tid < na) {
             const float mf = meas[a];
             if (tot - tot == 0.0 && mf > 0.0f && mf < __builtin_huge_valf()) {
                 const double m = mf, im = 1.0 / m;
@@ -205,8 +209,10 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
                 }
             }
         }
-        const uint64_t fw = __ballot(near);
-        if ((tid & 63) == 0 && a < n_apps) aflags[a >> 6] = fw;
+        if (MODE == 1) {
+            const uint64_t fw = __ballot(near);
+            if ((tid & 63) == 0 && a < n_apps) aflags[a >> 6] = fw;
+        }
         wa_s[tid] = wa;
         __syncthreads();
         // row-parallel pass: weights and the segment-parameter sums.  With one
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(256) void k_apps_redo(DescPtrs d, SegPtrs sg, int64
 // the count.
 __global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ grows, int ng,
                                                      const double* __restrict__ arows, int na,
-                                                     SegSet Q, double* __restrict__ out)
+                                                     SegSet Q, int vjp, double* __restrict__ out)
 {
     __shared__ double red[4 * kAcc];
     __shared__ double tg[kAcc], ta[kAppAcc];
@@ -370,6 +376,18 @@ __global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ 
         block_sum<kAppAcc>(acc, red, ta);
     }
     const int t = threadIdx.x;
+    if (vjp) {
+        // [grad theta[24], grad seg params[7]], plain sums
+        if (t >= kTheta + kSegParams) return;
+        double v;
+        if (t < kTheta) v = tg[2 + t] + (t == 13 ? ta[2] : 0.0);
+        else if (t < kTheta + 4) v = ta[3 + (t - kTheta)];
+        else if (t == kTheta + 4) v = -ta[7] * Q.inv_bw2_h2d;
+        else if (t == kTheta + 5) v = -ta[8] * Q.inv_bw2_d2h;
+        else v = ta[9];
+        out[t] = v;
+        return;
+    }
     if (t >= kAppsOut) return;
     const double c = ta[1];
     const double ic = c > 0.0 ? 1.0 / c : 0.0;
@@ -384,18 +402,18 @@ __global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ 
     out[t] = v;
 }
 
-template <int BLOCK, bool LOSS>
+template <int BLOCK, int MODE>
 static int apps_grid(int64_t n_apps, int grid_mult)
 {
     const int64_t chunks = (n_apps + BLOCK - 1) / BLOCK;
-    int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_apps<BLOCK, LOSS>), BLOCK) *
+    int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_apps<BLOCK, MODE>), BLOCK) *
                 (grid_mult < 1 ? 1 : grid_mult);
     b = b < chunks ? b : chunks;
     b = b < kAppsMaxBlocks ? b : kAppsMaxBlocks;
     return (int)(b < 1 ? 1 : b);
 }
 
-template <bool LOSS>
+template <int MODE>
 static hipError_t apps_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
                          const Set& S, const SegSet& Q, const float* meas, float* T_app,
                          float* T_seg, float* wseg, double* rows, uint64_t* aflags,
@@ -403,7 +421,7 @@ static hipError_t apps_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, in
 {
 #define WM_APPS_CASE(B)                                                                        \
     case B:                                                                                    \
-        k_apps<B, LOSS><<<apps_grid<B, LOSS>(n_apps, c.grid_mult), B, 0, s>>>(                 \
+        k_apps<B, MODE><<<apps_grid<B, MODE>(n_apps, c.grid_mult), B, 0, s>>>(                 \
             d, sg, n_seg, n_apps, S, Q, meas, T_app, T_seg, wseg, rows, aflags);               \
         break;
     switch (c.block) {
@@ -422,18 +440,20 @@ hipError_t launch_predict_apps(const DescPtrs& d, const SegPtrs& sg, int64_t n_s
                                const LaunchCfg& cfg, hipStream_t stream)
 {
     if (n_apps <= 0) return hipSuccess;
-    return apps_t<false>(d, sg, n_seg, n_apps, S, Q, nullptr, T_app, T_seg, nullptr, nullptr,
-                         nullptr, cfg, stream);
+    return apps_t<0>(d, sg, n_seg, n_apps, S, Q, nullptr, T_app, T_seg, nullptr, nullptr,
+                     nullptr, cfg, stream);
 }
 
-// Rows the application sweep writes for n_apps applications (at least one).
+// Rows the application sweep of mode MODE writes for n_apps applications
+// (at least one).
+template <int MODE>
 static int apps_rows(int64_t n_apps, const LaunchCfg& c)
 {
     switch (c.block) {
-    case 64: return apps_grid<64, true>(n_apps, c.grid_mult);
-    case 128: return apps_grid<128, true>(n_apps, c.grid_mult);
-    case 512: return apps_grid<512, true>(n_apps, c.grid_mult);
-    default: return apps_grid<256, true>(n_apps, c.grid_mult);
+    case 64: return apps_grid<64, MODE>(n_apps, c.grid_mult);
+    case 128: return apps_grid<128, MODE>(n_apps, c.grid_mult);
+    case 512: return apps_grid<512, MODE>(n_apps, c.grid_mult);
+    default: return apps_grid<256, MODE>(n_apps, c.grid_mult);
     }
 }
 
@@ -450,10 +470,10 @@ hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n
                                  const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
                                  hipStream_t stream)
 {
-    hipError_t e = apps_t<true>(d, sg, n_seg, n_apps, S, Q, measured, nullptr, nullptr, wseg,
-                                app_rows, aflags, cfg, stream);
+    hipError_t e = apps_t<1>(d, sg, n_seg, n_apps, S, Q, measured, nullptr, nullptr, wseg,
+                             app_rows, aflags, cfg, stream);
     if (e != hipSuccess) return e;
-    const int na1 = apps_rows(n_apps, cfg), na2 = apps_redo_blocks(n_apps);
+    const int na1 = apps_rows<1>(n_apps, cfg), na2 = apps_redo_blocks(n_apps);
     double* rows2 = app_rows + (int64_t)na1 * kAppAcc;
     k_apps_redo<<<na2, 256, 0, stream>>>(d, sg, n_seg, n_apps, S, Q, measured, aflags, app_rows,
                                          na1, wseg, rows2);
@@ -462,7 +482,24 @@ hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n
     e = launch_grad(0, d, n_seg, wseg, S, nullptr, partials, flags, L, vjp_cfg, nullptr, stream);
     if (e != hipSuccess) return e;
     const int nb = grad_grid(0, false, n_seg, vjp_cfg);
-    k_apps_reduce<<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, rows2, na2, Q, out);
+    k_apps_reduce<<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, rows2, na2, Q, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                           const float* w_app, const Set& S, const SegSet& Q, float* wseg,
+                           double* app_rows, double* partials, uint64_t* flags, const GradLayout& L,
+                           const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
+                           hipStream_t stream)
+{
+    hipError_t e = apps_t<2>(d, sg, n_seg, n_apps, S, Q, w_app, nullptr, nullptr, wseg, app_rows,
+                             nullptr, cfg, stream);
+    if (e != hipSuccess) return e;
+    e = launch_grad(0, d, n_seg, wseg, S, nullptr, partials, flags, L, vjp_cfg, nullptr, stream);
+    if (e != hipSuccess) return e;
+    const int nb = grad_grid(0, false, n_seg, vjp_cfg);
+    k_apps_reduce<<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, app_rows,
+                                         apps_rows<2>(n_apps, cfg), Q, 1, out);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad",
             "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion",
             "wm_bw_validate_params", "wm_bw_workspace_bytes", "wm_bw_predict", "wm_bw_predict_vjp",
-            "wm_bw_loss_grad", "wm_bw_calibrate")
+            "wm_bw_loss_grad", "wm_bw_calibrate", "wm_predict_apps_vjp")
 BW_OP_GRAD, BW_OP_CALIBRATE = 0, 1
 
 
@@ -150,6 +150,8 @@ def lib():
         L.wm_predict_apps.restype = i32
         L.wm_apps_loss_grad.argtypes = [D, SG, vp, P, SP, vp, vp, sz, vp]
         L.wm_apps_loss_grad.restype = i32
+        L.wm_predict_apps_vjp.argtypes = [D, SG, vp, P, SP, vp, vp, sz, vp]
+        L.wm_predict_apps_vjp.restype = i32
         L.wm_autotune_apps.argtypes = [i32, D, SG, vp, P, SP, vp, vp, vp, sz, vp, LP, dp]
         L.wm_autotune_apps.restype = i32
         L.wm_fit_multipliers.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz, vp]
@@ -576,6 +578,54 @@ def bw_calibrate(desc: DeviceBwDescriptors, measured: torch.Tensor, p0, steps=50
     if rc not in (WM_OK, WM_EDIVERGED):
         raise WmError(rc, "wm_bw_calibrate")
     return rc, np.array([pout.theta[j] for j in range(N_THETA)]), hist
+
+
+def apps_vjp(desc: DeviceDescriptors, segs: DeviceSegments, dL_dTapp: torch.Tensor, params, segp,
+             ws=None, stream=None, theta=None):
+    """dL/d(theta[24], kappa[4], bw_h2d, bw_d2h, tau_memcpy) float64 [31] on the
+    device for an upstream gradient of the application times."""
+    _check_rows(desc, segs)
+    out = torch.empty(N_THETA + N_SEGPARAMS, dtype=torch.float64, device=desc.device)
+    if ws is None:
+        ws = _workspace(apps_workspace_bytes(desc.n, segs.n_apps), desc.device)
+    rc = lib().wm_predict_apps_vjp(C.byref(desc.struct()), C.byref(segs.struct()), _ptr(dL_dTapp.contiguous()),
+                                   C.byref(params_struct(params, theta)), C.byref(segparams_struct(segp)),
+                                   _ptr(out), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream))
+    _check(rc, "wm_predict_apps_vjp")
+    return out
+
+
+class _SegVec:
+    """Segment parameters from a 7-vector (kappa[4], bw_h2d, bw_d2h, tau)."""
+
+    def __init__(self, v):
+        self.kappa = [float(x) for x in v[:4]]
+        self.bw_h2d, self.bw_d2h, self.tau_memcpy = float(v[4]), float(v[5]), float(v[6])
+
+
+class WMPredictApps(torch.autograd.Function):
+    """T_app = WMPredictApps.apply(desc, segs, theta, segvec, params): theta
+    float64 [24] and segvec float64 [7] (kappa[4], bw_h2d, bw_d2h,
+    tau_memcpy); T_app float32 [n_apps].  backward returns the gradients of
+    both from the application adjoint (wm_predict_apps_vjp)."""
+
+    @staticmethod
+    def forward(ctx, desc, segs, theta, segvec, params):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        sv = _SegVec(segvec.detach().to("cpu", torch.float64).numpy())
+        ctx.desc, ctx.segs, ctx.params, ctx.th, ctx.sv = desc, segs, params, th, sv
+        ctx.dev_t, ctx.dev_s = theta.device, segvec.device
+        T = torch.empty(segs.n_apps, dtype=torch.float32, device=desc.device)
+        rc = lib().wm_predict_apps(C.byref(desc.struct()), C.byref(segs.struct()),
+                                   C.byref(params_struct(params, th)), C.byref(segparams_struct(sv)),
+                                   _ptr(T), None, _stream())
+        _check(rc, "wm_predict_apps")
+        return T
+
+    @staticmethod
+    def backward(ctx, dL_dT):
+        g = apps_vjp(ctx.desc, ctx.segs, dL_dT.to(torch.float32).contiguous(), ctx.params, ctx.sv, theta=ctx.th)
+        return None, None, g[:N_THETA].to(ctx.dev_t), g[N_THETA:].to(ctx.dev_s), None
 
 
 def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,

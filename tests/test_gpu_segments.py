@@ -179,3 +179,31 @@ def test_apps_full_size(wmb, orc):
     m = Ra * synth.lognormal_noise(sg.n_apps, 151, 0.05)
     p0 = synth.perturb_theta(p, 152, factor=1.2)
     _grad_check(wmb, orc, p0, q, sg, d, m, "full size")
+
+
+def test_apps_vjp_and_autograd(wmb, orc):
+    p = synth.param_set(8)
+    q = synth.seg_params(18)
+    sg, d = synth.segments(40000, 153)
+    dd, ds = _dev(wmb, sg, d)
+    w = np.random.default_rng(9).standard_normal(sg.n_apps).astype(np.float32)
+    g = wmb.apps_vjp(dd, ds, torch.from_numpy(w).cuda(), p, q).cpu().numpy()
+    gth, gsp = orc.apps_vjp(p, q, d, sg, w.astype(np.float64))
+    e1, e2 = grad_err(g[:24], gth), grad_err(g[24:], gsp)
+    say("apps vjp err", e1, e2)
+    assert e1 <= GTOL and e2 <= GTOL
+    # through autograd: L = sum(w * T_app) over finite applications
+    theta = torch.tensor(p.theta, dtype=torch.float64, requires_grad=True)
+    sv = torch.tensor(list(q.kappa) + [q.bw_h2d, q.bw_d2h, q.tau_memcpy], dtype=torch.float64,
+                      requires_grad=True)
+    T = wmb.WMPredictApps.apply(dd, ds, theta, sv, p)
+    wt = torch.from_numpy(w).cuda()
+    fin = torch.isfinite(T)
+    (wt[fin] * T[fin]).double().sum().backward()
+    assert grad_err(theta.grad.numpy(), gth) <= GTOL and grad_err(sv.grad.numpy(), gsp) <= GTOL
+    # no applications: zeros
+    d0 = synth.descriptors(0, 1)
+    s0 = synth.Segments(np.zeros(1, np.int32), *[np.zeros(0, t) for t in
+                        (np.float32, np.int32, np.int32, np.float32, np.float32)])
+    z = wmb.apps_vjp(*_dev(wmb, s0, d0), torch.zeros(0, device="cuda"), p, q)
+    assert np.array_equal(z.cpu().numpy(), np.zeros(31))
