@@ -66,28 +66,43 @@ def kernel_name(kind, cfg):
     return kind
 
 
-def kernel_sources():
-    """Bytes of every device-code source file, in name order (the fingerprint
-    that ties a counter summary to the kernels it measured)."""
+KERNEL_FILES = (("wm::k_apps", "wm_segments.hip"), ("wm::k_fuse_costs", "wm_planning.hip"),
+                ("wm::k_plan", "wm_planning.hip"), ("wm::k_fit_mult", "wm_planning.hip"),
+                ("wm::k_bw", "wm_blackwell.hip"), ("wm::k_", "wm_kernels.hip"))
+
+
+def kernel_file(kernel: str) -> str:
+    """The source file that defines a kernel of this library."""
+    for key, f in KERNEL_FILES:
+        if key in kernel:
+            return f
+    return ""
+
+
+def kernel_sources(kernel: str) -> bytes:
+    """The bytes that determine a kernel's code: its defining file and every
+    device header, in name order (the fingerprint tying a counter summary to
+    the kernel instances it measured)."""
     csrc = os.path.join(ROOT, "paper_2605_04178_amd", "csrc")
-    names = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    names = sorted(f for f in os.listdir(csrc) if f.endswith(".hpp"))
+    kf = kernel_file(kernel)
+    names = ([kf] if kf else []) + names
     return b"".join(open(os.path.join(csrc, f), "rb").read() for f in names)
 
 
 def counted_traffic(kernel_prefix):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary (profiles/traffic.json), or None when the kernel sources changed
+    summary (profiles/traffic.json), or None when the kernel's sources changed
     since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = kernel_sources()
-    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
-        return None
     for name, v in rec["kernels"].items():
         if name.startswith(kernel_prefix):
+            if hashlib.sha256(kernel_sources(name)).hexdigest()[:16] != v.get("source_sha256_16"):
+                return None
             return v["read_bytes"] + v["write_bytes"]
     return None
 
