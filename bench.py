@@ -107,23 +107,44 @@ def counted_traffic(kernel_prefix):
     return None
 
 
-def cpu_baseline(p, d, seconds=10.0):
-    """The FP64 oracle's forward rate on a bounded sample of the workload."""
-    import oracle
-    n = min(d.n, 1 << 22)
-    sub = d.slice(0, n)
-    oracle.predict(p, sub)          # warm-up (thread pool, page faults)
+def _rate(fn, units, seconds):
+    fn()                                  # warm-up (thread pool, page faults)
     reps, t0 = 0, time.perf_counter()
     while True:
-        oracle.predict(p, sub)
+        fn()
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds and reps >= 3:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": reps * n / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle predict on the first {n} descriptors of the 2^24 workload, "
-                      f"{reps} repetitions, {el:.1f} s"}
+            return reps * units / el, reps, el
+
+
+def cpu_baseline(p, d, synth, seconds=10.0):
+    """The FP64 oracle on the host cores: forward rate on a bounded sample of
+    the workload (all cores: the reported baseline), plus shorter context
+    figures: the same on one core, loss + gradient, tile candidates."""
+    import oracle
+    n = min(d.n, 1 << 22)
+    sub = d.slice(0, n)
+    threads = oracle.set_threads(0)
+    rate, reps, el = _rate(lambda: oracle.predict(p, sub), n, seconds)
+    out = {"value": rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle predict on the first {n} descriptors of the 2^24 workload, "
+                     f"{reps} repetitions, {el:.1f} s"}
+    n1 = 1 << 18
+    oracle.set_threads(1)
+    r1, _, _ = _rate(lambda: oracle.predict(p, d.slice(0, n1)), n1, 3.0)
+    oracle.set_threads(threads)
+    ps = synth.param_set(1)
+    m = np.ones(n1, np.float32) * 1e-3
+    rg, _, _ = _rate(lambda: oracle.loss_grad(ps, d.slice(0, n1), m), n1, 3.0)
+    sh = synth.shapes(1 << 12, 102)
+    nc = int(sh.cand_code.shape[0])
+    rt, _, _ = _rate(lambda: oracle.select_tile(p, sh), nc, 3.0)
+    out["context"] = {"predict_1_core_evals_per_s": r1, "loss_grad_evals_per_s": rg,
+                      "select_tile_candidates_per_s": rt,
+                      "samples": f"2^18 descriptors (1 core; loss + gradient on {threads} cores), "
+                                 f"2^12 shapes / {nc} candidates on {threads} cores, about 3 s each"}
+    return out
 
 
 def profile_run(wm, synth, dd, p, n, dev):
@@ -538,7 +559,13 @@ def main():
         res["autotune_us"] = {k: v["us"] for k, v in tuned.items()}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(p, d)
+        res["cpu_baseline"] = cpu_baseline(p, d, synth)
+    res["paper_context"] = {
+        "note": "the paper reports prediction accuracy on its hardware, not evaluation throughput",
+        "MI300A_cdna_model_mae": "~0.09% calibrated with per-case multipliers (27 kernels); ~5-8% uncalibrated",
+        "MI250X_parameter_port_mae": "4.69% (19 kernels)",
+        "naive_roofline_mae": "99.6% MI300A, 97.9% MI250X",
+        "B200_blackwell_model_mae": "1.31-1.33% (21 kernels)"}
     print(json.dumps(res), flush=True)
 
 

@@ -517,3 +517,11 @@ def apps_vjp(p, q, d, sg, w_app):
     L.orc_apps_vjp(C.byref(params(p)), C.byref(segp(q)), C.byref(o), C.byref(so), w.ctypes.data,
                    out.ctypes.data)
     return out[:N_THETA].copy(), out[N_THETA:].copy()
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the OpenMP thread count (n > 0); returns the count in effect."""
+    L = lib()
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
+    return int(L.orc_set_threads(int(n)))

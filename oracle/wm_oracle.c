@@ -33,6 +33,9 @@
  *     HBM bandwidth is blended by Eq. (16).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -967,4 +970,17 @@ void orc_apps_vjp(const orc_params_t *p, const orc_segp_t *q, const orc_desc_t *
     for (int64_t a = 0; a < na; ++a)
         for (int j = 0; j < NO; ++j) out[j] += part[a * NO + j];
     free(part);
+}
+
+/* Thread count of the OpenMP loops (the CPU-baseline measurement times the
+ * oracle on one core and on all cores); returns the count in effect. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
