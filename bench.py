@@ -60,9 +60,9 @@ def kernel_name(kind, cfg):
     if kind == "loss_grad":
         return f"void wm::k_grad<1, false, {cfg['block']}>"
     if kind == "predict_apps":
-        return f"void wm::k_apps<{cfg['block']}, false>"
+        return f"void wm::k_apps<{cfg['block']}, 0>"
     if kind == "apps_loss_grad":
-        return f"void wm::k_apps<{cfg['block']}, true>"
+        return f"void wm::k_apps<{cfg['block']}, 1>"
     return kind
 
 
