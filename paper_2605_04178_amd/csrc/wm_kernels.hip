@@ -603,13 +603,15 @@ __device__ inline bool derive_tile(int32_t M, int32_t N, int32_t Kd, int32_t t, 
 {
     const uint32_t kdc = (code >> 4) & 3u;
     if ((code >> 9) != 0u || kdc == 3u || M < 1 || N < 1 || Kd < 1 || t < 0 || t > 3) return false;
-    const int64_t mt = 32ll << (code & 3u), nt = 32ll << ((code >> 2) & 3u), kd = 16ll << kdc;
+    // tile sizes are powers of two: the ceiling divisions are shifts
+    const uint32_t lmt = 5u + (code & 3u), lnt = 5u + ((code >> 2) & 3u), lkd = 4u + kdc;
+    const int64_t mt = 1ll << lmt, nt = 1ll << lnt, kd = 1ll << lkd;
     const int64_t wpw = ((code >> 6) & 7u) + 1;
     const int64_t e = 8 >> t;                 // 8, 4, 2, 1 bytes
     const int64_t eo = t == 3 ? 2 : e;        // fp8 writes 16-bit results
     const int64_t acc = t == 0 ? 2 : 1;
-    const int64_t gm = (M + mt - 1) / mt, gn = (N + nt - 1) / nt;
-    const int64_t G = gm * gn, Ks = (Kd + kd - 1) / kd;
+    const int64_t gm = ((int64_t)M + mt - 1) >> lmt, gn = ((int64_t)N + nt - 1) >> lnt;
+    const int64_t G = gm * gn, Ks = ((int64_t)Kd + kd - 1) >> lkd;
     const int64_t g = wpw << wave_shift;
     if (G > 0x7fffffffll || g > 1024) return false;
     const int64_t Fi = 2 * (gm * mt) * (gn * nt) * (Ks * kd);
@@ -624,7 +626,11 @@ __device__ inline bool derive_tile(int32_t M, int32_t N, int32_t Kd, int32_t t, 
     x.K = (R)Ks;
     x.u = (R)1;
     x.W = (R)0;
-    x.v = (int32_t)((mt * nt * acc + g - 1) / g + ((mt + nt) * kd * e + 4 * g - 1) / (4 * g) + 16);
+    // VGPRs: accumulators and the panel share per thread (numerators below
+    // 2^19, divisors at most 4096: exact float-reciprocal quotients)
+    const uint32_t ga = (uint32_t)g;
+    x.v = (int32_t)(udiv_small((uint32_t)(mt * nt * acc) + ga - 1u, ga) +
+                    udiv_small((uint32_t)((mt + nt) * kd * e) + 4u * ga - 1u, 4u * ga) + 16u);
     x.s = (int32_t)(2 * (mt + nt) * kd * e);
     x.gp = (int32_t)g | (t << 11);
     x.G = (int32_t)G;
@@ -654,11 +660,86 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Orders this wave's LDS stores before its later LDS loads from other lanes
+// (the LDS executes one wave's operations in issue order; the fences keep
+// the compiler from moving accesses across this point).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// float64 minimum, its lowest local index and the second-smallest value of
+// a multiset, accumulated in candidate order (exact ties keep the first)
+struct Best2 {
+    double c1, c2;
+    int32_t j1;
+    __device__ inline void add(double cd, int32_t jl)
+    {
+        if (cd < c1 || (cd == c1 && jl < j1)) {
+            c2 = c1;
+            c1 = cd;
+            j1 = jl;
+        } else if (cd < c2) {
+            c2 = cd;
+        }
+    }
+};
+
+__device__ inline void write_best(const Best2& r, int64_t i, int32_t* best, double* best_cost,
+                                  uint8_t* near_tie)
+{
+    const double dinf = __builtin_huge_val();
+    const bool fin = r.c1 < dinf;
+    best[i] = fin ? r.j1 : -1;
+    best_cost[i] = r.c1;
+    near_tie[i] = (fin && r.c2 < dinf && (r.c2 - r.c1) <= 1e-6 * r.c1) ? 1 : 0;
+}
+
+constexpr int kTileQueue = 128;   // queued float64 window candidates per wave
+constexpr int kTileSlots = 64;    // shapes per queue (one lane each at the end)
+
+// Per-wave queue of float64 window re-evaluations, shared across shapes.
+struct TileQueue {
+    int32_t M[kTileSlots], N[kTileSlots], K[kTileSlots], t[kTileSlots];
+    int32_t first[kTileSlots];       // first entry of each slot
+    int64_t shape[kTileSlots];
+    uint32_t key[kTileQueue];        // slot << 8 | local candidate index
+    uint32_t code[kTileQueue];
+    double cost[kTileQueue];
+};
+
+// Evaluates every queued candidate in float64 with all lanes, then one lane
+// per shape scans that shape's entries (ascending candidate index) and
+// writes its result.  Wave-uniform ns, qn.
+__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, int lane,
+                                   int32_t* best, double* best_cost, uint8_t* near_tie)
+{
+    wave_lds_sync();
+    for (int e = lane; e < qn; e += 64) {
+        const int sl = (int)(q.key[e] >> 8);
+        q.cost[e] = tile_cost<double>(S, q.M[sl], q.N[sl], q.K[sl], q.t[sl], q.code[e]);
+    }
+    wave_lds_sync();
+    if (lane < ns) {
+        const int e1 = lane + 1 < ns ? q.first[lane + 1] : qn;
+        Best2 r{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff};
+        for (int e = q.first[lane]; e < e1; ++e) r.add(q.cost[e], (int32_t)(q.key[e] & 0xffu));
+        write_best(r, q.shape[lane], best, best_cost, near_tie);
+    }
+    wave_lds_sync();   // the queue is refilled next
+}
+
 // One wave per shape (persistent over shapes).  Pass 1 takes the float32
-// minimum with a packed (cost bits, local index) key; pass 2 re-evaluates in
-// float64 every candidate whose float32 cost is within kTileWindow of that
-// minimum and keeps the smallest and second-smallest float64 costs, the
-// lowest index winning exact ties.
+// minimum with a packed (cost bits, local index) key.  Every candidate whose
+// float32 cost is within kTileWindow of that minimum is re-evaluated in
+// float64; the result per shape is the smallest float64 cost (the lowest
+// index winning exact ties) and the second-smallest, for the near-tie flag.
+// Lists of up to 128 candidates keep their float32 costs and codes in
+// registers and queue their window candidates, so that the float64 work of
+// many shapes runs on all lanes at once; longer lists re-evaluate their
+// window directly, lane-parallel.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
                                                       const uint32_t* __restrict__ code, int64_t n,
@@ -667,25 +748,30 @@ __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32
                                                       double* __restrict__ best_cost,
                                                       uint8_t* __restrict__ near_tie)
 {
+    __shared__ TileQueue queues[BLOCK / 64];
     const int lane = threadIdx.x & 63;
+    TileQueue& q = queues[threadIdx.x >> 6];
     const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * BLOCK + threadIdx.x) >> 6));
     const int nwaves = (int)((gridDim.x * BLOCK) >> 6);
     const double dinf = __builtin_huge_val();
+    const float finf = __builtin_huge_valf();
+    int ns = 0, qn = 0;
     for (int64_t i = wave; i < n; i += nwaves) {
         const int32_t M = sh.M[i], N = sh.N[i], K = sh.K[i], t = sh.dtype[i];
         // offsets are caller data: clamp them into the candidate array
         int64_t a = off[i], b = off[i + 1];
         a = a < 0 ? 0 : (a > n_cand ? n_cand : a);
         b = b < a ? a : (b > n_cand ? n_cand : b);
-        // float32 costs of the lane's first two candidates stay in registers
-        // for the second pass (covers lists of up to 128 candidates)
-        const float finf = __builtin_huge_valf();
         float cc0 = finf, cc1 = finf;
+        uint32_t cd0 = 0, cd1 = 0;
         uint64_t key = ~0ull;
         for (int64_t j = a + lane, r = 0; j < b; j += 64, ++r) {
-            const float c = tile_cost<float>(S, M, N, K, t, code[j]);
+            const uint32_t cj = code[j];
+            const float c = tile_cost<float>(S, M, N, K, t, cj);
             cc0 = r == 0 ? c : cc0;
             cc1 = r == 1 ? c : cc1;
+            cd0 = r == 0 ? cj : cd0;
+            cd1 = r == 1 ? cj : cd1;
             const uint64_t k = ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)(j - a);
             key = k < key ? k : key;
         }
@@ -695,7 +781,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32
             key = o < key ? o : key;
         }
         const float c32 = __uint_as_float((uint32_t)(key >> 32));
-        if (key == ~0ull || !(c32 < __builtin_huge_valf())) {
+        if (key == ~0ull || !(c32 < finf)) {
             if (lane == 0) {
                 best[i] = -1;
                 best_cost[i] = dinf;
@@ -704,41 +790,65 @@ __global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32
             continue;
         }
         const float thr = c32 * (1.0f + kTileWindow);
-        double c1 = dinf, c2 = dinf;
-        int32_t j1 = 0x7fffffff;
-        for (int64_t j = a + lane, r = 0; j < b; j += 64, ++r) {
-            const float c = r == 0 ? cc0 : (r == 1 ? cc1 : tile_cost<float>(S, M, N, K, t, code[j]));
-            if (!(c <= thr)) continue;
-            const double cd = tile_cost<double>(S, M, N, K, t, code[j]);
-            const int32_t jl = (int32_t)(j - a);
-            if (cd < c1 || (cd == c1 && jl < j1)) {
-                c2 = c1;
-                c1 = cd;
-                j1 = jl;
-            } else if (cd < c2) {
-                c2 = cd;
+        if (b - a <= 128) {
+            // lanes past the list hold +inf, which a +inf threshold would admit
+            const int64_t len = b - a;
+            const bool w0 = lane < len && cc0 <= thr, w1 = 64 + lane < len && cc1 <= thr;
+            const uint64_t m0 = __ballot(w0), m1 = __ballot(w1);
+            const int n0 = __popcll(m0), cnt = n0 + __popcll(m1);
+            if (qn + cnt > kTileQueue || ns == kTileSlots) {
+                flush_tiles(q, ns, qn, S, lane, best, best_cost, near_tie);
+                ns = 0;
+                qn = 0;
             }
+            if (lane == 0) {
+                q.M[ns] = M;
+                q.N[ns] = N;
+                q.K[ns] = K;
+                q.t[ns] = t;
+                q.first[ns] = qn;
+                q.shape[ns] = i;
+            }
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m0 >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m0, 0u));
+            const uint32_t below1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+            if (w0) {
+                const int e = qn + (int)below;
+                q.key[e] = ((uint32_t)ns << 8) | (uint32_t)lane;
+                q.code[e] = cd0;
+            }
+            if (w1) {
+                const int e = qn + n0 + (int)below1;
+                q.key[e] = ((uint32_t)ns << 8) | (uint32_t)(64 + lane);
+                q.code[e] = cd1;
+            }
+            qn += cnt;
+            ++ns;
+            continue;
+        }
+        Best2 r{dinf, dinf, 0x7fffffff};
+        for (int64_t j = a + lane, rr = 0; j < b; j += 64, ++rr) {
+            const float c = rr == 0 ? cc0 : (rr == 1 ? cc1 : tile_cost<float>(S, M, N, K, t, code[j]));
+            if (!(c <= thr)) continue;
+            r.add(tile_cost<double>(S, M, N, K, t, code[j]), (int32_t)(j - a));
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
-            const double oc1 = __shfl_xor(c1, m, 64);
-            const double oc2 = __shfl_xor(c2, m, 64);
-            const int32_t oj1 = __shfl_xor(j1, m, 64);
-            if (oc1 < c1 || (oc1 == c1 && oj1 < j1)) {
-                c2 = c1 < oc2 ? c1 : oc2;
-                c1 = oc1;
-                j1 = oj1;
+            const double oc1 = __shfl_xor(r.c1, m, 64);
+            const double oc2 = __shfl_xor(r.c2, m, 64);
+            const int32_t oj1 = __shfl_xor(r.j1, m, 64);
+            if (oc1 < r.c1 || (oc1 == r.c1 && oj1 < r.j1)) {
+                r.c2 = r.c1 < oc2 ? r.c1 : oc2;
+                r.c1 = oc1;
+                r.j1 = oj1;
             } else {
-                c2 = oc1 < c2 ? oc1 : c2;
+                r.c2 = oc1 < r.c2 ? oc1 : r.c2;
             }
         }
-        if (lane == 0) {
-            const bool fin = c1 < dinf;
-            best[i] = fin ? j1 : -1;
-            best_cost[i] = c1;
-            near_tie[i] = (fin && c2 < dinf && (c2 - c1) <= 1e-6 * c1) ? 1 : 0;
-        }
+        if (lane == 0) write_best(r, i, best, best_cost, near_tie);
     }
+    if (ns > 0) flush_tiles(q, ns, qn, S, lane, best, best_cost, near_tie);
 }
 
 template <int BLOCK>

@@ -89,6 +89,39 @@ def test_select_tile_edge_cases(wmb, orc):
     assert best[3] == 1 and best[4] == 1
 
 
+def test_select_tile_list_lengths_and_duplicates(wmb, orc):
+    """List lengths around one and two wavefronts (63..129, 200) and lists
+    built from two or three distinct codes repeated, so that a shape puts up
+    to its whole list into the float64 window; several thousand shapes so
+    that every wave handles many of them.  Exact duplicates cost the same,
+    so the pick must be the first occurrence of the winning code."""
+    p = synth.param_set(0)
+    rng = np.random.Generator(np.random.PCG64(31))
+    tiles = synth.all_tile_codes()
+    lens = np.array([1, 2, 63, 64, 65, 127, 128, 129, 200, 40])
+    n = 6000
+    cnt = lens[rng.integers(0, len(lens), n)]
+    lists = []
+    for i in range(n):
+        if i % 3 == 0:
+            pool = tiles[rng.permutation(len(tiles))[:int(rng.integers(2, 4))]]
+            lists.append(pool[rng.integers(0, len(pool), cnt[i])])
+        else:
+            lists.append(tiles[rng.integers(0, len(tiles), cnt[i])])
+    off = np.zeros(n + 1, np.int32)
+    off[1:] = np.cumsum(cnt)
+    M = np.round(np.exp(rng.uniform(np.log(128), np.log(16384), n))).astype(np.int32)
+    N = np.round(np.exp(rng.uniform(np.log(128), np.log(16384), n))).astype(np.int32)
+    K = np.round(np.exp(rng.uniform(np.log(128), np.log(16384), n))).astype(np.int32)
+    dt = rng.integers(0, 4, n).astype(np.int32)
+    sh = synth.Shapes(M, N, K, dt, off, np.concatenate(lists).astype(np.uint32))
+    best, cost, tie, bo, to = _check(wmb, orc, p, sh, "lengths/duplicates")
+    for i in np.nonzero(best >= 0)[0]:
+        L = lists[i]
+        assert best[i] == int(np.nonzero(L == L[best[i]])[0][0]), i
+    say("near ties:", int(to.sum()), "of", n)
+
+
 def test_select_tile_graph_replay(wmb, orc):
     """The launch captured in a HIP graph and replayed, with eager work and
     syncs between replays; every replay must equal the eager result."""
