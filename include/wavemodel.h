@@ -252,7 +252,7 @@ int32_t wm_loss_grad(const wm_desc_t *desc, const float *measured, const wm_para
  * zero.  The tile becomes a descriptor (grid ceil(M/mt) ceil(N/nt), K loop
  * ceil(K/kd) steps, padded flops, panel bytes, L2 reuse 1 - unique/loaded,
  * VGPRs for accumulators and panels, double-buffered LDS) whose predicted
- * time is its cost.  Outputs per shape: best [n] int32 local index of the
+ * time is its cost; a grid of more than 2^31 - 1 workgroups is infeasible.  Outputs per shape: best [n] int32 local index of the
  * cheapest candidate (ties to the lowest index; -1 if none is feasible),
  * best_cost [n] float64 its float64 cost (+inf if none), near_tie [n]
  * uint8 = 1 when the runner-up is within 1e-6 relative.  A float32 sweep

@@ -535,7 +535,9 @@ typedef struct {
  * mt x nt outputs with K-depth kd runs as one workgroup of 64 * waves
  * threads; the grid covers the padded output, the K loop has ceil(K/kd)
  * steps, each loading an (mt + nt) x kd panel; accumulators live in VGPRs
- * (two per FP64 value), input panels are double-buffered in LDS.
+ * (two per FP64 value), input panels are double-buffered in LDS.  A grid
+ * of more than 2^31 - 1 workgroups, or a workgroup of more than 1024
+ * threads, makes the tile infeasible.
  */
 void orc_tile_derive(int64_t M, int64_t N, int64_t Kd, int64_t t, uint32_t code,
                      int64_t wave, orc_tile_t *out)
@@ -555,13 +557,23 @@ void orc_tile_derive(int64_t M, int64_t N, int64_t Kd, int64_t t, uint32_t code,
     int64_t e = ESZ[t], eo = EOUT[t], acc = (t == 0) ? 2 : 1;
     int64_t gm = ceil_div(M, mt), gn = ceil_div(N, nt);
     int64_t G = gm * gn, Ks = ceil_div(Kd, kd), g = wave * wpw;
+    /* a descriptor counts workgroups in 32 bits and a workgroup holds at
+       most 1024 threads: larger grids or groups are not launchable */
+    if (G > 0x7fffffffll || g > 1024) {
+        out->valid = 0;
+        return;
+    }
     out->valid = 1;
     out->G = G;
     out->Ks = Ks;
     out->g = g;
     out->F = 2.0 * (double)(gm * mt) * (double)(gn * nt) * (double)(Ks * kd);
-    out->B = (double)(G * Ks * (mt + nt) * kd * e + M * N * eo);
-    out->U = (double)((M * Kd + Kd * N) * e + M * N * eo);
+    /* bytes are real counts: products formed in double, so that no shape
+       within the int32 limits overflows (exact below 2^53) */
+    out->B = (double)G * (double)Ks * (double)(mt + nt) * (double)kd * (double)e +
+             (double)M * (double)N * (double)eo;
+    out->U = ((double)M * (double)Kd + (double)Kd * (double)N) * (double)e +
+             (double)M * (double)N * (double)eo;
     double r2 = 1.0 - out->U / out->B;
     out->r2 = r2 > 0.0 ? r2 : 0.0;
     out->v = ceil_div(mt * nt * acc, g) + ceil_div((mt + nt) * kd * e, 4 * g) + 16;

@@ -89,6 +89,22 @@ def test_select_tile_edge_cases(wmb, orc):
     assert best[3] == 1 and best[4] == 1
 
 
+def test_select_tile_int32_limit_shapes(wmb, orc):
+    """Sides up to 2^31 - 1 with the full 384-tile sweep: flops and bytes past
+    2^63, tiles whose grid exceeds 2^31 - 1 workgroups (infeasible)."""
+    p = synth.param_set(0)
+    big = 2 ** 31 - 1
+    dims = [(big, big, big, 0), (big, big, big, 3), (big, 1, big, 0), (1 << 20, 1 << 20, big, 1),
+            (big, 64, big, 3), (65536, 65536, 65536, 2), (1 << 21, 1 << 21, 7, 2), (1, big, 1, 1)]
+    codes = synth.all_tile_codes().astype(np.uint32)
+    M, N, K, dt = (np.array(c, np.int32) for c in zip(*dims))
+    off = (np.arange(len(dims) + 1) * len(codes)).astype(np.int32)
+    sh = synth.Shapes(M, N, K, dt, off, np.tile(codes, len(dims)))
+    best, cost, tie, bo, to = _check(wmb, orc, p, sh, "int32 limits")
+    assert best[0] == -1 and best[1] == -1          # every grid too large
+    assert (best[2:] >= 0).all()
+
+
 def test_select_tile_list_lengths_and_duplicates(wmb, orc):
     """List lengths around one and two wavefronts (63..129, 200) and lists
     built from two or three distinct codes repeated, so that a shape puts up

@@ -406,6 +406,34 @@ def test_tile_derivation_brute_force(orc):
         assert td.r2 == pytest.approx(max(0.0, 1 - ref["U"] / ref["B"]), rel=1e-15)
 
 
+def test_tile_derivation_at_int32_limits(orc):
+    """Shapes up to 2^31 - 1 per side, where flops and bytes pass 2^63: the
+    closed forms the brute-force pin establishes, in exact Python integers,
+    against the oracle's double values (each product rounded once: a few
+    ulps at most)."""
+    big = 2 ** 31 - 1
+    cases = [(big, 1, big, 0, 0), (1 << 20, 1 << 20, big, 0, 0), (big, 64, big, 3, 0x2F),
+             (1 << 20, 1 << 20, big, 1, 2 | 2 << 2 | 2 << 4 | 7 << 6), (big, big, big, 2, 3 | 3 << 2)]
+    for M, N, K, t, code in cases:
+        mt = synth.TILE_MN[code & 3]
+        nt = synth.TILE_MN[(code >> 2) & 3]
+        kd = synth.TILE_KD[(code >> 4) & 3]
+        e, eo = (8, 4, 2, 1)[t], (8, 4, 2, 2)[t]
+        gm, gn, Ks = -(-M // mt), -(-N // nt), -(-K // kd)
+        td = orc.tile_derive(M, N, K, t, code)
+        if gm * gn > 2 ** 31 - 1:
+            assert td.valid == 0   # more workgroups than a descriptor can count
+            continue
+        F = 2 * (gm * mt) * (gn * nt) * (Ks * kd)
+        B = gm * gn * Ks * (mt + nt) * kd * e + M * N * eo
+        U = (M * K + K * N) * e + M * N * eo
+        assert F > 2 ** 63 or B > 2 ** 53
+        assert td.valid == 1 and td.G == gm * gn and td.Ks == Ks
+        assert td.F == pytest.approx(F, rel=4e-16)
+        assert td.B == pytest.approx(B, rel=6e-16)
+        assert td.U == pytest.approx(U, rel=6e-16)
+
+
 def test_tile_invalid_codes(orc):
     assert orc.tile_derive(128, 128, 128, 0, 3 << 4).valid == 0   # kd code 3
     assert orc.tile_derive(128, 128, 128, 0, 1 << 9).valid == 0   # reserved bit
