@@ -68,7 +68,8 @@ def kernel_name(kind, cfg):
 
 KERNEL_FILES = (("wm::k_apps", "wm_segments.hip"), ("wm::k_fuse_costs", "wm_planning.hip"),
                 ("wm::k_plan", "wm_planning.hip"), ("wm::k_fit_mult", "wm_planning.hip"),
-                ("wm::k_bw", "wm_blackwell.hip"), ("wm::k_", "wm_kernels.hip"))
+                ("wm::k_bw", "wm_blackwell.hip"), ("wm::k_select_tile", "wm_tile.hip"),
+                ("wm::k_", "wm_kernels.hip"))
 
 
 def kernel_file(kernel: str) -> str:

@@ -1,6 +1,6 @@
 // wm_kernels.hip -- gfx950 kernels of libwavemodel: forward sweep, naive
 // roofline, adjoint / loss-gradient with fixed-order FP64 reductions, device
-// Adam, occupancy-driven tile selection and the multi-set calibration sweep.
+// Adam and the multi-set calibration sweep.
 //
 // Memory layout: descriptors are structure-of-arrays; the forward kernel
 // streams them with 16-byte nontemporal loads (4 descriptors per thread per
@@ -590,478 +590,6 @@ hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, Cal
 {
     k_adam_batched<<<n_sets, 256, 0, stream>>>(partials, rows, n_sets, st, opts, S_all, steps,
                                                 loss_hist);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// tile selection
-// ---------------------------------------------------------------------------
-// GEMM tile -> descriptor.  Tile sizes are powers of two, so the grid, the
-// K steps and the panel sizes are shifts of 32-bit integers (every padded
-// extent is below 2^32).  Flops and bytes are real quantities formed in R
-// from those exact integers: in double they are exact while below 2^53 and
-// never overflow; in float they carry a few ulps, which the float64 window
-// of the selection absorbs.
-template <typename R>
-__device__ inline bool derive_tile(int32_t M, int32_t N, int32_t Kd, int32_t t, uint32_t code,
-                                   int wave_shift, Desc<R>& x)
-{
-#pragma clang fp contract(off)
-    const uint32_t kdc = (code >> 4) & 3u;
-    if ((code >> 9) != 0u || kdc == 3u || M < 1 || N < 1 || Kd < 1 || t < 0 || t > 3) return false;
-    const uint32_t lmt = 5u + (code & 3u), lnt = 5u + ((code >> 2) & 3u), lkd = 4u + kdc;
-    const uint32_t wpw = ((code >> 6) & 7u) + 1u;
-    const uint32_t le = 3u - (uint32_t)t;          // element bytes 8, 4, 2, 1
-    const uint32_t eo = t == 3 ? 2u : (1u << le);  // fp8 writes 16-bit results
-    const uint32_t acc = t == 0 ? 2u : 1u;
-    const uint32_t gm = ((uint32_t)M + (1u << lmt) - 1u) >> lmt;
-    const uint32_t gn = ((uint32_t)N + (1u << lnt) - 1u) >> lnt;
-    const uint32_t Ks = ((uint32_t)Kd + (1u << lkd) - 1u) >> lkd;
-    const uint64_t G = (uint64_t)gm * gn;
-    const uint32_t g = wpw << wave_shift;
-    if (G > 0x7fffffffull || g > 1024u) return false;
-    const uint32_t pan = ((1u << lmt) + (1u << lnt)) << (lkd + le);   // (mt + nt) kd e <= 2^18
-    const R fM = (R)(uint32_t)M, fN = (R)(uint32_t)N, fK = (R)(uint32_t)Kd;
-    const R Bi = (R)(uint32_t)G * (R)Ks * (R)pan + fM * fN * (R)eo;
-    const R Ui = (fM * fK + fK * fN) * (R)(1u << le) + fM * fN * (R)eo;
-    x.F = (R)2 * (R)(gm << lmt) * (R)(gn << lnt) * (R)(Ks << lkd);
-    x.B = Bi;
-    const R r2 = (R)1 - Ui * Ar<R>::rcp(Bi);
-    x.r2 = r2 > (R)0 ? r2 : (R)0;
-    x.r1 = (R)0;
-    x.r3 = (R)0;
-    x.K = (R)Ks;
-    x.u = (R)1;
-    x.W = (R)0;
-    // VGPRs: accumulators and the panel share per thread (numerators below
-    // 2^19, divisors at most 4096: exact float-reciprocal quotients)
-    x.v = (int32_t)(udiv_small((acc << (lmt + lnt)) + g - 1u, g) +
-                    udiv_small(pan + 4u * g - 1u, 4u * g) + 16u);
-    x.s = (int32_t)(2u * pan);
-    x.gp = (int32_t)g | (t << 11);
-    x.G = (int32_t)G;
-    return true;
-}
-
-template <typename R> __device__ inline const Const<R>& cst(const Set& S);
-template <> __device__ inline const Const<float>& cst<float>(const Set& S) { return S.cf; }
-template <> __device__ inline const Const<double>& cst<double>(const Set& S) { return S.cd; }
-
-// cost of one candidate; invalid codes and infeasible tiles cost +inf
-template <typename R>
-__device__ inline R tile_cost(const Set& S, int32_t M, int32_t N, int32_t K, int32_t t, uint32_t code)
-{
-    const R inf = (R)__builtin_huge_val();
-    Desc<R> x;
-    if (!derive_tile<R>(M, N, K, t, code, S.st.wave_shift, x)) return inf;
-    Eval<R> E;
-    evaluate<R, false>(S.st, cst<R>(S), x, E);
-    return E.T == E.T ? E.T : inf;
-}
-
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
-{
-    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Orders this wave's LDS stores before its later LDS loads from other lanes
-// (the LDS executes one wave's operations in issue order; the fences keep
-// the compiler from moving accesses across this point).
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// float64 minimum, its lowest local index and the second-smallest value of
-// a multiset, accumulated in candidate order (exact ties keep the first)
-struct Best2 {
-    double c1, c2;
-    int32_t j1;
-    __device__ inline void add(double cd, int32_t jl)
-    {
-        if (cd < c1 || (cd == c1 && jl < j1)) {
-            c2 = c1;
-            c1 = cd;
-            j1 = jl;
-        } else if (cd < c2) {
-            c2 = cd;
-        }
-    }
-};
-
-__device__ inline void write_best(const Best2& r, int64_t i, int32_t* best, double* best_cost,
-                                  uint8_t* near_tie)
-{
-    const double dinf = __builtin_huge_val();
-    const bool fin = r.c1 < dinf;
-    best[i] = fin ? r.j1 : -1;
-    best_cost[i] = r.c1;
-    near_tie[i] = (fin && r.c2 < dinf && (r.c2 - r.c1) <= 1e-6 * r.c1) ? 1 : 0;
-}
-
-constexpr int kTileQueue = 256;   // queued float64 window candidates per wave
-constexpr int kTileSlots = 64;    // shapes per queue (one lane each at the end)
-constexpr int kTileBatch = 8;     // consecutive shapes whose candidates share wavefronts
-constexpr int kTileRounds = 12;   // 64-candidate rounds a batch keeps in registers
-
-// Per-wave queue of float64 window re-evaluations, shared across shapes.
-// Entries are appended in (slot, local index) order.
-struct TileQueue {
-    int32_t M[kTileSlots], N[kTileSlots], K[kTileSlots], t[kTileSlots];
-    int64_t shape[kTileSlots];
-    uint32_t key[kTileQueue];        // slot << 24 | local candidate index
-    uint32_t code[kTileQueue];
-    double cost[kTileQueue];
-    unsigned long long bmin[kTileBatch];   // packed float32 minimum per batch shape
-};
-
-__device__ inline uint32_t lanes_below(uint64_t m)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// first entry in [0, qn) whose slot is >= sl
-__device__ inline int first_entry(const TileQueue& q, int qn, uint32_t sl)
-{
-    int lo = 0, hi = qn;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((q.key[mid] >> 24) < sl) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Evaluates every queued candidate in float64 with all lanes, then one lane
-// per shape scans that shape's entries (ascending candidate index) and
-// writes its result.  Wave-uniform ns, qn.
-__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, int lane,
-                                   int32_t* best, double* best_cost, uint8_t* near_tie)
-{
-    wave_lds_sync();
-    for (int e = lane; e < qn; e += 64) {
-        const int sl = (int)(q.key[e] >> 24);
-        q.cost[e] = tile_cost<double>(S, q.M[sl], q.N[sl], q.K[sl], q.t[sl], q.code[e]);
-    }
-    wave_lds_sync();
-    if (lane < ns) {
-        const int e1 = first_entry(q, qn, (uint32_t)lane + 1u);
-        Best2 r{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff};
-        for (int e = first_entry(q, qn, (uint32_t)lane); e < e1; ++e)
-            r.add(q.cost[e], (int32_t)(q.key[e] & 0xffffffu));
-        write_best(r, q.shape[lane], best, best_cost, near_tie);
-    }
-    wave_lds_sync();   // the queue is refilled next
-}
-
-struct TileCtx {
-    ShapePtrs sh;
-    const int32_t* off;
-    const uint32_t* code;
-    int64_t n_cand;
-    int32_t* best;
-    double* best_cost;
-    uint8_t* near_tie;
-};
-
-__device__ inline void clamp_list(int64_t n_cand, int64_t& a, int64_t& b)
-{
-    // offsets are caller data: clamp them into the candidate array
-    a = a < 0 ? 0 : (a > n_cand ? n_cand : a);
-    b = b < a ? a : (b > n_cand ? n_cand : b);
-}
-
-// One shape on the whole wave: float32 minimum over its list; lists of up to
-// 128 candidates queue their float64 window, longer lists evaluate it here.
-__device__ inline void shape_task(const TileCtx& C, const Set& S, TileQueue& q, int& ns, int& qn,
-                                  int64_t i, int lane)
-{
-    const double dinf = __builtin_huge_val();
-    const float finf = __builtin_huge_valf();
-    const int32_t M = C.sh.M[i], N = C.sh.N[i], K = C.sh.K[i], t = C.sh.dtype[i];
-    int64_t a = C.off[i], b = C.off[i + 1];
-    clamp_list(C.n_cand, a, b);
-    float cc0 = finf, cc1 = finf;
-    uint32_t cd0 = 0, cd1 = 0;
-    uint64_t key = ~0ull;
-    for (int64_t j = a + lane, r = 0; j < b; j += 64, ++r) {
-        const uint32_t cj = C.code[j];
-        const float c = tile_cost<float>(S, M, N, K, t, cj);
-        cc0 = r == 0 ? c : cc0;
-        cc1 = r == 1 ? c : cc1;
-        cd0 = r == 0 ? cj : cd0;
-        cd1 = r == 1 ? cj : cd1;
-        const uint64_t k = ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)(j - a);
-        key = k < key ? k : key;
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = shfl_xor_u64(key, m);
-        key = o < key ? o : key;
-    }
-    const float c32 = __uint_as_float((uint32_t)(key >> 32));
-    if (key == ~0ull || !(c32 < finf)) {
-        if (lane == 0) {
-            C.best[i] = -1;
-            C.best_cost[i] = dinf;
-            C.near_tie[i] = 0;
-        }
-        return;
-    }
-    const float thr = c32 * (1.0f + kTileWindow);
-    const int64_t len = b - a;
-    if (len <= 128) {
-        // lanes past the list hold +inf, which a +inf threshold would admit
-        const bool w0 = lane < len && cc0 <= thr, w1 = 64 + lane < len && cc1 <= thr;
-        const uint64_t m0 = __ballot(w0), m1 = __ballot(w1);
-        const int n0 = __popcll(m0), cnt = n0 + __popcll(m1);
-        if (qn + cnt > kTileQueue || ns == kTileSlots) {
-            flush_tiles(q, ns, qn, S, lane, C.best, C.best_cost, C.near_tie);
-            ns = 0;
-            qn = 0;
-        }
-        if (lane == 0) {
-            q.M[ns] = M;
-            q.N[ns] = N;
-            q.K[ns] = K;
-            q.t[ns] = t;
-            q.shape[ns] = i;
-        }
-        if (w0) {
-            const int e = qn + (int)lanes_below(m0);
-            q.key[e] = ((uint32_t)ns << 24) | (uint32_t)lane;
-            q.code[e] = cd0;
-        }
-        if (w1) {
-            const int e = qn + n0 + (int)lanes_below(m1);
-            q.key[e] = ((uint32_t)ns << 24) | (uint32_t)(64 + lane);
-            q.code[e] = cd1;
-        }
-        qn += cnt;
-        ++ns;
-        return;
-    }
-    Best2 r{dinf, dinf, 0x7fffffff};
-    for (int64_t j = a + lane, rr = 0; j < b; j += 64, ++rr) {
-        const float c = rr == 0 ? cc0 : (rr == 1 ? cc1 : tile_cost<float>(S, M, N, K, t, C.code[j]));
-        if (!(c <= thr)) continue;
-        r.add(tile_cost<double>(S, M, N, K, t, C.code[j]), (int32_t)(j - a));
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const double oc1 = __shfl_xor(r.c1, m, 64);
-        const double oc2 = __shfl_xor(r.c2, m, 64);
-        const int32_t oj1 = __shfl_xor(r.j1, m, 64);
-        if (oc1 < r.c1 || (oc1 == r.c1 && oj1 < r.j1)) {
-            r.c2 = r.c1 < oc2 ? r.c1 : oc2;
-            r.c1 = oc1;
-            r.j1 = oj1;
-        } else {
-            r.c2 = oc1 < r.c2 ? oc1 : r.c2;
-        }
-    }
-    if (lane == 0) write_best(r, i, C.best, C.best_cost, C.near_tie);
-}
-
-// kTileBatch consecutive shapes [s0, s0 + kTileBatch) on one wave with their
-// candidate lists laid end to end over the lanes, so that short lists do not
-// leave lanes idle.  Batches of more than kTileRounds * 64 candidates, or
-// whose float64 window would not fit the queue, go shape by shape instead.
-__device__ inline void batch_task(const TileCtx& C, const Set& S, TileQueue& q, int& ns, int& qn,
-                                  int64_t s0, int64_t n, int lane)
-{
-    constexpr int SB = kTileBatch;
-    const float finf = __builtin_huge_valf();
-    // lane k < SB holds shape s0 + k
-    const int64_t si = s0 + lane;
-    const bool has = lane < SB && si < n;
-    int32_t M = 0, N = 0, K = 0, t = 0;
-    int64_t a = 0, b = 0;
-    if (has) {
-        M = C.sh.M[si];
-        N = C.sh.N[si];
-        K = C.sh.K[si];
-        t = C.sh.dtype[si];
-        a = C.off[si];
-        b = C.off[si + 1];
-        clamp_list(C.n_cand, a, b);
-    }
-    // list lengths, saturated (a batch past kTileRounds * 64 goes shape by shape)
-    constexpr int32_t cap = kTileRounds * 64 + 1;
-    const int32_t len = (int32_t)(b - a < cap ? b - a : cap);
-    int32_t inc = len;   // inclusive prefix over lanes 0..SB-1
-#pragma unroll
-    for (int d = 1; d < SB; d <<= 1) {
-        const int32_t o = __shfl_up(inc, d, 64);
-        inc += lane >= d ? o : 0;
-    }
-    const int32_t T = __builtin_amdgcn_readlane(inc, SB - 1);
-    if (T > kTileRounds * 64) {
-        for (int k = 0; k < SB && s0 + k < n; ++k) shape_task(C, S, q, ns, qn, s0 + k, lane);
-        return;
-    }
-    const int32_t P = inc - len;   // first virtual position of lane's shape
-    int32_t Pk[SB];
-#pragma unroll
-    for (int k = 0; k < SB; ++k) Pk[k] = __builtin_amdgcn_readlane(P, k);
-    if (lane < SB) q.bmin[lane] = ~0ull;
-    wave_lds_sync();
-    // pass 1: float32 costs (kept in registers) and the per-shape minimum
-    const int R = (T + 63) >> 6;
-    float creg[kTileRounds];
-    uint64_t sbits = 0;   // 3 bits of batch slot per round
-#pragma unroll
-    for (int r = 0; r < kTileRounds; ++r) {
-        creg[r] = finf;
-        if (r < R) {
-            const int32_t v = r * 64 + lane;
-            int32_t sl = 0;
-#pragma unroll
-            for (int k = 1; k < SB; ++k) sl += v >= Pk[k] ? 1 : 0;
-            const int32_t Ms = __shfl(M, sl, 64), Ns = __shfl(N, sl, 64), Ks = __shfl(K, sl, 64);
-            const int32_t ts = __shfl(t, sl, 64), Ps = __shfl(P, sl, 64);
-            const int64_t as = __shfl(a, sl, 64);
-            sbits |= (uint64_t)sl << (3 * r);
-            if (v < T) {
-                const int32_t jl = v - Ps;
-                const float c = tile_cost<float>(S, Ms, Ns, Ks, ts, C.code[as + jl]);
-                creg[r] = c;
-                __hip_atomic_fetch_min(&q.bmin[sl],
-                                       ((unsigned long long)__float_as_uint(c) << 32) | (uint32_t)jl,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            }
-        }
-    }
-    wave_lds_sync();
-    // per shape: threshold, or the empty result when nothing is feasible
-    float thr = -finf;
-    bool fin = false;
-    if (has) {
-        const unsigned long long key = q.bmin[lane];
-        const float c32 = __uint_as_float((uint32_t)(key >> 32));
-        fin = key != ~0ull && c32 < finf;
-        if (fin) {
-            thr = c32 * (1.0f + kTileWindow);
-        } else {
-            C.best[si] = -1;
-            C.best_cost[si] = __builtin_huge_val();
-            C.near_tie[si] = 0;
-        }
-    }
-    const uint64_t fmask = __ballot(fin);
-    const int nf = __popcll(fmask);
-    // window membership per round
-    uint32_t wbits = 0;
-    int cnt = 0;
-#pragma unroll
-    for (int r = 0; r < kTileRounds; ++r) {
-        if (r < R) {
-            const int32_t sl = (int32_t)((sbits >> (3 * r)) & 7u);
-            const float th = __shfl(thr, sl, 64);
-            // positions past the batch hold +inf, which a +inf threshold would admit
-            const bool w = r * 64 + lane < T && creg[r] <= th;
-            wbits |= (uint32_t)w << r;
-            cnt += __popcll(__ballot(w));
-        }
-    }
-    if (cnt > kTileQueue) {
-        for (int k = 0; k < SB && s0 + k < n; ++k) shape_task(C, S, q, ns, qn, s0 + k, lane);
-        return;
-    }
-    if (qn + cnt > kTileQueue || ns + nf > kTileSlots) {
-        flush_tiles(q, ns, qn, S, lane, C.best, C.best_cost, C.near_tie);
-        ns = 0;
-        qn = 0;
-    }
-    // queue slots for the shapes with a finite minimum, in batch order
-    const int32_t qs = ns + (int32_t)lanes_below(fmask);
-    if (fin) {
-        q.M[qs] = M;
-        q.N[qs] = N;
-        q.K[qs] = K;
-        q.t[qs] = t;
-        q.shape[qs] = si;
-    }
-#pragma unroll
-    for (int r = 0; r < kTileRounds; ++r) {
-        if (r < R) {
-            const int32_t v = r * 64 + lane;
-            const int32_t sl = (int32_t)((sbits >> (3 * r)) & 7u);
-            const int32_t Ps = __shfl(P, sl, 64), qss = __shfl(qs, sl, 64);
-            const int64_t as = __shfl(a, sl, 64);
-            const bool w = (wbits >> r) & 1u;
-            const uint64_t m = __ballot(w);
-            if (w) {
-                const int e = qn + (int)lanes_below(m);
-                const int32_t jl = v - Ps;
-                q.key[e] = ((uint32_t)qss << 24) | (uint32_t)jl;
-                q.code[e] = C.code[as + jl];
-            }
-            qn += __popcll(m);
-        }
-    }
-    ns += nf;
-}
-
-// Persistent waves over batches of kTileBatch consecutive shapes.  Pass 1
-// takes each shape's float32 minimum with a packed (cost bits, local index)
-// key.  Every candidate whose float32 cost is within kTileWindow of that
-// minimum is re-evaluated in float64 through a per-wave queue, so that the
-// float64 work of many shapes runs on all lanes at once; the result per
-// shape is the smallest float64 cost (the lowest index winning exact ties)
-// and the second-smallest, for the near-tie flag.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
-                                                      const uint32_t* __restrict__ code, int64_t n,
-                                                      int64_t n_cand,
-                                                      Set S, int32_t* __restrict__ best,
-                                                      double* __restrict__ best_cost,
-                                                      uint8_t* __restrict__ near_tie)
-{
-    __shared__ TileQueue queues[BLOCK / 64];
-    const int lane = threadIdx.x & 63;
-    TileQueue& q = queues[threadIdx.x >> 6];
-    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * BLOCK + threadIdx.x) >> 6));
-    const int64_t nwaves = (int64_t)((gridDim.x * BLOCK) >> 6);
-    const TileCtx C{sh, off, code, n_cand, best, best_cost, near_tie};
-    const int64_t nb = (n + kTileBatch - 1) / kTileBatch;
-    int ns = 0, qn = 0;
-    for (int64_t bt = wave; bt < nb; bt += nwaves) batch_task(C, S, q, ns, qn, bt * kTileBatch, n, lane);
-    if (ns > 0) flush_tiles(q, ns, qn, S, lane, best, best_cost, near_tie);
-}
-
-template <int BLOCK>
-static void select_t(const ShapePtrs& sh, const int32_t* off, const uint32_t* code, int64_t n,
-                     int64_t n_cand, const Set& S, int32_t* best, double* best_cost,
-                     uint8_t* near_tie, int grid_mult, hipStream_t stream)
-{
-    const int64_t waves_per_block = BLOCK / 64;
-    const int64_t batches = (n + kTileBatch - 1) / kTileBatch;
-    const int64_t want = (batches + waves_per_block - 1) / waves_per_block;
-    int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_select_tile<BLOCK>), BLOCK) *
-                (grid_mult < 1 ? 1 : grid_mult);
-    b = b < want ? b : want;
-    k_select_tile<BLOCK><<<(int)(b < 1 ? 1 : b), BLOCK, 0, stream>>>(sh, off, code, n, n_cand, S, best,
-                                                                     best_cost, near_tie);
-}
-
-hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
-                              int64_t n, int64_t n_cand, const Set& S, int32_t* best,
-                              double* best_cost, uint8_t* near_tie, const LaunchCfg& c,
-                              hipStream_t stream)
-{
-    if (n <= 0) return hipSuccess;
-    switch (c.block) {
-    case 64: select_t<64>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
-    case 128: select_t<128>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
-    case 256: select_t<256>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
-    case 512: select_t<512>(sh, off, code, n, n_cand, S, best, best_cost, near_tie, c.grid_mult, stream); break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

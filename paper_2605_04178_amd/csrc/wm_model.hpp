@@ -104,7 +104,7 @@ template <> struct Ar<double> {
 __device__ inline uint32_t udiv_small(uint32_t a, uint32_t b)
 {
     uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
-    const int32_t r = (int32_t)(a - q * b);
+    const int32_t r = (int32_t)(a - __umul24(q, b));   // q, b < 2^24: low 32 bits
     q = r < 0 ? q - 1u : (r >= (int32_t)b ? q + 1u : q);
     return q;
 }
@@ -134,7 +134,7 @@ __device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t 
         w = (int32_t)udiv_small((uint32_t)st.vgpr_simd, (uint32_t)va);
         w = w < st.waves_simd ? w : st.waves_simd;
     }
-    int32_t o = (int32_t)udiv_small((uint32_t)(st.n_simd * w), (uint32_t)r.k);
+    int32_t o = (int32_t)udiv_small(__umul24((uint32_t)st.n_simd, (uint32_t)w), (uint32_t)r.k);
     if (s > 0) {
         int32_t ol = 0;
         if (s <= st.lds_cu) {
@@ -203,7 +203,8 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         E.T = (R)__builtin_huge_val();
         return;
     }
-    const uint32_t per_round = (uint32_t)st.n_cu * (uint32_t)oc.o;
+    // n_cu <= 65536 and o <= 1024: 24-bit multiplies are exact
+    const uint32_t per_round = __umul24((uint32_t)st.n_cu, (uint32_t)oc.o);
     const uint32_t num = (uint32_t)d.G + per_round - 1u;
     const int32_t nr = (int32_t)(num < (1u << 21) ? udiv_small(num, per_round) : num / per_round);
     E.nr = nr;
@@ -279,7 +280,7 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
             }
         }
     } else {
-        int32_t neff = oc.o * oc.k;
+        int32_t neff = (int32_t)__umul24((uint32_t)oc.o, (uint32_t)oc.k);
         if (st.mwp > 0) neff = neff < st.mwp ? neff : st.mwp;
         if (st.cwp > 0) neff = neff < st.cwp ? neff : st.cwp;
         const R a = (R)(neff - 1);
