@@ -170,10 +170,11 @@ __global__ __launch_bounds__(256) void k_bw_adam(const double* __restrict__ part
     __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     reduce_partials(partials, rows, kAcc, red, tot);
-    if (threadIdx.x != 0) return;
-    if (adam_theta_step(st, tot, o, loss_hist)) {
-        make_bw_const<float>(st->theta, S->st, S->cf);
-        make_bw_const<double>(st->theta, S->st, S->cd);
+    __shared__ double th[kTheta];
+    if (threadIdx.x >= 64) return;
+    if (adam_theta_step(st, tot, o, loss_hist, th) && threadIdx.x == 0) {
+        make_bw_const<float>(th, S->st, S->cf);
+        make_bw_const<double>(th, S->st, S->cd);
     }
 }
 

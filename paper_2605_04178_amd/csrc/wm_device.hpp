@@ -84,53 +84,63 @@ __device__ inline void reduce_partials(const double* __restrict__ partials, int 
 // device Adam on log(theta)
 // ---------------------------------------------------------------------------
 __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const AdamOpts& o,
-                                       double* loss_hist)
+                                       double* loss_hist, double* th_out /* LDS [kTheta] */)
 {
-    // one thread does the update (24 values); the step index lives in device
-    // memory so one captured graph serves every chunk of steps.  Returns true
-    // when theta changed (the caller rebuilds its constants).
+    // Called by the 64 lanes of one wave, converged; lane j < 24 updates
+    // theta_j.  The step index lives in device memory so one captured graph
+    // serves every chunk of steps.  Returns true (on every lane) when theta
+    // changed; th_out then holds the new theta, visible to the whole wave,
+    // and the caller rebuilds its constants from it.
+    const int lane = threadIdx.x & 63;
     const int step_index = st->t;
-    st->t = step_index + 1;
+    const int was_diverged = st->diverged;
     const double cnt = tot[1];
     const double loss = cnt > 0.0 ? tot[0] / cnt : 0.0;
-    if (loss_hist && step_index < o.steps)
-        loss_hist[step_index] = st->diverged ? __builtin_nan("") : loss;
-    if (st->diverged) return false;
-    bool finite = __builtin_isfinite(loss);
-    double g[kTheta];
-    for (int j = 0; j < kTheta; ++j) {
-        g[j] = cnt > 0.0 ? tot[2 + j] / cnt : 0.0;
-        finite = finite && __builtin_isfinite(g[j]);
+    if (lane == 0) {
+        st->t = step_index + 1;
+        if (loss_hist && step_index < o.steps)
+            loss_hist[step_index] = was_diverged ? __builtin_nan("") : loss;
     }
-    if (!finite) {
-        st->diverged = 1;
+    if (was_diverged) return false;
+    const bool mine = lane < kTheta;
+    const double g = mine && cnt > 0.0 ? tot[2 + lane] / cnt : 0.0;
+    if (!__builtin_isfinite(loss) || __ballot(!__builtin_isfinite(g)) != 0) {
+        if (lane == 0) st->diverged = 1;
         return false;
     }
-    for (int j = 0; j < kTheta; ++j) st->theta_ok[j] = st->theta[j];
+    const double th = mine ? st->theta[lane] : 1.0;
+    if (mine) st->theta_ok[lane] = th;
     const double t = (double)(step_index + 1);
     double lr = o.lr;
     if (o.lr_final > 0.0 && o.steps > 1)
         lr = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
     const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
-    double th_new[kTheta];
+    double th_new = th;
     bool ok = true;
-    for (int j = 0; j < kTheta; ++j) {
-        th_new[j] = st->theta[j];
-        if (!((o.free_mask >> j) & 1u)) continue;
-        const double gp = st->theta[j] * g[j];
-        st->m[j] = o.beta1 * st->m[j] + (1.0 - o.beta1) * gp;
-        st->v[j] = o.beta2 * st->v[j] + (1.0 - o.beta2) * gp * gp;
-        const double mh = st->m[j] / (1.0 - b1t);
-        const double vh = st->v[j] / (1.0 - b2t);
-        st->phi[j] -= lr * mh / (sqrt(vh) + o.eps);
-        th_new[j] = exp(st->phi[j]);
-        ok = ok && __builtin_isfinite(th_new[j]) && th_new[j] > 0.0;
+    if (mine && ((o.free_mask >> lane) & 1u)) {
+        const double gp = th * g;
+        const double m = o.beta1 * st->m[lane] + (1.0 - o.beta1) * gp;
+        const double v = o.beta2 * st->v[lane] + (1.0 - o.beta2) * gp * gp;
+        st->m[lane] = m;
+        st->v[lane] = v;
+        const double mh = m / (1.0 - b1t);
+        const double vh = v / (1.0 - b2t);
+        const double phi = st->phi[lane] - lr * mh / (sqrt(vh) + o.eps);
+        st->phi[lane] = phi;
+        th_new = exp(phi);
+        ok = __builtin_isfinite(th_new) && th_new > 0.0;
     }
-    if (!ok) {
-        st->diverged = 1;
+    if (__ballot(!ok) != 0) {
+        if (lane == 0) st->diverged = 1;
         return false;
     }
-    for (int j = 0; j < kTheta; ++j) st->theta[j] = th_new[j];
+    if (mine) {
+        st->theta[lane] = th_new;
+        th_out[lane] = th_new;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return true;
 }
 

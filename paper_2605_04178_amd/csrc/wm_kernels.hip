@@ -417,10 +417,12 @@ hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, c
 __device__ inline void adam_update(CalibState* st, const double* tot, const AdamOpts& o, Set* S,
                                    double* loss_hist)
 {
-    if (threadIdx.x != 0) return;
-    if (adam_theta_step(st, tot, o, loss_hist)) {
-        make_const<float>(st->theta, S->st, S->cf);
-        make_const<double>(st->theta, S->st, S->cd);
+    __shared__ double th[kTheta];
+    if (threadIdx.x >= 64) return;
+    // one group of constants per lane, from the new theta in LDS
+    if (adam_theta_step(st, tot, o, loss_hist, th) && threadIdx.x < kConstFields) {
+        const_field<float>(th, S->st, S->cf, threadIdx.x);
+        const_field<double>(th, S->st, S->cd, threadIdx.x);
     }
 }
 

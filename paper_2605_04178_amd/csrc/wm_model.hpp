@@ -59,27 +59,45 @@ struct Set {
     Const<double> cd;
 };
 
+// One group k of the theta-derived constants (k < kConstFields), so that a
+// device rebuild can give each group to its own lane.
+constexpr int kConstFields = 21;
+template <typename R>
+WM_HD void const_field(const double* th, const Struct& s, Const<R>& c, int k)
+{
+    const bool blend = th[22] > 0.0;
+    if (k < 5) {
+        c.inv_peak[k] = (R)(1.0 / th[8 + k]);
+    } else if (k < 9) {
+        const int l = k - 5;
+        c.bw[l] = (R)th[l];
+        c.latf[l] = (R)(th[4 + l] / s.f_clk);
+    } else if (k < 16) {
+        c.ov[k - 9] = (R)th[13 + (k - 9)];
+    } else if (k == 16) {
+        c.alpha = (R)th[20];
+        c.beta = (R)th[21];
+        c.blend_on = blend ? 1 : 0;
+        c.pad_ = 0;
+        c.w_lo = (R)s.w_lo_mib;
+        c.c_llc = (R)s.c_llc_mib;
+    } else if (k == 17) {
+        c.inv_w0 = blend ? (R)(1.0 / th[22]) : (R)0;
+    } else if (k == 18) {
+        c.blend_k = blend ? (R)(-1.4426950408889634 / th[22]) : (R)0;
+    } else if (k == 19) {
+        c.bp_minus_bw = (R)(th[23] - th[3]);
+        c.inv_lw = (R)(1.0 / (double)s.bytes_inflight_wave);
+    } else if (k == 20) {
+        c.inv_f = (R)(1.0 / s.f_clk);
+        c.inv_span = (R)(1.0 / (s.c_llc_mib - s.w_lo_mib));
+    }
+}
+
 template <typename R>
 WM_HD void make_const(const double* th, const Struct& s, Const<R>& c)
 {
-    for (int t = 0; t < 5; ++t) c.inv_peak[t] = (R)(1.0 / th[8 + t]);
-    for (int l = 0; l < 4; ++l) {
-        c.bw[l] = (R)th[l];
-        c.latf[l] = (R)(th[4 + l] / s.f_clk);
-    }
-    for (int j = 0; j < 7; ++j) c.ov[j] = (R)th[13 + j];
-    c.alpha = (R)th[20];
-    c.beta = (R)th[21];
-    c.blend_on = th[22] > 0.0 ? 1 : 0;
-    c.inv_w0 = c.blend_on ? (R)(1.0 / th[22]) : (R)0;
-    c.blend_k = c.blend_on ? (R)(-1.4426950408889634 / th[22]) : (R)0;
-    c.bp_minus_bw = (R)(th[23] - th[3]);
-    c.inv_lw = (R)(1.0 / (double)s.bytes_inflight_wave);
-    c.inv_f = (R)(1.0 / s.f_clk);
-    c.w_lo = (R)s.w_lo_mib;
-    c.c_llc = (R)s.c_llc_mib;
-    c.inv_span = (R)(1.0 / (s.c_llc_mib - s.w_lo_mib));
-    c.pad_ = 0;
+    for (int k = 0; k < kConstFields; ++k) const_field<R>(th, s, c, k);
 }
 
 // ---------------------------------------------------------------------------
