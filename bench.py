@@ -367,6 +367,28 @@ def hardware_model_leg(wm, log):
     return out
 
 
+def platform(dev):
+    """What the numbers were measured on: the GPU as the runtime reports it,
+    its shader clock measured by wmb_clock, the host CPU."""
+    import torch
+    from paper_2605_04178_amd import microbench as mb
+    pr = torch.cuda.get_device_properties(dev)
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"gpu": pr.name, "arch": getattr(pr, "gcnArchName", ""), "cus": pr.multi_processor_count,
+            "hbm_gib": pr.total_memory / 2 ** 30, "l2_mib": getattr(pr, "L2_cache_size", 0) / 2 ** 20,
+            "hip_runtime": torch.version.hip, "torch": torch.__version__,
+            "shader_clock_ghz": {"one_wave": mb.clock_hz(1) / 1e9,
+                                 "loaded_32_waves_per_cu": mb.clock_hz(pr.multi_processor_count * 32) / 1e9},
+            "host_cpu": cpu, "host_threads_visible": len(os.sched_getaffinity(0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -558,6 +580,7 @@ def main():
 
     if tuned:
         res["autotune_us"] = {k: v["us"] for k, v in tuned.items()}
+    res["platform"] = platform(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(p, d, synth)

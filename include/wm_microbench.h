@@ -67,6 +67,15 @@ int32_t wmb_read_bw(const void *buf, int64_t bytes, int32_t passes, int32_t bloc
 int32_t wmb_chase(const uint32_t *next, int64_t n_nodes, int64_t steps, uint32_t *sink,
                   int64_t *ticks, void *stream, double *ns_per_step);
 
+/* Shader clock: `blocks` workgroups of one wave each run `spins` dependent
+ * FMAs; block 0 reads the shader-cycle counter and the constant-rate wall
+ * clock around its chain.  hz (host) = cycles / seconds of that chain, on the
+ * second of two launches.  blocks 1 gives the clock of a lightly loaded
+ * part, several per CU the clock under load.  sink: 1 float (never
+ * written); ticks: 2 int64 (device scratch). */
+int32_t wmb_clock(int32_t blocks, int32_t spins, float *sink, int64_t *ticks, void *stream,
+                  double *hz);
+
 /* Throughput of data type `kind` (WMB_PEAK_*): `blocks` blocks of 4 waves,
  * `iters` iterations of independent instruction chains per wave.  flops:
  * operations per launch (host); seconds: median time per launch.

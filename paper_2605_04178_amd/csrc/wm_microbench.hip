@@ -79,6 +79,25 @@ __global__ __launch_bounds__(64) void k_mb_chase(const uint32_t* __restrict__ ne
     ticks[0] = t1 - t0;
 }
 
+// Shader clock: every thread runs a chain of `spins` dependent FMAs; the
+// first lane of block 0 reads the shader-cycle counter (clock64) and the
+// constant-rate wall clock (wall_clock64) before and after its chain.
+__global__ __launch_bounds__(64) void k_mb_clock(int32_t spins, float seed, float* __restrict__ sink,
+                                                 int64_t* __restrict__ ticks)
+{
+    const int64_t c0 = clock64(), w0 = wall_clock64();
+    float x = seed + (float)threadIdx.x + (float)(c0 & 1);
+    for (int32_t i = 0; i < spins; ++i) x = __builtin_fmaf(x, 0.9999999f, 1e-7f);
+    // the chain's result enters the second reading, which therefore follows it
+    const int64_t c1 = clock64() + (x == -1.0f ? 1 : 0);
+    const int64_t w1 = wall_clock64();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ticks[0] = c1 - c0;
+        ticks[1] = w1 - w0;
+    }
+    if (x == -1.0f) sink[0] = x;  // keeps the chain; it never reaches -1
+}
+
 // Throughput per data type: independent accumulator chains per wave.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_mb_peak(int32_t iters, float seed, float* __restrict__ sink)
@@ -398,6 +417,27 @@ int32_t wmb_chase(const uint32_t* next, int64_t n_nodes, int64_t steps, uint32_t
     WMB_HIP(hipMemcpyAsync(&t, ticks, sizeof(t), hipMemcpyDeviceToHost, s));
     WMB_HIP(hipStreamSynchronize(s));
     *ns_per_step = (double)t * 1e6 / (double)khz / (double)steps;
+    return WMB_OK;
+}
+
+int32_t wmb_clock(int32_t blocks, int32_t spins, float* sink, int64_t* ticks, void* stream, double* hz)
+{
+    if (blocks < 1 || blocks > (1 << 20) || spins < 1 || !sink || !ticks || !hz) return WMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, khz = 0;
+    WMB_HIP(hipGetDevice(&dev));
+    WMB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return WMB_EHIP;
+    // a warm-up launch (the clock ramps under load), then the measured one
+    k_mb_clock<<<blocks, 64, 0, s>>>(spins, 1.0f, sink, ticks);
+    WMB_HIP(hipGetLastError());
+    k_mb_clock<<<blocks, 64, 0, s>>>(spins, 1.0f, sink, ticks);
+    WMB_HIP(hipGetLastError());
+    int64_t t[2] = {0, 0};
+    WMB_HIP(hipMemcpyAsync(t, ticks, sizeof(t), hipMemcpyDeviceToHost, s));
+    WMB_HIP(hipStreamSynchronize(s));
+    if (t[1] <= 0) return WMB_EHIP;
+    *hz = (double)t[0] * (double)khz * 1e3 / (double)t[1];
     return WMB_OK;
 }
 

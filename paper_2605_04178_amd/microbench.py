@@ -67,6 +67,8 @@ def lib():
         L.wmb_read_bw.restype = i32
         L.wmb_chase.argtypes = [vp, i64, i64, vp, vp, vp, dp]
         L.wmb_chase.restype = i32
+        L.wmb_clock.argtypes = [i32, i32, vp, vp, vp, dp]
+        L.wmb_clock.restype = i32
         L.wmb_peak.argtypes = [i32, i32, i32, vp, i32, vp, dp, dp]
         L.wmb_peak.restype = i32
         L.wmb_empty.argtypes = [i32, i32, i32, vp, i32, vp, dp]
@@ -95,6 +97,19 @@ def _stream(torch, s=None):
 # ---------------------------------------------------------------------------
 # measurement (needs a GPU)
 # ---------------------------------------------------------------------------
+def clock_hz(blocks: int = 1, spins: int = 1 << 20) -> float:
+    """Shader clock (Hz) measured by wmb_clock on cuda:0: blocks = 1 for a
+    lightly loaded part, several per CU for the clock under load."""
+    import torch
+    L = lib()
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ticks = torch.zeros(2, dtype=torch.int64, device="cuda")
+    hz = C.c_double()
+    _check(L.wmb_clock(int(blocks), int(spins), C.c_void_p(sink.data_ptr()), C.c_void_p(ticks.data_ptr()),
+                       _stream(torch), C.byref(hz)), "wmb_clock")
+    return hz.value
+
+
 def chase_chain(n_nodes: int, stride_words: int, seed: int) -> np.ndarray:
     """A random single cycle over n_nodes nodes spaced stride_words uint32
     apart: entry node*stride holds the index of the next node's entry."""
@@ -123,6 +138,9 @@ def measure(quick: bool = False, log=print) -> dict:
     sinki = torch.zeros(4, dtype=torch.int32, device=dev)
     sec = C.c_double()
     cus = props.multi_processor_count
+    out["clock_hz"] = {"one_wave": clock_hz(1), "loaded": clock_hz(cus * 32)}
+    log(f"shader clock {out['clock_hz']['one_wave'] / 1e9:.3f} GHz (one wave), "
+        f"{out['clock_hz']['loaded'] / 1e9:.3f} GHz (32 waves per CU)")
 
     # --- read bandwidth against working set ---
     # every block reads the whole buffer up to 4 MiB (per-CU L1, per-XCD L2),

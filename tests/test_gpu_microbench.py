@@ -122,6 +122,16 @@ def test_microbenchmarks_run(mb):
     assert 0 < sec.value < 1e-2
 
 
+def test_shader_clock(mb):
+    """The shader-cycle counter against the constant-rate wall clock: a
+    plausible clock for this part, lightly loaded and under load."""
+    f1 = mb.clock_hz(1, 1 << 18)
+    props = torch.cuda.get_device_properties(0)
+    f2 = mb.clock_hz(props.multi_processor_count * 32, 1 << 18)
+    say("shader clock GHz: one wave", f1 / 1e9, "loaded", f2 / 1e9)
+    assert 0.5e9 < f1 < 5e9 and 0.5e9 < f2 < 5e9
+
+
 def test_shipped_mi355x_parameters_predict_held_out_kernels(mb):
     """The shipped parameter file is valid and, on the held-out validation
     kernels re-timed on this GPU, the calibrated model beats the naive

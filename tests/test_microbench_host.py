@@ -173,6 +173,9 @@ def test_wmbench_argument_checks_without_a_gpu():
     assert L.wmb_chase(C.c_void_p(0x1000), 1000, 10, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
     assert L.wmb_peak(7, 10, 1, C.c_void_p(0x100), 1, None, C.byref(d), C.byref(d)) == -1
     assert L.wmb_empty(1, 100, 0, C.c_void_p(0x100), 1, None, C.byref(d)) == -1
+    assert L.wmb_clock(0, 10, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
+    assert L.wmb_clock(1, 0, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
+    assert L.wmb_clock(1, 10, None, C.c_void_p(0x200), None, C.byref(d)) == -1
     assert L.wmb_val_bytes(99, 1024, 0) == -1
     assert L.wmb_val_bytes(mb.VAL["copy"], 1023, 0) == -1
     assert L.wmb_val_bytes(mb.VAL["gemm_mfma"], 100, 0) == -1
@@ -196,7 +199,7 @@ def test_wmbench_exports_every_declared_symbol():
                        "wm_microbench.h")
     src = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
     declared = set(re.findall(r"\b(wmb_[a-z_]+)\s*\(", src))
-    assert {"wmb_read_bw", "wmb_chase", "wmb_peak", "wmb_empty", "wmb_val_run"} <= declared
+    assert {"wmb_read_bw", "wmb_chase", "wmb_peak", "wmb_empty", "wmb_val_run", "wmb_clock"} <= declared
     out = subprocess.run(["nm", "-D", "--defined-only", mb.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     assert declared <= set(re.findall(r"\s[TW]\s+(wmb_\w+)", out))
