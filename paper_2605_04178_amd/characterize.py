@@ -240,7 +240,7 @@ def summary_md(res: dict) -> str:
          "The recalibration suite's validation kernels, characterized from their algorithms and from "
          "rocprofv3 counters; the same measured times, the shipped microbenchmark parameters and the same "
          f"calibration (Adam, {res['steps']} steps, training split) -- `paper_2605_04178_amd/characterize.py`.\n",
-         "Commands (from /tmp with TMPDIR=/tmp and PYTHONPATH=$R; R = repository root; O = $R/gpurun_out/char):\n",
+         "Commands (from /tmp with TMPDIR=/tmp and PYTHONPATH=$R; R = repository root; O = an output directory):\n",
          "```\n"
          "python -m paper_2605_04178_amd.characterize run --out $O/T.json\n"
          "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/F -o fetch -- "
