@@ -49,6 +49,9 @@ extern "C" {
 #define WMB_VAL_GEMM16 8           /* same, 16 x 16 */
 #define WMB_VAL_GEMM32 9           /* same, 32 x 32 */
 #define WMB_VAL_GEMM_MFMA 10       /* BF16 C = A B^T on matrix cores, 64 x 64 tiles, n % 64 == 0 */
+#define WMB_VAL_BIAS 11            /* c[r][col] += a[col], n x n floats, n % 64 == 0 */
+#define WMB_VAL_GEMM_MFMA_BIAS 12  /* GEMM_MFMA with the bias added in its epilogue: b holds
+                                      B^T (bf16) followed by the n float bias values */
 
 int32_t wmb_last_hip_error(void);
 
@@ -88,6 +91,12 @@ int32_t wmb_peak(int32_t kind, int32_t iters, int32_t blocks, float *sink, int32
  * `barriers` workgroup barriers; sink: 1 int32 (never written). */
 int32_t wmb_empty(int32_t blocks, int32_t block, int32_t barriers, int32_t *sink, int32_t launches,
                   void *stream, double *seconds);
+
+/* Cost of one host synchronisation (Section IV-E, tau_sync): `reps` empty
+ * kernels each followed by hipStreamSynchronize against `reps` launched back
+ * to back and synchronised once; per_sync (host) = the difference per
+ * kernel, host wall clock.  sink: 1 int32 (never written). */
+int32_t wmb_sync(int32_t reps, int32_t *sink, void *stream, double *per_sync);
 
 /* Resources of validation kernel `kind` as compiled: VGPRs per thread, static
  * LDS bytes per workgroup, threads per workgroup (host outputs). */

@@ -43,7 +43,8 @@ VAL_KERNEL = "k_val_"
 STEM = {"copy": "k_val_copy", "triad": "k_val_triad", "reduce": "k_val_reduce", "fma": "k_val_fma",
         "stencil": "k_val_stencil", "transpose_naive": "k_val_transpose_naive",
         "transpose_lds": "k_val_transpose_lds", "gemm8": "k_val_gemm_tile", "gemm16": "k_val_gemm_tile",
-        "gemm32": "k_val_gemm_tile", "gemm_mfma": "k_val_gemm_mfma"}
+        "gemm32": "k_val_gemm_tile", "gemm_mfma": "k_val_gemm_mfma", "bias": "k_val_bias",
+        "gemm_mfma_bias": "k_val_gemm_mfma"}
 
 
 # ---------------------------------------------------------------------------
@@ -255,7 +256,7 @@ def summary_md(res: dict) -> str:
          "--params $R/paper_2605_04178_amd/params/mi355x.json --out $O/result.json --md $O/summary.md\n```\n",
          "Counter scales from the reference copy: " +
          ", ".join(f"{k} {v:.4g}" for k, v in res["scales"].items() if not isinstance(v, list)) + ".\n",
-         "## Mean absolute relative error (all 58 kernels / held out)\n",
+         f"## Mean absolute relative error (all {len(res['cases'])} kernels / held out)\n",
          "| characterization | naive roofline | model, microbenchmark theta | model, calibrated (train) | model, calibrated (held out) |",
          "|---|---|---|---|---|"]
     for tag in tags:

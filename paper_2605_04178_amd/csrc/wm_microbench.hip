@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <chrono>
 #include <functional>
 #include <vector>
 
@@ -300,8 +301,12 @@ __global__ __launch_bounds__(T * T) void k_val_gemm_tile(const float* __restrict
 // tile, each wave one 32 x 32 quarter, v_mfma_f32_32x32x16_bf16 over K in
 // steps of 16; operands are read straight from global memory (each lane
 // loads 8 consecutive bf16 = 16 bytes of one row).  n must be a multiple of 64.
+// BIAS: the epilogue adds bias[column] (the fused GEMM + bias of the fusion
+// microbenchmark).
+template <bool BIAS>
 __global__ __launch_bounds__(256) void k_val_gemm_mfma(const __bf16* __restrict__ A,
                                                        const __bf16* __restrict__ Bt,
+                                                       const float* __restrict__ bias,
                                                        float* __restrict__ C, int32_t n)
 {
     const int32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -317,11 +322,25 @@ __global__ __launch_bounds__(256) void k_val_gemm_mfma(const __bf16* __restrict_
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     // result layout: lane l holds column (l % 32), rows 8 (j / 4) + 4 (l / 32) + (j % 4)
+    const float bc = BIAS ? bias[c0 + rr] : 0.0f;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int32_t r = r0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-        C[(int64_t)r * n + c0 + rr] = acc[j];
+        C[(int64_t)r * n + c0 + rr] = BIAS ? acc[j] + bc : acc[j];
     }
+}
+
+// C[r][c] += bias[c] over an n x n float matrix (n % 4 == 0), one float4
+// per thread: the unfused second kernel of the fusion microbenchmark.
+__global__ __launch_bounds__(256) void k_val_bias(const float* __restrict__ bias, f4* __restrict__ C,
+                                                  int32_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n4 = (int64_t)n * n / 4;
+    if (i >= n4) return;
+    const int32_t c = (int32_t)((i * 4) % n);
+    const f4 b = *reinterpret_cast<const f4*>(bias + c);
+    C[i] += b;
 }
 
 const void* val_kernel(int32_t kind)
@@ -337,7 +356,9 @@ const void* val_kernel(int32_t kind)
     case WMB_VAL_GEMM8: return reinterpret_cast<const void*>(&k_val_gemm_tile<8>);
     case WMB_VAL_GEMM16: return reinterpret_cast<const void*>(&k_val_gemm_tile<16>);
     case WMB_VAL_GEMM32: return reinterpret_cast<const void*>(&k_val_gemm_tile<32>);
-    case WMB_VAL_GEMM_MFMA: return reinterpret_cast<const void*>(&k_val_gemm_mfma);
+    case WMB_VAL_GEMM_MFMA: return reinterpret_cast<const void*>(&k_val_gemm_mfma<false>);
+    case WMB_VAL_BIAS: return reinterpret_cast<const void*>(&k_val_bias);
+    case WMB_VAL_GEMM_MFMA_BIAS: return reinterpret_cast<const void*>(&k_val_gemm_mfma<true>);
     default: return nullptr;
     }
 }
@@ -473,6 +494,33 @@ int32_t wmb_empty(int32_t blocks, int32_t block, int32_t barriers, int32_t* sink
     }, seconds);
 }
 
+int32_t wmb_sync(int32_t reps, int32_t* sink, void* stream, double* per_sync)
+{
+    if (reps < 1 || !sink || !per_sync) return WMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    using clk = std::chrono::steady_clock;
+    k_mb_empty<<<1, 64, 0, s>>>(0, sink);
+    WMB_HIP(hipGetLastError());
+    WMB_HIP(hipStreamSynchronize(s));
+    const auto t0 = clk::now();
+    for (int32_t r = 0; r < reps; ++r) {
+        k_mb_empty<<<1, 64, 0, s>>>(0, sink);
+        WMB_HIP(hipGetLastError());
+        WMB_HIP(hipStreamSynchronize(s));
+    }
+    const auto t1 = clk::now();
+    for (int32_t r = 0; r < reps; ++r) {
+        k_mb_empty<<<1, 64, 0, s>>>(0, sink);
+        WMB_HIP(hipGetLastError());
+    }
+    WMB_HIP(hipStreamSynchronize(s));
+    const auto t2 = clk::now();
+    const double with_sync = std::chrono::duration<double>(t1 - t0).count();
+    const double without = std::chrono::duration<double>(t2 - t1).count();
+    *per_sync = (with_sync - without) / (double)reps;
+    return WMB_OK;
+}
+
 int32_t wmb_val_attr(int32_t kind, int32_t* vgprs, int32_t* lds_bytes, int32_t* block)
 {
     const void* k = val_kernel(kind);
@@ -493,6 +541,12 @@ int32_t wmb_val_attr(int32_t kind, int32_t* vgprs, int32_t* lds_bytes, int32_t* 
 int64_t wmb_val_bytes(int32_t kind, int64_t n, int32_t which)
 {
     if (!val_kernel(kind) || n < 1 || which < 0 || which > 2) return -1;
+    if (kind == WMB_VAL_BIAS || kind == WMB_VAL_GEMM_MFMA_BIAS) {
+        if (n > 65536 || n % 64) return -1;
+        const int64_t el = n * n;
+        if (kind == WMB_VAL_BIAS) return which == 0 ? n * 4 : (which == 1 ? 0 : el * 4);
+        return which == 0 ? el * 2 : (which == 1 ? el * 2 + n * 4 : el * 4);
+    }
     const bool two_d = kind == WMB_VAL_STENCIL || kind == WMB_VAL_TRANSPOSE_NAIVE ||
                        kind == WMB_VAL_TRANSPOSE_LDS || kind >= WMB_VAL_GEMM8;
     if (two_d) {
@@ -586,7 +640,29 @@ int32_t wmb_val_run(int32_t kind, const void* a, int64_t a_bytes, const void* b,
         const dim3 g(m / 64, m / 64);
         *grid = (int64_t)g.x * g.y;
         run = [=]() {
-            k_val_gemm_mfma<<<g, 256, 0, s>>>((const __bf16*)a, (const __bf16*)b, (float*)c, m);
+            k_val_gemm_mfma<false><<<g, 256, 0, s>>>((const __bf16*)a, (const __bf16*)b, nullptr, (float*)c, m);
+            return hipGetLastError();
+        };
+        break;
+    }
+    case WMB_VAL_GEMM_MFMA_BIAS: {
+        if (((uintptr_t)a & 15) || ((uintptr_t)b & 15)) return WMB_EINVAL;
+        const dim3 g(m / 64, m / 64);
+        *grid = (int64_t)g.x * g.y;
+        // the bias vector follows Bt in buffer b
+        const float* bias = (const float*)((const char*)b + (int64_t)m * m * 2);
+        run = [=]() {
+            k_val_gemm_mfma<true><<<g, 256, 0, s>>>((const __bf16*)a, (const __bf16*)b, bias, (float*)c, m);
+            return hipGetLastError();
+        };
+        break;
+    }
+    case WMB_VAL_BIAS: {
+        if (((uintptr_t)a & 15) || ((uintptr_t)c & 15)) return WMB_EINVAL;
+        const int64_t g = ((int64_t)m * m / 4 + 255) / 256;
+        *grid = g;
+        run = [=]() {
+            k_val_bias<<<g, 256, 0, s>>>((const float*)a, (f4*)c, m);
             return hipGetLastError();
         };
         break;

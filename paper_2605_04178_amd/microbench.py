@@ -40,7 +40,7 @@ MIB = 1 << 20
 
 PEAK_KINDS = ("fp64", "fp32", "bf16", "fp8", "int8")
 VAL = dict(copy=0, triad=1, fma=2, stencil=3, transpose_naive=4, transpose_lds=5, reduce=6,
-           gemm8=7, gemm16=8, gemm32=9, gemm_mfma=10)
+           gemm8=7, gemm16=8, gemm32=9, gemm_mfma=10, bias=11, gemm_mfma_bias=12)
 
 # MI355X (gfx950) structure: 256 CUs of 4 SIMDs, 64-wide waves, 512 VGPRs and
 # 8 wave slots per SIMD, 160 KB LDS per CU, 256 MB Infinity Cache, 2.4 GHz.
@@ -69,6 +69,8 @@ def lib():
         L.wmb_chase.restype = i32
         L.wmb_clock.argtypes = [i32, i32, vp, vp, vp, dp]
         L.wmb_clock.restype = i32
+        L.wmb_sync.argtypes = [i32, vp, vp, dp]
+        L.wmb_sync.restype = i32
         L.wmb_peak.argtypes = [i32, i32, i32, vp, i32, vp, dp, dp]
         L.wmb_peak.restype = i32
         L.wmb_empty.argtypes = [i32, i32, i32, vp, i32, vp, dp]
@@ -122,6 +124,36 @@ def chase_chain(n_nodes: int, stride_words: int, seed: int) -> np.ndarray:
     nxt[src] = dst.astype(np.uint32)
     assert int(nxt.max()) < nxt.shape[0]
     return nxt
+
+
+def fusion_times(sizes, launches: int = 10, log=print) -> list:
+    """(n, T_gemm, T_bias, T_fused) for the BF16 matrix-core GEMM, the bias
+    kernel and the GEMM with the bias fused into its epilogue."""
+    import torch
+    L = lib()
+    st = _stream(torch)
+    sec, grid = C.c_double(), C.c_int64()
+    res = []
+    for n in sizes:
+        nb = [[int(L.wmb_val_bytes(k, n, w)) for w in range(3)] for k in (VAL["gemm_mfma"], VAL["bias"],
+                                                                           VAL["gemm_mfma_bias"])]
+        A = torch.rand(n * n, device="cuda").to(torch.bfloat16)
+        Bb = torch.zeros(nb[2][1] // 2, dtype=torch.bfloat16, device="cuda")
+        Bb[: n * n] = torch.rand(n * n, device="cuda").to(torch.bfloat16)
+        Bb[n * n:].view(torch.float32).copy_(torch.rand(n, device="cuda"))
+        Cm = torch.empty(n * n, dtype=torch.float32, device="cuda")
+        bias = Bb[n * n:].view(torch.float32)
+        t = []
+        for k, (a, b) in ((VAL["gemm_mfma"], (A, Bb)), (VAL["bias"], (bias, None)), (VAL["gemm_mfma_bias"], (A, Bb))):
+            kb = nb[[VAL["gemm_mfma"], VAL["bias"], VAL["gemm_mfma_bias"]].index(k)]
+            _check(L.wmb_val_run(k, C.c_void_p(a.data_ptr()), kb[0], C.c_void_p(b.data_ptr()) if b is not None else None,
+                                 kb[1], C.c_void_p(Cm.data_ptr()), kb[2], n, 0, launches, st, C.byref(sec),
+                                 C.byref(grid)), "wmb_val_run fusion")
+            t.append(sec.value)
+        res.append((n, t[0], t[1], t[2]))
+        log(f"fusion n={n}: GEMM {t[0] * 1e6:.1f} us + bias {t[1] * 1e6:.1f} us unfused, fused {t[2] * 1e6:.1f} us")
+        del A, Bb, Cm
+    return res
 
 
 def measure(quick: bool = False, log=print) -> dict:
@@ -205,6 +237,18 @@ def measure(quick: bool = False, log=print) -> dict:
     out["barriers"] = [(k, empty(res_blocks, 256, k)) for k in (0, 1024, 4096, 16384)]
     out["barrier_blocks"] = res_blocks
     log(f"empty kernel {out['empty_1'] * 1e6:.2f} us")
+
+    # --- host synchronisation (tau_sync) ---
+    per = C.c_double()
+    syncs = []
+    for _ in range(5):
+        _check(L.wmb_sync(200, C.c_void_p(sinki.data_ptr()), st, C.byref(per)), "wmb_sync")
+        syncs.append(per.value)
+    out["sync_s"] = syncs
+    log(f"host synchronisation {float(np.median(syncs)) * 1e6:.2f} us")
+
+    # --- fusion: GEMM, bias and the fused GEMM + bias (tau_fusion) ---
+    out["fusion"] = fusion_times([2048, 4096] if quick else [2048, 4096, 8192], log=log)
 
     # --- two concurrent streams (interference) ---
     buf = torch.ones((64 << 20) // 4, dtype=torch.float32, device=dev)
@@ -386,8 +430,12 @@ def derive_params(meas: dict, struct: Optional[dict] = None) -> "synth.ParamSet"
     th[15] = max(tau_bar, 0.0)
     th[16] = tau_interf
     th[17] = 0.0        # one GPU: no multi-device measurement
-    th[18] = 0.0        # fusion overhead not measured
-    th[19] = 0.0        # host synchronisation is outside kernel times
+    # the fused kernel's time over the plain GEMM's (the epilogue's own flops
+    # and bytes are below 0.05 % of the GEMM's, so the model's two
+    # descriptors differ by a negligible amount): median over sizes
+    fus = meas.get("fusion", [])
+    th[18] = float(np.median([max(0.0, tf - tg) for _, tg, _, tf in fus])) if fus else 0.0
+    th[19] = max(0.0, float(np.median(meas["sync_s"]))) if meas.get("sync_s") else 0.0
     th[20] = alpha if alpha else 1.0
     th[21] = beta if beta else 1.0
     th[22] = 0.0        # Eq. (16) blend off (not identifiable with an LLC)
@@ -431,6 +479,7 @@ class Case:
     vgpr: int = 0
     lds: int = 0
     block: int = 256
+    fused: int = 0      # 1: a fused kernel (the model adds tau_fusion)
 
 
 def case_list(quick: bool = False) -> List[Case]:
@@ -466,6 +515,13 @@ def case_list(quick: bool = False) -> List[Case]:
         unique = 8.0 * m * m
         cs.append(Case(f"gemm_mfma_{m}", "gemm_mfma", m, 0, 2.0 * m ** 3, loaded + 4.0 * m * m, 0.5,
                        max(0.0, 1.0 - unique / (loaded / 2.0)), m / 16, unique, 2))
+        # the fusion pair: the bias kernel alone (read C and the bias, write
+        # C) and the GEMM with the bias added in its epilogue
+        cs.append(Case(f"bias_{m}", "bias", m, 0, 1.0 * m * m, 8.0 * m * m + 4.0 * m, 0, 0, 1,
+                       8.0 * m * m, 1))
+        cs.append(Case(f"gemm_mfma_bias_{m}", "gemm_mfma_bias", m, 0, 2.0 * m ** 3 + m * m,
+                       loaded + 4.0 * m * m + 4.0 * m, 0.5, max(0.0, 1.0 - unique / (loaded / 2.0)), m / 16,
+                       unique, 2, fused=1))
     return cs
 
 
@@ -496,7 +552,7 @@ def run_cases(cases: List[Case], launches: int = 10, log=print) -> List[Case]:
         nbytes = [int(L.wmb_val_bytes(kind, c.n, w)) for w in range(3)]
         if nbytes[0] < 0:
             raise ValueError(c.name)
-        dt = torch.bfloat16 if c.kind == "gemm_mfma" else torch.float32
+        dt = torch.bfloat16 if c.kind in ("gemm_mfma", "gemm_mfma_bias") else torch.float32
         a = buf("a", nbytes[0], dt)
         b = buf("b", nbytes[1], dt) if nbytes[1] > 0 else None
         cc = buf("c", nbytes[2])
@@ -516,7 +572,8 @@ def descriptors_of(cases: List[Case]) -> "synth.Descriptors":
     n = len(cases)
     g = np.array([c.block for c in cases], np.int64)
     gp = synth.pack_gpack(g, np.array([c.dtype for c in cases]), np.ones(n, np.int64),
-                          np.ones(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64))
+                          np.ones(n, np.int64), np.array([c.fused for c in cases], np.int64),
+                          np.zeros(n, np.int64))
     return synth.Descriptors(
         F=np.array([c.F for c in cases], f32), B=np.array([c.B for c in cases], f32),
         r1=np.array([c.r1 for c in cases], f32), r2=np.array([c.r2 for c in cases], f32),

@@ -94,6 +94,43 @@ def test_matrix_core_gemm(mb, m):
     assert np.allclose(c.cpu().numpy().reshape(m, m), ref, rtol=1e-3, atol=1e-3)
 
 
+@pytest.mark.parametrize("m", [128, 256])
+def test_bias_and_fused_gemm_bias(mb, m):
+    """The fusion pair: the bias kernel adds bias[col] to every row; the fused
+    GEMM equals the plain GEMM plus the bias."""
+    rng = np.random.default_rng(m + 1)
+    A = torch.from_numpy(rng.standard_normal((m, m)).astype(np.float32)).to(torch.bfloat16)
+    Bt = torch.from_numpy(rng.standard_normal((m, m)).astype(np.float32)).to(torch.bfloat16)
+    bias = rng.standard_normal(m).astype(np.float32)
+    bbuf = torch.zeros(m * m + 2 * m, dtype=torch.bfloat16)
+    bbuf[: m * m] = Bt.reshape(-1)
+    bbuf[m * m:].view(torch.float32).copy_(torch.from_numpy(bias))
+    c = torch.zeros(m * m, dtype=torch.float32, device="cuda")
+    _run(mb, "gemm_mfma_bias", A.cuda().contiguous().reshape(-1), bbuf.cuda(), c, m)
+    ref = A.double().numpy() @ Bt.double().numpy().T + bias[None, :]
+    assert np.allclose(c.cpu().numpy().reshape(m, m), ref, rtol=1e-3, atol=1e-3)
+    x = rng.standard_normal((m, m)).astype(np.float32)
+    cb = torch.from_numpy(x.reshape(-1)).cuda()
+    # wmb_val_run runs the kernel once untimed and `launches` times timed
+    L = mb.lib()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sec, g = C.c_double(), C.c_int64()
+    bd = torch.from_numpy(bias).cuda()
+    assert L.wmb_val_run(mb.VAL["bias"], C.c_void_p(bd.data_ptr()), m * 4, None, 0, C.c_void_p(cb.data_ptr()),
+                         m * m * 4, m, 0, 2, st, C.byref(sec), C.byref(g)) == 0
+    assert np.allclose(cb.cpu().numpy().reshape(m, m), x + 3 * bias[None, :], rtol=1e-5, atol=1e-5)
+
+
+def test_host_sync_cost(mb):
+    L = mb.lib()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    si = torch.zeros(4, dtype=torch.int32, device="cuda")
+    per = C.c_double()
+    assert L.wmb_sync(50, C.c_void_p(si.data_ptr()), st, C.byref(per)) == 0
+    say("host sync us", per.value * 1e6)
+    assert -1e-4 < per.value < 1e-3
+
+
 def test_microbenchmarks_run(mb):
     L = mb.lib()
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)

@@ -109,6 +109,8 @@ def _synthetic_measurements():
         "barriers": [(k, 5e-6 + 3e-8 * k) for k in (0, 1024, 4096, 16384)],
         "barrier_blocks": 2048,
         "interference": {"solo": 20e-6, "concurrent": [31e-6, 29e-6]},
+        "sync_s": [7e-6, 6e-6, 9e-6],
+        "fusion": [(2048, 100e-6, 30e-6, 101e-6), (4096, 700e-6, 110e-6, 703e-6), (8192, 5e-3, 4e-4, 4.99e-3)],
         "copies": {"h2d": [(n, 2e-6 + n / 50e9) for n in (1 << 12, 1 << 20, 1 << 28)],
                    "d2h": [(n, 3e-6 + n / 40e9) for n in (1 << 12, 1 << 20, 1 << 28)]},
     }
@@ -126,6 +128,9 @@ def test_derive_params_recovers_planted_values(wmb_lib):
     assert th[8:13] == [70e12, 80e12, 2.2e15, 4.4e15, 4.3e15]
     assert abs(th[13] - 4e-6) < 1e-18 and abs(th[14] - 2e-9) < 1e-15 and abs(th[15] - 3e-8) < 1e-14
     assert abs(th[16] - 10e-6) < 1e-12
+    # tau_fusion: median of the fused-over-plain GEMM excess, floored at 0;
+    # tau_sync: median per-sync cost
+    assert abs(th[18] - 1e-6) < 1e-15 and abs(th[19] - 7e-6) < 1e-15
     assert abs(th[20] - 1.5) < 1e-6 and abs(th[21] - 1.1) < 1e-6
     assert p.n_cu == 256 and p.n_levels == 4
     # the derived set is one the library accepts
@@ -176,6 +181,11 @@ def test_wmbench_argument_checks_without_a_gpu():
     assert L.wmb_clock(0, 10, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
     assert L.wmb_clock(1, 0, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
     assert L.wmb_clock(1, 10, None, C.c_void_p(0x200), None, C.byref(d)) == -1
+    assert L.wmb_sync(0, C.c_void_p(0x100), None, C.byref(d)) == -1
+    assert L.wmb_val_bytes(mb.VAL["bias"], 100, 0) == -1                       # n % 64
+    assert L.wmb_val_bytes(mb.VAL["bias"], 128, 0) == 128 * 4
+    assert L.wmb_val_bytes(mb.VAL["bias"], 128, 2) == 128 * 128 * 4
+    assert L.wmb_val_bytes(mb.VAL["gemm_mfma_bias"], 128, 1) == 128 * 128 * 2 + 128 * 4
     assert L.wmb_val_bytes(99, 1024, 0) == -1
     assert L.wmb_val_bytes(mb.VAL["copy"], 1023, 0) == -1
     assert L.wmb_val_bytes(mb.VAL["gemm_mfma"], 100, 0) == -1
@@ -199,7 +209,8 @@ def test_wmbench_exports_every_declared_symbol():
                        "wm_microbench.h")
     src = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
     declared = set(re.findall(r"\b(wmb_[a-z_]+)\s*\(", src))
-    assert {"wmb_read_bw", "wmb_chase", "wmb_peak", "wmb_empty", "wmb_val_run", "wmb_clock"} <= declared
+    assert {"wmb_read_bw", "wmb_chase", "wmb_peak", "wmb_empty", "wmb_val_run", "wmb_clock",
+            "wmb_sync"} <= declared
     out = subprocess.run(["nm", "-D", "--defined-only", mb.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     assert declared <= set(re.findall(r"\s[TW]\s+(wmb_\w+)", out))
