@@ -353,13 +353,20 @@ def hardware_model_leg(wm, log):
     mb.run_cases(cases, launches=5, log=lambda *a: None)
     meas = np.array([c.seconds for c in cases])
     out = {"cases": len(cases), "params": "paper_2605_04178_amd/params/mi355x.json"}
+    preds = {}
     for which in ("microbench", "calibrated"):
         T, _ = rc.predict(wm, rc.load_params(path, which), cases)
         out[f"mae_{which}"] = mb.mae(T, meas)
+        preds[which] = T
     fm = rec.get("family_multipliers", {})
     if fm:
         out["mae_calibrated_multiplied"] = mb.mae(np.array([fm[c.kind] for c in cases]) * T, meas)
     out["mae_roofline"] = mb.mae(mb.roofline_naive(cases), meas)
+    # adaptive tile selection against the measured best tile, live
+    out["tile_choice"] = rc.tile_choice([dict(name=c.name, kind=c.kind, n=c.n, seconds=c.seconds,
+                                              pred_microbench=float(preds["microbench"][i]),
+                                              pred_calibrated=float(preds["calibrated"][i]))
+                                         for i, c in enumerate(cases)])
     out["mae_recorded"] = {k: rec["mae"][k] for k in ("calibrated_holdout", "multipliers_holdout",
                                                        "roofline_holdout") if k in rec["mae"]}
     log(f"hardware model on held-out kernels: MAE calibrated {out['mae_calibrated']:.3f}, "

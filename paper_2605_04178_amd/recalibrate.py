@@ -73,6 +73,37 @@ def family_multipliers(wm, cases, T_pred, train_idx):
     return dict(zip(fams, mult.cpu().numpy().tolist())), scaled
 
 
+TILE_FAMILIES = ("gemm8", "gemm16", "gemm32")
+TILE_PREDS = ("pred_microbench", "pred_calibrated", "pred_multiplied", "pred_roofline")
+
+
+def tile_choice(cases: list) -> list:
+    """Adaptive tile selection scored on measured kernels (Section IV-B; the
+    paper's parameter table lists it as predicted against measured best
+    tile): per matrix order, the fastest of the 8/16/32 LDS-tiled FP32 GEMMs
+    as measured and as each prediction ranks them, with the measured
+    slowdown of each prediction's pick.  `cases`: dicts with name, kind, n,
+    seconds and the pred_* fields of the recalibration record."""
+    by: dict = {}
+    for c in cases:
+        if c["kind"] in TILE_FAMILIES:
+            by.setdefault(c["n"], {})[c["kind"]] = c
+    out = []
+    for n in sorted(by):
+        fam = by[n]
+        if len(fam) < 2:
+            continue
+        best = min(fam, key=lambda k: fam[k]["seconds"])
+        row = {"n": n, "measured_us": {k: fam[k]["seconds"] * 1e6 for k in sorted(fam)}, "measured_best": best}
+        for pk in TILE_PREDS:
+            if all(pk in fam[k] for k in fam):
+                pick = min(fam, key=lambda k: fam[k][pk])
+                row[pk.replace("pred_", "") + "_pick"] = pick
+                row[pk.replace("pred_", "") + "_slowdown"] = fam[pick]["seconds"] / fam[best]["seconds"] - 1.0
+        out.append(row)
+    return out
+
+
 def params_record(res: dict) -> dict:
     """The shipped parameter file: structure, both theta vectors, the
     transfer model, the scores and the per-kernel table of a run."""
@@ -89,6 +120,7 @@ def params_record(res: dict) -> dict:
         "copy_model": {k: {"bw": v[0], "tau": v[1]} for k, v in res["copy_model"].items()},
         "peaks_measured": res["microbench"]["peak"],
         "mae": res["mae"],
+        "tile_choice": tile_choice(res["cases"]),
         "cases": [{k: c[k] for k in keep} for c in res["cases"]],
         "command": "python -m paper_2605_04178_amd.recalibrate --out <raw.json> --params-out <this file>",
     }
@@ -164,6 +196,9 @@ def main(argv=None):
         with open(args.params_out, "w") as f:
             json.dump(params_record(json.loads(json.dumps(res, default=float))), f, indent=1)
     log("MAE:", json.dumps(res["mae"]))
+    for r in tile_choice(res["cases"]):
+        log(f"tile choice n={r['n']}: measured best {r['measured_best']}, calibrated model picks "
+            f"{r.get('calibrated_pick')} (+{r.get('calibrated_slowdown', 0.0) * 100:.1f} %)")
     for i, c in enumerate(cases):
         log(f"{c.name:24s} meas {c.seconds * 1e6:10.1f} us  model {T_mb[i] * 1e6:10.1f}  "
             f"cal {T_cal[i] * 1e6:10.1f}  mult {T_mult[i] * 1e6:10.1f}  roof {T_roof[i] * 1e6:10.1f}  "

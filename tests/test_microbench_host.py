@@ -214,3 +214,17 @@ def test_wmbench_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", mb.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     assert declared <= set(re.findall(r"\s[TW]\s+(wmb_\w+)", out))
+
+
+def test_tile_choice_scores_predicted_against_measured_best():
+    from paper_2605_04178_amd import recalibrate as rc
+    mk = lambda kind, n, s, pc, pm: dict(name=f"{kind}_{n}", kind=kind, n=n, seconds=s, pred_calibrated=pc,
+                                         pred_microbench=pm, pred_multiplied=pc, pred_roofline=pm)
+    cases = [mk("gemm8", 512, 3.0, 3.0, 1.0), mk("gemm16", 512, 2.0, 2.5, 2.0), mk("gemm32", 512, 2.2, 1.0, 3.0),
+             mk("gemm8", 1024, 9.0, 9.0, 9.0), mk("copy", 1024, 1.0, 1.0, 1.0)]
+    rows = rc.tile_choice(cases)
+    assert len(rows) == 1 and rows[0]["n"] == 512          # one tile at 1024: nothing to choose
+    r = rows[0]
+    assert r["measured_best"] == "gemm16"
+    assert r["calibrated_pick"] == "gemm32" and abs(r["calibrated_slowdown"] - 0.1) < 1e-12
+    assert r["microbench_pick"] == "gemm8" and abs(r["microbench_slowdown"] - 0.5) < 1e-12
