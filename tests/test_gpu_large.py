@@ -1,0 +1,73 @@
+"""Arrays past 4 GiB: 257 copies of a 2^22-descriptor set (1.08e9
+descriptors; every float array holds 4.3 GB, so element byte offsets pass
+2^31 and 2^32) through the forward sweep and the loss gradient.  Each output
+depends on its own descriptor only, so sampled outputs must equal the oracle
+on the base set, and the loss and gradient (means over descriptors) must
+equal the base set's."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_04178_amd import synth
+from gpu_common import grad_err, need_gpu, rel_err, say
+
+pytestmark = pytest.mark.gpu
+N0 = 1 << 22
+REPS = 257
+TOL = 1e-5
+GTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def wmb():
+    need_gpu()
+    from paper_2605_04178_amd import wavemodel
+    wavemodel.lib()
+    return wavemodel
+
+
+def test_forward_and_loss_grad_past_4_gib(wmb, orc):
+    n = REPS * N0
+    free, _ = torch.cuda.mem_get_info()
+    need = n * (48 + 4 + 4 + 4) + (4 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of device memory, {free / 2 ** 30:.0f} free")
+    p_true = synth.param_set(1)
+    p0 = synth.perturb_theta(p_true, 3)
+    d = synth.descriptors(N0, 104)
+    m0 = (orc.predict(p_true, d)[0] * synth.lognormal_noise(N0, 5, 0.02)).astype(np.float32)
+    say("large: base set and measurements ready; replicating to", n)
+    base = wmb.DeviceDescriptors.from_host(d)
+    fields = wmb.DeviceDescriptors.FLOATS + wmb.DeviceDescriptors.INTS
+    big = wmb.DeviceDescriptors({f: getattr(base, f).repeat(REPS) for f in fields})
+    assert big.n == n and big.F.numel() * 4 > (1 << 32)
+
+    # forward: sampled outputs, including the elements at byte offsets 2^31 and 2^32
+    T, occ = wmb.predict(big, p0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    edges = np.array([(1 << 29) - 1, 1 << 29, (1 << 30) - 1, 1 << 30, (1 << 30) + 1, n - 2, n - 1])
+    idx = np.unique(np.concatenate([rng.choice(n, 1 << 14, replace=False), edges]))
+    it = torch.from_numpy(idx).cuda()
+    Ts = T[it].cpu().numpy()
+    occs = occ[it].cpu().numpy()
+    del T, occ
+    To, occo = orc.predict(p0, d.take(idx % N0))
+    assert np.array_equal(occs, occo)
+    assert rel_err(Ts, To).max() <= TOL
+    say("large: forward sampled outputs match")
+
+    # loss and gradient: the same mean as the base set
+    mt = torch.from_numpy(m0).cuda()
+    out_big = wmb.loss_grad(big, mt.repeat(REPS), p0).cpu().numpy()
+    out_base = wmb.loss_grad(base, mt, p0).cpu().numpy()
+    del big
+    torch.cuda.empty_cache()
+    assert int(out_big[1]) == REPS * int(out_base[1])
+    assert abs(out_big[0] - out_base[0]) <= 1e-9 * out_base[0]
+    assert grad_err(out_big[2:], out_base[2:]) <= 1e-9
+    loss, cnt, g = orc.loss_grad(p0, d, m0)
+    assert int(out_base[1]) == cnt
+    assert abs(out_big[0] - loss) <= 1e-5 * loss
+    assert grad_err(out_big[2:], g) <= GTOL
+    say("large: loss gradient over", n, "descriptors matches the base set and the oracle")
