@@ -1,9 +1,10 @@
-"""Arrays past 4 GiB: 257 copies of a 2^22-descriptor set (1.08e9
-descriptors; every float array holds 4.3 GB, so element byte offsets pass
-2^31 and 2^32) through the forward sweep and the loss gradient.  Each output
-depends on its own descriptor only, so sampled outputs must equal the oracle
-on the base set, and the loss and gradient (means over descriptors) must
-equal the base set's."""
+"""Maximum sizes.  (1) Arrays past 4 GiB: 257 copies of a 2^22-descriptor set
+(1.08e9 descriptors; every float array holds 4.3 GB, so element byte offsets
+pass 2^31 and 2^32) through the forward sweep and the loss gradient.  Each
+output depends on its own descriptor only, so sampled outputs must equal the
+oracle on the base set, and the loss and gradient (means over descriptors)
+must equal the base set's.  (2) Tile selection with 2.11e9 candidates, just
+under the int32 offset limit."""
 import numpy as np
 import pytest
 import torch
@@ -71,3 +72,42 @@ def test_forward_and_loss_grad_past_4_gib(wmb, orc):
     assert abs(out_big[0] - loss) <= 1e-5 * loss
     assert grad_err(out_big[2:], g) <= GTOL
     say("large: loss gradient over", n, "descriptors matches the base set and the oracle")
+
+
+def test_select_tile_near_the_int32_candidate_limit(wmb, orc):
+    """2^25 shapes of 63 candidates each: 2.11e9 candidates, just under the
+    int32 offset limit (8.5 GB of codes), as 512 copies of a 2^16-shape set;
+    sampled shapes against the oracle on the base set, the tail included."""
+    n0, per, reps = 1 << 16, 63, 512
+    n = n0 * reps
+    free, _ = torch.cuda.mem_get_info()
+    need = n * per * 4 + n * 40 + (4 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of device memory, {free / 2 ** 30:.0f} free")
+    sh = synth.shapes(n0, 105, cmin=per, cmax=per)
+    assert np.all(np.diff(sh.cand_off) == per)
+    p = synth.param_set(0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+    big = wmb.DeviceShapes(t(sh.M).repeat(reps), t(sh.N).repeat(reps), t(sh.K).repeat(reps),
+                           t(sh.dtype).repeat(reps),
+                           torch.arange(n + 1, dtype=torch.int64, device="cuda").mul_(per).to(torch.int32),
+                           t(sh.cand_code.view(np.int32)).repeat(reps))
+    assert int(big.cand_off[-1].item()) == n * per < 2 ** 31
+    say("large: select_tile over", n, "shapes,", n * per, "candidates")
+    best, cost, tie = wmb.select_tile(big, p)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+    idx = np.unique(np.concatenate([rng.choice(n, 1 << 13, replace=False), [n // 2, n - 2, n - 1]]))
+    it = torch.from_numpy(idx).cuda()
+    b, c, tt = (x[it].cpu().numpy() for x in (best, cost, tie))
+    del big, best, cost, tie
+    torch.cuda.empty_cache()
+    bo, co, to = orc.select_tile(p, sh)
+    j = idx % n0
+    assert np.array_equal(tt, to[j])
+    clean = to[j] == 0
+    assert np.array_equal(b[clean], bo[j][clean])
+    fin = np.isfinite(co[j])
+    assert np.array_equal(np.isfinite(c), fin)
+    assert np.all(np.abs(c[fin] - co[j][fin]) <= 1e-12 * co[j][fin])
+    say("large: sampled tile choices match")
