@@ -4,7 +4,8 @@ pass 2^31 and 2^32) through the forward sweep and the loss gradient.  Each
 output depends on its own descriptor only, so sampled outputs must equal the
 oracle on the base set, and the loss and gradient (means over descriptors)
 must equal the base set's.  (2) Tile selection with 2.11e9 candidates, just
-under the int32 offset limit."""
+under the int32 offset limit.  (3) Application totals over 1.09e9 segment
+rows."""
 import numpy as np
 import pytest
 import torch
@@ -111,3 +112,40 @@ def test_select_tile_near_the_int32_candidate_limit(wmb, orc):
     assert np.array_equal(np.isfinite(c), fin)
     assert np.all(np.abs(c[fin] - co[j][fin]) <= 1e-12 * co[j][fin])
     say("large: sampled tile choices match")
+
+
+def test_application_totals_past_2p30_rows(wmb, orc):
+    """640 copies of 2^18 applications: 1.09e9 segment rows (74 GB of rows
+    and descriptors, row indices past 2^30); sampled application totals
+    against the oracle on the base set."""
+    na0, reps = 1 << 18, 640
+    sg, d = synth.segments(na0, 150)
+    rows0 = int(sg.app_off[-1])
+    n_rows, n_apps = rows0 * reps, na0 * reps
+    free, _ = torch.cuda.mem_get_info()
+    need = n_rows * (48 + 20) + n_apps * 8 + (4 << 30)
+    if free < need or n_rows >= 2 ** 31:
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of device memory, {free / 2 ** 30:.0f} free")
+    p, q = synth.param_set(0), synth.seg_params(7)
+    base = wmb.DeviceDescriptors.from_host(d)
+    fields = wmb.DeviceDescriptors.FLOATS + wmb.DeviceDescriptors.INTS
+    big = wmb.DeviceDescriptors({f: getattr(base, f).repeat(reps) for f in fields})
+    del base
+    s0 = wmb.DeviceSegments.from_host(sg)
+    off0 = s0.app_off[:-1].to(torch.int64)
+    shift = (torch.arange(reps, dtype=torch.int64, device="cuda") * rows0).repeat_interleave(na0)
+    off = torch.cat([off0.repeat(reps) + shift, torch.tensor([n_rows], dtype=torch.int64, device="cuda")])
+    segs = wmb.DeviceSegments({"app_off": off.to(torch.int32), **{f: getattr(s0, f).repeat(reps)
+                                                                  for f, _ in wmb.DeviceSegments.FIELDS[1:]}})
+    assert segs.n == n_rows > 2 ** 30 and segs.n_apps == n_apps
+    say("large: application totals over", n_apps, "applications,", n_rows, "rows")
+    Ta, _ = wmb.predict_apps(big, segs, p, q)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    idx = np.unique(np.concatenate([rng.choice(n_apps, 1 << 14, replace=False), [n_apps - 1]]))
+    Ts = Ta[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del big, segs, Ta, off, shift
+    torch.cuda.empty_cache()
+    Ra, _ = orc.predict_apps(p, q, d, sg)
+    assert rel_err(Ts, Ra[idx % na0]).max() <= TOL
+    say("large: sampled application totals match")
