@@ -5,7 +5,7 @@ output depends on its own descriptor only, so sampled outputs must equal the
 oracle on the base set, and the loss and gradient (means over descriptors)
 must equal the base set's.  (2) Tile selection with 2.11e9 candidates, just
 under the int32 offset limit.  (3) Application totals over 1.09e9 segment
-rows."""
+rows.  (4) The Blackwell forward over 1.08e9 descriptors."""
 import numpy as np
 import pytest
 import torch
@@ -149,3 +149,35 @@ def test_application_totals_past_2p30_rows(wmb, orc):
     Ra, _ = orc.predict_apps(p, q, d, sg)
     assert rel_err(Ts, Ra[idx % na0]).max() <= TOL
     say("large: sampled application totals match")
+
+
+def test_blackwell_forward_past_4_gib(wmb, orc):
+    """The Blackwell forward over 1.08e9 descriptors (257 copies of 2^22;
+    4.3 GB per array); sampled times and CTA residencies against the oracle
+    on the base set."""
+    n0, reps = 1 << 22, 257
+    n = n0 * reps
+    free, _ = torch.cuda.mem_get_info()
+    need = n * (32 + 8) + (4 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 2 ** 30:.0f} GiB of device memory, {free / 2 ** 30:.0f} free")
+    p = synth.bw_param_set(1)
+    d = synth.bw_descriptors(n0, 230)
+    base = wmb.DeviceBwDescriptors.from_host(d)
+    big = wmb.DeviceBwDescriptors({f: getattr(base, f).repeat(reps)
+                                   for f in wmb.DeviceBwDescriptors.INTS + wmb.DeviceBwDescriptors.FLOATS})
+    del base
+    say("large: Blackwell forward over", n, "descriptors")
+    T, cta = wmb.bw_predict(big, p)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(19)
+    idx = np.unique(np.concatenate([rng.choice(n, 1 << 14, replace=False), [(1 << 30) - 1, 1 << 30, n - 1]]))
+    it = torch.from_numpy(idx).cuda()
+    Ts, cs = T[it].cpu().numpy(), cta[it].cpu().numpy()
+    del big, T, cta
+    torch.cuda.empty_cache()
+    To, co = orc.bw_predict(p, d)
+    j = idx % n0
+    assert np.array_equal(cs, co[j])
+    assert rel_err(Ts, To[j]).max() <= TOL
+    say("large: sampled Blackwell outputs match")
