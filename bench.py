@@ -350,7 +350,7 @@ def hardware_model_leg(wm, log):
     rec = json.load(open(path))
     names = {c["name"] for c in rec["cases"] if c["split"] == "hold"}
     cases = [c for c in mb.case_list() if c.name in names]
-    mb.run_cases(cases, launches=5, log=lambda *a: None)
+    mb.run_cases(cases, log=lambda *a: None)
     meas = np.array([c.seconds for c in cases])
     out = {"cases": len(cases), "params": "paper_2605_04178_amd/params/mi355x.json"}
     preds = {}

@@ -17,7 +17,8 @@ Both keep the footprint W, through which h_LLC(W) splits the traffic below L2
 between the Infinity Cache and HBM.  Flops stay the algorithmic ones (the GPU
 tests check every kernel's output, so they are the work done).  Each case's
 counter value is the mean over its timed launches (the warm-up launch that
-precedes them in `wmb_val_run` is skipped).  The commands are in the summary
+precedes them in `wmb_val_run`, and the warm-up launches before that, are
+skipped).  The commands are in the summary
 that `score --md` writes.
 """
 from __future__ import annotations
@@ -66,12 +67,14 @@ def read_dispatches(path: str, counter: str) -> List[Tuple[int, str, float]]:
     return [(d, name[d], val[d]) for d in sorted(val)]
 
 
-def per_case(dispatches: Sequence[Tuple[int, str, float]], kinds: Sequence[str], launches: int) -> np.ndarray:
-    """Mean counter value per case.  Every case ran 1 + `launches`
-    dispatches of its validation kernel, cases in order; other kernels (the
-    allocators' fills, the reference copy) are skipped."""
+def per_case(dispatches: Sequence[Tuple[int, str, float]], kinds: Sequence[str], launches: int,
+             warmup: int = 0) -> np.ndarray:
+    """Mean counter value per case over its `launches` timed dispatches.
+    Every case ran `warmup` + 1 + `launches` dispatches of its validation
+    kernel (the warm-ups and one untimed launch first), cases in order; other
+    kernels (the allocators' fills, the reference copy) are skipped."""
     val = [(n, v) for _, n, v in dispatches if VAL_KERNEL in n]
-    per = 1 + launches
+    per = warmup + 1 + launches
     if len(val) != per * len(kinds):
         raise ValueError(f"{len(val)} validation dispatches for {len(kinds)} cases x {per}")
     out = np.empty(len(kinds))
@@ -79,7 +82,7 @@ def per_case(dispatches: Sequence[Tuple[int, str, float]], kinds: Sequence[str],
         chunk = val[i * per:(i + 1) * per]
         if not all(STEM[k] in n for n, _ in chunk):
             raise ValueError(f"case {i} ({k}): kernels {sorted({n for n, _ in chunk})}")
-        out[i] = float(np.mean([v for _, v in chunk[1:]]))
+        out[i] = float(np.mean([v for _, v in chunk[per - launches:]]))
     return out
 
 
@@ -95,29 +98,31 @@ def copy_scale(dispatches: Sequence[Tuple[int, str, float]], bytes_per_copy: flo
     return bytes_per_copy / (float(np.mean(cp)) * unit)
 
 
-def profiler_bytes(fetch_csv: str, write_csv: str, kinds: Sequence[str], launches: int) -> Tuple[np.ndarray, dict]:
+def profiler_bytes(fetch_csv: str, write_csv: str, kinds: Sequence[str], launches: int,
+                   warmup: int = 0) -> Tuple[np.ndarray, dict]:
     """Scaled (FETCH_SIZE + WRITE_SIZE) bytes per launch of every case: the
     traffic between the L2 and the memory fabric."""
     fd = read_dispatches(fetch_csv, "FETCH_SIZE")
     wd = read_dispatches(write_csv, "WRITE_SIZE")
     fs, ws = copy_scale(fd), copy_scale(wd)
-    rb = per_case(fd, kinds, launches) * 1024.0 * fs
-    wb = per_case(wd, kinds, launches) * 1024.0 * ws
+    rb = per_case(fd, kinds, launches, warmup) * 1024.0 * fs
+    wb = per_case(wd, kinds, launches, warmup) * 1024.0 * ws
     return rb + wb, {"fetch_scale": fs, "write_scale": ws, "read_bytes": rb.tolist(), "write_bytes": wb.tolist()}
 
 
 L2_COUNTERS = ("TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum", "TCC_HIT_sum", "TCC_MISS_sum")
 
 
-def l2_traffic(l2_csv: str, kinds: Sequence[str], launches: int) -> Tuple[np.ndarray, np.ndarray, dict]:
+def l2_traffic(l2_csv: str, kinds: Sequence[str], launches: int,
+               warmup: int = 0) -> Tuple[np.ndarray, np.ndarray, dict]:
     """Bytes requested from the L2 per launch (read and write requests from
     the L1s, each scaled by what the reference copy's requests carry) and
     the fraction of L2 requests that hit."""
     rd, wr, hit, miss = (read_dispatches(l2_csv, c) for c in L2_COUNTERS)
     rs = copy_scale(rd, unit=1.0)
     ws = copy_scale(wr, unit=1.0)
-    B = per_case(rd, kinds, launches) * rs + per_case(wr, kinds, launches) * ws
-    h, m = per_case(hit, kinds, launches), per_case(miss, kinds, launches)
+    B = per_case(rd, kinds, launches, warmup) * rs + per_case(wr, kinds, launches, warmup) * ws
+    h, m = per_case(hit, kinds, launches, warmup), per_case(miss, kinds, launches, warmup)
     r2 = np.where(h + m > 0, h / np.maximum(h + m, 1.0), 0.0)
     return B, r2, {"read_req_bytes": rs, "write_req_bytes": ws}
 
@@ -125,17 +130,19 @@ def l2_traffic(l2_csv: str, kinds: Sequence[str], launches: int) -> Tuple[np.nda
 # ---------------------------------------------------------------------------
 # GPU steps
 # ---------------------------------------------------------------------------
-def run(out: str, quick: bool = False, launches: int = 5) -> None:
+def run(out: str, quick: bool = False, launches: int = 100, warmup: int = 10) -> None:
     """Time every validation case, then make the reference copies."""
     import torch
-    cases = mb.run_cases(mb.case_list(quick), launches=launches, log=lambda *a: print(*a, flush=True))
+    cases = mb.run_cases(mb.case_list(quick), launches=launches, warmup=warmup,
+                         log=lambda *a: print(*a, flush=True))
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(COPY_REPS):
         b.copy_(a)
     torch.cuda.synchronize()
     with open(out, "w") as f:
-        json.dump({"launches": launches, "quick": quick, "cases": [dataclasses.asdict(c) for c in cases]}, f)
+        json.dump({"launches": launches, "warmup": warmup, "quick": quick,
+                   "cases": [dataclasses.asdict(c) for c in cases]}, f)
     print(f"{len(cases)} cases timed, {COPY_REPS} reference copies of {COPY_BYTES} bytes", flush=True)
 
 
@@ -182,12 +189,13 @@ def score(times: str, fetch_csv: str, write_csv: str, params: str, out: str, ste
     cases = [mb.Case(**c) for c in rec["cases"]]
     kinds = [c.kind for c in cases]
     meas = np.array([c.seconds for c in cases])
-    B_fab, scales = profiler_bytes(fetch_csv, write_csv, kinds, rec["launches"])
+    warm = rec.get("warmup", 0)
+    B_fab, scales = profiler_bytes(fetch_csv, write_csv, kinds, rec["launches"], warm)
     B = {"first_principles": np.array([c.B for c in cases]), "profiler_fabric": B_fab}
     descs = {"first_principles": mb.descriptors_of(cases), "profiler_fabric": _desc_with(cases, B_fab)}
     r2_l2 = None
     if l2_csv:
-        B_l2, r2_l2, sc2 = l2_traffic(l2_csv, kinds, rec["launches"])
+        B_l2, r2_l2, sc2 = l2_traffic(l2_csv, kinds, rec["launches"], warm)
         scales.update(sc2)
         B["profiler_l2"] = B_l2
         descs["profiler_l2"] = _desc_with(cases, B_l2, r2_l2)
@@ -284,7 +292,8 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--out", required=True)
     r.add_argument("--quick", action="store_true")
-    r.add_argument("--launches", type=int, default=5)
+    r.add_argument("--launches", type=int, default=100)
+    r.add_argument("--warmup", type=int, default=10)
     s = sub.add_parser("score")
     for k in ("times", "fetch", "write", "params", "out"):
         s.add_argument("--" + k, required=True)
@@ -293,7 +302,7 @@ def main(argv=None):
     s.add_argument("--l2", default=None, help="counter file of the L1-to-L2 requests and L2 hits")
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run(a.out, a.quick, a.launches)
+        run(a.out, a.quick, a.launches, a.warmup)
     else:
         score(a.times, a.fetch, a.write, a.params, a.out, a.steps, a.md, a.l2)
     return 0

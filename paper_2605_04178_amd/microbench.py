@@ -525,7 +525,12 @@ def case_list(quick: bool = False) -> List[Case]:
     return cs
 
 
-def run_cases(cases: List[Case], launches: int = 10, log=print) -> List[Case]:
+def run_cases(cases: List[Case], launches: int = 100, log=print, warmup: int = 10) -> List[Case]:
+    """Time every case: `warmup` untimed launches, then the median of
+    `launches` event-timed ones (the paper's protocol, Section V: 10 warm-ups,
+    100 timed runs, median).  Each case issues warmup + 1 + launches
+    dispatches of its kernel (wmb_val_run itself runs one untimed launch
+    before its timed ones)."""
     import torch
     L = lib()
     dev = torch.device("cuda:0")
@@ -556,10 +561,12 @@ def run_cases(cases: List[Case], launches: int = 10, log=print) -> List[Case]:
         a = buf("a", nbytes[0], dt)
         b = buf("b", nbytes[1], dt) if nbytes[1] > 0 else None
         cc = buf("c", nbytes[2])
-        _check(L.wmb_val_run(kind, C.c_void_p(a.data_ptr()), nbytes[0],
-                             C.c_void_p(b.data_ptr()) if b is not None else None, nbytes[1],
-                             C.c_void_p(cc.data_ptr()), nbytes[2], c.n, c.iters, launches, st,
-                             C.byref(sec), C.byref(grid)), "wmb_val_run " + c.name)
+        args = (kind, C.c_void_p(a.data_ptr()), nbytes[0],
+                C.c_void_p(b.data_ptr()) if b is not None else None, nbytes[1],
+                C.c_void_p(cc.data_ptr()), nbytes[2], c.n, c.iters)
+        if warmup > 1:
+            _check(L.wmb_val_run(*args, warmup - 1, st, C.byref(sec), C.byref(grid)), "wmb_val_run " + c.name)
+        _check(L.wmb_val_run(*args, launches, st, C.byref(sec), C.byref(grid)), "wmb_val_run " + c.name)
         c.seconds, c.grid = sec.value, grid.value
         if c.kind == "reduce":     # grid-stride loop: iterations per workgroup
             c.K = float(math.ceil(c.n / 4 / (c.grid * 256)))

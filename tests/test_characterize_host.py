@@ -19,7 +19,7 @@ def _write(path, rows):
             w.writerow(r)
 
 
-def _rows(counter, kinds, launches, per_case_kib, copy_kib, extra_rows=2):
+def _rows(counter, kinds, launches, per_case_kib, copy_kib, extra_rows=2, warmup=0):
     """Dispatches as the run step makes them: fills interleaved, each case's
     warm-up + timed launches, then the reference copies; one dispatch split
     over two rows (instances) to exercise the per-dispatch sum."""
@@ -29,9 +29,9 @@ def _rows(counter, kinds, launches, per_case_kib, copy_kib, extra_rows=2):
             d += 1
             rows.append(dict(Correlation_Id=d, Dispatch_Id=d, Kernel_Name="void at::native::fill_kernel(...)",
                              Counter_Name=counter, Counter_Value=123.0))
-        for j in range(1 + launches):
+        for j in range(warmup + 1 + launches):
             d += 1
-            v = 1e9 if j == 0 else per_case_kib[i]          # the warm-up is skipped
+            v = 1e9 if j <= warmup else per_case_kib[i]     # the warm-ups are skipped
             name = f"(anonymous namespace)::{ch.STEM[k]}(float const*)"
             rows.append(dict(Correlation_Id=d, Dispatch_Id=d, Kernel_Name=name, Counter_Name=counter,
                              Counter_Value=v / 2))
@@ -94,3 +94,12 @@ def test_l2_requests_and_hit_fraction(tmp_path):
     assert sc["read_req_bytes"] == pytest.approx(64.0) and sc["write_req_bytes"] == pytest.approx(64.0)
     assert np.allclose(B, [(1000 + 500) * 64.0, (4000 + 100) * 64.0])
     assert np.allclose(r2, [300 / 1500, 3000 / 4100])
+
+
+def test_warmup_dispatches_are_skipped(tmp_path):
+    kinds = ["triad", "bias", "gemm_mfma_bias"]
+    _write(tmp_path / "f.csv", _rows("FETCH_SIZE", kinds, 4, [3.0, 5.0, 7.0], 1000.0, warmup=10))
+    d = ch.read_dispatches(str(tmp_path / "f.csv"), "FETCH_SIZE")
+    assert np.allclose(ch.per_case(d, kinds, 4, warmup=10), [3.0, 5.0, 7.0])
+    with pytest.raises(ValueError):
+        ch.per_case(d, kinds, 4)                    # the warm-ups must be declared
