@@ -199,20 +199,23 @@ struct Eval {
     bool near_kink;    // within 1e-5 relative of a max/min switch
 };
 
-template <typename R, bool FULL>
+// TILE: the descriptor comes from derive_tile, so it is valid by
+// construction and has r1 = r3 = 0, W = 0, u = 1 and no concurrency, device,
+// fusion or sync counts; the terms those zeros and ones cancel are skipped.
+template <typename R, bool FULL, bool TILE = false>
 __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<R>& d, Eval<R>& E)
 {
     typedef Ar<R> A;
     E.T = (R)__builtin_nan("");
     E.occ = -1;
-    if (!desc_valid(d)) return;
+    if (!TILE && !desc_valid(d)) return;
     const int32_t g = d.gp & 2047;
     const int32_t dt = (d.gp >> 11) & 7;
     E.dt = dt;
-    E.cnt[0] = (d.gp >> 14) & 7;
-    E.cnt[1] = (d.gp >> 17) & 7;
-    E.cnt[2] = (d.gp >> 20) & 1;
-    E.cnt[3] = (d.gp >> 21) & 15;
+    E.cnt[0] = TILE ? 0 : (d.gp >> 14) & 7;
+    E.cnt[1] = TILE ? 0 : (d.gp >> 17) & 7;
+    E.cnt[2] = TILE ? 0 : (d.gp >> 20) & 1;
+    E.cnt[3] = TILE ? 0 : (d.gp >> 21) & 15;
     E.G = d.G;
 
     Occ oc = occupancy(st, d.v, d.s, g);
@@ -233,7 +236,7 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     R h3 = d.r3;
     E.llc_regime = 0;
     E.base_log = (R)0;
-    if (st.n_levels == 4 && d.W > (R)0) {
+    if (!TILE && st.n_levels == 4 && d.W > (R)0) {
         const R Wm = d.W * (R)(1.0 / 1048576.0);
         const int reg = Wm < c.w_lo ? 0 : (Wm <= c.c_llc ? 1 : 2);
         // (1 - (W - W_lo)/(C - W_lo)) written as (C - W)/(C - W_lo): same
@@ -246,23 +249,24 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         E.llc_regime = reg;
         if (FULL) E.base_log = x > (R)0 ? l2 * (R)0.69314718055994531 : (R)0;
     }
-    const R m1 = (R)1 - d.r1;
-    const R s1 = d.r1;
-    const R s2 = m1 * d.r2;
-    const R a12 = m1 * ((R)1 - d.r2);
+    const R m1 = TILE ? (R)1 : (R)1 - d.r1;
+    const R s1 = TILE ? (R)0 : d.r1;
+    const R s2 = TILE ? d.r2 : m1 * d.r2;
+    const R a12 = TILE ? (R)1 - d.r2 : m1 * ((R)1 - d.r2);
     R s3 = (R)0, sh = a12;
-    if (st.n_levels == 4) {
+    if (!TILE && st.n_levels == 4) {
         s3 = a12 * h3;
         sh = a12 * ((R)1 - h3);
     }
     // Eq. (16) blend of the HBM bandwidth
     R e = (R)0, bwh = c.bw[3];
-    if (c.blend_on && d.W > (R)0) {
+    if (!TILE && c.blend_on && d.W > (R)0) {
         e = A::ex2(d.W * c.blend_k);
         bwh = c.bw[3] + c.bp_minus_bw * e;
     }
-    const R S = s1 * c.bw[0] + s2 * c.bw[1] + s3 * c.bw[2] + sh * bwh;
-    const R Lf = s1 * c.latf[0] + s2 * c.latf[1] + s3 * c.latf[2] + sh * c.latf[3];
+    const R S = TILE ? s2 * c.bw[1] + sh * bwh : s1 * c.bw[0] + s2 * c.bw[1] + s3 * c.bw[2] + sh * bwh;
+    const R Lf = TILE ? s2 * c.latf[1] + sh * c.latf[3]
+                      : s1 * c.latf[0] + s2 * c.latf[1] + s3 * c.latf[2] + sh * c.latf[3];
 
     // stage times
     R ip = c.inv_peak[0];
@@ -270,14 +274,15 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     ip = dt == 2 ? c.inv_peak[2] : ip;
     ip = dt == 3 ? c.inv_peak[3] : ip;
     ip = dt == 4 ? c.inv_peak[4] : ip;
-    const R Tc = d.F * ip * A::rcp(d.u);
+    const R Tc = TILE ? d.F * ip : d.F * ip * A::rcp(d.u);
     const R Tb = d.B * A::rcp(S);
     const R q = (R)nr * d.B * A::rcp((R)d.G * (R)oc.k) * c.inv_lw;
     const R Tlat = q * Lf;
 
     const R nrK = (R)nr * d.K;
-    const R Tov = c.ov[0] + c.ov[1] * (R)d.G + c.ov[2] * nrK + (R)E.cnt[0] * c.ov[3] +
-                  (R)E.cnt[1] * c.ov[4] + (R)E.cnt[2] * c.ov[5] + (R)E.cnt[3] * c.ov[6];
+    const R Tov = TILE ? c.ov[0] + c.ov[1] * (R)d.G + c.ov[2] * nrK
+                       : c.ov[0] + c.ov[1] * (R)d.G + c.ov[2] * nrK + (R)E.cnt[0] * c.ov[3] +
+                             (R)E.cnt[1] * c.ov[4] + (R)E.cnt[2] * c.ov[5] + (R)E.cnt[3] * c.ov[6];
 
     R wc = (R)0, wb = (R)0, wl = (R)0, step;
     const bool mem_b = Tb >= Tlat;

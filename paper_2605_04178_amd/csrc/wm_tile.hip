@@ -70,7 +70,7 @@ __device__ inline R tile_cost(const Set& S, int32_t M, int32_t N, int32_t K, int
     Desc<R> x;
     if (!derive_tile<R>(M, N, K, t, code, S.st.wave_shift, x)) return inf;
     Eval<R> E;
-    evaluate<R, false>(S.st, cst<R>(S), x, E);
+    evaluate<R, false, true>(S.st, cst<R>(S), x, E);
     return E.T == E.T ? E.T : inf;
 }
 
