@@ -129,7 +129,6 @@ constexpr int kTileSpan = 768;    // candidates a batch may hold (12 rounds of 6
 struct TileQueue {
     float cost32[kTileSpan];
     uint8_t slot32[kTileSpan];       // batch shape of each candidate
-    int32_t M[kTileSlots], N[kTileSlots], K[kTileSlots], t[kTileSlots];
     int64_t shape[kTileSlots];
     uint32_t key[kTileQueue];        // slot << 24 | local candidate index
     uint32_t code[kTileQueue];
@@ -157,13 +156,16 @@ __device__ inline int first_entry(const TileQueue& q, int qn, uint32_t sl)
 // Evaluates every queued candidate in float64 with all lanes, then one lane
 // per shape scans that shape's entries (ascending candidate index) and
 // writes its result.  Wave-uniform ns, qn.
-__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, int lane,
+__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, const ShapePtrs& sh, int lane,
                                    int32_t* best, double* best_cost, uint8_t* near_tie)
 {
     wave_lds_sync();
     for (int e = lane; e < qn; e += 64) {
         const int sl = (int)(q.key[e] >> 24);
-        q.cost[e] = tile_cost<double>(S, q.M[sl], q.N[sl], q.K[sl], q.t[sl], q.code[e]);
+        // the shape's fields come back from global memory (cached): keeping
+        // them in LDS would cost a wave's sixth slot per SIMD
+        const int64_t i = q.shape[sl];
+        q.cost[e] = tile_cost<double>(S, sh.M[i], sh.N[i], sh.K[i], sh.dtype[i], q.code[e]);
     }
     wave_lds_sync();
     if (lane < ns) {
@@ -249,11 +251,10 @@ __device__ inline void direct_shape(const TileCtx& C, const Set& S, int64_t i, i
 // lowest index winning exact ties) and the second-smallest, for the
 // near-tie flag.  A batch of more than kTileSpan candidates, or whose window
 // would not fit an empty queue, goes shape by shape without the queue.
-// The LDS of a wave (7.5 KB) leaves room for 20 waves per CU, so the kernel
-// asks for 5 waves per SIMD (at most 96 VGPRs); 512-thread blocks (60 KB)
-// fit only two per CU and keep 4.
+// The LDS of a wave (6.3 KB) leaves room for 24 waves per CU, so the kernel
+// asks for 6 waves per SIMD (at most 80 VGPRs).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK >= 512 ? 4 : 5))) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
                                                       const uint32_t* __restrict__ code, int64_t n,
                                                       int64_t n_cand,
                                                       Set S, int32_t* __restrict__ best,
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK >= 
         // the one flush site: at the end, or when this batch does not fit
         const bool flush = done ? ns > 0 : (queued && (qn + cnt > kTileQueue || ns + nf > kTileSlots));
         if (flush) {
-            flush_tiles(q, ns, qn, S, lane, best, best_cost, near_tie);
+            flush_tiles(q, ns, qn, S, sh, lane, best, best_cost, near_tie);
             ns = 0;
             qn = 0;
         }
@@ -363,10 +364,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK >= 
         // queue slots for the shapes with a finite minimum, in batch order
         const int32_t qs = ns + (int32_t)lanes_below(__ballot(fin));
         if (fin) {
-            q.M[qs] = M;
-            q.N[qs] = N;
-            q.K[qs] = K;
-            q.t[qs] = t;
             q.shape[qs] = si;
         }
         for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
