@@ -89,6 +89,12 @@ def test_select_tile_edge_cases(wmb, orc):
     assert best[3] == 1 and best[4] == 1
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 9, 13, 1001])
+def test_select_tile_ragged_shape_counts(wmb, orc, n):
+    """Shape counts that leave the last batch of eight partly empty."""
+    _check(wmb, orc, synth.param_set(0), synth.shapes(n, 40 + n), f"n={n}")
+
+
 def test_select_tile_int32_limit_shapes(wmb, orc):
     """Sides up to 2^31 - 1 with the full 384-tile sweep: flops and bytes past
     2^63, tiles whose grid exceeds 2^31 - 1 workgroups (infeasible)."""
