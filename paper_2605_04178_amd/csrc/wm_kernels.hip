@@ -503,9 +503,10 @@ __global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict
         partials[(int64_t)b * n_sets * kAcc + j] = per_set[j];
 }
 
-// Phase 2 for every set in turn (set loop uniform; fixed order): fold the
-// phase-1 rows b, b + nb2, ... of the set, then re-evaluate its flagged
-// descriptors in float64.
+// Phase 2, block (b, s) for set s = blockIdx.y, so the sets' float64
+// re-evaluations run side by side: fold the phase-1 rows b, b + nb2, ... of
+// the set (fixed order), then re-evaluate its flagged descriptors in the
+// block's share of the flag words.
 __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __restrict__ sets,
                                                             const float* const* __restrict__ meas,
                                                             const Set* __restrict__ S_all,
@@ -520,34 +521,33 @@ __global__ __launch_bounds__(256) void k_grad_redo_batched(const DescPtrs* __res
     __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int s = 0; s < n_sets; ++s) {
-        double acc[kAcc];
+    const int s = blockIdx.y;
+    if (s >= n_sets) return;
+    double acc[kAcc];
 #pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-        for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
-            const double* row = rows1 + ((int64_t)r * n_sets + s) * kAcc;
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
+        const double* row = rows1 + ((int64_t)r * n_sets + s) * kAcc;
 #pragma unroll
-            for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
-        }
-        const DescPtrs d = sets[s];
-        const float* m = meas[s];
-        const Set& S = S_all[s];
-        const uint64_t* fl = flags + flag_off[s];
-        const int64_t nwords = (set_n[s] + 63) >> 6;
-        for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
-            uint64_t mk = fl[wi];
-            while (mk) {
-                const int bit = __builtin_ctzll(mk);
-                mk &= mk - 1;
-                const int64_t i = (wi << 6) + bit;
-                grad_exact<1>(S, load_desc(d, i), m[i], acc);
-            }
-        }
-        block_reduce_acc(acc, red, tot);
-        if (threadIdx.x < kAcc)
-            partials[((int64_t)blockIdx.x * n_sets + s) * kAcc + threadIdx.x] = tot[threadIdx.x];
-        __syncthreads();
+        for (int j = 0; j < kAcc; ++j) acc[j] += row[j];
     }
+    const DescPtrs d = sets[s];
+    const float* m = meas[s];
+    const Set& S = S_all[s];
+    const uint64_t* fl = flags + flag_off[s];
+    const int64_t nwords = (set_n[s] + 63) >> 6;
+    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
+        uint64_t mk = fl[wi];
+        while (mk) {
+            const int bit = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int64_t i = (wi << 6) + bit;
+            grad_exact<1>(S, load_desc(d, i), m[i], acc);
+        }
+    }
+    block_reduce_acc(acc, red, tot);
+    if (threadIdx.x < kAcc)
+        partials[((int64_t)blockIdx.x * n_sets + s) * kAcc + threadIdx.x] = tot[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_adam_batched(const double* __restrict__ partials, int rows,
@@ -580,7 +580,7 @@ hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, c
     k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, items, n_items, n_sets, flag_off,
                                            flags, partials);
     (void)total_words;
-    k_grad_redo_batched<<<nb2, 256, 0, stream>>>(sets, meas, S_all, set_n, flag_off, flags, n_sets,
+    k_grad_redo_batched<<<dim3(nb2, n_sets), 256, 0, stream>>>(sets, meas, S_all, set_n, flag_off, flags, n_sets,
                                                  partials, nb,
                                                  partials + (int64_t)nb * n_sets * kAcc);
     return hipGetLastError();
