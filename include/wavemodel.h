@@ -456,7 +456,7 @@ int32_t wm_bw_calibrate(const wm_bw_desc_t *desc, const float *measured, const w
  * 512); per_thread = descriptors per thread of the forward sweep (1, 2, 4,
  * 8; other ops ignore it); grid_mult = persistent grid as a multiple of the
  * blocks resident at once (1..8; gradient, tile and batched sweeps); chunk =
- * descriptors per work item of the batched sweep (power of two, 4096..65536;
+ * descriptors per work item of the batched sweep (power of two, 256..65536;
  * that op requires block 256).  Results do not depend on the configuration
  * except through the order of FP64 additions in gradient sums (differences
  * of order 1e-15 relative).  Entries live in process memory; if the

@@ -560,7 +560,10 @@ int32_t batch_prepare(int32_t n_sets, const wm_desc_t* sets, const float* const*
     run->steps = opts[0].steps;
     run->n_items = (int)items.size();
     run->nb = batched_grid(run->n_items, cfg.grid_mult);
-    run->nb2 = L.nb2;
+    int64_t max_words = 0;
+    for (int k = 0; k < n_sets; ++k)
+        max_words = std::max<int64_t>(max_words, (sets[k].n + 63) / 64);
+    run->nb2 = batched_redo_grid(n_sets, max_words, L.nb2);
     run->words = words;
     run->S_dev = (Set*)(base + L.sets);
     run->st_dev = (CalibState*)(base + L.states);

@@ -571,6 +571,19 @@ int batched_grid(int n_items, int grid_mult)
     return m < 1 ? 1 : (r < m ? r : m);
 }
 
+int batched_redo_grid(int n_sets, int64_t max_set_words, int cap)
+{
+    // the pass is latency-bound (one float64 evaluation chain per flagged
+    // descriptor, a few per thousand words), so a second residency round
+    // would double its time
+    int per = resident_blocks(reinterpret_cast<const void*>(&k_grad_redo_batched), 256) /
+              (n_sets < 1 ? 1 : n_sets);
+    const int64_t need = (max_set_words + 255) / 256;
+    if (need < per) per = (int)need;
+    if (cap < per) per = cap;
+    return per < 1 ? 1 : per;
+}
+
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
                                const WorkItem* items, int n_items, int n_sets,
                                const int64_t* set_n, const int64_t* flag_off, uint64_t* flags,

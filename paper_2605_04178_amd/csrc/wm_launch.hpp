@@ -25,7 +25,7 @@ struct LaunchCfg {
 // op codes as in the public header
 constexpr int kOpPredict = 0, kOpVjp = 2, kOpLossGrad = 3, kOpSelectTile = 4,
               kOpCalibrate = 5, kOpCalibrateBatched = 6, kOpPredictApps = 7, kOpAppsLossGrad = 8;
-constexpr int64_t kMinChunk = 4096;
+constexpr int64_t kMinChunk = 256;
 
 LaunchCfg default_cfg(int op);
 bool cfg_valid(int op, const LaunchCfg& c);
@@ -108,6 +108,9 @@ int grad_grid(int mode, bool from_device_set, int64_t n, const LaunchCfg& cfg);
 int resident_blocks(const void* kernel, int block);
 // blocks for the multi-set sweep over n_items work items
 int batched_grid(int n_items, int grid_mult);
+// blocks per set of the multi-set float64 pass (at most cap): all sets'
+// blocks resident at once, no more than the largest set's flag words need
+int batched_redo_grid(int n_sets, int64_t max_set_words, int cap);
 
 hipError_t launch_predict(const DescPtrs& d, int64_t n, const Set& S, float* T, int32_t* occ,
                           bool vec_ok, const LaunchCfg& cfg, hipStream_t stream);

@@ -121,7 +121,7 @@ LaunchCfg default_cfg(int op)
     c.chunk = 0;
     switch (canonical_op(op)) {
     case kOpPredict: c.vec = 4; break;
-    case kOpCalibrateBatched: c.chunk = 16384; break;
+    case kOpCalibrateBatched: c.chunk = 2048; break;
     default: break;
     }
     return c;

@@ -322,7 +322,7 @@ def test_set_launch_rejects_invalid_configs_without_a_gpu(wmb):
     bad = [(wmb.OP_PREDICT, (96, 4, 1, 0)), (wmb.OP_PREDICT, (256, 3, 1, 0)),
            (wmb.OP_LOSS_GRAD, (256, 1, 0, 0)), (wmb.OP_LOSS_GRAD, (256, 1, 9, 0)),
            (wmb.OP_SELECT_TILE, (1024, 1, 1, 0)), (wmb.OP_CALIBRATE_BATCHED, (128, 1, 1, 16384)),
-           (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 3000)), (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 1 << 17)),
+           (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 3000)), (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 128)), (wmb.OP_CALIBRATE_BATCHED, (256, 1, 1, 1 << 17)),
            (wmb.OP_ROOFLINE, (256, 1, 1, 0)), (99, (256, 1, 1, 0))]
     for op, cfg in bad:
         c = wmb.WmLaunch(*cfg)

@@ -27,7 +27,7 @@ def wmb():
 
 
 def _restore(wmb, op, n):
-    d = {wmb.OP_PREDICT: (256, 4, 1, 0), wmb.OP_CALIBRATE_BATCHED: (256, 1, 1, 16384)}.get(op, (256, 1, 1, 0))
+    d = {wmb.OP_PREDICT: (256, 4, 1, 0), wmb.OP_CALIBRATE_BATCHED: (256, 1, 1, 2048)}.get(op, (256, 1, 1, 0))
     wmb.set_launch(op, n, *d)
 
 
@@ -102,7 +102,7 @@ def test_batched_chunks_match(wmb, orc):
         opts.append(wmb.calib_opts(steps=25, free_mask=mask))
     ntot = sum(sizes)
     _, th_ref, h_ref = wmb.calibrate_batched(descs, meas, p0s, opts)
-    for chunk in (4096, 32768, 65536):
+    for chunk in (256, 4096, 65536):
         for gm in (1, 2):
             wmb.set_launch(wmb.OP_CALIBRATE_BATCHED, ntot, 256, 1, gm, chunk)
             _, th, h = wmb.calibrate_batched(descs, meas, p0s, opts)
@@ -111,7 +111,7 @@ def test_batched_chunks_match(wmb, orc):
     _restore(wmb, wmb.OP_CALIBRATE_BATCHED, ntot)
     best = wmb.autotune_batched(descs, meas, p0s, opts)
     say("batched tuned", best)
-    assert best["block"] == 256 and best["chunk"] in (4096, 8192, 16384, 32768, 65536)
+    assert best["block"] == 256 and best["chunk"] in [1 << k for k in range(8, 17)]
     _restore(wmb, wmb.OP_CALIBRATE_BATCHED, ntot)
 
 
