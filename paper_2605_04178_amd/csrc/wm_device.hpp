@@ -39,21 +39,42 @@ __device__ inline Desc<double> widen(const Desc<float>& x)
 // ---------------------------------------------------------------------------
 // block reduction of the 26 FP64 accumulators (fixed order)
 // ---------------------------------------------------------------------------
+// One step of the wave's recursive halving over lane bit m: a lane keeps the
+// upper half of its H x 2 remaining columns if its bit m is set, else the
+// lower half, and adds the partner lane's copy of the half it keeps.
+template <int H>
+__device__ inline void halve_columns(double* v, int lane, int m)
+{
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const double send = hi ? v[j] : v[j + H];
+        const double keep = hi ? v[j + H] : v[j];
+        v[j] = keep + __shfl_xor(send, m, 64);
+    }
+}
+
+// Block sum of the 26 per-thread accumulators (fixed order).  Within a wave
+// the columns are halved over lane bits 5..1 (32 doubles cross lanes, not
+// 26 x 6 for one butterfly per column), after which lanes 2c and 2c + 1
+// hold column c over 32 lanes each; then the waves' rows are added in LDS.
+// Must be called by every thread of the block.  acc is clobbered.
 __device__ inline void block_reduce_acc(double* acc, double* lds /* [waves][26] */, double* out)
 {
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
+    static_assert(kAcc <= 32, "the halving covers 32 columns");
+    double v[32];
 #pragma unroll
-    for (int j = 0; j < kAcc; ++j) {
-        double v = acc[j];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-        acc[j] = v;
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < kAcc; ++j) lds[wid * kAcc + j] = acc[j];
-    }
+    for (int j = 0; j < 32; ++j) v[j] = j < kAcc ? acc[j] : 0.0;
+    halve_columns<16>(v, lane, 32);
+    halve_columns<8>(v, lane, 16);
+    halve_columns<4>(v, lane, 8);
+    halve_columns<2>(v, lane, 4);
+    halve_columns<1>(v, lane, 2);
+    const double s = v[0] + __shfl_xor(v[0], 1, 64);
+    const int col = lane >> 1;
+    if ((lane & 1) == 0 && col < kAcc) lds[wid * kAcc + col] = s;
     __syncthreads();
     if (threadIdx.x < kAcc) {
         const int nw = blockDim.x >> 6;
