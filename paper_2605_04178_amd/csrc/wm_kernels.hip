@@ -447,7 +447,7 @@ hipError_t launch_adam(const double* partials, int rows, CalibState* st, const A
 // multi-set calibration sweep: one persistent launch over a (set, chunk)
 // work list; per-block, per-set sums staged in LDS
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_grad_batched(const DescPtrs* __restrict__ sets,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_grad_batched(const DescPtrs* __restrict__ sets,
                                                        const float* const* __restrict__ meas,
                                                        const Set* __restrict__ S_all,
                                                        const WorkItem* __restrict__ items,
