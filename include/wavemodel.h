@@ -174,7 +174,7 @@ int32_t wm_validate_params(const wm_params_t *params);
  *  WM_OP_CALIBRATE: device parameter set, Adam state, a `steps`-entry loss
  *      history and the partial sums for n descriptors.
  *  WM_OP_CALIBRATE_BATCHED: the same for n_sets sets holding n descriptors
- *      in total, plus the work list.
+ *      in total, plus the per-set pointer tables and item offsets.
  *  WM_OP_PREDICT_APPS: 0.
  *  WM_OP_APPS_LOSS_GRAD: 0 here; its size depends on the application count
  *      too: use wm_apps_workspace_bytes().
@@ -281,8 +281,9 @@ int32_t wm_calibrate(const wm_desc_t *desc, const float *measured, const wm_para
  * Several calibration problems (one parameter set and one descriptor set
  * each; different sizes and hierarchies, as in porting the model to several
  * architectures by parameters alone, Section IV-B) advanced together: each
- * step is one persistent launch over a (set, chunk) work list plus one
- * per-set reduce-and-Adam launch.  sets, measured, p0, opts, p_out: host
+ * step is one persistent sweep over all sets' descriptors in items of
+ * `chunk` (each block takes a contiguous range of items), one float64 pass
+ * with a block row per set, and one per-set reduce-and-Adam launch.  sets, measured, p0, opts, p_out: host
  * arrays of n_sets entries (measured[s] device pointers); every set uses
  * opts[s] but all must have the same step count; loss_hist host
  * [n_sets][steps] or NULL.  Workspace: wm_workspace_bytes(

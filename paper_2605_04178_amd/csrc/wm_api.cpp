@@ -401,7 +401,7 @@ BatchLayout batch_layout(int64_t n_total, int32_t n_sets, int32_t steps)
     L.meas = off;
     off += up256(sizeof(float*) * n_sets);
     L.items = off;
-    off += up256(sizeof(WorkItem) * (size_t)L.max_items);
+    off += up256(sizeof(int32_t) * (size_t)(n_sets + 1));
     L.setn = off;
     off += up256(sizeof(int64_t) * n_sets);
     L.flagoff = off;
@@ -495,17 +495,18 @@ int32_t capture_stream(void* user, hipStream_t* out)
 
 // Device images of a multi-set calibration in a workspace: the per-set
 // parameter images, Adam states, options, descriptor and measurement pointer
-// tables, and the (set, begin, end) work list in items of `chunk`
-// descriptors.  step() enqueues one sweep plus one reduce-and-Adam launch.
+// tables, and each set's first item (items of `chunk` descriptors, set by
+// set).  step() enqueues the sweep, the float64 pass and one
+// reduce-and-Adam launch.
 struct BatchRun {
     int n_sets = 0, steps = 0, n_items = 0, nb = 0, nb2 = 0;
-    int64_t words = 0;
+    int64_t chunk = 0;
     Set* S_dev = nullptr;
     CalibState* st_dev = nullptr;
     AdamOpts* o_dev = nullptr;
     DescPtrs* d_dev = nullptr;
     const float** m_dev = nullptr;
-    WorkItem* it_dev = nullptr;
+    int32_t* io_dev = nullptr;
     int64_t* n_dev = nullptr;
     int64_t* fo_dev = nullptr;
     double* hist_dev = nullptr;
@@ -515,8 +516,8 @@ struct BatchRun {
 
     hipError_t step() const
     {
-        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, it_dev, n_items, n_sets, n_dev,
-                                           fo_dev, flags_dev, words, part_dev, nb, nb2, s);
+        hipError_t e = launch_grad_batched(d_dev, m_dev, S_dev, io_dev, n_items, chunk, n_sets,
+                                           n_dev, fo_dev, flags_dev, part_dev, nb, nb2, s);
         if (e != hipSuccess) return e;
         return launch_adam_batched(part_dev + (int64_t)nb * n_sets * kAcc, nb2, n_sets, st_dev,
                                    o_dev, S_dev, steps, hist_dev, s);
@@ -533,9 +534,10 @@ int32_t batch_prepare(int32_t n_sets, const wm_desc_t* sets, const float* const*
     std::vector<DescPtrs> dh((size_t)n_sets);
     std::vector<const float*> mh((size_t)n_sets);
     std::vector<int64_t> nh((size_t)n_sets), foh((size_t)n_sets);
-    std::vector<WorkItem> items;
-    int64_t words = 0;
+    std::vector<int32_t> ioh((size_t)n_sets + 1);
+    int64_t words = 0, n_items = 0;
     const int64_t chunk = cfg.chunk;
+    if (chunk < 64 || chunk % 64 != 0) return WM_EINVAL;
     for (int k = 0; k < n_sets; ++k) {
         nh[k] = sets[k].n;
         foh[k] = words;
@@ -545,32 +547,27 @@ int32_t batch_prepare(int32_t n_sets, const wm_desc_t* sets, const float* const*
         oh[k] = adam_of(&opts[k]);
         dh[k] = ptrs_of(&sets[k]);
         mh[k] = measured[k];
-        for (int64_t b = 0; b < sets[k].n; b += chunk) {
-            WorkItem w;
-            w.set = k;
-            w.pad_ = 0;
-            w.begin = b;
-            w.end = b + chunk < sets[k].n ? b + chunk : sets[k].n;
-            items.push_back(w);
-        }
+        ioh[k] = (int32_t)n_items;
+        n_items += (sets[k].n + chunk - 1) / chunk;
+        if (n_items > L.max_items) return WM_EINVAL;
     }
-    if ((int)items.size() > L.max_items) return WM_EINVAL;
+    ioh[n_sets] = (int32_t)n_items;
     char* base = (char*)ws;
     run->n_sets = n_sets;
     run->steps = opts[0].steps;
-    run->n_items = (int)items.size();
+    run->n_items = (int)n_items;
+    run->chunk = chunk;
     run->nb = batched_grid(run->n_items, cfg.grid_mult);
     int64_t max_words = 0;
     for (int k = 0; k < n_sets; ++k)
         max_words = std::max<int64_t>(max_words, (sets[k].n + 63) / 64);
     run->nb2 = batched_redo_grid(n_sets, max_words, L.nb2);
-    run->words = words;
     run->S_dev = (Set*)(base + L.sets);
     run->st_dev = (CalibState*)(base + L.states);
     run->o_dev = (AdamOpts*)(base + L.opts);
     run->d_dev = (DescPtrs*)(base + L.descs);
     run->m_dev = (const float**)(base + L.meas);
-    run->it_dev = (WorkItem*)(base + L.items);
+    run->io_dev = (int32_t*)(base + L.items);
     run->n_dev = (int64_t*)(base + L.setn);
     run->fo_dev = (int64_t*)(base + L.flagoff);
     run->hist_dev = (double*)(base + L.hist);
@@ -584,9 +581,8 @@ int32_t batch_prepare(int32_t n_sets, const wm_desc_t* sets, const float* const*
     WM_HIP(hipMemcpyAsync(run->m_dev, mh.data(), sizeof(float*) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(run->n_dev, nh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(run->fo_dev, foh.data(), sizeof(int64_t) * n_sets, hipMemcpyHostToDevice, s));
-    if (!items.empty())
-        WM_HIP(hipMemcpyAsync(run->it_dev, items.data(), sizeof(WorkItem) * items.size(),
-                              hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(run->io_dev, ioh.data(), sizeof(int32_t) * (n_sets + 1),
+                          hipMemcpyHostToDevice, s));
     WM_HIP(hipStreamSynchronize(s));  // the host images above go out of scope
     return WM_OK;
 }

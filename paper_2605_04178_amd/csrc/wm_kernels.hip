@@ -444,17 +444,17 @@ hipError_t launch_adam(const double* partials, int rows, CalibState* st, const A
 }
 
 // ---------------------------------------------------------------------------
-// multi-set calibration sweep: one persistent launch over a (set, chunk)
-// work list; per-block, per-set sums staged in LDS
+// multi-set calibration sweep: one persistent launch over the sets' items of
+// `chunk` descriptors; block b takes the contiguous item range
+// [n_items b / nb, n_items (b + 1) / nb), which covers a run of consecutive
+// descriptors in each set it touches; per-block, per-set sums staged in LDS
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_grad_batched(const DescPtrs* __restrict__ sets,
-                                                       const float* const* __restrict__ meas,
-                                                       const Set* __restrict__ S_all,
-                                                       const WorkItem* __restrict__ items,
-                                                       int n_items, int n_sets,
-                                                       const int64_t* __restrict__ flag_off,
-                                                       uint64_t* __restrict__ flags,
-                                                       double* __restrict__ partials)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_grad_batched(
+    const DescPtrs* __restrict__ sets, const float* const* __restrict__ meas,
+    const Set* __restrict__ S_all, const int32_t* __restrict__ item_off, int n_items,
+    int64_t chunk, int n_sets, const int64_t* __restrict__ set_n,
+    const int64_t* __restrict__ flag_off, uint64_t* __restrict__ flags,
+    double* __restrict__ partials)
 {
     __shared__ double red[16 * kAcc];
     __shared__ double tot[kAcc];
@@ -465,40 +465,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int it0 = (int)((int64_t)n_items * b / nb);
     const int it1 = (int)((int64_t)n_items * (b + 1) / nb);
     const int lane = threadIdx.x & 63;
-    int cur = -1;
-    double acc[kAcc];
+    for (int k = 0; k < n_sets; ++k) {  // uniform over the block
+        const int o0 = item_off[k], o1 = item_off[k + 1];
+        const int lo = it0 > o0 ? it0 : o0, hi = it1 < o1 ? it1 : o1;
+        if (lo >= hi) continue;
+        // items start at multiples of chunk (a multiple of 64), so each wave
+        // covers whole flag words
+        const int64_t nk = set_n[k];
+        const int64_t begin = (int64_t)(lo - o0) * chunk;
+        const int64_t end_items = (int64_t)(hi - o0) * chunk;
+        const int64_t end = end_items < nk ? end_items : nk;
+        const DescPtrs d = sets[k];
+        const float* m = meas[k];
+        const Set& S = S_all[k];
+        uint64_t* fl = flags + flag_off[k];
+        double acc[kAcc];
 #pragma unroll
-    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-    for (int it = it0; it < it1; ++it) {
-        const WorkItem w = items[it];
-        if (w.set != cur) {
-            if (cur >= 0) {
-                block_reduce_acc(acc, red, tot);
-                if (threadIdx.x < kAcc) per_set[cur * kAcc + threadIdx.x] += tot[threadIdx.x];
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-            }
-            cur = w.set;
-        }
-        const DescPtrs d = sets[w.set];
-        const float* m = meas[w.set];
-        const Set& S = S_all[w.set];
-        uint64_t* fl = flags + flag_off[w.set];
-        // items start at multiples of 64, so each wave covers whole flag words
-        for (int64_t base = w.begin + (threadIdx.x & ~63); base < w.end; base += blockDim.x) {
+        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        for (int64_t base = begin + (threadIdx.x & ~63); base < end; base += blockDim.x) {
             const int64_t i = base + lane;
             bool redo = false;
-            if (i < w.end) redo = grad_fast<1>(S, load_desc(d, i), ntload(m + i), acc);
+            if (i < end) redo = grad_fast<1>(S, load_desc(d, i), ntload(m + i), acc);
             const uint64_t msk = __ballot(redo);
             if (lane == 0) fl[base >> 6] = msk;
         }
-    }
-    if (cur >= 0) {
         block_reduce_acc(acc, red, tot);
-        if (threadIdx.x < kAcc) per_set[cur * kAcc + threadIdx.x] += tot[threadIdx.x];
-        __syncthreads();
+        if (threadIdx.x < kAcc) per_set[k * kAcc + threadIdx.x] = tot[threadIdx.x];
     }
+    __syncthreads();
     for (int j = threadIdx.x; j < n_sets * kAcc; j += blockDim.x)
         partials[(int64_t)b * n_sets * kAcc + j] = per_set[j];
 }
@@ -585,14 +579,12 @@ int batched_redo_grid(int n_sets, int64_t max_set_words, int cap)
 }
 
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
-                               const WorkItem* items, int n_items, int n_sets,
+                               const int32_t* item_off, int n_items, int64_t chunk, int n_sets,
                                const int64_t* set_n, const int64_t* flag_off, uint64_t* flags,
-                               int64_t total_words, double* partials, int nb, int nb2,
-                               hipStream_t stream)
+                               double* partials, int nb, int nb2, hipStream_t stream)
 {
-    k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, items, n_items, n_sets, flag_off,
-                                           flags, partials);
-    (void)total_words;
+    k_grad_batched<<<nb, 256, 0, stream>>>(sets, meas, S_all, item_off, n_items, chunk, n_sets,
+                                           set_n, flag_off, flags, partials);
     k_grad_redo_batched<<<dim3(nb2, n_sets), 256, 0, stream>>>(sets, meas, S_all, set_n, flag_off, flags, n_sets,
                                                  partials, nb,
                                                  partials + (int64_t)nb * n_sets * kAcc);

@@ -88,11 +88,6 @@ struct CalibState {
     int32_t t;         // index of the next step
 };
 
-struct WorkItem {
-    int32_t set, pad_;
-    int64_t begin, end;
-};
-
 // Gradient sweep geometry for n descriptors: nb phase-1 blocks, nb2 phase-2
 // blocks (partial rows nb + nb2), nwords 64-bit redo-flag words.
 struct GradLayout {
@@ -128,11 +123,13 @@ hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, c
 hipError_t launch_reduce(int mode, const double* partials, int rows, double* out, hipStream_t stream);
 hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream);
+// Multi-set step: the work is n_items items of `chunk` descriptors (the
+// last item of a set may be short); set k owns items item_off[k] ..
+// item_off[k + 1] - 1 (device int32 [n_sets + 1]).
 hipError_t launch_grad_batched(const DescPtrs* sets, const float* const* meas, const Set* S_all,
-                               const WorkItem* items, int n_items, int n_sets,
+                               const int32_t* item_off, int n_items, int64_t chunk, int n_sets,
                                const int64_t* set_n, const int64_t* flag_off, uint64_t* flags,
-                               int64_t total_words, double* partials, int nb, int nb2,
-                               hipStream_t stream);
+                               double* partials, int nb, int nb2, hipStream_t stream);
 hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, CalibState* st,
                                const AdamOpts* opts, Set* S_all, int steps, double* loss_hist,
                                hipStream_t stream);
