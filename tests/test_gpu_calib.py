@@ -171,3 +171,48 @@ def test_batched_recovery_within_3pct(wmb, orc):
         e = _rec_err(thb[k], pk, masks[k])
         say("set", k, "recovery error", e)
         assert e <= 0.03
+
+
+def test_batched_sixteen_ragged_sets_match_per_set(wmb, orc):
+    """The 16-set maximum with ragged sizes: an empty set, sets shorter than
+    one wave, sizes on both sides of 64, 256 and the 2048-descriptor default
+    item; work items of 256 and of 2048 descriptors.  Every set's loss
+    history and theta equal its own plain calibration (FP64 sums in another
+    order only)."""
+    sizes = [0, 1, 63, 64, 65, 255, 256, 257, 1000, 2047, 2048, 2049, 4097, 700, 3, 9000]
+    base = synth.multi_arch_sets()
+    descs, meas, p0s, opts, masks = [], [], [], [], []
+    for k, nk in enumerate(sizes):
+        pk = base[k % len(base)]
+        mask = MASK_L4 if pk.n_levels == 4 else MASK_L3
+        if nk == 0:
+            dd = wmb.DeviceDescriptors.from_host(synth.descriptors(64, 300)).slice(0, 0)
+            mt = torch.ones(1, dtype=torch.float32, device="cuda")
+        else:
+            dk = synth.descriptors(nk, 300 + k)
+            Tk, _ = orc.predict(pk, dk)
+            dd = wmb.DeviceDescriptors.from_host(dk)
+            mt = torch.from_numpy((Tk * synth.lognormal_noise(nk, 330 + k, 0.02)).astype(np.float32)).cuda()
+        descs.append(dd)
+        meas.append(mt)
+        p0s.append(synth.perturb_theta(pk, 360 + k, mask=mask))
+        opts.append(wmb.calib_opts(steps=20, free_mask=mask))
+        masks.append(mask)
+    ntot = sum(sizes)
+    default = wmb.get_launch(wmb.OP_CALIBRATE_BATCHED, ntot)
+    ref = [wmb.calibrate(descs[k], meas[k], p0s[k], steps=20, free_mask=masks[k]) for k in range(len(sizes))]
+    try:
+        for chunk in (256, 2048):
+            wmb.set_launch(wmb.OP_CALIBRATE_BATCHED, ntot, 256, 1, 1, chunk)
+            say("16 ragged sets, chunk", chunk)
+            rc, thb, histb = wmb.calibrate_batched(descs, meas, p0s, opts)
+            assert rc == wmb.WM_OK
+            for k, (rck, thk, histk) in enumerate(ref):
+                assert np.allclose(histb[k], histk, rtol=1e-9, atol=0), (chunk, k, sizes[k])
+                assert np.allclose(thb[k], thk, rtol=1e-9, atol=0), (chunk, k, sizes[k])
+        # the empty set: zero loss, theta unchanged (up to exp(log theta))
+        assert np.all(histb[0] == 0.0)
+        assert np.allclose(thb[0], np.asarray(p0s[0].theta), rtol=1e-12, atol=0)
+    finally:
+        wmb.set_launch(wmb.OP_CALIBRATE_BATCHED, ntot, default["block"], default["per_thread"],
+                       default["grid_mult"], default["chunk"])
