@@ -593,7 +593,8 @@ bool batch_args_ok(int32_t n_sets, const wm_desc_t* sets, const float* const* me
     if (n_sets < 1 || n_sets > kMaxSets || !sets || !measured || !p0 || !opts) return false;
     int64_t t = 0;
     for (int k = 0; k < n_sets; ++k) {
-        if (!desc_ok(&sets[k]) || !measured[k] || !params_ok(&p0[k]) || !opts_ok(&opts[k]))
+        if (!desc_ok(&sets[k]) || (sets[k].n > 0 && !measured[k]) || !params_ok(&p0[k]) ||
+            !opts_ok(&opts[k]))
             return false;
         if (!free_slots_ok(&p0[k], opts[k].free_mask)) return false;
         if (opts[k].steps != opts[0].steps) return false;
@@ -810,7 +811,8 @@ int32_t wm_bw_calibrate(const wm_bw_desc_t* desc, const float* measured, const w
                         const wm_calib_opts_t* opts, wm_bw_params_t* p_out, double* loss_hist,
                         void* ws, size_t ws_bytes, void* stream)
 {
-    if (!bw_desc_ok(desc) || !measured || !bw_params_ok(p0) || !opts_ok(opts) || !p_out)
+    if (!bw_desc_ok(desc) || (desc->n > 0 && !measured) || !bw_params_ok(p0) || !opts_ok(opts) ||
+        !p_out)
         return WM_EINVAL;
     for (int j = 0; j < WM_N_THETA; ++j)
         if (((opts->free_mask >> j) & 1u) && !(p0->theta[j] > 0.0)) return WM_EINVAL;
@@ -1040,7 +1042,8 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
                      const wm_calib_opts_t* opts, wm_params_t* p_out, double* loss_hist, void* ws,
                      size_t ws_bytes, void* stream)
 {
-    if (!desc_ok(desc) || !measured || !params_ok(p0) || !opts_ok(opts) || !p_out) return WM_EINVAL;
+    if (!desc_ok(desc) || (desc->n > 0 && !measured) || !params_ok(p0) || !opts_ok(opts) || !p_out)
+        return WM_EINVAL;
     if (!free_slots_ok(p0, opts->free_mask)) return WM_EINVAL;
     const CalibLayout L = calib_layout(desc->n, opts->steps);
     if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
