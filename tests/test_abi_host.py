@@ -185,6 +185,13 @@ def test_argument_errors_before_any_hip_call(wmb):
     assert L.wm_calibrate_batched(2, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_calibrate_batched(0, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_calibrate_batched(17, D, M, P0, O, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    # measurements may be NULL only for an empty set
+    o = wmb.calib_opts(steps=5)
+    assert L.wm_calibrate(C.byref(d), None, C.byref(p), C.byref(o), C.byref(pout), None,
+                          C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    O2 = (wmb.WmCalibOpts * 2)(o, o)
+    M0 = (C.c_void_p * 2)(0x4000, None)
+    assert L.wm_calibrate_batched(2, D, M0, P0, O2, PO, None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_last_hip_error() == 0
 
 
@@ -297,6 +304,10 @@ def test_blackwell_calls_validate_before_any_hip_call(wmb):
     th[17] = 0.0
     assert L.wm_bw_calibrate(C.byref(d), x, C.byref(wmb.bw_params_struct(p.copy(theta=th))), C.byref(o),
                              C.byref(wmb.WmBwParams()), None, C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    # measurements may be NULL only when there are no descriptors
+    o = wmb.calib_opts(steps=5, free_mask=1 << 0)
+    assert L.wm_bw_calibrate(C.byref(d), None, C.byref(ps), C.byref(o), C.byref(wmb.WmBwParams()), None,
+                             C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_last_hip_error() == 0
 
 
