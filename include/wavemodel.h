@@ -20,7 +20,9 @@
  *    validated on the host before any HIP call, so a bad call never launches
  *    a kernel.  n == 0 returns WM_OK without a launch (array pointers may
  *    then be NULL), except that wm_predict_vjp and wm_loss_grad still write
- *    their zero-valued outputs.  Problems of single
+ *    their zero-valued outputs and the calibration calls still take their
+ *    steps over the empty set (loss 0, gradient 0, so theta keeps its value
+ *    up to the rounding of exp(log theta)).  Problems of single
  *    descriptors are not errors: an invalid descriptor yields T = NaN and
  *    occ = -1; a resource-infeasible one (zero resident workgroups) yields
  *    T = +inf and occ = 0.
