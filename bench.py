@@ -529,6 +529,9 @@ def main():
         if not args.no_tune:
             tuned["loss_grad_2^20"] = wm.autotune_grad(wm.OP_LOSS_GRAD, ddc, mc, p0c)
         res["launch"]["calibrate"] = wm.get_launch(wm.OP_CALIBRATE, nc)
+        # one untimed call first (code-object loading, the allocator's first
+        # workspace); the timed call runs every step, graph capture included
+        wm.calibrate(ddc, mc, p0c, steps=args.calib_steps, free_mask=mask)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, th, hist = wm.calibrate(ddc, mc, p0c, steps=args.calib_steps, free_mask=mask)
@@ -536,6 +539,7 @@ def main():
         idx = [j for j in range(24) if mask >> j & 1]
         err = float(np.max(np.abs(th[idx] / np.array(ps.theta)[idx] - 1)))
         res["calibrate"] = {"descriptors": nc, "steps": args.calib_steps, "seconds": el,
+                            "timing": "second call (graph capture and instantiation included)",
                             "fwd_adj_evals_per_s": nc * args.calib_steps / el,
                             "max_recovery_err": err, "status": rc,
                             "loss_first_last": [float(hist[0]), float(hist[-1])]}
