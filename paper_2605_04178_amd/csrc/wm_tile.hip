@@ -131,7 +131,7 @@ struct TileQueue {
     uint8_t slot32[kTileSpan];       // batch shape of each candidate
     int64_t shape[kTileSlots];
     uint32_t key[kTileQueue];        // slot << 24 | local candidate index
-    uint32_t code[kTileQueue];
+    uint32_t cand[kTileQueue];       // index into the candidate-code array
     double cost[kTileQueue];
     unsigned long long bmin[kTileBatch];   // packed float32 minimum per batch shape
 };
@@ -153,11 +153,13 @@ __device__ inline int first_entry(const TileQueue& q, int qn, uint32_t sl)
     return lo;
 }
 
-// Evaluates every queued candidate in float64 with all lanes, then one lane
-// per shape scans that shape's entries (ascending candidate index) and
-// writes its result.  Wave-uniform ns, qn.
-__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, const ShapePtrs& sh, int lane,
-                                   int32_t* best, double* best_cost, uint8_t* near_tie)
+// Evaluates every queued candidate in float64 with all lanes (their codes
+// are read here, one load per lane), then one lane per shape scans that
+// shape's entries (ascending candidate index) and writes its result.
+// Wave-uniform ns, qn.
+__device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, const ShapePtrs& sh,
+                                   const uint32_t* __restrict__ code, int lane, int32_t* best,
+                                   double* best_cost, uint8_t* near_tie)
 {
     wave_lds_sync();
     for (int e = lane; e < qn; e += 64) {
@@ -165,7 +167,7 @@ __device__ inline void flush_tiles(TileQueue& q, int ns, int qn, const Set& S, c
         // the shape's fields come back from global memory (cached): keeping
         // them in LDS would cost a wave's sixth slot per SIMD
         const int64_t i = q.shape[sl];
-        q.cost[e] = tile_cost<double>(S, sh.M[i], sh.N[i], sh.K[i], sh.dtype[i], q.code[e]);
+        q.cost[e] = tile_cost<double>(S, sh.M[i], sh.N[i], sh.K[i], sh.dtype[i], code[q.cand[e]]);
     }
     wave_lds_sync();
     if (lane < ns) {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         // the one flush site: at the end, or when this batch does not fit
         const bool flush = done ? ns > 0 : (queued && (qn + cnt > kTileQueue || ns + nf > kTileSlots));
         if (flush) {
-            flush_tiles(q, ns, qn, S, sh, lane, best, best_cost, near_tie);
+            flush_tiles(q, ns, qn, S, sh, code, lane, best, best_cost, near_tie);
             ns = 0;
             qn = 0;
         }
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 const int e = qn + (int)lanes_below(m);
                 const int32_t jl = v - Ps;
                 q.key[e] = ((uint32_t)qss << 24) | (uint32_t)jl;
-                q.code[e] = code[as + jl];
+                q.cand[e] = (uint32_t)(as + jl);
             }
             qn += __popcll(m);
         }
