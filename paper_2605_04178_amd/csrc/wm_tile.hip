@@ -248,8 +248,9 @@ __device__ inline void direct_shape(const TileCtx& C, const Set& S, int64_t i, i
 // leave no lane idle.  Pass 1 writes each candidate's float32 cost to LDS
 // and takes each shape's minimum with a packed (cost bits, local index) key.
 // Every candidate within kTileWindow of its shape's minimum is queued for a
-// float64 re-evaluation; the queue fills across batches and runs on all
-// lanes at once.  The result per shape is the smallest float64 cost (the
+// float64 re-evaluation by a second pass that counts as it appends (a queue
+// that overflows is evaluated and the window appended again); the queue
+// fills across batches and runs on all lanes at once.  The result per shape is the smallest float64 cost (the
 // lowest index winning exact ties) and the second-smallest, for the
 // near-tie flag.  A batch of more than kTileSpan candidates, or whose window
 // would not fit an empty queue, goes shape by shape without the queue.
@@ -300,10 +301,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         }
         const int32_t T = __builtin_amdgcn_readlane(inc, SB - 1);
         const int32_t P = inc - len;   // first batch position of lane's shape
-        bool queued = !done && T <= kTileSpan;
+        const bool queued = !done && T <= kTileSpan;
         float thr = -finf;
         bool fin = false;
-        int cnt = 0;
         if (queued) {
             int32_t Pk[SB];
 #pragma unroll
@@ -342,47 +342,53 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                     near_tie[si] = 0;
                 }
             }
-            for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
-                // every lane takes part in the shuffle: an inactive source lane reads as garbage
-                const float th = __shfl(thr, v < T ? (int)q.slot32[v] : 0, 64);
-                const bool w = v < T && q.cost32[v] <= th;
-                cnt += __popcll(__ballot(w));
-            }
-            queued = cnt <= kTileQueue;
         }
         const int nf = __popcll(__ballot(fin));
-        // the one flush site: at the end, or when this batch does not fit
-        const bool flush = done ? ns > 0 : (queued && (qn + cnt > kTileQueue || ns + nf > kTileSlots));
-        if (flush) {
-            flush_tiles(q, ns, qn, S, sh, code, lane, best, best_cost, near_tie);
-            ns = 0;
-            qn = 0;
+        // The one flush site.  Attempt 0 flushes at the end, or when the
+        // batch's shapes would not find queue slots; then the batch's window
+        // is appended after entry qn (shapes taking slots from ns in batch
+        // order), entries past the queue's end counted but not written.  If
+        // the queue overflowed, attempt 1 evaluates what it held and appends
+        // the window again to the empty queue.
+        bool flush = done ? ns > 0 : (queued && ns + nf > kTileSlots);
+        int cnt = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (flush) {
+                flush_tiles(q, ns, qn, S, sh, code, lane, best, best_cost, near_tie);
+                ns = 0;
+                qn = 0;
+            }
+            if (done || !queued) break;
+            const int32_t qs = ns + (int32_t)lanes_below(__ballot(fin));
+            if (fin) q.shape[qs] = si;
+            cnt = 0;
+            for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
+                // every lane takes part in the shuffles: an inactive source lane reads as garbage
+                const int sl = v < T ? (int)q.slot32[v] : 0;
+                const int32_t Ps = __shfl(P, sl, 64), qss = __shfl(qs, sl, 64);
+                const int64_t as = __shfl(a, sl, 64);
+                const float th = __shfl(thr, sl, 64);
+                const bool w = v < T && q.cost32[v] <= th;
+                const uint64_t m = __ballot(w);
+                const int e = qn + cnt + (int)lanes_below(m);
+                if (w && e < kTileQueue) {
+                    const int32_t jl = v - Ps;
+                    q.key[e] = ((uint32_t)qss << 24) | (uint32_t)jl;
+                    q.cand[e] = (uint32_t)(as + jl);
+                }
+                cnt += __popcll(m);
+            }
+            flush = qn + cnt > kTileQueue && qn > 0;
+            if (!flush) break;
         }
         if (done) break;
-        if (!queued) {
+        if (!queued || cnt > kTileQueue) {
+            // too many candidates for LDS, or a window longer than the whole
+            // queue: shape by shape
             for (int k = 0; k < SB && s0 + k < n; ++k) direct_shape(C, S, s0 + k, lane);
             continue;
         }
-        // queue slots for the shapes with a finite minimum, in batch order
-        const int32_t qs = ns + (int32_t)lanes_below(__ballot(fin));
-        if (fin) {
-            q.shape[qs] = si;
-        }
-        for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
-            const int sl = v < T ? (int)q.slot32[v] : 0;
-            const int32_t Ps = __shfl(P, sl, 64), qss = __shfl(qs, sl, 64);
-            const int64_t as = __shfl(a, sl, 64);
-            const float th = __shfl(thr, sl, 64);
-            const bool w = v < T && q.cost32[v] <= th;
-            const uint64_t m = __ballot(w);
-            if (w) {
-                const int e = qn + (int)lanes_below(m);
-                const int32_t jl = v - Ps;
-                q.key[e] = ((uint32_t)qss << 24) | (uint32_t)jl;
-                q.cand[e] = (uint32_t)(as + jl);
-            }
-            qn += __popcll(m);
-        }
+        qn += cnt;
         ns += nf;
     }
 }
