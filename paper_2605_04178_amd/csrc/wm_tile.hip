@@ -123,10 +123,21 @@ constexpr int kTileSlots = 64;    // shapes per queue (one lane each at the end)
 constexpr int kTileBatch = 8;     // consecutive shapes whose candidates share wavefronts
 constexpr int kTileSpan = 768;    // candidates a batch may hold (12 rounds of 64)
 
-// Per-wave LDS: the float32 costs of the current batch and the queue of
-// float64 window re-evaluations, shared across batches.  Queue entries are
-// appended in (slot, local index) order.
+// A batch shape as the lanes of its candidates read it: extents, dtype,
+// first batch position P, code index minus batch position D, window
+// threshold and rank among the batch's shapes with a finite minimum.
+struct alignas(16) TileShape {
+    int32_t M, N, K, t;
+    int32_t P, D;
+    float thr;
+    int32_t rank;
+};
+
+// Per-wave LDS: the current batch's shapes and float32 costs, and the queue
+// of float64 window re-evaluations, shared across batches.  Queue entries
+// are appended in (slot, local index) order.
 struct TileQueue {
+    TileShape bs[kTileBatch];
     float cost32[kTileSpan];
     uint8_t slot32[kTileSpan];       // batch shape of each candidate
     int64_t shape[kTileSlots];
@@ -254,8 +265,10 @@ __device__ inline void direct_shape(const TileCtx& C, const Set& S, int64_t i, i
 // lowest index winning exact ties) and the second-smallest, for the
 // near-tie flag.  A batch of more than kTileSpan candidates, or whose window
 // would not fit an empty queue, goes shape by shape without the queue.
-// The LDS of a wave (6.3 KB) leaves room for 24 waves per CU, so the kernel
-// asks for 6 waves per SIMD (at most 80 VGPRs).
+// The batch's shapes sit in LDS as 32-byte records that a candidate's lane
+// reads by its slot (two 16-byte reads where cross-lane shuffles took seven).
+// The LDS of a wave (6720 bytes) leaves room for 24 waves per CU, so the
+// kernel asks for 6 waves per SIMD (at most 80 VGPRs).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_select_tile(ShapePtrs sh, const int32_t* __restrict__ off,
                                                       const uint32_t* __restrict__ code, int64_t n,
@@ -304,29 +317,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
         const bool queued = !done && T <= kTileSpan;
         float thr = -finf;
         bool fin = false;
+        int32_t rank = 0;   // among the batch's shapes with a finite minimum
         if (queued) {
             int32_t Pk[SB];
 #pragma unroll
             for (int k = 0; k < SB; ++k) Pk[k] = __builtin_amdgcn_readlane(P, k);
-            if (lane < SB) q.bmin[lane] = ~0ull;
+            if (lane < SB) {
+                q.bmin[lane] = ~0ull;
+                // a <= n_cand < 2^31 and P < kTileSpan, so D fits 32 bits
+                q.bs[lane] = TileShape{M, N, K, t, P, (int32_t)(a - P), 0.0f, 0};
+            }
             wave_lds_sync();
             // pass 1: float32 costs to LDS and the per-shape minimum
-            for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
+            for (int32_t v = lane; v < T; v += 64) {
                 int32_t sl = 0;
 #pragma unroll
                 for (int k = 1; k < SB; ++k) sl += v >= Pk[k] ? 1 : 0;
-                const int32_t Ms = __shfl(M, sl, 64), Ns = __shfl(N, sl, 64), Ks = __shfl(K, sl, 64);
-                const int32_t ts = __shfl(t, sl, 64), Ps = __shfl(P, sl, 64);
-                const int64_t as = __shfl(a, sl, 64);
-                if (v < T) {
-                    const int32_t jl = v - Ps;
-                    const float c = tile_cost<float>(S, Ms, Ns, Ks, ts, code[as + jl]);
-                    q.cost32[v] = c;
-                    q.slot32[v] = (uint8_t)sl;
-                    __hip_atomic_fetch_min(&q.bmin[sl],
-                                           ((unsigned long long)__float_as_uint(c) << 32) | (uint32_t)jl,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                }
+                const TileShape z = q.bs[sl];
+                const int32_t jl = v - z.P;
+                const float c = tile_cost<float>(S, z.M, z.N, z.K, z.t, code[(int64_t)v + z.D]);
+                q.cost32[v] = c;
+                q.slot32[v] = (uint8_t)sl;
+                __hip_atomic_fetch_min(&q.bmin[sl],
+                                       ((unsigned long long)__float_as_uint(c) << 32) | (uint32_t)jl,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
             wave_lds_sync();
             // per shape: the window threshold, or the empty result
@@ -341,6 +355,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                     best_cost[si] = __builtin_huge_val();
                     near_tie[si] = 0;
                 }
+            }
+            rank = (int32_t)lanes_below(__ballot(fin));
+            if (lane < SB) {
+                q.bs[lane].thr = thr;
+                q.bs[lane].rank = rank;
             }
         }
         const int nf = __popcll(__ballot(fin));
@@ -359,22 +378,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
                 qn = 0;
             }
             if (done || !queued) break;
-            const int32_t qs = ns + (int32_t)lanes_below(__ballot(fin));
-            if (fin) q.shape[qs] = si;
+            if (fin) q.shape[ns + rank] = si;
+            wave_lds_sync();   // the shapes' thresholds and ranks
             cnt = 0;
             for (int32_t v = lane; v < ((T + 63) & ~63); v += 64) {
-                // every lane takes part in the shuffles: an inactive source lane reads as garbage
+                // every lane takes part in the ballot
                 const int sl = v < T ? (int)q.slot32[v] : 0;
-                const int32_t Ps = __shfl(P, sl, 64), qss = __shfl(qs, sl, 64);
-                const int64_t as = __shfl(a, sl, 64);
-                const float th = __shfl(thr, sl, 64);
-                const bool w = v < T && q.cost32[v] <= th;
+                const TileShape z = q.bs[sl];
+                const bool w = v < T && q.cost32[v] <= z.thr;
                 const uint64_t m = __ballot(w);
                 const int e = qn + cnt + (int)lanes_below(m);
                 if (w && e < kTileQueue) {
-                    const int32_t jl = v - Ps;
-                    q.key[e] = ((uint32_t)qss << 24) | (uint32_t)jl;
-                    q.cand[e] = (uint32_t)(as + jl);
+                    const int32_t jl = v - z.P;
+                    q.key[e] = ((uint32_t)(ns + z.rank) << 24) | (uint32_t)jl;
+                    q.cand[e] = (uint32_t)(v + z.D);
                 }
                 cnt += __popcll(m);
             }
