@@ -221,7 +221,8 @@ __device__ inline void bw_accumulate(const BwConst<R>& c, const BwEval<R>& E, A 
     g[0] += -wc * (A)E.Dread * (A)c.inv_tr * (A)c.inv_tr;
     g[1] += -wc * (A)E.Dacc * (A)c.inv_tw * (A)c.inv_tw;
     g[2] += wc * inv_f;
-    g[20] += wc * inv_f / Kt;
+    // once per round, not per K step: wc inv_f / Kt with the K steps cancelled
+    g[20] += E.compute_bound ? w * nr * inv_f : (A)0;
     // d/dR_TC[dt] of Tmma = -Tmma / R_TC[dt]
     const A dR = -wc * (A)E.Tmma * (A)c.inv_rtc[E.dt];
     g[3] += E.dt == 0 ? dR : (A)0;
