@@ -322,6 +322,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void
             int32_t Pk[SB];
 #pragma unroll
             for (int k = 0; k < SB; ++k) Pk[k] = __builtin_amdgcn_readlane(P, k);
+            wave_lds_sync();   // the previous batch's lanes are done reading bs
             if (lane < SB) {
                 q.bmin[lane] = ~0ull;
                 // a <= n_cand < 2^31 and P < kTileSpan, so D fits 32 bits
