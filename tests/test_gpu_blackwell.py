@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import grad_err, need_gpu, rel_err, say
+from gpu_common import check_grad, need_gpu, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -64,16 +64,15 @@ def test_bw_vjp_and_loss_grad_parity(wmb, orc, seed):
     w = np.random.default_rng(seed).standard_normal(d.n).astype(np.float32)
     g = wmb.bw_vjp(dd, p, torch.from_numpy(w).cuda()).cpu().numpy()
     go = orc.bw_vjp(p, d, w)
-    say("bw vjp err", grad_err(g, go))
-    assert grad_err(g, go) <= 1e-4
+    check_grad(g, go, p.theta, f"bw vjp seed {seed}", 1e-4, names=synth.BW_THETA_NAMES)
     To, _ = orc.bw_predict(p, d)
     p0 = synth.bw_param_set(seed + 10)
     m = (To * synth.lognormal_noise(d.n, seed, 0.05)).astype(np.float32)
     out = wmb.bw_loss_grad(dd, torch.from_numpy(m).cuda(), p0).cpu().numpy()
     loss, cnt, gl = orc.bw_loss_grad(p0, d, m)
-    say("bw loss", out[0], loss, "count", out[1], cnt, "grad err", grad_err(out[2:], gl))
+    say("bw loss", out[0], loss, "count", out[1], cnt)
     assert int(out[1]) == cnt and abs(out[0] - loss) <= 1e-5 * loss
-    assert grad_err(out[2:], gl) <= 1e-4
+    check_grad(out[2:], gl, p0.theta, f"bw loss gradient seed {seed}", 1e-4, names=synth.BW_THETA_NAMES)
 
 
 def test_bw_loss_grad_near_optimum_and_switch(wmb, orc):
@@ -88,7 +87,7 @@ def test_bw_loss_grad_near_optimum_and_switch(wmb, orc):
     out = wmb.bw_loss_grad(dd, torch.from_numpy(m).cuda(), p).cpu().numpy()
     loss, cnt, gl = orc.bw_loss_grad(p, d, m)
     assert int(out[1]) == cnt and abs(out[0] - loss) <= 1e-5 * max(loss, 1e-12) + 1e-9
-    assert grad_err(out[2:], gl) <= 1e-4
+    check_grad(out[2:], gl, p.theta, "bw loss gradient with m = T", 1e-4, names=synth.BW_THETA_NAMES)
     # put descriptors at the switch: scale eps so that T_io equals T_compute for one tile shape
     tr = orc.bw_trace(p, d)
     fin = np.isfinite(tr["T"])
@@ -102,7 +101,7 @@ def test_bw_loss_grad_near_optimum_and_switch(wmb, orc):
     say("descriptors at the switch", len(same))
     w = np.ones(d.n, np.float32)
     g = wmb.bw_vjp(dd, p2, torch.from_numpy(w).cuda()).cpu().numpy()
-    assert grad_err(g, orc.bw_vjp(p2, d, w)) <= 1e-4
+    check_grad(g, orc.bw_vjp(p2, d, w), p2.theta, "bw vjp at the switch", 1e-4, names=synth.BW_THETA_NAMES)
 
 
 def test_bw_calibration_recovers_parameters(wmb, orc):

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import grad_err, need_gpu, say
+from gpu_common import check_grad, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -83,9 +83,7 @@ def test_gradients_along_the_trajectory(wmb, orc):
         loss, cnt, g = orc.loss_grad(p, d, m)
         assert int(out[1]) == cnt
         assert abs(out[0] - loss) <= 1e-5 * loss
-        e = grad_err(out[2:], g)
-        say("trajectory point", k, "grad err", e)
-        assert e <= 1e-4
+        check_grad(out[2:], g, p.theta, f"trajectory point {k}", 1e-4, names=synth.THETA_NAMES)
 
 
 def test_calibration_matches_oracle_adam_loss_history(wmb, orc):

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import grad_err, need_gpu, rel_err, say
+from gpu_common import check_grad, need_gpu, rel_err, say, slot_errors
 
 pytestmark = pytest.mark.gpu
 GTOL = 1e-4
@@ -38,7 +38,8 @@ def test_loss_grad_parity_at_theta0(wmb, orc, L, combine):
     loss, cnt, g = orc.loss_grad(p0, d, m)
     assert int(out[1]) == cnt
     assert abs(out[0] - loss) <= 1e-5 * loss
-    assert grad_err(out[2:], g) <= GTOL, (grad_err(out[2:], g), out[2:], g)
+    check_grad(out[2:], g, p0.theta, f"loss gradient at theta0, L={L} combine={combine}", GTOL,
+               names=synth.THETA_NAMES)
 
 
 def test_loss_grad_parity_near_optimum(wmb, orc):
@@ -56,7 +57,8 @@ def test_loss_grad_parity_near_optimum(wmb, orc):
         loss, cnt, g = orc.loss_grad(p, d, m)
         assert int(out[1]) == cnt
         assert abs(out[0] - loss) <= 1e-5 * loss
-        assert grad_err(out[2:], g) <= GTOL, (f, grad_err(out[2:], g))
+        check_grad(out[2:], g, p.theta, f"loss gradient near the optimum, factor {f} on slots {k} mod 3",
+                   GTOL, names=synth.THETA_NAMES)
 
 
 def test_loss_grad_exact_measurements(wmb, orc):
@@ -72,7 +74,7 @@ def test_loss_grad_exact_measurements(wmb, orc):
     loss, cnt, g = orc.loss_grad(ps, d, m)
     assert int(out[1]) == cnt
     assert abs(out[0] - loss) <= 1e-5 * max(loss, 1e-12) + 1e-12
-    assert grad_err(out[2:], g) <= GTOL
+    check_grad(out[2:], g, ps.theta, "loss gradient with m = T", GTOL, names=synth.THETA_NAMES)
 
 
 @pytest.mark.parametrize("L,combine", [(4, 0), (3, 1)])
@@ -84,7 +86,7 @@ def test_vjp_parity(wmb, orc, L, combine):
     dd = wmb.DeviceDescriptors.from_host(d)
     g = wmb.vjp(dd, p, torch.from_numpy(w).cuda()).cpu().numpy()
     go = orc.vjp(p, d, w)
-    assert grad_err(g, go) <= GTOL, (grad_err(g, go), g, go)
+    check_grad(g, go, p.theta, f"vjp L={L} combine={combine}", GTOL, names=synth.THETA_NAMES)
 
 
 def test_vjp_empty_and_deterministic(wmb):
@@ -116,7 +118,7 @@ def test_autograd_function_matches_vjp_and_central_differences(wmb, orc):
     gv = wmb.vjp(dd, p, c).cpu().numpy()
     assert np.array_equal(g, gv)
     go = orc.vjp(p, d, c.cpu().numpy())
-    assert grad_err(g, go) <= GTOL
+    check_grad(g, go, p.theta, "autograd backward", GTOL, names=synth.THETA_NAMES)
     # central differences of the float32 forward sweep, h = 1e-4 relative
     h = 1e-4
     fd = np.zeros(24)
@@ -129,9 +131,14 @@ def test_autograd_function_matches_vjp_and_central_differences(wmb, orc):
         dp = (torch.where(fin, Tp, torch.zeros_like(Tp)).double() * c.double()).sum()
         dm = (torch.where(fin, Tm, torch.zeros_like(Tm)).double() * c.double()).sum()
         fd[j] = (dp - dm).item() / (2 * h * p.theta[j])
-    scale = np.abs(g * np.array(p.theta))
-    rel = np.abs(fd - g) * np.abs(np.array(p.theta)) / np.maximum(scale.max(), 1e-300)
-    assert rel.max() <= 1e-3, (rel, fd, g)
+    # float32 forward values carry ~1e-7 relative rounding, which central
+    # differences at h = 1e-4 turn into ~1e-3 of a slot's own term; slots
+    # at 1e-2 of the largest log-space gradient or more are checked one by one
+    ab, rel, big = slot_errors(fd, g, p.theta, floor=1e-2)
+    say("finite differences vs autograd, per slot:", np.array2string(ab, precision=2),
+        np.array2string(rel, precision=2))
+    assert ab.max() <= 1e-3, (ab, fd, g)
+    assert np.nanmax(rel) <= 3e-3, (rel, fd, g)
 
 
 def test_loss_grad_workspace_reuse_and_determinism(wmb, orc):

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import grad_err, need_gpu, rel_err, say
+from gpu_common import check_grad, need_gpu, rel_err, say
 
 pytestmark = pytest.mark.gpu
 N0 = 1 << 22
@@ -67,11 +67,13 @@ def test_forward_and_loss_grad_past_4_gib(wmb, orc):
     torch.cuda.empty_cache()
     assert int(out_big[1]) == REPS * int(out_base[1])
     assert abs(out_big[0] - out_base[0]) <= 1e-9 * out_base[0]
-    assert grad_err(out_big[2:], out_base[2:]) <= 1e-9
+    check_grad(out_big[2:], out_base[2:], p0.theta, "large: replicated set against the base set", 1e-9,
+               names=synth.THETA_NAMES)
     loss, cnt, g = orc.loss_grad(p0, d, m0)
     assert int(out_base[1]) == cnt
     assert abs(out_big[0] - loss) <= 1e-5 * loss
-    assert grad_err(out_big[2:], g) <= GTOL
+    check_grad(out_big[2:], g, p0.theta, "large: loss gradient against the oracle", GTOL,
+               names=synth.THETA_NAMES)
     say("large: loss gradient over", n, "descriptors matches the base set and the oracle")
 
 

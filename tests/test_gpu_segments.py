@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import grad_err, need_gpu, rel_err, say
+from gpu_common import check_grad, need_gpu, rel_err, say
 
 pytestmark = pytest.mark.gpu
 TTOL = 1e-5
@@ -88,12 +88,23 @@ def _grad_check(wmb, orc, p, q, sg, d, m, tag):
     mt = torch.from_numpy(m.astype(np.float32)).cuda()
     out = wmb.apps_loss_grad(dd, ds, mt, p, q).cpu().numpy()
     loss, cnt, gth, gsp = orc.apps_loss_grad(p, q, d, sg, m.astype(np.float32).astype(np.float64))
-    e1, e2 = grad_err(out[2:26], gth), grad_err(out[26:], gsp)
-    say(tag, "count", int(out[1]), cnt, "loss", out[0], loss, "grad err", e1, e2)
+    say(tag, "count", int(out[1]), cnt, "loss", out[0], loss)
     assert int(out[1]) == cnt
     assert abs(out[0] - loss) <= 1e-5 * loss
-    assert e1 <= GTOL and e2 <= GTOL
+    _check_both(out[2:26], out[26:], gth, gsp, p, q, tag)
     return out
+
+
+def _seg_x(q):
+    return np.array(list(q.kappa) + [q.bw_h2d, q.bw_d2h, q.tau_memcpy])
+
+
+def _check_both(g_th, g_sp, gth, gsp, p, q, tag):
+    """theta and the segment parameters share one log-space scale (both are
+    fitted together), then each group is also checked slot by slot."""
+    names = list(synth.THETA_NAMES) + ["kappa0", "kappa1", "kappa2", "kappa3", "bw_h2d", "bw_d2h", "tau_memcpy"]
+    check_grad(np.concatenate([g_th, g_sp]), np.concatenate([gth, gsp]),
+               np.concatenate([np.asarray(p.theta), _seg_x(q)]), tag, GTOL, names=names)
 
 
 @pytest.mark.parametrize("L,combine", [(4, 0), (3, 0), (4, 1)])
@@ -189,9 +200,7 @@ def test_apps_vjp_and_autograd(wmb, orc):
     w = np.random.default_rng(9).standard_normal(sg.n_apps).astype(np.float32)
     g = wmb.apps_vjp(dd, ds, torch.from_numpy(w).cuda(), p, q).cpu().numpy()
     gth, gsp = orc.apps_vjp(p, q, d, sg, w.astype(np.float64))
-    e1, e2 = grad_err(g[:24], gth), grad_err(g[24:], gsp)
-    say("apps vjp err", e1, e2)
-    assert e1 <= GTOL and e2 <= GTOL
+    _check_both(g[:24], g[24:], gth, gsp, p, q, "apps vjp")
     # through autograd: L = sum(w * T_app) over finite applications
     theta = torch.tensor(p.theta, dtype=torch.float64, requires_grad=True)
     sv = torch.tensor(list(q.kappa) + [q.bw_h2d, q.bw_d2h, q.tau_memcpy], dtype=torch.float64,
@@ -200,7 +209,7 @@ def test_apps_vjp_and_autograd(wmb, orc):
     wt = torch.from_numpy(w).cuda()
     fin = torch.isfinite(T)
     (wt[fin] * T[fin]).double().sum().backward()
-    assert grad_err(theta.grad.numpy(), gth) <= GTOL and grad_err(sv.grad.numpy(), gsp) <= GTOL
+    _check_both(theta.grad.numpy(), sv.grad.numpy(), gth, gsp, p, q, "apps autograd")
     # no applications: zeros
     d0 = synth.descriptors(0, 1)
     s0 = synth.Segments(np.zeros(1, np.int32), *[np.zeros(0, t) for t in
