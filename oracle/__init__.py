@@ -59,32 +59,39 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        P, D = C.POINTER(OrcParams), C.POINTER(OrcDesc)
-        vp = C.c_void_p
-        L.orc_occupancy.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
-        L.orc_occupancy.restype = C.c_int64
-        L.orc_h_llc.argtypes = [P, C.c_double]
-        L.orc_h_llc.restype = C.c_double
-        L.orc_bw_hbm_eff.argtypes = [P, C.c_double]
-        L.orc_bw_hbm_eff.restype = C.c_double
-        L.orc_eval.argtypes = [P] + [C.c_double] * 8 + [C.c_int64] * 4 + [C.POINTER(OrcTrace), vp]
-        L.orc_eval.restype = None
-        L.orc_predict.argtypes = [P, D, vp, vp]
-        L.orc_trace.argtypes = [P, D, vp]
-        L.orc_jacobian.argtypes = [P, D, vp]
-        L.orc_roofline.argtypes = [P, D, vp]
-        L.orc_weighted_grad.argtypes = [P, D, vp, C.c_int, vp]
-        L.orc_calibrate.argtypes = [P, D, vp, C.POINTER(OrcCalibOpts), P, vp]
-        L.orc_calibrate.restype = C.c_int
-        L.orc_tile_derive.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
-                                      C.c_int64, C.POINTER(OrcTile)]
-        L.orc_tile_cost.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32]
-        L.orc_tile_cost.restype = C.c_double
-        L.orc_tile_costs.argtypes = [P, C.c_int64] + [vp] * 7
-        L.orc_select_tile.argtypes = [P, C.c_int64] + [vp] * 9
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path):
+    """Open an oracle library built from these sources (the default one, or a
+    variant that the tests build, e.g. with sanitizers or a planted mistake)
+    and declare its entry points."""
+    L = C.CDLL(path)
+    P, D = C.POINTER(OrcParams), C.POINTER(OrcDesc)
+    vp = C.c_void_p
+    L.orc_occupancy.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
+    L.orc_occupancy.restype = C.c_int64
+    L.orc_h_llc.argtypes = [P, C.c_double]
+    L.orc_h_llc.restype = C.c_double
+    L.orc_bw_hbm_eff.argtypes = [P, C.c_double]
+    L.orc_bw_hbm_eff.restype = C.c_double
+    L.orc_eval.argtypes = [P] + [C.c_double] * 8 + [C.c_int64] * 4 + [C.POINTER(OrcTrace), vp]
+    L.orc_eval.restype = None
+    L.orc_predict.argtypes = [P, D, vp, vp]
+    L.orc_trace.argtypes = [P, D, vp]
+    L.orc_jacobian.argtypes = [P, D, vp]
+    L.orc_roofline.argtypes = [P, D, vp]
+    L.orc_weighted_grad.argtypes = [P, D, vp, C.c_int, vp]
+    L.orc_calibrate.argtypes = [P, D, vp, C.POINTER(OrcCalibOpts), P, vp]
+    L.orc_calibrate.restype = C.c_int
+    L.orc_tile_derive.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
+                                  C.c_int64, C.POINTER(OrcTile)]
+    L.orc_tile_cost.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32]
+    L.orc_tile_cost.restype = C.c_double
+    L.orc_tile_costs.argtypes = [P, C.c_int64] + [vp] * 7
+    L.orc_select_tile.argtypes = [P, C.c_int64] + [vp] * 9
+    return L
 
 
 # ----------------------------------------------------------------------------
@@ -143,10 +150,10 @@ def trace(p, d):
     return {name: np.array(arr[name]) for name in arr.dtype.names if not name.startswith("pad")}
 
 
-def eval_one(p, F, B, r1, r2, r3, K, u, W, v, s, gpack, G, with_grad=False):
+def eval_one(p, F, B, r1, r2, r3, K, u, W, v, s, gpack, G, with_grad=False, L=None):
     tr = OrcTrace()
     J = np.zeros(N_THETA) if with_grad else None
-    lib().orc_eval(C.byref(params(p)), float(F), float(B), float(r1), float(r2), float(r3),
+    (L or lib()).orc_eval(C.byref(params(p)), float(F), float(B), float(r1), float(r2), float(r3),
                    float(K), float(u), float(W), int(v), int(s), int(gpack), int(G), C.byref(tr),
                    J.ctypes.data if with_grad else None)
     return (tr, J) if with_grad else tr

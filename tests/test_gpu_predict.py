@@ -181,3 +181,37 @@ def test_predict_full_size_sampled(wmb, orc):
     assert np.all((occ >= -1) & (occ <= p.n_simd * p.waves_simd))
     assert np.all(np.isinf(T[occ == 0])) and np.all(np.isfinite(T[occ > 0]))
     assert np.all(T[occ > 0] >= p.theta[13] * (1 - 1e-6))
+
+
+def test_predict_hand_worked_latency_and_overhead_rows(wmb):
+    """The rows of tests/golden/latency_stage.txt and overhead_terms.txt
+    (values worked by hand) through the forward sweep: occupancy exact, T
+    within the float32 bound of the hand-worked value."""
+    from test_oracle_latency_overhead import U, _params, _rows
+    p = _params()
+    lat, ovh = _rows("latency_stage.txt"), _rows("overhead_terms.txt")
+    n1, n2 = len(lat), len(ovh)
+    f = lambda v: np.array(v, np.float32)
+    d = synth.Descriptors(
+        F=np.zeros(n1 + n2, np.float32),
+        B=f([float(r[5]) for r in lat] + [0.0] * n2),
+        r1=f([float(r[6]) for r in lat] + [0.0] * n2),
+        r2=f([float(r[7]) for r in lat] + [0.0] * n2),
+        r3=np.zeros(n1 + n2, np.float32),
+        K=f([0.0] * n1 + [float(r[2]) for r in ovh]),
+        u=np.ones(n1 + n2, np.float32), W=np.zeros(n1 + n2, np.float32),
+        vgpr=np.array([int(r[2]) for r in lat] + [128] * n2, np.int32),
+        lds=np.array([int(r[3]) for r in lat] + [0] * n2, np.int32),
+        gpack=np.concatenate([synth.pack_gpack(np.array([int(r[1]) for r in lat]), 1),
+                              synth.pack_gpack(256, 1, np.array([int(r[3]) for r in ovh]),
+                                               np.array([int(r[4]) for r in ovh]),
+                                               np.array([int(r[5]) for r in ovh]),
+                                               np.array([int(r[6]) for r in ovh]))]),
+        grid=np.array([int(r[4]) for r in lat] + [int(r[1]) for r in ovh], np.int32))
+    T, occ = wmb.predict(wmb.DeviceDescriptors.from_host(d), p)
+    want_T = np.array([float(r[14]) * U for r in lat] + [float(r[14]) * U for r in ovh])
+    want_o = np.array([int(r[9]) for r in lat] + [4] * n2, np.int32)
+    assert np.array_equal(occ.cpu().numpy(), want_o)
+    err = rel_err(T.cpu().numpy(), want_T)
+    say("hand-worked rows on the GPU: max rel err", err.max())
+    assert err.max() <= TOL
