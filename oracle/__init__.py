@@ -54,12 +54,15 @@ _lib = None
 
 
 def lib():
+    """The oracle library: oracle/liboracle.so, or the variant build named by
+    the WM_ORACLE_LIB environment variable (the sanitizer run of the pins)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("WM_ORACLE_LIB") or LIB_PATH
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        _lib = load(LIB_PATH)
+        _lib = load(path)
     return _lib
 
 
