@@ -59,6 +59,7 @@ extern "C" {
 #define WM_EWORKSPACE (-2)  /* workspace missing, too small or misaligned */
 #define WM_EHIP (-3)        /* a HIP call failed; see wm_last_hip_error() */
 #define WM_EDIVERGED (-4)   /* calibration loss became non-finite */
+#define WM_ETOOLARGE (-5)   /* input larger than a fixed-size scratch allows */
 
 #define WM_N_THETA 24
 
@@ -243,6 +244,24 @@ int32_t wm_predict_vjp(const wm_desc_t *desc, const wm_params_t *params, const f
  */
 int32_t wm_loss_grad(const wm_desc_t *desc, const float *measured, const wm_params_t *params,
                      double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * wm_loss_grad without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and status codes as wm_loss_grad; the workspace is a fixed device array of
+ * wm_noalloc_scratch_bytes() bytes (about 9.7 MiB) inside the library, one
+ * copy per GPU, held until the process ends.  n above WM_NOALLOC_MAX_N
+ * returns WM_ETOOLARGE.  The array's device address is looked up on the
+ * first call on each device (a HIP symbol lookup, no allocation; call once
+ * before a graph capture starts).  All calls on one GPU share its array:
+ * calls that overlap in time on one GPU (two streams, or two host threads)
+ * race and give wrong results; calls in one stream are ordered and safe.
+ */
+#define WM_NOALLOC_MAX_N (1 << 26)
+size_t wm_noalloc_scratch_bytes(void);
+int32_t wm_loss_grad_noalloc(const wm_desc_t *desc, const float *measured, const wm_params_t *params,
+                             double *out, void *stream);
 
 /*
  * Adaptive tile selection (Section IV-B: evaluate candidate tiles with the

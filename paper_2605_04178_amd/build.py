@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwavemodel.so")
-SOURCES = ["wm_kernels.hip", "wm_tile.hip", "wm_segments.hip", "wm_planning.hip", "wm_blackwell.hip", "wm_api.cpp", "wm_tune.cpp"]
+SOURCES = ["wm_kernels.hip", "wm_tile.hip", "wm_segments.hip", "wm_planning.hip", "wm_blackwell.hip", "wm_api.cpp", "wm_tune.cpp", "wm_noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -719,6 +719,14 @@ std::vector<LaunchCfg> candidates(int op)
 }  // namespace
 
 // ===========================================================================
+int32_t wm::record_hip_error(hipError_t e) { return hip_fail(e); }
+
+bool wm::grad_args_ok(const wm_desc_t* desc, const float* w, const wm_params_t* params, const double* out)
+{
+    if (!desc_ok(desc) || !params_ok(params) || !out) return false;
+    return !(desc->n > 0 && !w);
+}
+
 extern "C" {
 
 const char* wm_strerror(int32_t s)
@@ -729,6 +737,7 @@ const char* wm_strerror(int32_t s)
     case WM_EWORKSPACE: return "workspace missing, too small or misaligned";
     case WM_EHIP: return "HIP runtime error";
     case WM_EDIVERGED: return "calibration diverged";
+    case WM_ETOOLARGE: return "input larger than the fixed scratch allows";
     default: return "unknown status";
     }
 }
@@ -934,8 +943,7 @@ int32_t wm_roofline(const wm_desc_t* desc, const wm_params_t* params, float* T, 
 static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, const wm_params_t* params,
                            double* out, void* ws, size_t ws_bytes, void* stream)
 {
-    if (!desc_ok(desc) || !params_ok(params) || !out) return WM_EINVAL;
-    if (desc->n > 0 && !w) return WM_EINVAL;
+    if (!wm::grad_args_ok(desc, w, params, out)) return WM_EINVAL;
     const size_t need = wm_workspace_bytes(mode == 1 ? WM_OP_LOSS_GRAD : WM_OP_VJP, desc->n, 1, 0);
     if (!ws_ok(ws, ws_bytes, need)) return WM_EWORKSPACE;
     const Set S = make_set(params);

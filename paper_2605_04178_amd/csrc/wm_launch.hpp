@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/wavemodel.h"
 #include "wm_model.hpp"
 
 namespace wm {
@@ -95,6 +96,11 @@ struct GradLayout {
     int64_t nwords;
 };
 GradLayout grad_layout(int64_t n);
+// records e as the library's last HIP error and returns WM_EHIP
+int32_t record_hip_error(hipError_t e);
+// argument check of the gradient calls (wm_predict_vjp, wm_loss_grad): a
+// valid descriptor set and parameter set, an output, weights unless n = 0
+bool grad_args_ok(const wm_desc_t* desc, const float* w, const wm_params_t* params, const double* out);
 // phase-1 blocks actually launched (<= grad_layout(n).nb): the blocks
 // resident at once on the current device times cfg.grid_mult, so partial
 // rows = that + nb2

@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwavemodel.so")
 N_THETA = 24
 
-WM_OK, WM_EINVAL, WM_EWORKSPACE, WM_EHIP, WM_EDIVERGED = 0, -1, -2, -3, -4
+WM_OK, WM_EINVAL, WM_EWORKSPACE, WM_EHIP, WM_EDIVERGED, WM_ETOOLARGE = 0, -1, -2, -3, -4, -5
+NOALLOC_MAX_N = 1 << 26
 (OP_PREDICT, OP_ROOFLINE, OP_VJP, OP_LOSS_GRAD, OP_SELECT_TILE, OP_CALIBRATE, OP_CALIBRATE_BATCHED,
  OP_PREDICT_APPS, OP_APPS_LOSS_GRAD, OP_FIT_MULTIPLIERS) = range(10)
 N_SEGPARAMS = 7
@@ -31,7 +32,8 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_autotune_batched", "wm_apps_workspace_bytes", "wm_predict_apps", "wm_apps_loss_grad",
             "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion",
             "wm_bw_validate_params", "wm_bw_workspace_bytes", "wm_bw_predict", "wm_bw_predict_vjp",
-            "wm_bw_loss_grad", "wm_bw_calibrate", "wm_predict_apps_vjp")
+            "wm_bw_loss_grad", "wm_bw_calibrate", "wm_predict_apps_vjp", "wm_loss_grad_noalloc",
+            "wm_noalloc_scratch_bytes")
 BW_OP_GRAD, BW_OP_CALIBRATE = 0, 1
 
 
@@ -123,6 +125,10 @@ def lib():
         L.wm_predict_vjp.restype = i32
         L.wm_loss_grad.argtypes = [D, vp, P, vp, vp, sz, vp]
         L.wm_loss_grad.restype = i32
+        L.wm_loss_grad_noalloc.argtypes = [D, vp, P, vp, vp]
+        L.wm_loss_grad_noalloc.restype = i32
+        L.wm_noalloc_scratch_bytes.argtypes = []
+        L.wm_noalloc_scratch_bytes.restype = sz
         L.wm_select_tile.argtypes = [C.POINTER(WmShapes), vp, vp, i64, P, vp, vp, vp, vp]
         L.wm_select_tile.restype = i32
         L.wm_calibrate.argtypes = [D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
@@ -378,6 +384,16 @@ def loss_grad(desc: DeviceDescriptors, measured: torch.Tensor, params, ws=None, 
     rc = lib().wm_loss_grad(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(params, theta)),
                             _ptr(out), _ptr(ws), nb, _stream(stream))
     _check(rc, "wm_loss_grad")
+    return out
+
+
+def loss_grad_noalloc(desc: DeviceDescriptors, measured: torch.Tensor, params, out, stream=None):
+    """wm_loss_grad_noalloc: the same [loss, count, grad[24]] as loss_grad,
+    written into the caller's float64 tensor `out` [26], with the library's
+    fixed per-GPU scratch as workspace (nothing is allocated)."""
+    rc = lib().wm_loss_grad_noalloc(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(params)),
+                                    _ptr(out), _stream(stream))
+    _check(rc, "wm_loss_grad_noalloc")
     return out
 
 

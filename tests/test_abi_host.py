@@ -347,3 +347,27 @@ def test_set_launch_rejects_invalid_configs_without_a_gpu(wmb):
     assert L.wm_autotune_predict(None, C.byref(p), None, None, None, None, None) == wmb.WM_EINVAL
     assert L.wm_autotune_grad(wmb.OP_PREDICT, None, None, C.byref(p), None, None, 0, None, None,
                               None) == wmb.WM_EINVAL
+
+
+def test_noalloc_loss_grad_rejects_bad_arguments_and_sizes_before_any_hip_call(wmb):
+    """wm_loss_grad_noalloc checks every argument and the size limit on the
+    host; none of these calls reaches HIP (there is no GPU here)."""
+    L = wmb.lib()
+    p = wmb.params_struct(synth.param_set(0))
+    out, w = C.c_void_p(0x20000), C.c_void_p(0x30000)
+    d = _fake_desc(wmb, wmb.NOALLOC_MAX_N + 1)
+    assert L.wm_loss_grad_noalloc(C.byref(d), w, C.byref(p), out, None) == wmb.WM_ETOOLARGE
+    d.n = 1 << 40
+    assert L.wm_loss_grad_noalloc(C.byref(d), w, C.byref(p), out, None) == wmb.WM_ETOOLARGE
+    d.n = -1
+    assert L.wm_loss_grad_noalloc(C.byref(d), w, C.byref(p), out, None) == wmb.WM_EINVAL
+    d.n = 16
+    assert L.wm_loss_grad_noalloc(C.byref(d), None, C.byref(p), out, None) == wmb.WM_EINVAL
+    assert L.wm_loss_grad_noalloc(C.byref(d), w, C.byref(p), None, None) == wmb.WM_EINVAL
+    assert L.wm_loss_grad_noalloc(None, w, C.byref(p), out, None) == wmb.WM_EINVAL
+    bad = wmb.params_struct(synth.param_set(0).copy(n_levels=5))
+    assert L.wm_loss_grad_noalloc(C.byref(d), w, C.byref(bad), out, None) == wmb.WM_EINVAL
+    # the fixed scratch covers the workspace of the largest accepted input
+    assert L.wm_noalloc_scratch_bytes() >= wmb.workspace_bytes(wmb.OP_LOSS_GRAD, wmb.NOALLOC_MAX_N)
+    assert L.wm_noalloc_scratch_bytes() < 16 << 20
+    assert L.wm_strerror(wmb.WM_ETOOLARGE).decode() == "input larger than the fixed scratch allows"
