@@ -487,6 +487,13 @@ def main():
                               "bytes_per_eval": ADJ_BYTES, "dtype": "f32 + f64 reductions",
                               "traffic": counted_traffic(kernel_name("loss_grad", res["launch"]["loss_grad"]))}
         log(f"fwd+adjoint: {wall_a:.4f} ms/step, {ach_a:.0f} GB/s")
+        # the float64-exact variant of the same call
+        lx = lambda: wm.loss_grad(dd, meas, p0, ws=ws, out=out, exact=True)
+        wall_x, ev_x = timed(lx, max(args.steps // 2, 3), 2)
+        ach_x = ADJ_BYTES * n / (ev_x * 1e-3) / 1e9
+        res["fwd_adjoint_exact"] = {"value": n / (wall_x * 1e-3), "unit": "evals/s", "ms_per_step": wall_x,
+                                    "achieved_GBs": ach_x, "hbm_frac": ach_x / HBM_PEAK_GBS, "dtype": "f64"}
+        log(f"fwd+adjoint, float64-exact call: {wall_x:.4f} ms/step, {ach_x:.0f} GB/s")
         del meas, ws
 
         # ---- tile selection ----
@@ -520,11 +527,11 @@ def main():
 
         # ---- calibration: 2^20 descriptors, Adam in captured graphs ----
         nc = 1 << 20
-        dc = synth.descriptors(nc, 103)
+        dc = synth.calibration_descriptors(nc, 103)
         ddc = wm.DeviceDescriptors.from_host(dc, dev)
         Tc, _ = wm.predict(ddc, ps, want_occ=False)
         mc = (Tc * torch.from_numpy(synth.lognormal_noise(nc, 2, 0.02).astype(np.float32)).to(dev)).contiguous()
-        mask = 0x3FFFFF
+        mask = synth.fit_mask(ps.n_levels)
         p0c = synth.perturb_theta(ps, 3, mask=mask)
         if not args.no_tune:
             tuned["loss_grad_2^20"] = wm.autotune_grad(wm.OP_LOSS_GRAD, ddc, mc, p0c)
@@ -544,18 +551,30 @@ def main():
                             "max_recovery_err": err, "status": rc,
                             "loss_first_last": [float(hist[0]), float(hist[-1])]}
         log(f"calibrate: {el:.3f} s, max recovery err {err:.4f}")
-        del ddc, mc, Tc
+        # the same problem under the Eq. (9)/(12) occupancy-overlap combine
+        pe = ps.copy(combine=1)
+        Te, _ = wm.predict(ddc, pe, want_occ=False)
+        me = (Te * torch.from_numpy(synth.lognormal_noise(nc, 2, 0.02).astype(np.float32)).to(dev)).contiguous()
+        p0e = synth.perturb_theta(pe, 3, mask=mask)
+        t0 = time.perf_counter()
+        rce, the, histe = wm.calibrate(ddc, me, p0e, steps=args.calib_steps, free_mask=mask)
+        el_e = time.perf_counter() - t0
+        err_e = float(np.max(np.abs(the[idx] / np.array(pe.theta)[idx] - 1)))
+        res["calibrate_overlap_combine"] = {"descriptors": nc, "steps": args.calib_steps, "seconds": el_e,
+                                            "max_recovery_err": err_e, "status": rce}
+        log(f"calibrate (overlap combine): {el_e:.3f} s, max recovery err {err_e:.4f}")
+        del ddc, mc, Tc, me, Te
 
         # ---- batched calibration of six architectures vs six plain launches ----
         sets = synth.multi_arch_sets()
         sizes = synth.multi_arch_sizes()
         descs, meas_l, p0s, opts = [], [], [], []
         for k, (pk, nk) in enumerate(zip(sets, sizes)):
-            dk = synth.descriptors(nk, 120 + k)
+            dk = synth.calibration_descriptors(nk, 120 + k)
             ddk = wm.DeviceDescriptors.from_host(dk, dev)
             Tk, _ = wm.predict(ddk, pk, want_occ=False)
             mk = (Tk * torch.from_numpy(synth.lognormal_noise(nk, 130 + k, 0.02).astype(np.float32)).to(dev)).contiguous()
-            mk_mask = 0x3FFFFF if pk.n_levels == 4 else (0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21) | (1 << 22)))
+            mk_mask = synth.fit_mask(pk.n_levels)
             descs.append(ddk)
             meas_l.append(mk)
             p0s.append(synth.perturb_theta(pk, 140 + k, mask=mk_mask))

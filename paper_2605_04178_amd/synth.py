@@ -42,6 +42,19 @@ THETA_NAMES = [
 N_THETA = 24
 MIB = float(1 << 20)
 
+# Slots the calibration tests fit (bit j = slot j).  Three-level sets leave
+# the LLC slots (BW_LLC, Lat_LLC, alpha, beta) unused.  With an LLC, w0 (the
+# Eq. (16) blend scale) is held: the cache serves every working set below
+# W_lo, so the blend is seen only through its tail exp(-W/w0) beyond W_lo,
+# where its amplitude (B_peak) and scale (w0) are nearly collinear (the
+# Fisher identifiability pin in the oracle tests measures both).
+FIT_MASK_L4 = 0xFFFFFF & ~(1 << 22)
+FIT_MASK_L3 = 0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21))
+
+
+def fit_mask(n_levels: int) -> int:
+    return FIT_MASK_L4 if n_levels == 4 else FIT_MASK_L3
+
 # gpack bit layout of the int32 descriptor field: WG threads, dtype, counts
 GPACK_G_BITS = 11
 GPACK_DTYPE_SHIFT = 11
@@ -278,6 +291,48 @@ def descriptors(n: int, seed: int = 100) -> Descriptors:
     nsync = np.where(rng.random(n) < 0.5, 0, rng.integers(1, 16, n))
     gpack = pack_gpack(g, dtype, nconc, ndev, fused, nsync)
     return Descriptors(F, B, r1, r2, r3, K, u, W, vgpr, lds, gpack, grid)
+
+
+def streaming_descriptors(n: int, seed: int = 500, w_lo_mib: float = 205.0,
+                          c_llc_mib: float = 256.0) -> Descriptors:
+    """Memory-streaming descriptors that sweep the working-set regimes, the
+    synthetic counterpart of the paper's bandwidth and working-set
+    microbenchmarks (Section IV-D): bytes log-U[1e8, 1e11], flops per byte
+    log-U[1e-3, 1e-1], L1 / L2 hit rates U[0, 0.2], grids round(log-U[2^12,
+    2^20]) of workgroups with U-int[16, 128] VGPRs and U-int[0, 16 KiB] LDS,
+    K round(log-U[1, 64]); the other fields as in descriptors().  Working
+    sets: 30 % W = 0 with an explicit LLC hit rate r3 ~ U(0, 1), 20 % inside
+    the Infinity-Cache transition zone U[W_lo + 0.5, C - 0.5] MiB (Table
+    "hlcc-piecewise"), 50 % log-U[8 MiB, 2 GiB] (below, across and above the
+    cache, where Eq. (16) blends the HBM bandwidth)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = descriptors(n, seed + 1)
+    f32 = np.float32
+    d.B = _logu(rng, 1e8, 1e11, n).astype(f32)
+    d.F = (d.B.astype(np.float64) * _logu(rng, 1e-3, 1e-1, n)).astype(f32)
+    d.r1 = rng.uniform(0.0, 0.2, n).astype(f32)
+    d.r2 = rng.uniform(0.0, 0.2, n).astype(f32)
+    d.r3 = rng.random(n, dtype=f32)
+    sel = rng.random(n)
+    W = np.where(sel < 0.3, 0.0,
+                 np.where(sel < 0.5, rng.uniform(w_lo_mib + 0.5, c_llc_mib - 0.5, n) * MIB,
+                          _logu(rng, 8.0 * MIB, 2048.0 * MIB, n)))
+    d.W = W.astype(f32)
+    d.grid = np.round(_logu(rng, float(1 << 12), float(1 << 20), n)).astype(np.int32)
+    d.vgpr = rng.integers(16, 129, n, dtype=np.int32)
+    d.lds = rng.integers(0, 16385, n, dtype=np.int32)
+    d.K = np.round(_logu(rng, 1.0, 64.0, n)).astype(f32)
+    return d
+
+
+def calibration_descriptors(n: int, seed: int = 103, stream_frac: float = 0.5) -> Descriptors:
+    """The calibration sweep: descriptors(n - n_s, seed) followed by
+    n_s = round(stream_frac * n) streaming_descriptors(n_s, seed + 400), so
+    that the working-set slots (alpha, beta, w0, B_peak) are excited for a
+    real share of the measurements, as the paper's calibration draws each
+    parameter from a microbenchmark that isolates it."""
+    ns = int(round(stream_frac * n))
+    return Descriptors.concat([descriptors(n - ns, seed), streaming_descriptors(ns, seed + 400)])
 
 
 def lognormal_noise(n: int, seed: int = 2, sigma: float = 0.02) -> np.ndarray:
@@ -551,3 +606,46 @@ def bw_descriptors(n: int, seed: int = 200) -> BwDescriptors:
     CR = np.where(comp == 1, rng.uniform(1.0, 4.0, n), 1.0).astype(np.float32)
     ob = np.array([2.0, 4.0], np.float32)[rng.integers(0, 2, n)]
     return BwDescriptors(bM, bN, bK, G, pack_bw_flags(dt, pair, sb, PA, PB, nbar, comp), Kt, CR, ob)
+
+
+def bw_tmem_tiles(n: int, seed: int = 600) -> BwDescriptors:
+    """Compute-heavy Blackwell tiles that bring the TMEM and tensor-core
+    terms of Eq. (2)/(3) forward: FP16/BF16, FP8 or FP4, bM in {128, 256},
+    bN in {64, 128, 256}, bK in {16, 128}, TMEM strategy B and 2-SM pairs
+    Bernoulli(1/2), multicast P_A, P_B in {2, 4} (less I/O per CTA), one or
+    two barriers, no compression; K-steps, CTAs and output bytes as in
+    bw_descriptors()."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = bw_descriptors(n, seed + 1)
+    d.bM = np.array([128, 256])[rng.integers(0, 2, n)].astype(np.int32)
+    d.bN = np.array([64, 128, 256])[rng.integers(0, 3, n)].astype(np.int32)
+    d.bK = np.array([16, 128])[rng.integers(0, 2, n)].astype(np.int32)
+    dt = rng.integers(2, 5, n)
+    pair = (rng.random(n) < 0.5).astype(np.int64)
+    sb = (rng.random(n) < 0.5).astype(np.int64)
+    PA = np.array([2, 4])[rng.integers(0, 2, n)]
+    PB = np.array([2, 4])[rng.integers(0, 2, n)]
+    nbar = rng.integers(1, 3, n)
+    d.flags = pack_bw_flags(dt, pair, sb, PA, PB, nbar, np.zeros(n, np.int64))
+    d.CR = np.ones(n, np.float32)
+    return d
+
+
+def bw_calibration_descriptors(n: int, seed: int = 226, tmem_frac: float = 0.25) -> BwDescriptors:
+    """The Blackwell calibration sweep: bw_descriptors(n - n_t, seed)
+    followed by n_t = round(tmem_frac * n) bw_tmem_tiles(n_t, seed + 400)."""
+    nt = int(round(tmem_frac * n))
+    a, b = bw_descriptors(n - nt, seed), bw_tmem_tiles(nt, seed + 400)
+    return BwDescriptors(*[np.concatenate([getattr(a, f.name), getattr(b, f.name)])
+                           for f in dataclasses.fields(BwDescriptors)])
+
+
+# Blackwell slots the calibration tests fit.  Held: eta_DE (Eq. (5) sees only
+# the product BW_link eta_DE), the exposed fraction eps (it multiplies every
+# I/O term, so it trades exactly against a common scale of the I/O rates and
+# latencies), O_misc (a per-step constant in both regimes, it trades exactly
+# against L_mma on compute-bound and eps L_TMA on I/O-bound steps) and the
+# TMEM read rate (apart from the accumulator, which it shares with the write
+# rate, it only sees the strategy-B A-tile read, at most ~2 % of a step).
+BW_FIT_MASK = 0xFFFFFF & ~((1 << 0) | (1 << 14) | (1 << 17) | (1 << 21))
+

@@ -105,30 +105,34 @@ def test_bw_loss_grad_near_optimum_and_switch(wmb, orc):
 
 
 def test_bw_calibration_recovers_parameters(wmb, orc):
+    """2^18 measurements over the Blackwell calibration sweep, sigma = 0.02,
+    500 Adam steps from a +-30 % start: all 20 fitted slots (every slot but
+    the four the oracle tests show unidentifiable: eta_DE, the exposed
+    fraction, O_misc and the TMEM read rate) within 3 %."""
     p_true = synth.bw_param_set(7)
-    d = synth.bw_descriptors(1 << 18, 226)
+    d = synth.bw_calibration_descriptors(1 << 18, 226)
     To, _ = orc.bw_predict(p_true, d)
     m = (To * synth.lognormal_noise(d.n, 227, 0.02)).astype(np.float32)
-    # slots whose Fisher standard error at sigma = 0.02 is below 0.5 % on this
-    # sweep; the TMEM rates (5-9 %) and O_misc (3 %) stay fixed
-    free = [3, 4, 5, 6, 7, 9, 10, 17, 18, 22]
-    mask = sum(1 << j for j in free)
+    mask = synth.BW_FIT_MASK
+    free = [j for j in range(24) if mask >> j & 1]
+    assert len(free) == 20
     rng = np.random.default_rng(3)
     th0 = list(p_true.theta)
     for j in free:
         th0[j] *= float(np.exp(rng.uniform(-np.log(1.3), np.log(1.3))))
     p0 = p_true.copy(theta=th0)
     rc, th, hist = wmb.bw_calibrate(wmb.DeviceBwDescriptors.from_host(d), torch.from_numpy(m).cuda(), p0,
-                                    steps=500, lr=0.02, lr_final=1e-4, free_mask=mask)
-    err = max(abs(th[j] / p_true.theta[j] - 1) for j in free)
-    say("bw calibration", rc, "loss", hist[0], "->", hist[-1], "max err", err)
-    assert rc == 0 and hist[-1] < hist[0] and err < 0.03
+                                    steps=500, lr=0.05, lr_final=1e-3, free_mask=mask)
+    err = {synth.BW_THETA_NAMES[j]: abs(th[j] / p_true.theta[j] - 1) for j in free}
+    say("bw calibration", rc, "loss", hist[0], "->", hist[-1], "recovery error per fitted slot:",
+        " ".join(f"{k}={v * 100:.2f}%" for k, v in err.items()))
+    assert rc == 0 and hist[-1] < hist[0] and max(err.values()) < 0.03
     assert all(th[j] == p0.theta[j] for j in range(24) if j not in free)
     # the oracle's calibration from the same start, on a sample, follows the same path
     sub = d.slice(0, 1 << 14)
-    rc_o, th_o, hist_o = orc.bw_calibrate(p0, sub, m[: 1 << 14], steps=50, lr=0.02, lr_final=1e-4, free_mask=mask)
+    rc_o, th_o, hist_o = orc.bw_calibrate(p0, sub, m[: 1 << 14], steps=50, lr=0.05, lr_final=1e-3, free_mask=mask)
     rc_g, th_g, hist_g = wmb.bw_calibrate(wmb.DeviceBwDescriptors.from_host(sub),
-                                          torch.from_numpy(m[: 1 << 14]).cuda(), p0, steps=50, lr=0.02,
-                                          lr_final=1e-4, free_mask=mask)
+                                          torch.from_numpy(m[: 1 << 14]).cuda(), p0, steps=50, lr=0.05,
+                                          lr_final=1e-3, free_mask=mask)
     assert np.allclose(hist_g, hist_o, rtol=1e-5)
     assert np.allclose(th_g, th_o, rtol=1e-4)

@@ -29,7 +29,7 @@ def test_empty_descriptor_calls(wmb):
     assert torch.count_nonzero(out).item() == 0
     T, occ = wmb.predict(d0, p)
     assert T.numel() == 0 and occ.numel() == 0
-    rc, th, hist = wmb.calibrate(d0, none, p, steps=5, free_mask=0x3FFFFF)
+    rc, th, hist = wmb.calibrate(d0, none, p, steps=5, free_mask=synth.FIT_MASK_L4)
     assert rc == wmb.WM_OK and np.all(hist == 0.0)
     assert np.allclose(th, np.asarray(p.theta), rtol=1e-12, atol=0)
 

@@ -97,7 +97,7 @@ def test_batched_chunks_match(wmb, orc):
         Tk, _ = orc.predict(pk, dk)
         descs.append(wmb.DeviceDescriptors.from_host(dk))
         meas.append(torch.from_numpy((Tk * synth.lognormal_noise(nk, 160 + k, 0.02)).astype(np.float32)).cuda())
-        mask = 0x3FFFFF if pk.n_levels == 4 else 0xFFFFFF & ~((1 << 2) | (1 << 6) | (1 << 20) | (1 << 21) | (1 << 22))
+        mask = synth.fit_mask(pk.n_levels)
         p0s.append(synth.perturb_theta(pk, 170 + k, mask=mask))
         opts.append(wmb.calib_opts(steps=25, free_mask=mask))
     ntot = sum(sizes)

@@ -146,42 +146,110 @@ def test_jacobian_matches_central_differences(orc):
     assert checked > 100
 
 
+BW_FREE = [j for j in range(24) if synth.BW_FIT_MASK >> j & 1]
+
+
 def test_loss_gradient_and_calibration_recovery(orc):
+    """Noise-free measurements: the loss is zero at theta*, and 500 Adam
+    steps from a +-30 % start recover all 20 fitted slots to 0.5 %."""
     p_true = synth.bw_param_set(7)
-    d = synth.bw_descriptors(1 << 14, 202)
+    d = synth.bw_calibration_descriptors(1 << 15, 202)
     T, _ = orc.bw_predict(p_true, d)
     m = T.astype(np.float32)
     loss, cnt, g = orc.bw_loss_grad(p_true, d, m)
     assert cnt == np.isfinite(T).sum() and loss < 1e-6
-    # well-determined slots: tensor throughputs, TMEM rates, TMA rate and
-    # latency, exposed fraction, launch, store rate, O_misc
-    free = [0, 1, 3, 4, 5, 6, 7, 9, 10, 17, 18, 21, 22]
-    mask = sum(1 << j for j in free)
+    mask = synth.BW_FIT_MASK
     rng = np.random.default_rng(3)
     th0 = list(p_true.theta)
-    for j in free:
+    for j in BW_FREE:
         th0[j] *= float(np.exp(rng.uniform(-np.log(1.3), np.log(1.3))))
     p0 = p_true.copy(theta=th0)
-    rc, th, hist = orc.bw_calibrate(p0, d, m, steps=800, lr=0.02, lr_final=1e-4, free_mask=mask)
+    rc, th, hist = orc.bw_calibrate(p0, d, m, steps=500, lr=0.05, lr_final=1e-3, free_mask=mask)
     assert rc == 0 and hist[-1] < 0.1 * hist[0]
-    err = max(abs(th[j] / p_true.theta[j] - 1) for j in free)
-    assert err < 0.03, (err, [(j, th[j] / p_true.theta[j]) for j in free])
-    # fixed slots did not move
-    assert all(th[j] == p0.theta[j] for j in range(24) if j not in free)
+    err = max(abs(th[j] / p_true.theta[j] - 1) for j in BW_FREE)
+    assert err < 0.005, (err, [(j, th[j] / p_true.theta[j]) for j in BW_FREE])
+    # held slots did not move
+    assert all(th[j] == p0.theta[j] for j in range(24) if j not in BW_FREE)
+
+
+@pytest.mark.slow
+def test_noisy_calibration_recovers_every_fitted_slot(orc):
+    """2^18 measurements over the calibration sweep, sigma = 0.02, 500 Adam
+    steps: every one of the 20 fitted slots within 3 %."""
+    p_true = synth.bw_param_set(7)
+    d = synth.bw_calibration_descriptors(1 << 18, 226)
+    T, _ = orc.bw_predict(p_true, d)
+    m = (T * synth.lognormal_noise(d.n, 227, 0.02)).astype(np.float32)
+    rng = np.random.default_rng(3)
+    th0 = list(p_true.theta)
+    for j in BW_FREE:
+        th0[j] *= float(np.exp(rng.uniform(-np.log(1.3), np.log(1.3))))
+    rc, th, hist = orc.bw_calibrate(p_true.copy(theta=th0), d, m, steps=500, lr=0.05, lr_final=1e-3,
+                                    free_mask=synth.BW_FIT_MASK)
+    err = {synth.BW_THETA_NAMES[j]: abs(th[j] / p_true.theta[j] - 1) for j in BW_FREE}
+    print("Blackwell recovery:", " ".join(f"{k}={v * 100:.2f}%" for k, v in err.items()))
+    assert rc == 0 and max(err.values()) < 0.03, err
+
+
+def test_held_slots_are_structurally_unidentifiable(orc):
+    """The three exact invariances of the model behind the held slots: every
+    predicted time is unchanged (to rounding) under
+      (a) BW_link -> c BW_link, eta_DE -> eta_DE / c  (Eq. (5) sees the product);
+      (b) eps -> c eps with every I/O rate times c and every I/O latency over c
+          (Eq. (7)'s exposed fraction multiplies all of T_io's raw terms);
+      (c) O_misc -> O_misc + t, L_mma -> L_mma - t f, L_TMA -> L_TMA - t f / eps
+          (one per-step constant per regime: Eq. (8)'s O_misc against Eq. (2)'s
+          L_mma when compute-bound and Eq. (4)'s L_TMA when I/O-bound)."""
+    p = synth.bw_param_set(7)
+    d = synth.bw_calibration_descriptors(1 << 14, 230)
+    T0, c0 = orc.bw_predict(p, d)
+    fin = np.isfinite(T0)
+    th = list(p.theta)
+    f = p.f_clk
+    c = 1.37
+    ta = list(th)
+    ta[13] *= c
+    ta[14] /= c
+    tb = list(th)
+    tb[17] *= c
+    for j in (10, 13, 15, 23):          # B_TMA, BW_link, R_decomp, BW_dsmem
+        tb[j] *= c
+    for j in (9, 16):                   # L_TMA, L_decomp_setup
+        tb[j] /= c
+    tc = list(th)
+    t = 0.25 * min(th[2] / f, th[17] * th[9] / f)
+    tc[21] += t
+    tc[2] -= t * f
+    tc[9] -= t * f / th[17]
+    for name, tv in (("a", ta), ("b", tb), ("c", tc)):
+        T1, c1 = orc.bw_predict(p.copy(theta=tv), d)
+        assert np.array_equal(c1, c0)
+        rel = np.abs(T1[fin] / T0[fin] - 1)
+        assert rel.max() < 1e-12, (name, rel.max())
+    # and the Jacobian's columns are linearly dependent along those directions
+    J = orc.bw_jacobian(p, d)[fin]
+    va = np.zeros(24)
+    va[13], va[14] = th[13], -th[14]
+    assert np.abs(J @ va).max() <= 1e-9 * np.abs(J).max() * max(th[13], 1.0)
+
+
+def _bw_se(orc, p, d, cols, sigma=0.02):
+    T, _ = orc.bw_predict(p, d)
+    ok = np.isfinite(T)
+    J = orc.bw_jacobian(p, d)[ok]
+    Jr = J[:, cols] * np.array([p.theta[j] for j in cols]) / T[ok][:, None]
+    return dict(zip(cols, np.sqrt(np.diag(np.linalg.inv(Jr.T @ Jr))) * sigma * np.sqrt(np.pi / 2)))
 
 
 def test_identifiability_of_the_fitted_slots(orc):
-    """Fisher information of the noisy least-squares problem at theta*
-    (sigma = 0.02, 2^16 descriptors): the slots fitted in the GPU recovery
-    test have standard errors below 0.5 %; the TMEM rates and O_misc are
-    only weakly identified by this sweep (their terms rarely dominate)."""
+    """Fisher information at theta* on the 2^18 calibration sweep (sigma =
+    0.02): all 20 fitted slots below 1 %, so the 3 % recovery bound is a
+    3-sigma statement.  Freeing the TMEM read rate as well leaves it above
+    3 %: apart from the accumulator traffic it shares with the write rate, it
+    only sees the strategy-B A-tile read."""
     p = synth.bw_param_set(7)
-    d = synth.bw_descriptors(1 << 16, 226)
-    T, _ = orc.bw_predict(p, d)
-    J = orc.bw_jacobian(p, d)
-    ok = np.isfinite(T)
-    cols = [0, 1, 3, 4, 5, 6, 7, 9, 10, 17, 18, 21, 22]
-    Jr = J[ok][:, cols] * np.array([p.theta[j] for j in cols]) / T[ok][:, None]
-    se = dict(zip(cols, np.sqrt(np.diag(np.linalg.inv(Jr.T @ Jr / 0.02 ** 2)))))
-    assert all(se[j] < 0.005 for j in (3, 4, 5, 6, 7, 9, 10, 17, 18, 22)), se
-    assert se[0] > 0.02 and se[1] > 0.02 and se[21] > 0.01
+    d = synth.bw_calibration_descriptors(1 << 18, 226)
+    se = _bw_se(orc, p, d, BW_FREE)
+    assert max(se.values()) < 0.01, se
+    se0 = _bw_se(orc, p, d, sorted(BW_FREE + [0]))
+    assert se0[0] > 0.03, se0
