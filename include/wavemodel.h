@@ -246,6 +246,23 @@ int32_t wm_loss_grad(const wm_desc_t *desc, const float *measured, const wm_para
                      double *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * The exact variants of wm_predict_vjp and wm_loss_grad: the same sums, but
+ * every descriptor is evaluated and differentiated in float64 (no float32
+ * stage, no near-switch redo).  The default calls form each descriptor's
+ * Jacobian row in float32 (relative rounding ~1e-7 per term); near a
+ * calibration optimum the signed terms of the loss gradient cancel to
+ * ~1e-6 of their absolute sum, so that rounding alone can reach ~1e-4 of a
+ * small slot's gradient.  These calls keep every slot to float64 rounding
+ * at about 1.4x the sweep time.  Same arguments, workspace
+ * (wm_workspace_bytes(WM_OP_VJP / WM_OP_LOSS_GRAD, n, 1, 0)) and status
+ * codes as the default calls.
+ */
+int32_t wm_predict_vjp_exact(const wm_desc_t *desc, const wm_params_t *params, const float *dL_dT,
+                             double *dL_dtheta, void *ws, size_t ws_bytes, void *stream);
+int32_t wm_loss_grad_exact(const wm_desc_t *desc, const float *measured, const wm_params_t *params,
+                           double *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * wm_loss_grad without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc).  Same arguments, results

@@ -941,7 +941,7 @@ int32_t wm_roofline(const wm_desc_t* desc, const wm_params_t* params, float* T, 
 }
 
 static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, const wm_params_t* params,
-                           double* out, void* ws, size_t ws_bytes, void* stream)
+                           double* out, void* ws, size_t ws_bytes, void* stream, bool exact = false)
 {
     if (!wm::grad_args_ok(desc, w, params, out)) return WM_EINVAL;
     const size_t need = wm_workspace_bytes(mode == 1 ? WM_OP_LOSS_GRAD : WM_OP_VJP, desc->n, 1, 0);
@@ -951,8 +951,12 @@ static int32_t grad_common(int mode, const wm_desc_t* desc, const float* w, cons
     char* base = (char*)ws;
     // n == 0 still writes zeros through the (empty) sweep and reduction
     const LaunchCfg cfg = launch_cfg(mode == 1 ? kOpLossGrad : kOpVjp, desc->n);
-    WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)(base + W.partials),
-                       (uint64_t*)(base + W.flags), W.g, cfg, out, (hipStream_t)stream));
+    if (exact)
+        WM_HIP(launch_grad_exact(mode, ptrs_of(desc), desc->n, w, S, (double*)(base + W.partials),
+                                 (uint64_t*)(base + W.flags), W.g, cfg.grid_mult, out, (hipStream_t)stream));
+    else
+        WM_HIP(launch_grad(mode, ptrs_of(desc), desc->n, w, S, nullptr, (double*)(base + W.partials),
+                           (uint64_t*)(base + W.flags), W.g, cfg, out, (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -966,6 +970,18 @@ int32_t wm_loss_grad(const wm_desc_t* desc, const float* measured, const wm_para
                      double* out, void* ws, size_t ws_bytes, void* stream)
 {
     return grad_common(1, desc, measured, params, out, ws, ws_bytes, stream);
+}
+
+int32_t wm_predict_vjp_exact(const wm_desc_t* desc, const wm_params_t* params, const float* dL_dT,
+                             double* dL_dtheta, void* ws, size_t ws_bytes, void* stream)
+{
+    return grad_common(0, desc, dL_dT, params, dL_dtheta, ws, ws_bytes, stream, true);
+}
+
+int32_t wm_loss_grad_exact(const wm_desc_t* desc, const float* measured, const wm_params_t* params,
+                           double* out, void* ws, size_t ws_bytes, void* stream)
+{
+    return grad_common(1, desc, measured, params, out, ws, ws_bytes, stream, true);
 }
 
 int32_t wm_predict_apps(const wm_desc_t* desc, const wm_segs_t* segs, const wm_params_t* params,

@@ -210,8 +210,10 @@ __device__ inline void grad_exact(const Set& S, const Desc<float>& x, float wi, 
 
 // Phase 1 sweep.  The loop runs over wave-aligned groups of 64 consecutive
 // descriptors so that every group's redo flags leave as one 64-bit ballot
-// word, written exactly once (no clearing needed, order fixed).
-template <int MODE, bool PTR, int BLOCK>
+// word, written exactly once (no clearing needed, order fixed).  X64: every
+// descriptor is evaluated and differentiated in float64 (the exact variant);
+// nothing is flagged, so the float64 pass only folds the partial rows.
+template <int MODE, bool PTR, int BLOCK, bool X64 = false>
 __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const float* __restrict__ wv,
                                                Set sv, const Set* __restrict__ sp,
                                                double* __restrict__ partials,
@@ -243,7 +245,10 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
             wn = ntload(wv + inext);
         }
         bool redo = false;
-        if (i < n) redo = grad_fast<MODE>(S, x, w, acc);
+        if (i < n) {
+            if (X64) grad_exact<MODE>(S, x, w, acc);
+            else redo = grad_fast<MODE>(S, x, w, acc);
+        }
         const uint64_t m = __ballot(redo);
         if (lane == 0) flags[base >> 6] = m;
     }
@@ -306,6 +311,34 @@ hipError_t launch_reduce(int mode, const double* partials, int rows, double* out
 {
     if (mode == 1) k_reduce<1><<<1, 256, 0, stream>>>(partials, rows, out);
     else k_reduce<0><<<1, 256, 0, stream>>>(partials, rows, out);
+    return hipGetLastError();
+}
+
+// The exact variant: float64 sweep (k_grad<MODE, false, 256, true>), the
+// row fold of the float64 pass (no flags are set), the fixed-order reduce.
+template <int MODE>
+static void launch_grad_exact_t(const DescPtrs& d, int64_t n, const float* w, const Set& S, double* partials,
+                                uint64_t* flags, const GradLayout& L, int grid_mult, double* out,
+                                hipStream_t stream)
+{
+    const int64_t want = (n + 255) / 256;
+    int64_t nb = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_grad<MODE, false, 256, true>), 256) *
+                 (grid_mult < 1 ? 1 : grid_mult);
+    nb = nb < want ? nb : want;
+    nb = nb < L.nb ? nb : L.nb;
+    nb = nb < 1 ? 1 : nb;
+    k_grad<MODE, false, 256, true><<<(int)nb, 256, 0, stream>>>(d, n, w, S, nullptr, partials, flags);
+    k_grad_redo<MODE, false><<<L.nb2, 256, 0, stream>>>(d, n, w, S, nullptr, flags, partials, (int)nb,
+                                                        partials + nb * kAcc);
+    if (out) k_reduce<MODE><<<1, 256, 0, stream>>>(partials + nb * kAcc, L.nb2, out);
+}
+
+hipError_t launch_grad_exact(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                             double* partials, uint64_t* flags, const GradLayout& L, int grid_mult,
+                             double* out, hipStream_t stream)
+{
+    if (mode == 1) launch_grad_exact_t<1>(d, n, w, S, partials, flags, L, grid_mult, out, stream);
+    else launch_grad_exact_t<0>(d, n, w, S, partials, flags, L, grid_mult, out, stream);
     return hipGetLastError();
 }
 

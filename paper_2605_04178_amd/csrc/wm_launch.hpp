@@ -124,6 +124,11 @@ hipError_t launch_roofline(const DescPtrs& d, int64_t n, const Set& S, float* T,
 hipError_t launch_grad(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
                        const Set* S_dev, double* partials, uint64_t* flags, const GradLayout& L,
                        const LaunchCfg& cfg, double* out, hipStream_t stream);
+// The exact variant of launch_grad: every descriptor evaluated and
+// differentiated in float64 (persistent grid of resident blocks x grid_mult).
+hipError_t launch_grad_exact(int mode, const DescPtrs& d, int64_t n, const float* w, const Set& S,
+                             double* partials, uint64_t* flags, const GradLayout& L, int grid_mult,
+                             double* out, hipStream_t stream);
 // Fixed-order reduction of `rows` partial rows of 26 doubles: mode 0 writes
 // the 24 gradient sums, mode 1 [loss, count, grad[24]] divided by the count.
 hipError_t launch_reduce(int mode, const double* partials, int rows, double* out, hipStream_t stream);

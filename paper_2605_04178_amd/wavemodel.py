@@ -33,7 +33,7 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion",
             "wm_bw_validate_params", "wm_bw_workspace_bytes", "wm_bw_predict", "wm_bw_predict_vjp",
             "wm_bw_loss_grad", "wm_bw_calibrate", "wm_predict_apps_vjp", "wm_loss_grad_noalloc",
-            "wm_noalloc_scratch_bytes")
+            "wm_noalloc_scratch_bytes", "wm_predict_vjp_exact", "wm_loss_grad_exact")
 BW_OP_GRAD, BW_OP_CALIBRATE = 0, 1
 
 
@@ -125,6 +125,10 @@ def lib():
         L.wm_predict_vjp.restype = i32
         L.wm_loss_grad.argtypes = [D, vp, P, vp, vp, sz, vp]
         L.wm_loss_grad.restype = i32
+        L.wm_predict_vjp_exact.argtypes = [D, P, vp, vp, vp, sz, vp]
+        L.wm_predict_vjp_exact.restype = i32
+        L.wm_loss_grad_exact.argtypes = [D, vp, P, vp, vp, sz, vp]
+        L.wm_loss_grad_exact.restype = i32
         L.wm_loss_grad_noalloc.argtypes = [D, vp, P, vp, vp]
         L.wm_loss_grad_noalloc.restype = i32
         L.wm_noalloc_scratch_bytes.argtypes = []
@@ -361,29 +365,34 @@ def roofline(desc: DeviceDescriptors, params, stream=None):
     return T
 
 
-def vjp(desc: DeviceDescriptors, params, dL_dT: torch.Tensor, ws=None, theta=None, stream=None):
-    """dL/dtheta (float64 [24], device) for an upstream gradient dL/dT."""
+def vjp(desc: DeviceDescriptors, params, dL_dT: torch.Tensor, ws=None, theta=None, stream=None,
+        exact=False):
+    """dL/dtheta (float64 [24], device) for an upstream gradient dL/dT;
+    exact=True calls wm_predict_vjp_exact (float64 throughout the sweep)."""
     out = torch.empty(N_THETA, dtype=torch.float64, device=desc.device)
     if ws is None:
         ws = _workspace(workspace_bytes(OP_VJP, desc.n), desc.device)
     nb = 0 if ws is None else ws.numel()
-    rc = lib().wm_predict_vjp(C.byref(desc.struct()), C.byref(params_struct(params, theta)),
-                              _ptr(dL_dT.contiguous()), _ptr(out), _ptr(ws), nb, _stream(stream))
-    _check(rc, "wm_predict_vjp")
+    fn = lib().wm_predict_vjp_exact if exact else lib().wm_predict_vjp
+    rc = fn(C.byref(desc.struct()), C.byref(params_struct(params, theta)),
+            _ptr(dL_dT.contiguous()), _ptr(out), _ptr(ws), nb, _stream(stream))
+    _check(rc, "wm_predict_vjp_exact" if exact else "wm_predict_vjp")
     return out
 
 
 def loss_grad(desc: DeviceDescriptors, measured: torch.Tensor, params, ws=None, theta=None,
-              out=None, stream=None):
-    """[loss, count, grad[24]] float64 on the device (mean relative error)."""
+              out=None, stream=None, exact=False):
+    """[loss, count, grad[24]] float64 on the device (mean relative error);
+    exact=True calls wm_loss_grad_exact (float64 throughout the sweep)."""
     if out is None:
         out = torch.empty(26, dtype=torch.float64, device=desc.device)
     if ws is None:
         ws = _workspace(workspace_bytes(OP_LOSS_GRAD, desc.n), desc.device)
     nb = 0 if ws is None else ws.numel()
-    rc = lib().wm_loss_grad(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(params, theta)),
-                            _ptr(out), _ptr(ws), nb, _stream(stream))
-    _check(rc, "wm_loss_grad")
+    fn = lib().wm_loss_grad_exact if exact else lib().wm_loss_grad
+    rc = fn(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(params, theta)),
+            _ptr(out), _ptr(ws), nb, _stream(stream))
+    _check(rc, "wm_loss_grad_exact" if exact else "wm_loss_grad")
     return out
 
 

@@ -151,6 +151,9 @@ def test_argument_errors_before_any_hip_call(wmb):
     assert L.wm_loss_grad(C.byref(d), w, C.byref(p), out, C.c_void_p(0x10008), need, None) == wmb.WM_EWORKSPACE
     assert L.wm_loss_grad(C.byref(d), None, C.byref(p), out, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
     assert L.wm_predict_vjp(C.byref(d), C.byref(p), w, None, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    assert L.wm_loss_grad_exact(C.byref(d), w, C.byref(p), out, C.c_void_p(0x10000), 8, None) == wmb.WM_EWORKSPACE
+    assert L.wm_loss_grad_exact(C.byref(d), None, C.byref(p), out, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
+    assert L.wm_predict_vjp_exact(C.byref(d), C.byref(p), w, None, C.c_void_p(0x10000), need, None) == wmb.WM_EINVAL
     # tile selection
     sh = wmb.WmShapes(0x100, 0x200, 0x300, 0x400, 4)
     assert L.wm_select_tile(C.byref(sh), None, None, 0, C.byref(p), out, out, out, None) == wmb.WM_EINVAL

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2605_04178_amd import synth
-from gpu_common import check_grad, need_gpu, rel_err, say, slot_errors
+from gpu_common import check_grad, loss_grad_absum, need_gpu, rel_err, say, slot_errors
 
 pytestmark = pytest.mark.gpu
 GTOL = 1e-4
@@ -58,7 +58,11 @@ def test_loss_grad_parity_near_optimum(wmb, orc):
         assert int(out[1]) == cnt
         assert abs(out[0] - loss) <= 1e-5 * loss
         check_grad(out[2:], g, p.theta, f"loss gradient near the optimum, factor {f} on slots {k} mod 3",
-                   GTOL, names=synth.THETA_NAMES)
+                   GTOL, names=synth.THETA_NAMES, absum=loss_grad_absum(orc, p, d, m))
+        ex = wmb.loss_grad(dd, mt, p, exact=True).cpu().numpy()
+        assert int(ex[1]) == cnt and abs(ex[0] - loss) <= 1e-12 * loss
+        check_grad(ex[2:], g, p.theta, f"exact loss gradient near the optimum, factor {f}", GTOL,
+                   names=synth.THETA_NAMES)
 
 
 def test_loss_grad_exact_measurements(wmb, orc):
@@ -152,3 +156,26 @@ def test_loss_grad_workspace_reuse_and_determinism(wmb, orc):
     a = wmb.loss_grad(dd, mt, ps, ws=ws)
     b = wmb.loss_grad(dd, mt, ps, ws=ws)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L,combine", [(4, 0), (3, 1)])
+def test_exact_variants_match_the_oracle_slot_by_slot(wmb, orc, L, combine):
+    """wm_predict_vjp_exact and wm_loss_grad_exact (float64 throughout the
+    sweep) against the oracle, per slot in log space, at theta0 and at the
+    true parameters (where the loss gradient is a cancelled sum)."""
+    n = 1 << 18
+    ps = synth.param_set(1, n_levels=L, combine=combine)
+    d = synth.calibration_descriptors(n, 110)
+    m = _measured(orc, ps, d)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    for tag, p in (("theta0", synth.perturb_theta(ps, 3)), ("theta*", ps)):
+        out = wmb.loss_grad(dd, mt, p, exact=True).cpu().numpy()
+        loss, cnt, g = orc.loss_grad(p, d, m)
+        assert int(out[1]) == cnt and abs(out[0] - loss) <= 1e-12 * loss
+        check_grad(out[2:], g, p.theta, f"exact loss gradient at {tag}, L={L} combine={combine}", 1e-9,
+                   names=synth.THETA_NAMES)
+    w = np.random.default_rng(5).standard_normal(n).astype(np.float32)
+    gv = wmb.vjp(dd, ps, torch.from_numpy(w).cuda(), exact=True).cpu().numpy()
+    check_grad(gv, orc.vjp(ps, d, w), ps.theta, f"exact vjp, L={L} combine={combine}", 1e-9,
+               names=synth.THETA_NAMES)
