@@ -132,9 +132,12 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
 
     // residency: accumulator bytes (8 per element for FP64, else 4); TMEM is
     // below 2^30 bytes, so once the accumulator fits every quotient is a
-    // 32-bit one (n_sm * cta <= 2^22, G < 2^31)
-    const int64_t acc = (int64_t)d.bM * (int64_t)d.bN * (dt == 0 ? 8 : 4);
-    uint32_t cta = acc > st.tmem_bytes ? 0u : (uint32_t)st.tmem_bytes / (uint32_t)acc;
+    // 32-bit one (n_sm * cta <= 2^22, G < 2^31).  An extent above the TMEM
+    // size cannot fit; otherwise both are below 2^30 and the product, at
+    // most 2^63, is exact in 64 unsigned bits.
+    const bool too_wide = (uint32_t)d.bM > (uint32_t)st.tmem_bytes || (uint32_t)d.bN > (uint32_t)st.tmem_bytes;
+    const uint64_t acc = too_wide ? ~(uint64_t)0 : (uint64_t)d.bM * (uint64_t)d.bN * (dt == 0 ? 8u : 4u);
+    uint32_t cta = acc > (uint64_t)st.tmem_bytes ? 0u : (uint32_t)st.tmem_bytes / (uint32_t)acc;
     cta = cta < (uint32_t)st.max_cta ? cta : (uint32_t)st.max_cta;
     E.cta = (int32_t)cta;
     if (cta < 1) {

@@ -56,6 +56,32 @@ def test_bw_forward_edge_cases(wmb, orc):
     assert all(np.isnan(T[i]) and cta[i] == -1 for i in range(1, 7))
 
 
+def test_bw_tile_extents_at_the_int32_limit(wmb, orc):
+    """Tile extents up to 2^31 - 1: accumulators that cannot fit in TMEM are
+    infeasible (+inf, 0 CTAs) on both sides, for FP64 and narrower types,
+    including products of the extents beyond 2^63; the largest tiles that
+    still fit stay finite and match."""
+    p = synth.b200_like().copy(max_cta=2)
+    d = synth.bw_descriptors(12, 232)
+    big = 2 ** 31 - 1
+    F = synth.pack_bw_flags
+    rows = [(big, big, 0), (big, big, 2), (big, 1, 2), (1, big, 0), (65536, 65536, 2), (1 << 20, 1 << 20, 3),
+            (2 ** 30, 1, 2), (256, 256, 2), (256, 256, 0), (256, 128, 0), (1, 65536, 2), (1, 32768, 0)]
+    for i, (bm, bn, dt) in enumerate(rows):
+        d.bM[i], d.bN[i] = bm, bn
+        d.flags[i] = F(dt, 0, 0, 1, 1, 1, 0)
+        d.bK[i] = 16
+    T, cta = wmb.bw_predict(wmb.DeviceBwDescriptors.from_host(d), p)
+    To, co = orc.bw_predict(p, d)
+    cta, T = cta.cpu().numpy(), T.cpu().numpy()
+    say("int32-limit tiles: CTAs", cta, "oracle", co)
+    assert np.array_equal(cta, co)
+    fits = np.array([0, 0, 0, 0, 0, 0, 0, 1, 0, 1, 1, 1], bool)   # 256 x 256 x 8 B = 2 x TMEM does not
+    assert np.all(cta[~fits] == 0) and np.all(np.isinf(T[~fits]))
+    assert np.all(cta[fits] >= 1) and np.all(np.isfinite(T[fits]))
+    assert rel_err(T, To).max() <= 1e-5
+
+
 @pytest.mark.parametrize("seed", [3, 4])
 def test_bw_vjp_and_loss_grad_parity(wmb, orc, seed):
     p = synth.bw_param_set(seed)
