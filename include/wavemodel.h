@@ -302,6 +302,18 @@ int32_t wm_select_tile(const wm_shapes_t *shapes, const int32_t *cand_off,
                        int32_t *best, double *best_cost, uint8_t *near_tie, void *stream);
 
 /*
+ * The float32 cost of every candidate, as the first pass of wm_select_tile
+ * computes it (same tile derivation and model evaluation; Section IV-B,
+ * adaptive tile selection): cost [n_cand] float32, +inf for an invalid code
+ * or an infeasible tile.  Shapes and CSR lists as for wm_select_tile; a
+ * candidate outside every shape's (clamped) list is not written.  For
+ * ranking tiles, and for bounding the float32 error that the selection's
+ * float64 window must cover.
+ */
+int32_t wm_tile_costs(const wm_shapes_t *shapes, const int32_t *cand_off, const uint32_t *cand_code,
+                      int64_t n_cand, const wm_params_t *params, float *cost, void *stream);
+
+/*
  * Calibration (Section IV-D): fit the free slots of theta to measured times
  * by Adam on log(theta) over the mean relative error (wm_loss_grad), all on
  * the device; the step loop is captured once as a HIP graph and replayed.
@@ -314,6 +326,39 @@ int32_t wm_select_tile(const wm_shapes_t *shapes, const int32_t *cand_off,
 int32_t wm_calibrate(const wm_desc_t *desc, const float *measured, const wm_params_t *p0,
                      const wm_calib_opts_t *opts, wm_params_t *p_out, double *loss_hist,
                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Calibration state, for checkpointing a calibration and resuming it: the
+ * Adam iterate on log(theta) (Section IV-D's calibration) in plain doubles,
+ * to be saved and restored by the caller as it is.
+ */
+typedef struct {
+    double theta[WM_N_THETA];     /* current parameters */
+    double theta_ok[WM_N_THETA];  /* parameters after the last step with a finite loss */
+    double phi[WM_N_THETA];       /* log(theta) of the fitted slots, 0 for the others */
+    double m[WM_N_THETA];         /* Adam first moments */
+    double v[WM_N_THETA];         /* Adam second moments */
+    int32_t step;                 /* steps taken (index of the next step) */
+    int32_t diverged;             /* 1 once the loss became non-finite */
+} wm_calib_state_t;
+
+/*
+ * wm_calibrate in pieces: run `run_steps` steps of the schedule that
+ * opts->steps defines (the learning rate decays over opts->steps steps),
+ * starting from state_in (host; NULL = a fresh start from p0's theta, with
+ * zero moments) and write the state after the last step to state_out (host,
+ * may be NULL).  Requires state_in->step + run_steps <= opts->steps; with a
+ * state, p0 supplies the structure and the state the parameters (a
+ * diverged state is rejected with WM_EINVAL).  A calibration split into calls with the state carried over (or saved and
+ * restored) gives the same parameters and loss history, bit for bit, as one
+ * call.  loss_hist (host, [run_steps], may be NULL): the losses of these
+ * steps.  p_out, status and synchronisation as for wm_calibrate.
+ * Workspace: wm_workspace_bytes(WM_OP_CALIBRATE, n, 1, opts->steps).
+ */
+int32_t wm_calibrate_resume(const wm_desc_t *desc, const float *measured, const wm_params_t *p0,
+                            const wm_calib_opts_t *opts, const wm_calib_state_t *state_in,
+                            int32_t run_steps, wm_calib_state_t *state_out, wm_params_t *p_out,
+                            double *loss_hist, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Several calibration problems (one parameter set and one descriptor set

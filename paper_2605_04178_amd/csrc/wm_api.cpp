@@ -1062,13 +1062,55 @@ int32_t wm_select_tile(const wm_shapes_t* shapes, const int32_t* cand_off,
     return WM_OK;
 }
 
-int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_params_t* p0,
-                     const wm_calib_opts_t* opts, wm_params_t* p_out, double* loss_hist, void* ws,
-                     size_t ws_bytes, void* stream)
+int32_t wm_tile_costs(const wm_shapes_t* shapes, const int32_t* cand_off, const uint32_t* cand_code,
+                      int64_t n_cand, const wm_params_t* params, float* cost, void* stream)
+{
+    if (!shapes || shapes->n < 0 || !params_ok(params) || n_cand < 0) return WM_EINVAL;
+    if (shapes->n == 0) return WM_OK;
+    if (!shapes->M || !shapes->N || !shapes->K || !shapes->dtype || !cand_off) return WM_EINVAL;
+    if (n_cand > 0 && (!cand_code || !cost)) return WM_EINVAL;
+    if (n_cand > 0x7fffffffll) return WM_EINVAL;
+    ShapePtrs sp;
+    sp.M = shapes->M;
+    sp.N = shapes->N;
+    sp.K = shapes->K;
+    sp.dtype = shapes->dtype;
+    const Set S = make_set(params);
+    WM_HIP(launch_tile_costs(sp, cand_off, cand_code, shapes->n, n_cand, S, cost, (hipStream_t)stream));
+    return WM_OK;
+}
+
+int32_t wm_calibrate_resume(const wm_desc_t* desc, const float* measured, const wm_params_t* p0,
+                            const wm_calib_opts_t* opts, const wm_calib_state_t* state_in, int32_t run,
+                            wm_calib_state_t* state_out, wm_params_t* p_out, double* loss_hist, void* ws,
+                            size_t ws_bytes, void* stream)
 {
     if (!desc_ok(desc) || (desc->n > 0 && !measured) || !params_ok(p0) || !opts_ok(opts) || !p_out)
         return WM_EINVAL;
-    if (!free_slots_ok(p0, opts->free_mask)) return WM_EINVAL;
+    if (run < 1) return WM_EINVAL;
+    wm_params_t pc = *p0;
+    CalibState st0;
+    if (state_in) {
+        // the state's parameters must form a valid set with p0's structure
+        if (state_in->step < 0 || state_in->step > opts->steps - run) return WM_EINVAL;
+        if (state_in->diverged != 0) return WM_EINVAL;   // nothing to resume
+        for (int j = 0; j < WM_N_THETA; ++j) pc.theta[j] = state_in->theta[j];
+        if (!params_ok(&pc)) return WM_EINVAL;
+        std::memset(&st0, 0, sizeof(st0));
+        for (int j = 0; j < WM_N_THETA; ++j) {
+            st0.theta[j] = state_in->theta[j];
+            st0.theta_ok[j] = state_in->theta_ok[j];
+            st0.phi[j] = state_in->phi[j];
+            st0.m[j] = state_in->m[j];
+            st0.v[j] = state_in->v[j];
+        }
+        st0.t = state_in->step;
+        st0.diverged = state_in->diverged;
+    } else {
+        if (run > opts->steps) return WM_EINVAL;
+        st0 = init_state(p0, opts->free_mask);
+    }
+    if (!free_slots_ok(&pc, opts->free_mask)) return WM_EINVAL;
     const CalibLayout L = calib_layout(desc->n, opts->steps);
     if (!ws_ok(ws, ws_bytes, L.total)) return WM_EWORKSPACE;
     hipStream_t s = nullptr;
@@ -1081,8 +1123,7 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
     double* hist_dev = (double*)(base + L.hist);
     double* part_dev = (double*)(base + L.grad + L.g.partials);
     uint64_t* flags_dev = (uint64_t*)(base + L.grad + L.g.flags);
-    const Set S = make_set(p0);
-    const CalibState st0 = init_state(p0, opts->free_mask);
+    const Set S = make_set(&pc);
     const AdamOpts ao = adam_of(opts);
     WM_HIP(hipMemcpyAsync(S_dev, &S, sizeof(S), hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(st_dev, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
@@ -1100,19 +1141,38 @@ int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_para
         if (e != hipSuccess) return e;
         return launch_adam(rows2_dev, G.nb2, st_dev, ao, S_dev, hist_dev, s);
     };
-    rc = run_steps(s, opts->steps, step);
+    rc = run_steps(s, run, step);
     if (rc != WM_OK) return rc;
 
     CalibState st;
     WM_HIP(hipMemcpyAsync(&st, st_dev, sizeof(st), hipMemcpyDeviceToHost, s));
-    std::vector<double> hist((size_t)opts->steps);
-    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev, sizeof(double) * opts->steps,
-                          hipMemcpyDeviceToHost, s));
+    std::vector<double> hist((size_t)run);
+    WM_HIP(hipMemcpyAsync(hist.data(), hist_dev + st0.t, sizeof(double) * run, hipMemcpyDeviceToHost, s));
     WM_HIP(hipStreamSynchronize(s));
-    *p_out = *p0;
+    *p_out = pc;
     for (int j = 0; j < WM_N_THETA; ++j) p_out->theta[j] = st.diverged ? st.theta_ok[j] : st.theta[j];
-    if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * opts->steps);
+    if (loss_hist) std::memcpy(loss_hist, hist.data(), sizeof(double) * run);
+    if (state_out) {
+        for (int j = 0; j < WM_N_THETA; ++j) {
+            state_out->theta[j] = st.theta[j];
+            state_out->theta_ok[j] = st.theta_ok[j];
+            state_out->phi[j] = st.phi[j];
+            state_out->m[j] = st.m[j];
+            state_out->v[j] = st.v[j];
+        }
+        state_out->step = st.t;
+        state_out->diverged = st.diverged;
+    }
     return st.diverged ? WM_EDIVERGED : WM_OK;
+}
+
+int32_t wm_calibrate(const wm_desc_t* desc, const float* measured, const wm_params_t* p0,
+                     const wm_calib_opts_t* opts, wm_params_t* p_out, double* loss_hist, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    if (!opts_ok(opts)) return WM_EINVAL;
+    return wm_calibrate_resume(desc, measured, p0, opts, nullptr, opts->steps, nullptr, p_out, loss_hist, ws,
+                               ws_bytes, stream);
 }
 
 int32_t wm_calibrate_batched(int32_t n_sets, const wm_desc_t* sets, const float* const* measured,

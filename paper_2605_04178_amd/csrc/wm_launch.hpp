@@ -176,6 +176,9 @@ hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, 
                            double* app_rows, double* partials, uint64_t* flags, const GradLayout& L,
                            const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
                            hipStream_t stream);
+// every candidate's float32 cost, as the selection's first pass computes it
+hipError_t launch_tile_costs(const ShapePtrs& sh, const int32_t* off, const uint32_t* code, int64_t n,
+                             int64_t n_cand, const Set& S, float* cost, hipStream_t stream);
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
                               double* best_cost, uint8_t* near_tie, const LaunchCfg& cfg,

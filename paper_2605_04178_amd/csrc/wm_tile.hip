@@ -426,6 +426,33 @@ static void select_t(const ShapePtrs& sh, const int32_t* off, const uint32_t* co
                                                                      best_cost, near_tie);
 }
 
+// Every candidate's float32 cost (the selection's first pass): a wave per
+// shape, its lanes over the shape's list; grid-stride over shapes.
+__global__ __launch_bounds__(256) void k_tile_costs(ShapePtrs sh, const int32_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ code, int64_t n,
+                                                     int64_t n_cand, Set S, float* __restrict__ cost)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += nw) {
+        int64_t a = off[i], b = off[i + 1];
+        clamp_list(n_cand, a, b);
+        const int32_t M = sh.M[i], N = sh.N[i], K = sh.K[i], t = sh.dtype[i];
+        for (int64_t j = a + lane; j < b; j += 64) cost[j] = tile_cost<float>(S, M, N, K, t, code[j]);
+    }
+}
+
+hipError_t launch_tile_costs(const ShapePtrs& sh, const int32_t* off, const uint32_t* code, int64_t n,
+                             int64_t n_cand, const Set& S, float* cost, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 3) / 4;
+    const int64_t cap = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_tile_costs), 256) * 4;
+    const int64_t b = want < cap ? want : cap;
+    k_tile_costs<<<(int)(b < 1 ? 1 : b), 256, 0, stream>>>(sh, off, code, n, n_cand, S, cost);
+    return hipGetLastError();
+}
+
 hipError_t launch_select_tile(const ShapePtrs& sh, const int32_t* off, const uint32_t* code,
                               int64_t n, int64_t n_cand, const Set& S, int32_t* best,
                               double* best_cost, uint8_t* near_tie, const LaunchCfg& c,

@@ -33,7 +33,8 @@ EXPORTED = ("wm_strerror", "wm_last_hip_error", "wm_validate_params", "wm_worksp
             "wm_autotune_apps", "wm_fit_multipliers", "wm_plan_workspace_bytes", "wm_plan_fusion",
             "wm_bw_validate_params", "wm_bw_workspace_bytes", "wm_bw_predict", "wm_bw_predict_vjp",
             "wm_bw_loss_grad", "wm_bw_calibrate", "wm_predict_apps_vjp", "wm_loss_grad_noalloc",
-            "wm_noalloc_scratch_bytes", "wm_predict_vjp_exact", "wm_loss_grad_exact")
+            "wm_noalloc_scratch_bytes", "wm_predict_vjp_exact", "wm_loss_grad_exact", "wm_tile_costs",
+            "wm_calibrate_resume")
 BW_OP_GRAD, BW_OP_CALIBRATE = 0, 1
 
 
@@ -90,6 +91,11 @@ class WmBwDesc(C.Structure):
         ("n", C.c_int64)]
 
 
+class WmCalibState(C.Structure):
+    _fields_ = [(n, C.c_double * N_THETA) for n in ("theta", "theta_ok", "phi", "m", "v")] + [
+        ("step", C.c_int32), ("diverged", C.c_int32)]
+
+
 class WmCalibOpts(C.Structure):
     _fields_ = [("steps", C.c_int32), ("reserved", C.c_int32)] + [
         (n, C.c_double) for n in ("lr", "lr_final", "beta1", "beta2", "eps")] + [
@@ -134,9 +140,14 @@ def lib():
         L.wm_noalloc_scratch_bytes.argtypes = []
         L.wm_noalloc_scratch_bytes.restype = sz
         L.wm_select_tile.argtypes = [C.POINTER(WmShapes), vp, vp, i64, P, vp, vp, vp, vp]
+        L.wm_tile_costs.argtypes = [C.POINTER(WmShapes), vp, vp, i64, P, vp, vp]
+        L.wm_tile_costs.restype = i32
         L.wm_select_tile.restype = i32
         L.wm_calibrate.argtypes = [D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
         L.wm_calibrate.restype = i32
+        L.wm_calibrate_resume.argtypes = [D, vp, P, C.POINTER(WmCalibOpts), C.POINTER(WmCalibState), i32,
+                                          C.POINTER(WmCalibState), P, vp, vp, sz, vp]
+        L.wm_calibrate_resume.restype = i32
         L.wm_calibrate_batched.argtypes = [i32, D, vp, P, C.POINTER(WmCalibOpts), P, vp, vp, sz, vp]
         L.wm_calibrate_batched.restype = i32
         LP = C.POINTER(WmLaunch)
@@ -423,6 +434,19 @@ def select_tile(shapes: DeviceShapes, params, out=None, stream=None):
     return best, cost, tie
 
 
+def tile_costs(shapes: DeviceShapes, params, out=None, stream=None):
+    """Every candidate's float32 cost (float32 [n_cand], +inf if infeasible)."""
+    nc = int(shapes.cand_code.numel())
+    if out is None:
+        out = torch.empty(nc, dtype=torch.float32, device=shapes.device)
+    s = WmShapes(shapes.M.data_ptr(), shapes.N.data_ptr(), shapes.K.data_ptr(),
+                 shapes.dtype.data_ptr(), shapes.n)
+    rc = lib().wm_tile_costs(C.byref(s), _ptr(shapes.cand_off), _ptr(shapes.cand_code), nc,
+                             C.byref(params_struct(params)), _ptr(out), _stream(stream))
+    _check(rc, "wm_tile_costs")
+    return out
+
+
 def apps_workspace_bytes(n: int, n_apps: int) -> int:
     return int(lib().wm_apps_workspace_bytes(n, n_apps))
 
@@ -674,6 +698,42 @@ def calibrate(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps=500, lr
     if rc not in (WM_OK, WM_EDIVERGED) or (raise_on_diverged and rc != WM_OK):
         raise WmError(rc, "wm_calibrate")
     return rc, theta_of(pout), hist
+
+
+def calibrate_resume(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps, run_steps, state=None,
+                     lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None,
+                     stream=None):
+    """Run `run_steps` steps of a `steps`-step calibration from `state` (a
+    WmCalibState; None = fresh start from p0).  Returns (status, theta, loss
+    history of these steps, state after them)."""
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+    if ws is None:
+        ws = _workspace(workspace_bytes(OP_CALIBRATE, desc.n, 1, steps), desc.device)
+    pout = WmParams()
+    hist = np.zeros(run_steps)
+    out = WmCalibState()
+    rc = lib().wm_calibrate_resume(C.byref(desc.struct()), _ptr(measured), C.byref(params_struct(p0)),
+                                   C.byref(opts), None if state is None else C.byref(state), int(run_steps),
+                                   C.byref(out), C.byref(pout), hist.ctypes.data, _ptr(ws), ws.numel(),
+                                   _stream(stream))
+    if rc not in (WM_OK, WM_EDIVERGED):
+        raise WmError(rc, "wm_calibrate_resume")
+    return rc, theta_of(pout), hist, out
+
+
+def save_calib_state(path, state: WmCalibState):
+    """Write a calibration state to an .npz file (exact doubles, no pickling)."""
+    np.savez(path, **{f: np.array(getattr(state, f)) for f in ("theta", "theta_ok", "phi", "m", "v")},
+             step=np.int32(state.step), diverged=np.int32(state.diverged))
+
+
+def load_calib_state(path) -> WmCalibState:
+    z = np.load(path, allow_pickle=False)
+    st = WmCalibState()
+    for f in ("theta", "theta_ok", "phi", "m", "v"):
+        getattr(st, f)[:] = [float(x) for x in z[f]]
+    st.step, st.diverged = int(z["step"]), int(z["diverged"])
+    return st
 
 
 def calibrate_batched(descs: List[DeviceDescriptors], measured: List[torch.Tensor], p0s, opts_list,

@@ -374,3 +374,38 @@ def test_noalloc_loss_grad_rejects_bad_arguments_and_sizes_before_any_hip_call(w
     assert L.wm_noalloc_scratch_bytes() >= wmb.workspace_bytes(wmb.OP_LOSS_GRAD, wmb.NOALLOC_MAX_N)
     assert L.wm_noalloc_scratch_bytes() < 16 << 20
     assert L.wm_strerror(wmb.WM_ETOOLARGE).decode() == "input larger than the fixed scratch allows"
+
+
+def test_calibrate_resume_rejects_bad_states_before_any_hip_call(wmb):
+    L = wmb.lib()
+    p = wmb.params_struct(synth.param_set(0))
+    d = _fake_desc(wmb, 64)
+    w = C.c_void_p(0x30000)
+    o = wmb.calib_opts(steps=100, free_mask=synth.FIT_MASK_L4)
+    pout = wmb.WmParams()
+    st = wmb.WmCalibState()
+    for j in range(24):
+        st.theta[j] = synth.param_set(0).theta[j]
+        st.theta_ok[j] = st.theta[j]
+    ws = C.c_void_p(0x10000)
+    call = lambda state, run: L.wm_calibrate_resume(C.byref(d), w, C.byref(p), C.byref(o), state, run, None,
+                                                    C.byref(pout), None, ws, 1 << 40, None)
+    assert call(None, 0) == wmb.WM_EINVAL              # no steps
+    assert call(None, 101) == wmb.WM_EINVAL            # past the schedule
+    st.step = 90
+    assert call(C.byref(st), 11) == wmb.WM_EINVAL      # 90 + 11 > 100
+    st.step = -1
+    assert call(C.byref(st), 1) == wmb.WM_EINVAL
+    st.step = 10
+    st.diverged = 1
+    assert call(C.byref(st), 1) == wmb.WM_EINVAL       # a diverged state
+    st.diverged = 0
+    st.theta[0] = float("nan")
+    assert call(C.byref(st), 1) == wmb.WM_EINVAL       # parameters that are not a valid set
+    st.theta[0] = synth.param_set(0).theta[0]
+    st.theta[13] = 0.0
+    assert call(C.byref(st), 1) == wmb.WM_EINVAL       # a fitted slot must stay positive
+    # a valid state with a workspace that is too small stops at the workspace check
+    st.theta[13] = synth.param_set(0).theta[13]
+    assert L.wm_calibrate_resume(C.byref(d), w, C.byref(p), C.byref(o), C.byref(st), 5, None, C.byref(pout),
+                                 None, ws, 8, None) == wmb.WM_EWORKSPACE

@@ -231,3 +231,32 @@ def test_batched_sixteen_ragged_sets_match_per_set(wmb, orc):
     finally:
         wmb.set_launch(wmb.OP_CALIBRATE_BATCHED, ntot, default["block"], default["per_thread"],
                        default["grid_mult"], default["chunk"])
+
+
+def test_calibration_resumes_bit_identically_from_a_checkpoint(wmb, orc, tmp_path):
+    """A 120-step calibration run as 45 steps, a checkpoint written to disk
+    and read back, then 75 more steps (and as 30 + 30 + 60 with the state
+    carried in memory) gives the parameters and loss history of one call,
+    bit for bit."""
+    n = 1 << 16
+    ps, d, m, p0 = _problem(orc, n)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    rc, th, hist = wmb.calibrate(dd, mt, p0, steps=120, free_mask=MASK_L4)
+    assert rc == wmb.WM_OK
+    rc1, th1, h1, st1 = wmb.calibrate_resume(dd, mt, p0, 120, 45, free_mask=MASK_L4)
+    assert rc1 == wmb.WM_OK and st1.step == 45 and st1.diverged == 0
+    path = tmp_path / "calib_checkpoint.npz"
+    wmb.save_calib_state(path, st1)
+    st = wmb.load_calib_state(path)
+    assert st.step == 45 and list(st.m) == list(st1.m) and list(st.theta) == list(st1.theta)
+    rc2, th2, h2, st2 = wmb.calibrate_resume(dd, mt, p0, 120, 75, state=st, free_mask=MASK_L4)
+    assert rc2 == wmb.WM_OK and st2.step == 120
+    assert np.array_equal(th2, th)
+    assert np.array_equal(np.concatenate([h1, h2]), hist)
+    pieces, state = [], None
+    for k in (30, 30, 60):
+        _, thk, hk, state = wmb.calibrate_resume(dd, mt, p0, 120, k, state=state, free_mask=MASK_L4)
+        pieces.append(hk)
+    assert np.array_equal(thk, th) and np.array_equal(np.concatenate(pieces), hist)
+    say("resume: 45 + 75 and 30 + 30 + 60 steps equal one 120-step call bit for bit")

@@ -170,3 +170,25 @@ def test_select_tile_graph_replay(wmb, orc):
         for a, b in zip(out, eager):
             assert torch.equal(a, b), r
         _ = torch.randn(1000, device="cuda").sum().item()   # eager work between replays
+
+
+@pytest.mark.parametrize("pset", ["seed0", "seed1", "L3", "mi300a_like"])
+def test_float32_cost_error_is_inside_the_window(wmb, orc, pset):
+    """The selection re-evaluates in float64 every candidate within delta =
+    3e-5 of the float32 minimum; that is sound if delta >= 4 x the float32
+    cost error.  Every candidate of the 2^16-shape sweep (about 3.4 million)
+    through wm_tile_costs (the selection's own first pass) against the
+    oracle's float64 costs: infeasibility identical, largest relative error
+    at most delta / 4."""
+    p = {"seed0": synth.param_set(0), "seed1": synth.param_set(1), "L3": synth.param_set(2, n_levels=3),
+         "mi300a_like": synth.mi300a_like()}[pset]
+    sh = synth.shapes(1 << 16, 102)
+    c32 = wmb.tile_costs(wmb.DeviceShapes.from_host(sh), p).cpu().numpy().astype(np.float64)
+    c64 = orc.tile_costs(p, sh)
+    fin = np.isfinite(c64)
+    assert np.array_equal(np.isfinite(c32), fin)
+    assert np.all(np.isposinf(c32[~fin]))
+    err = np.abs(c32[fin] / c64[fin] - 1.0)
+    say(f"tile costs ({pset}): {int(fin.sum())} feasible of {c64.size}, float32 error max {err.max():.2e}, "
+        f"99.9th percentile {np.quantile(err, 0.999):.2e}; window 3e-5 / 4 = 7.5e-6")
+    assert 4.0 * err.max() <= 3e-5
