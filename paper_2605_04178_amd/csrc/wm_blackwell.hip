@@ -54,23 +54,28 @@ __device__ inline bool bw_weight(R T, float wi, double& w, double& lt)
     return true;
 }
 
+// float32 pass: the descriptor's terms go into the lane's float32 partial
+// sums unless it sits within 1e-5 of the compute / I-O switch or (mode 1) of
+// T = m (returns true: left to the float64 pass)
 template <int MODE>
-__device__ inline bool bw_grad_fast(const BwSet& S, const BwDesc& x, float wi, double* acc)
+__device__ inline bool bw_grad_fast(const BwSet& S, const BwDesc& x, float wi, float* acc)
 {
     BwEval<float> E;
     evaluate_bw<float, true>(S.st, S.cf, x, E);
     if (!(E.T < __builtin_huge_valf())) return false;
-    bool redo = E.near_kink;
-    if (MODE == 1 && wi > 0.0f && wi < __builtin_huge_valf())
-        redo = redo || (__builtin_fabsf(E.T * __builtin_amdgcn_rcpf(wi) - 1.0f) <= 1e-5f);
-    if (redo) return true;
-    double w, lt;
-    if (!bw_weight<MODE>(E.T, wi, w, lt)) return false;
+    float w = wi;
     if (MODE == 1) {
-        acc[0] += lt;
-        acc[1] += 1.0;
+        if (!(wi > 0.0f && wi < __builtin_huge_valf())) return false;
+        const float r0 = __builtin_amdgcn_rcpf(wi);
+        if (E.near_kink || __builtin_fabsf(E.T * r0 - 1.0f) <= 1e-5f) return true;
+        const float r = r0 * (2.0f - wi * r0);
+        w = E.T > wi ? r : (E.T < wi ? -r : 0.0f);
+        acc[0] += __builtin_fabsf(E.T - wi) * r;
+        acc[1] += 1.0f;
+    } else if (E.near_kink) {
+        return true;
     }
-    bw_accumulate<float, double>(S.cf, E, w, acc);
+    bw_accumulate<float, float>(S.cf, E, w, acc);
     return false;
 }
 
@@ -99,34 +104,22 @@ __global__ __launch_bounds__(BLOCK) void k_bw_grad(BwDescPtrs d, int64_t n, cons
 {
     __shared__ double red[16 * kAcc];
     const BwSet& S = PTR ? *sp : sv;
-    double acc[kAcc];
+    float acc[kAcc];   // the lane's partial sums; float64 from the wave reduction on
 #pragma unroll
-    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    // software pipeline: the next group's loads are in flight while this
-    // group is evaluated
-    int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63);
-    BwDesc xn;
-    float wn = 0.0f;
-    if (base + lane < n) {
-        xn = load_bw_desc(d, base + lane);
-        wn = ntload(wv + base + lane);
-    }
-    for (; base < n; base += stride) {
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63); base < n; base += stride) {
         const int64_t i = base + lane;
-        const BwDesc x = xn;
-        const float w = wn;
-        if (i + stride < n) {
-            xn = load_bw_desc(d, i + stride);
-            wn = ntload(wv + i + stride);
-        }
         bool redo = false;
-        if (i < n) redo = bw_grad_fast<MODE>(S, x, w, acc);
+        if (i < n) redo = bw_grad_fast<MODE>(S, load_bw_desc(d, i), ntload(wv + i), acc);
         const uint64_t m = __ballot(redo);
         if (lane == 0) flags[base >> 6] = m;
     }
-    block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
+    double a64[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) a64[j] = (double)acc[j];
+    block_reduce_acc(a64, red, partials + (int64_t)blockIdx.x * kAcc);
 }
 
 // Phase 2: fold the phase-1 rows (fixed order) and redo flagged descriptors

@@ -12,6 +12,7 @@
 #include "wm_device.hpp"
 
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <utility>
 
@@ -167,28 +168,29 @@ __device__ inline bool weight_of(R T, float wi, double& w, double& loss_term)
     return true;
 }
 
-// Phase 1, float32: accumulate the descriptor's contribution unless it lies
-// within 1e-5 of a max/min switch or (mode 1) of T = m; those return true and
-// are left to the float64 pass.
+// Phase 1, float32: accumulate the descriptor's contribution into the lane's
+// float32 partial sums unless it lies within 1e-5 of a max/min switch or
+// (mode 1) of T = m; those return true and are left to the float64 pass.
+// Mode 1's weight 1/m is a float32 reciprocal refined by one Newton step.
 template <int MODE>
-__device__ inline bool grad_fast(const Set& S, const Desc<float>& x, float wi, double* acc)
+__device__ inline bool grad_fast(const Set& S, const Desc<float>& x, float wi, float* acc)
 {
     Eval<float> E;
     evaluate<float, true>(S.st, S.cf, x, E);
     if (!(E.T < __builtin_huge_valf())) return false;  // invalid (NaN) or infeasible (+inf)
-    bool redo = E.near_kink;
-    if (MODE == 1 && wi > 0.0f && wi < __builtin_huge_valf()) {
-        const float rho = E.T * __builtin_amdgcn_rcpf(wi) - 1.0f;
-        redo = redo || (__builtin_fabsf(rho) <= 1e-5f);
-    }
-    if (redo) return true;
-    double w, lt;
-    if (!weight_of<MODE>(E.T, wi, w, lt)) return false;
+    float w = wi;
     if (MODE == 1) {
-        acc[0] += lt;
-        acc[1] += 1.0;
+        if (!(wi > 0.0f && wi < __builtin_huge_valf())) return false;
+        const float r0 = __builtin_amdgcn_rcpf(wi);
+        if (E.near_kink || __builtin_fabsf(E.T * r0 - 1.0f) <= 1e-5f) return true;
+        const float r = r0 * (2.0f - wi * r0);
+        w = E.T > wi ? r : (E.T < wi ? -r : 0.0f);
+        acc[0] += __builtin_fabsf(E.T - wi) * r;
+        acc[1] += 1.0f;
+    } else if (E.near_kink) {
+        return true;
     }
-    accumulate_partials<float, double>(S.st, S.cf, E, w, acc);
+    accumulate_partials<float>(S.st, S.cf, E, w, acc);
     return false;
 }
 
@@ -205,7 +207,7 @@ __device__ inline void grad_exact(const Set& S, const Desc<float>& x, float wi, 
         acc[0] += lt;
         acc[1] += 1.0;
     }
-    accumulate_partials<double, double>(S.st, S.cd, D, w, acc);
+    accumulate_partials<double>(S.st, S.cd, D, w, acc);
 }
 
 // Phase 1 sweep.  The loop runs over wave-aligned groups of 64 consecutive
@@ -221,38 +223,31 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
 {
     __shared__ double red[16 * kAcc];
     const Set& S = PTR ? *sp : sv;
-    double acc[kAcc];
+    // per-lane partial sums: float32 in the bulk sweep (each lane adds the
+    // ~n / (grid threads) descriptors it visits), float64 in the exact
+    // variant; float64 from the wave reduction on
+    typedef typename std::conditional<X64, double, float>::type A;
+    A acc[kAcc];
 #pragma unroll
-    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kAcc; ++j) acc[j] = (A)0;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    // software pipeline: the next group's loads are in flight while this
-    // group is evaluated
-    int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63);
-    Desc<float> xn;
-    float wn = 0.0f;
-    if (base + lane < n) {
-        xn = load_desc(d, base + lane);
-        wn = ntload(wv + base + lane);
-    }
-    for (; base < n; base += stride) {
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63); base < n; base += stride) {
         const int64_t i = base + lane;
-        const Desc<float> x = xn;
-        const float w = wn;
-        const int64_t inext = i + stride;
-        if (inext < n) {
-            xn = load_desc(d, inext);
-            wn = ntload(wv + inext);
-        }
         bool redo = false;
         if (i < n) {
-            if (X64) grad_exact<MODE>(S, x, w, acc);
+            const Desc<float> x = load_desc(d, i);
+            const float w = ntload(wv + i);
+            if constexpr (X64) grad_exact<MODE>(S, x, w, acc);
             else redo = grad_fast<MODE>(S, x, w, acc);
         }
         const uint64_t m = __ballot(redo);
         if (lane == 0) flags[base >> 6] = m;
     }
-    block_reduce_acc(acc, red, partials + (int64_t)blockIdx.x * kAcc);
+    double a64[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) a64[j] = (double)acc[j];
+    block_reduce_acc(a64, red, partials + (int64_t)blockIdx.x * kAcc);
 }
 
 // Phase 2: (a) block b first folds the phase-1 partial rows b, b + nb2, ...
@@ -512,9 +507,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const float* m = meas[k];
         const Set& S = S_all[k];
         uint64_t* fl = flags + flag_off[k];
-        double acc[kAcc];
+        float acc[kAcc];
 #pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
         for (int64_t base = begin + (threadIdx.x & ~63); base < end; base += blockDim.x) {
             const int64_t i = base + lane;
             bool redo = false;
@@ -522,7 +517,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const uint64_t msk = __ballot(redo);
             if (lane == 0) fl[base >> 6] = msk;
         }
-        block_reduce_acc(acc, red, tot);
+        double a64[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) a64[j] = (double)acc[j];
+        block_reduce_acc(a64, red, tot);
         if (threadIdx.x < kAcc) per_set[k * kAcc + threadIdx.x] = tot[threadIdx.x];
     }
     __syncthreads();

@@ -43,9 +43,9 @@ struct Const {
     R latf[4];   // Lat_l / f_clk, seconds
     R ov[7];     // T_launch, tau_wg, tau_bar, tau_interf, tau_gpu, tau_fusion, tau_sync
     R alpha, beta;
-    R inv_w0;    // 1 / w0 when the Eq. (16) blend is on, else 0
     R blend_k;   // -log2(e) / w0: exp(-W/w0) = exp2(W * blend_k)
     R bp_minus_bw;
+    R dw0_coef;  // (B_peak - BW_HBM) / w0^2 (0 without the blend): dS/dw0 = s_hbm e W dw0_coef
     R inv_lw;    // 1 / bytes in flight per wave
     R inv_f;     // 1 / f_clk
     R w_lo, c_llc, inv_span;  // MiB
@@ -82,7 +82,7 @@ WM_HD void const_field(const double* th, const Struct& s, Const<R>& c, int k)
         c.w_lo = (R)s.w_lo_mib;
         c.c_llc = (R)s.c_llc_mib;
     } else if (k == 17) {
-        c.inv_w0 = blend ? (R)(1.0 / th[22]) : (R)0;
+        c.dw0_coef = blend ? (R)((th[23] - th[3]) / (th[22] * th[22])) : (R)0;
     } else if (k == 18) {
         c.blend_k = blend ? (R)(-1.4426950408889634 / th[22]) : (R)0;
     } else if (k == 19) {
@@ -347,54 +347,58 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     }
 }
 
-// dT/dtheta_j of an evaluated descriptor times `w`, added into acc[2 + j]
-template <typename R, typename Acc>
-__device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E,
-                                           Acc w, Acc* acc)
+// dT/dtheta_j of an evaluated descriptor times `w`, added into acc[2 + j].
+// The weight is folded into each stage's coefficient once, so every slot
+// costs one multiply-add.  R is the accumulator type too: float for the
+// bulk sweeps (per-lane partial sums, reduced in float64 across lanes,
+// waves and blocks), double for the float64 re-evaluations.
+template <typename R>
+__device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E, R w, R* acc)
 {
     typedef Ar<R> A;
     // overhead slots: data only
     acc[2 + 13] += w;
-    acc[2 + 14] += w * (Acc)E.G;
-    acc[2 + 15] += w * (Acc)E.nrK;
-    acc[2 + 16] += w * (Acc)E.cnt[0];
-    acc[2 + 17] += w * (Acc)E.cnt[1];
-    acc[2 + 18] += w * (Acc)E.cnt[2];
-    acc[2 + 19] += w * (Acc)E.cnt[3];
+    acc[2 + 14] += w * (R)E.G;
+    acc[2 + 15] += w * E.nrK;
+    acc[2 + 16] += w * (R)E.cnt[0];
+    acc[2 + 17] += w * (R)E.cnt[1];
+    acc[2 + 18] += w * (R)E.cnt[2];
+    acc[2 + 19] += w * (R)E.cnt[3];
     // compute: d(F/(uP))/dP = -T_c / P
     R ipk = c.inv_peak[0];
     ipk = E.dt == 1 ? c.inv_peak[1] : ipk;
     ipk = E.dt == 2 ? c.inv_peak[2] : ipk;
     ipk = E.dt == 3 ? c.inv_peak[3] : ipk;
     ipk = E.dt == 4 ? c.inv_peak[4] : ipk;
-    const Acc gP = w * (Acc)(-E.wc * E.Tc * ipk);
-    acc[2 + 8] += E.dt == 0 ? gP : (Acc)0;
-    acc[2 + 9] += E.dt == 1 ? gP : (Acc)0;
-    acc[2 + 10] += E.dt == 2 ? gP : (Acc)0;
-    acc[2 + 11] += E.dt == 3 ? gP : (Acc)0;
-    acc[2 + 12] += E.dt == 4 ? gP : (Acc)0;
+    const R gP = -(w * E.wc) * E.Tc * ipk;
+    acc[2 + 8] += E.dt == 0 ? gP : (R)0;
+    acc[2 + 9] += E.dt == 1 ? gP : (R)0;
+    acc[2 + 10] += E.dt == 2 ? gP : (R)0;
+    acc[2 + 11] += E.dt == 3 ? gP : (R)0;
+    acc[2 + 12] += E.dt == 4 ? gP : (R)0;
     // bandwidth: dT_b/dX = -(T_b / S) dS/dX.  Without the working-set blend
     // e = 0, which zeroes the B_peak and w0 terms; outside the h_LLC regimes
     // base_log = 0 -- so every slot is updated unconditionally.
-    const R cb = -E.wb * E.Tb * A::rcp(E.S);
+    const R cb = -(w * E.wb) * E.Tb * A::rcp(E.S);
     const R cbh = cb * E.sh;
-    acc[2 + 0] += w * (Acc)(cb * E.s1);
-    acc[2 + 1] += w * (Acc)(cb * E.s2);
-    acc[2 + 2] += w * (Acc)(cb * E.s3);
-    acc[2 + 3] += w * (Acc)(cbh * ((R)1 - E.e));
-    acc[2 + 23] += w * (Acc)(cbh * E.e);
-    acc[2 + 22] += w * (Acc)(cbh * c.bp_minus_bw * E.e * E.W * c.inv_w0 * c.inv_w0);
+    acc[2 + 0] += cb * E.s1;
+    acc[2 + 1] += cb * E.s2;
+    acc[2 + 2] += cb * E.s3;
+    acc[2 + 3] += cbh * ((R)1 - E.e);
+    acc[2 + 23] += cbh * E.e;
+    acc[2 + 22] += (cbh * E.e) * (E.W * c.dw0_coef);
     // latency: T_lat = q * sum s_l Lat_l / f
-    const R cl = E.wl * E.q * c.inv_f;
-    acc[2 + 4] += w * (Acc)(cl * E.s1);
-    acc[2 + 5] += w * (Acc)(cl * E.s2);
-    acc[2 + 6] += w * (Acc)(cl * E.s3);
-    acc[2 + 7] += w * (Acc)(cl * E.sh);
+    const R clq = (w * E.wl) * E.q;
+    const R cl = clq * c.inv_f;
+    acc[2 + 4] += cl * E.s1;
+    acc[2 + 5] += cl * E.s2;
+    acc[2 + 6] += cl * E.s3;
+    acc[2 + 7] += cl * E.sh;
     // h_LLC(W) exponents through s3 and s_hbm
-    const R dTdh = cb * E.a12 * (c.bw[2] - E.bwh) + E.wl * E.q * E.a12 * (c.latf[2] - c.latf[3]);
-    const Acc gh = w * (Acc)(dTdh * E.h3 * E.base_log);
-    acc[2 + 20] += E.llc_regime == 1 ? gh : (Acc)0;
-    acc[2 + 21] += E.llc_regime == 2 ? gh : (Acc)0;
+    const R dTdh = E.a12 * (cb * (c.bw[2] - E.bwh) + clq * (c.latf[2] - c.latf[3]));
+    const R gh = dTdh * E.h3 * E.base_log;
+    acc[2 + 20] += E.llc_regime == 1 ? gh : (R)0;
+    acc[2 + 21] += E.llc_regime == 2 ? gh : (R)0;
 }
 
 }  // namespace wm

@@ -15,6 +15,10 @@ pytestmark = pytest.mark.gpu
 # oracle tests)
 MASK_L4 = synth.FIT_MASK_L4
 MASK_L3 = synth.FIT_MASK_L3
+# Runs that split the same descriptors differently over lanes (batched against
+# per-set sweeps, other work-item sizes) agree to the float32 rounding of the
+# lanes' partial sums (~1e-7 relative in the loss), not to the float64 order.
+PARTITION_RTOL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -170,8 +174,11 @@ def test_batched_matches_plain_per_set(wmb, orc):
     for k in range(len(sets)):
         rck, thk, histk = wmb.calibrate(descs[k], meas[k], p0s[k], steps=steps, free_mask=masks[k])
         say("set", k, "n", sizes[k], "L", sets[k].n_levels)
-        assert np.allclose(histb[k], histk, rtol=1e-9, atol=0), k
-        assert np.allclose(thb[k], thk, rtol=1e-9, atol=0), k
+        # the two runs split the descriptors differently over lanes, and each
+        # lane sums its descriptors in float32 before the float64 reductions:
+        # they agree to float32 rounding of those partial sums
+        assert np.allclose(histb[k], histk, rtol=PARTITION_RTOL, atol=0), k
+        assert np.allclose(thb[k], thk, rtol=PARTITION_RTOL, atol=0), k
         # first-step loss equals the oracle's at theta0
         l0 = orc.loss_grad(p0s[k], hdesc[k], meas[k].cpu().numpy())[0]
         assert abs(histb[k][0] - l0) <= 1e-5 * l0
@@ -223,8 +230,8 @@ def test_batched_sixteen_ragged_sets_match_per_set(wmb, orc):
             rc, thb, histb = wmb.calibrate_batched(descs, meas, p0s, opts)
             assert rc == wmb.WM_OK
             for k, (rck, thk, histk) in enumerate(ref):
-                assert np.allclose(histb[k], histk, rtol=1e-9, atol=0), (chunk, k, sizes[k])
-                assert np.allclose(thb[k], thk, rtol=1e-9, atol=0), (chunk, k, sizes[k])
+                assert np.allclose(histb[k], histk, rtol=PARTITION_RTOL, atol=0), (chunk, k, sizes[k])
+                assert np.allclose(thb[k], thk, rtol=PARTITION_RTOL, atol=0), (chunk, k, sizes[k])
         # the empty set: zero loss, theta unchanged (up to exp(log theta))
         assert np.all(histb[0] == 0.0)
         assert np.allclose(thb[0], np.asarray(p0s[0].theta), rtol=1e-12, atol=0)

@@ -66,8 +66,10 @@ def test_forward_and_loss_grad_past_4_gib(wmb, orc):
     del big
     torch.cuda.empty_cache()
     assert int(out_big[1]) == REPS * int(out_base[1])
-    assert abs(out_big[0] - out_base[0]) <= 1e-9 * out_base[0]
-    check_grad(out_big[2:], out_base[2:], p0.theta, "large: replicated set against the base set", 1e-9,
+    # the replicated sweep gives each lane ~2700 descriptors, the base sweep a
+    # few: they agree to the float32 rounding of the lanes' partial sums
+    assert abs(out_big[0] - out_base[0]) <= 1e-6 * out_base[0]
+    check_grad(out_big[2:], out_base[2:], p0.theta, "large: replicated set against the base set", 1e-6,
                names=synth.THETA_NAMES)
     loss, cnt, g = orc.loss_grad(p0, d, m0)
     assert int(out_base[1]) == cnt

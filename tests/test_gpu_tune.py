@@ -1,7 +1,9 @@
 """Launch configurations and the autotuner: every candidate configuration of
-every op gives the same results (forward and tile selection bit for bit,
-gradient sums to 1e-12 relative -- only the FP64 addition order changes), the
-tuners install a valid configuration, and the JSON-lines cache round-trips."""
+every op gives the same results (forward and tile selection bit for bit;
+gradient sums to 1e-12 relative where every lane sees one descriptor, so only
+the FP64 addition order changes, and to the float32 rounding of the lanes'
+partial sums, 1e-6, where lanes sum several), the tuners install a valid
+configuration, and the JSON-lines cache round-trips."""
 import json
 import os
 import subprocess
@@ -106,8 +108,10 @@ def test_batched_chunks_match(wmb, orc):
         for gm in (1, 2):
             wmb.set_launch(wmb.OP_CALIBRATE_BATCHED, ntot, 256, 1, gm, chunk)
             _, th, h = wmb.calibrate_batched(descs, meas, p0s, opts)
-            assert np.allclose(h, h_ref, rtol=1e-9, atol=0), (chunk, gm)
-            assert np.allclose(th, th_ref, rtol=1e-9, atol=0), (chunk, gm)
+            # other work items split the descriptors differently over lanes,
+            # which sum in float32 before the float64 reductions
+            assert np.allclose(h, h_ref, rtol=1e-6, atol=0), (chunk, gm)
+            assert np.allclose(th, th_ref, rtol=1e-6, atol=0), (chunk, gm)
     _restore(wmb, wmb.OP_CALIBRATE_BATCHED, ntot)
     best = wmb.autotune_batched(descs, meas, p0s, opts)
     say("batched tuned", best)
