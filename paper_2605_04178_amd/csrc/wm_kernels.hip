@@ -230,10 +230,10 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
     A acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = (A)0;
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63u;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63); base < n; base += stride) {
-        const int64_t i = base + lane;
+        const int64_t i = base + (int64_t)lane;
         bool redo = false;
         if (i < n) {
             const Desc<float> x = load_desc(d, i);

@@ -196,6 +196,7 @@ struct Eval {
     R wc, wb, wl;      // dT/dT_c, dT/dT_b, dT/dT_lat
     R nrK, base_log;   // n_r K; ln(base) (transition) or ln(C/W_MiB) (streaming)
     R q;               // n_r * B / (G k L_w): serialised load batches
+    R ip, iS;          // 1 / P of the descriptor's dtype, 1 / S
     bool near_kink;    // within 1e-5 relative of a max/min switch
 };
 
@@ -227,7 +228,15 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     // n_cu <= 65536 and o <= 1024: 24-bit multiplies are exact
     const uint32_t per_round = __umul24((uint32_t)st.n_cu, (uint32_t)oc.o);
     const uint32_t num = (uint32_t)d.G + per_round - 1u;
-    const int32_t nr = (int32_t)(num < (1u << 21) ? udiv_small(num, per_round) : num / per_round);
+    // udiv_small is exact below 2^21; larger counts (grids beyond ~2^21
+    // workgroups) take an exact division, behind a branch that the whole
+    // wave skips unless one of its lanes needs it
+    const bool big = num >= (1u << 21);
+    uint32_t nru = udiv_small(big ? 0u : num, per_round);
+    if (__builtin_expect(__ballot(big) != 0, 0)) {
+        if (big) nru = num / per_round;
+    }
+    const int32_t nr = (int32_t)nru;
     E.nr = nr;
 
     // traffic split: with W > 0 and an LLC, h_LLC(W) replaces r3
@@ -275,7 +284,8 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     ip = dt == 3 ? c.inv_peak[3] : ip;
     ip = dt == 4 ? c.inv_peak[4] : ip;
     const R Tc = TILE ? d.F * ip : d.F * ip * A::rcp(d.u);
-    const R Tb = d.B * A::rcp(S);
+    const R iS = A::rcp(S);
+    const R Tb = d.B * iS;
     const R q = (R)nr * d.B * A::rcp((R)d.G * (R)oc.k) * c.inv_lw;
     const R Tlat = q * Lf;
 
@@ -342,7 +352,7 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         E.h3 = h3; E.s1 = s1; E.s2 = s2; E.s3 = s3; E.sh = sh; E.a12 = a12;
         E.S = S; E.Lf = Lf; E.e = e; E.bwh = bwh; E.W = d.W;
         E.Tc = Tc; E.Tb = Tb; E.Tlat = Tlat; E.Tm = Tm;
-        E.wc = wc; E.wb = wb; E.wl = wl; E.nrK = nrK; E.q = q;
+        E.wc = wc; E.wb = wb; E.wl = wl; E.nrK = nrK; E.q = q; E.ip = ip; E.iS = iS;
         E.near_kink = near;
     }
 }
@@ -365,12 +375,7 @@ __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, 
     acc[2 + 18] += w * (R)E.cnt[2];
     acc[2 + 19] += w * (R)E.cnt[3];
     // compute: d(F/(uP))/dP = -T_c / P
-    R ipk = c.inv_peak[0];
-    ipk = E.dt == 1 ? c.inv_peak[1] : ipk;
-    ipk = E.dt == 2 ? c.inv_peak[2] : ipk;
-    ipk = E.dt == 3 ? c.inv_peak[3] : ipk;
-    ipk = E.dt == 4 ? c.inv_peak[4] : ipk;
-    const R gP = -(w * E.wc) * E.Tc * ipk;
+    const R gP = -(w * E.wc) * E.Tc * E.ip;
     acc[2 + 8] += E.dt == 0 ? gP : (R)0;
     acc[2 + 9] += E.dt == 1 ? gP : (R)0;
     acc[2 + 10] += E.dt == 2 ? gP : (R)0;
@@ -379,7 +384,7 @@ __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, 
     // bandwidth: dT_b/dX = -(T_b / S) dS/dX.  Without the working-set blend
     // e = 0, which zeroes the B_peak and w0 terms; outside the h_LLC regimes
     // base_log = 0 -- so every slot is updated unconditionally.
-    const R cb = -(w * E.wb) * E.Tb * A::rcp(E.S);
+    const R cb = -(w * E.wb) * E.Tb * E.iS;
     const R cbh = cb * E.sh;
     acc[2 + 0] += cb * E.s1;
     acc[2 + 1] += cb * E.s2;
