@@ -62,7 +62,7 @@ def kernel_name(kind, cfg):
     if kind == "predict_apps":
         return f"void wm::k_apps<{cfg['block']}, 0>"
     if kind == "apps_loss_grad":
-        return f"void wm::k_apps<{cfg['block']}, 1>"
+        return f"void wm::k_apps_grad<{cfg['block']}, 1>"
     return kind
 
 

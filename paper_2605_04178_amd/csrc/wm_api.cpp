@@ -331,23 +331,24 @@ GradWs grad_ws(int64_t n)
 // application loss-gradient workspace: row weights, application rows,
 // application flag words, then the gradient sweep's partials and flags
 struct AppsWs {
-    size_t wseg, rows, aflags, grad, total;
-    GradWs g;
+    size_t rows, aflags, lflags, rflags, wrow, total;
 };
 
 AppsWs apps_ws(int64_t n, int64_t n_apps)
 {
     AppsWs W;
-    W.g = grad_ws(n);
     size_t off = 0;
-    W.wseg = off;
-    off += up256(sizeof(float) * (size_t)(n > 0 ? n : 1));
     W.rows = off;
-    off += up256(sizeof(double) * kAppAcc * (size_t)(kAppsMaxBlocks + kRedoMaxBlocks));
+    off += up256(sizeof(double) * kAppRow * (size_t)(kAppsMaxBlocks + kAppsLongBlocks + kRedoMaxBlocks));
+    const size_t awords = (size_t)((n_apps + 63) / 64 > 0 ? (n_apps + 63) / 64 : 1);
     W.aflags = off;
-    off += up256(sizeof(uint64_t) * (size_t)((n_apps + 63) / 64 > 0 ? (n_apps + 63) / 64 : 1));
-    W.grad = off;
-    off += W.g.total;
+    off += up256(sizeof(uint64_t) * awords);
+    W.lflags = off;
+    off += up256(sizeof(uint64_t) * awords);
+    W.rflags = off;
+    off += up256(sizeof(uint64_t) * (size_t)((n + 63) / 64 > 0 ? (n + 63) / 64 : 1));
+    W.wrow = off;
+    off += up256(sizeof(float) * (size_t)(n > 0 ? n : 1));
     W.total = off;
     return W;
 }
@@ -1011,12 +1012,9 @@ int32_t wm_apps_loss_grad(const wm_desc_t* desc, const wm_segs_t* segs, const fl
     const Set S = make_set(params);
     // no applications: the sweeps write zero rows, so out is still written
     WM_HIP(launch_apps_loss_grad(ptrs_of(desc), segptrs_of(segs), desc->n, segs->n_apps, measured,
-                                 S, make_segset(segp), (float*)(base + W.wseg),
-                                 (double*)(base + W.rows), (uint64_t*)(base + W.aflags),
-                                 (double*)(base + W.grad + W.g.partials),
-                                 (uint64_t*)(base + W.grad + W.g.flags), W.g.g,
-                                 launch_cfg(kOpAppsLossGrad, segs->n_apps),
-                                 launch_cfg(kOpVjp, desc->n), out, (hipStream_t)stream));
+                                 S, make_segset(segp), (double*)(base + W.rows), (uint64_t*)(base + W.aflags),
+                                 (uint64_t*)(base + W.lflags), (uint64_t*)(base + W.rflags), (float*)(base + W.wrow),
+                                 launch_cfg(kOpAppsLossGrad, segs->n_apps), out, (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -1032,11 +1030,10 @@ int32_t wm_predict_apps_vjp(const wm_desc_t* desc, const wm_segs_t* segs, const 
     char* base = (char*)ws;
     const Set S = make_set(params);
     WM_HIP(launch_apps_vjp(ptrs_of(desc), segptrs_of(segs), desc->n, segs->n_apps, dL_dTapp, S,
-                           make_segset(segp), (float*)(base + W.wseg), (double*)(base + W.rows),
-                           (double*)(base + W.grad + W.g.partials),
-                           (uint64_t*)(base + W.grad + W.g.flags), W.g.g,
-                           launch_cfg(kOpAppsLossGrad, segs->n_apps), launch_cfg(kOpVjp, desc->n),
-                           out, (hipStream_t)stream));
+                           make_segset(segp), (double*)(base + W.rows), (uint64_t*)(base + W.lflags),
+                           (uint64_t*)(base + W.rflags), (float*)(base + W.wrow),
+                           launch_cfg(kOpAppsLossGrad, segs->n_apps), out,
+                           (hipStream_t)stream));
     return WM_OK;
 }
 
@@ -1300,14 +1297,12 @@ int32_t wm_autotune_apps(int32_t op, const wm_desc_t* desc, const wm_segs_t* seg
     const AppsWs W = apps_ws(n, na);
     if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
     char* base = (char*)ws;
-    const LaunchCfg vc = launch_cfg(kOpVjp, n);
     return tune_over(op, na, candidates(op), s, 10,
                      [&](const LaunchCfg& c) {
-                         return launch_apps_loss_grad(
-                             dp, sp, n, na, measured, S, Q, (float*)(base + W.wseg),
-                             (double*)(base + W.rows), (uint64_t*)(base + W.aflags),
-                             (double*)(base + W.grad + W.g.partials),
-                             (uint64_t*)(base + W.grad + W.g.flags), W.g.g, c, vc, out, s);
+                         return launch_apps_loss_grad(dp, sp, n, na, measured, S, Q, (double*)(base + W.rows),
+                                                      (uint64_t*)(base + W.aflags), (uint64_t*)(base + W.lflags),
+                                                      (uint64_t*)(base + W.rflags), (float*)(base + W.wrow), c,
+                                                      out, s);
                      },
                      best, best_us);
 }

@@ -62,9 +62,11 @@ struct SegSet {
     double inv_bw2_h2d, inv_bw2_d2h;  // 1 / B^2, for the bandwidth gradients
 };
 constexpr int kSegParams = 7;                 // kappa[4], bw_h2d, bw_d2h, tau_memcpy
-constexpr int kAppAcc = 10;                   // loss, count, T_launch, kappa[4], h2d, d2h, tau sums
+constexpr int kAppRow = kAcc + 8;             // loss, count, grad theta[24], then the segment sums:
+                                              // extra launches, kappa[4], h2d, d2h, transfers
 constexpr int kAppsOut = kAcc + kSegParams;   // loss, count, grad theta[24], grad seg params[7]
 constexpr int kAppsMaxBlocks = 4096;          // partial-row cap of the application sweep
+constexpr int kAppsLongBlocks = 64;           // blocks of the pass over applications longer than a piece
 constexpr int kFitMultMaxBlocks = 1024;       // multiplier sweep: rows = 4 x blocks
 constexpr int kPlanMaxRun = 32;               // longest fused run
 
@@ -148,16 +150,15 @@ hipError_t launch_adam_batched(const double* partials, int rows, int n_sets, Cal
 hipError_t launch_predict_apps(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
                                const Set& S, const SegSet& Q, float* T_app, float* T_seg,
                                const LaunchCfg& cfg, hipStream_t stream);
-// Application mean relative error and its gradient [kAppsOut] (float64).
-// Workspace: wseg (n_seg floats), app_rows ((kAppsMaxBlocks + kRedoMaxBlocks)
-// x kAppAcc), aflags ((n_apps + 63) / 64 words), the gradient sweep's
-// partials / flags for n_seg descriptors.
-hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg,
-                                 int64_t n_apps, const float* measured, const Set& S,
-                                 const SegSet& Q, float* wseg, double* app_rows, uint64_t* aflags,
-                                 double* partials, uint64_t* flags, const GradLayout& L,
-                                 const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
-                                 hipStream_t stream);
+// Application mean relative error and its gradient [kAppsOut] (float64), in
+// one sweep over the rows.  Workspace: rows ((kAppsMaxBlocks + kAppsLongBlocks
+// + kRedoMaxBlocks) x kAppRow doubles), aflags and lflags ((n_apps + 63) / 64
+// words each), rflags ((n_seg + 63) / 64 words, cleared here), wrow (n_seg
+// floats, written for flagged rows).
+hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                                 const float* measured, const Set& S, const SegSet& Q, double* rows,
+                                 uint64_t* aflags, uint64_t* lflags, uint64_t* rflags, float* wrow,
+                                 const LaunchCfg& cfg, double* out, hipStream_t stream);
 // Per-group weighted-median multipliers; rows: 4 x kFitMultMaxBlocks x 4
 // doubles of workspace; stats [4] float64 device.
 hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32_t* off,
@@ -172,10 +173,8 @@ hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_
 // Vector-Jacobian product of the application totals: out [31] = sum_a
 // w_app[a] dT_a/d(theta[24], seg params[7]); workspace as the loss gradient.
 hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
-                           const float* w_app, const Set& S, const SegSet& Q, float* wseg,
-                           double* app_rows, double* partials, uint64_t* flags, const GradLayout& L,
-                           const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
-                           hipStream_t stream);
+                           const float* w_app, const Set& S, const SegSet& Q, double* rows, uint64_t* lflags,
+                           uint64_t* rflags, float* wrow, const LaunchCfg& cfg, double* out, hipStream_t stream);
 // every candidate's float32 cost, as the selection's first pass computes it
 hipError_t launch_tile_costs(const ShapePtrs& sh, const int32_t* off, const uint32_t* code, int64_t n,
                              int64_t n_cand, const Set& S, float* cost, hipStream_t stream);

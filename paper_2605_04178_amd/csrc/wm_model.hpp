@@ -365,7 +365,6 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
 template <typename R>
 __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E, R w, R* acc)
 {
-    typedef Ar<R> A;
     // overhead slots: data only
     acc[2 + 13] += w;
     acc[2 + 14] += w * (R)E.G;

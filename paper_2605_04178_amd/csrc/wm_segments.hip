@@ -8,8 +8,8 @@
 // Layout: applications are CSR offsets over the segment rows, which run
 // parallel to the descriptor rows.  A block takes `BLOCK` consecutive
 // applications; their rows are contiguous, so it streams them with coalesced
-// loads in pieces of 8 x BLOCK rows staged in LDS, then each thread adds its own
-// application's rows in float64, in row order.
+// loads in pieces staged in LDS, and each application's owner thread adds its
+// rows in float64, in row order.
 #include "wm_device.hpp"
 
 namespace wm {
@@ -20,25 +20,14 @@ struct SegRow {
     int32_t nk, c;
 };
 
-// KEEP = true: ordinary loads, so that a second pass over the same rows
-// finds them in the caches; false: streaming (nontemporal) loads.
-template <bool KEEP = false>
 __device__ inline SegRow load_seg(const SegPtrs& sg, int64_t i)
 {
     SegRow r;
-    if (KEEP) {
-        r.ne = sg.n_exec[i];
-        r.nk = sg.n_kern[i];
-        r.c = sg.cls[i];
-        r.h = sg.h2d[i];
-        r.dd = sg.d2h[i];
-    } else {
-        r.ne = ntload(sg.n_exec + i);
-        r.nk = ntload(sg.n_kern + i);
-        r.c = ntload(sg.cls + i);
-        r.h = ntload(sg.h2d + i);
-        r.dd = ntload(sg.d2h + i);
-    }
+    r.ne = ntload(sg.n_exec + i);
+    r.nk = ntload(sg.n_kern + i);
+    r.c = ntload(sg.cls + i);
+    r.h = ntload(sg.h2d + i);
+    r.dd = ntload(sg.d2h + i);
     return r;
 }
 
@@ -101,43 +90,22 @@ __device__ inline void block_sum(double* acc, double* lds /* [waves][NA] */, dou
     __syncthreads();
 }
 
-// Application sweep.  A block takes BLOCK consecutive applications (one per
+// Application totals.  A block takes BLOCK consecutive applications (one per
 // thread); their rows are staged in LDS in pieces of 8 x BLOCK rows (one
-// piece unless the chunk averages more than 8 rows per application).
-// MODE 0: T_app[a] (float32) and optionally the segment times.
-// MODE 1 (loss) and MODE 2 (vector-Jacobian product, weights dL/dT_app read
-// from `meas`): after the application totals, a second row-parallel pass
-// writes the adjoint weights wseg[j] = w_a * n_exec_j * kappa_cls(j) for the
-// kernel model's vector-Jacobian product, with w_a = sign(T_a - m_a) / m_a
-// (MODE 1) or dL/dT_app[a] (MODE 2), and adds w_a times each row's n_exec (n_kern - 1), n_exec Tk (per class),
-// n_exec h2d, n_exec d2h and n_exec x transfers; per block one row of
-// kAppAcc float64 sums (loss, count, those seven).  In MODE 1 an application
-// with |T_a/m_a - 1| <= 1e-5 in this float32 sweep gets zero weights and is
-// flagged in aflags (one 64-bit ballot word per 64 applications) for
-// k_apps_redo.  Offsets are caller data: they are clamped into [0, n_seg],
-// so malformed offsets give unspecified values but no out-of-range access.
+// piece unless the chunk averages more than 8 rows per application); each
+// thread adds its application's segment times in float64, in row order.
+// T_app [n_apps] float32, and the segment times if T_seg != nullptr.
+// Offsets are caller data: they are clamped into [0, n_seg], so malformed
+// offsets give unspecified values but no out-of-range access.
 template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t n_seg,
                                                int64_t n_apps, Set S, SegSet Q,
-                                               const float* __restrict__ meas,
-                                               float* __restrict__ T_app, float* __restrict__ T_seg,
-                                               float* __restrict__ wseg, double* __restrict__ rows,
-                                               uint64_t* __restrict__ aflags)
+                                               float* __restrict__ T_app, float* __restrict__ T_seg)
 {
-    constexpr bool LOSS = MODE != 0;  // loss (1) and vector-Jacobian product (2) share the weights pass
+    static_assert(MODE == 0, "the loss and its gradient are k_apps_grad");
     constexpr int CAP = 8 * BLOCK;
-    constexpr int LC = LOSS ? CAP : 1;
     __shared__ float ts[CAP];
-    __shared__ float ekn[LC];       // n_exec * T_kernel
-    __shared__ uint8_t ecl[LC];     // class
-    __shared__ uint16_t own[LC];    // application (index in the chunk) of the row
     __shared__ int32_t lo_s[BLOCK], hi_s[BLOCK];
-    __shared__ float wa_s[LOSS ? BLOCK : 1];
-    __shared__ double red[LOSS ? 8 * kAppAcc : 1];
-
-    double acc[kAppAcc];
-#pragma unroll
-    for (int j = 0; j < kAppAcc; ++j) acc[j] = 0.0;
     const int tid = threadIdx.x;
     const int64_t nchunks = (n_apps + BLOCK - 1) / BLOCK;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
@@ -156,7 +124,6 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
         hi_s[tid] = hi;
         __syncthreads();
         const int32_t sb = lo_s[0], se = hi_s[na - 1];
-        const bool one_piece = se - sb <= CAP;
         double tot = 0.0;
         for (int32_t pb = sb; pb < se; pb += CAP) {
             const int32_t pe = se - pb < CAP ? se : pb + CAP;
@@ -165,141 +132,268 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
             for (int32_t j = (pb & ~63) + tid; j < pe; j += BLOCK) {
                 if (j < pb) continue;
                 const Desc<float> x = load_desc(d, j);
-                const SegRow r = load_seg<LOSS>(sg, j);
+                const SegRow r = load_seg(sg, j);
                 Eval<float> E;
                 evaluate<float, false>(S.st, S.cf, x, E);
                 const float t = seg_time<float>(E.T, r, Q.f, S.cf.ov[0]);
                 ts[j - pb] = t;
                 if (T_seg) __builtin_nontemporal_store(t, T_seg + j);
-                if (LOSS) {
-                    ekn[j - pb] = r.ne * E.T;
-                    ecl[j - pb] = (uint8_t)(r.c & 3);
-                }
             }
             __syncthreads();
             if (tid < na) {
                 const int32_t jb = lo > pb ? lo : pb, je = hi < pe ? hi : pe;
-                for (int32_t j = jb; j < je; ++j) {
-                    tot += (double)ts[j - pb];
-                    if (LOSS) own[j - pb] = (uint16_t)tid;
-                }
+                for (int32_t j = jb; j < je; ++j) tot += (double)ts[j - pb];
             }
             __syncthreads();
         }
-        if (!LOSS) {
-            if (tid < na) __builtin_nontemporal_store((float)tot, T_app + a);
-            __syncthreads();  // lo_s / hi_s are rewritten by the next chunk
-            continue;
-        }
-        float wa = 0.0f;
-        bool near = false;
-        if (MODE == 2 && tid < na && tot - tot == 0.0) {
-            wa = meas[a];  // dL/dT_app
-        } else if (MODE == 1 && tid < na) {
-            const float mf = meas[a];
-            if (tot - tot == 0.0 && mf > 0.0f && mf < __builtin_huge_valf()) {
-                const double m = mf, im = 1.0 / m;
-                const double T = tot;
-                near = __builtin_fabs(T * im - 1.0) <= 1e-5;
-                if (!near) {
-                    const double w = T > m ? im : (T < m ? -im : 0.0);
-                    acc[0] += __builtin_fabs(T - m) * im;
-                    acc[1] += 1.0;
-                    wa = (float)w;
-                }
-            }
-        }
-        if (MODE == 1) {
-            const uint64_t fw = __ballot(near);
-            if ((tid & 63) == 0 && a < n_apps) aflags[a >> 6] = fw;
-        }
-        wa_s[tid] = wa;
-        __syncthreads();
-        // row-parallel pass: weights and the segment-parameter sums.  With one
-        // piece the owner, class and n_exec Tk are still in LDS; otherwise the
-        // owner is found by binary search and Tk is evaluated again.
-        for (int32_t j = (sb & ~63) + tid; j < se; j += BLOCK) {
-            if (j < sb) continue;
-            int t0;
-            float ek;
-            int32_t c;
-            bool mine = true;
-            if (one_piece) {
-                t0 = own[j - sb];
-                t0 = t0 < na ? t0 : na - 1;  // rows no application owns (bad offsets)
-                mine = j >= lo_s[t0] && j < hi_s[t0];
-                ek = ekn[j - sb];
-                c = ecl[j - sb];
-            } else {
-                int t1 = na - 1;
-                t0 = 0;
-                while (t0 < t1) {
-                    const int mid = (t0 + t1 + 1) >> 1;
-                    if (lo_s[mid] <= j) t0 = mid;
-                    else t1 = mid - 1;
-                }
-                mine = j >= lo_s[t0] && j < hi_s[t0];
-                ek = 0.0f;
-                c = 0;
-            }
-            const float wt = mine ? wa_s[t0] : 0.0f;
-            float w = 0.0f;
-            if (wt != 0.0f) {
-                const SegRow r = load_seg<true>(sg, j);
-                if (!one_piece) {
-                    Eval<float> E;
-                    evaluate<float, false>(S.st, S.cf, load_desc(d, j), E);
-                    ek = r.ne * E.T;
-                    c = r.c;
-                }
-                w = wt * r.ne * kappa_of(Q.f, c);
-                const double wd = wt;
-                acc[2] += wd * (double)(r.ne * (float)(r.nk - 1));
-                const double v = wd * (double)ek;
-                acc[3] += c == 0 ? v : 0.0;
-                acc[4] += c == 1 ? v : 0.0;
-                acc[5] += c == 2 ? v : 0.0;
-                acc[6] += c == 3 ? v : 0.0;
-                if (r.h > 0.0f) {
-                    acc[7] += wd * (double)(r.ne * r.h);
-                    acc[9] += wd * (double)r.ne;
-                }
-                if (r.dd > 0.0f) {
-                    acc[8] += wd * (double)(r.ne * r.dd);
-                    acc[9] += wd * (double)r.ne;
-                }
-            }
-            wseg[j] = w;
-        }
-        __syncthreads();
+        if (tid < na) __builtin_nontemporal_store((float)tot, T_app + a);
+        __syncthreads();  // lo_s / hi_s are rewritten by the next chunk
     }
-    if (LOSS) block_sum<kAppAcc>(acc, red, rows + (int64_t)blockIdx.x * kAppAcc);
 }
 
-// The applications flagged by k_apps: float64 totals decide the sign; their
-// loss and gradient sums go to this kernel's rows and their row weights to
-// wseg.  Block b first folds the sweep's rows b, b + gridDim.x, ... (fixed
-// order), so the final reduction sees gridDim.x rows.
-__global__ __launch_bounds__(256) void k_apps_redo(DescPtrs d, SegPtrs sg, int64_t n_seg,
+// ---------------------------------------------------------------------------
+// application loss (MODE 1) or vector-Jacobian product (MODE 2) in one sweep
+// ---------------------------------------------------------------------------
+// Per application a weight w_a: MODE 1 sign(T_a - m_a) / m_a over finite
+// totals and measurements m_a > 0 (its |T_a - m_a| / m_a and a count go to
+// the loss), MODE 2 the supplied dL/dT_app.  A row j of application a then
+// contributes w_a n_exec_j kappa_cls(j) dT_kernel,j/dtheta to the theta
+// gradient and w_a times n_exec (n_kern - 1), n_exec T_kernel (per class),
+// n_exec h2d, n_exec d2h and n_exec x transfers to the segment-parameter sums
+// (the derivatives of the segment time, Eq. (15)).  In MODE 1 a total within
+// 1e-5 of its measurement gets weight 0 here and is flagged for the float64
+// pass (returned in `near`).
+template <int MODE>
+__device__ inline float app_weight(double T, float mv, float* acc, bool& near)
+{
+    near = false;
+    if (!(T - T == 0.0)) return 0.0f;   // NaN or infinite total
+    if (MODE == 2) return mv;
+    if (!(mv > 0.0f && mv < __builtin_huge_valf())) return 0.0f;
+    // 1/m: the float32 reciprocal refined by two float64 Newton steps (~1e-15)
+    const double m = mv, r0 = (double)__builtin_amdgcn_rcpf(mv);
+    const double r1 = r0 * (2.0 - m * r0);
+    const double im = r1 * (2.0 - m * r1);
+    if (__builtin_fabs(T * im - 1.0) <= 1e-5) {
+        near = true;
+        return 0.0f;
+    }
+    acc[0] += (float)(__builtin_fabs(T - m) * im);
+    acc[1] += 1.0f;
+    return (float)(T > m ? im : (T < m ? -im : 0.0));
+}
+
+// One row's terms for an application weight wa != 0 and an evaluated
+// (finite) kernel: the kernel model's Jacobian row times wa n_exec kappa into
+// acc -- or, within 1e-5 of one of its max/min switches, a flag for the
+// float64 pass with that weight kept in wrow[j] -- and the segment-parameter
+// sums into sacc.
+__device__ inline void app_row_terms(const Set& S, const SegSet& Q, const Eval<float>& E, const SegRow& r,
+                                     float wa, int64_t j, float* acc, float* sacc, uint64_t* rflags,
+                                     float* wrow)
+{
+    const float wr = wa * r.ne * kappa_of(Q.f, r.c);
+    if (E.near_kink) {
+        wrow[j] = wr;
+        atomicOr((unsigned long long*)(rflags + (j >> 6)), 1ull << (j & 63));
+    } else {
+        accumulate_partials<float>(S.st, S.cf, E, wr, acc);
+    }
+    sacc[0] += wa * (r.ne * (float)(r.nk - 1));
+    const float v = wa * (r.ne * E.T);
+    sacc[1] += r.c == 0 ? v : 0.0f;
+    sacc[2] += r.c == 1 ? v : 0.0f;
+    sacc[3] += r.c == 2 ? v : 0.0f;
+    sacc[4] += r.c == 3 ? v : 0.0f;
+    if (r.h > 0.0f) {
+        sacc[5] += wa * (r.ne * r.h);
+        sacc[7] += wa * r.ne;
+    }
+    if (r.dd > 0.0f) {
+        sacc[6] += wa * (r.ne * r.dd);
+        sacc[7] += wa * r.ne;
+    }
+}
+
+// float64 sum of one value over the block (fixed order); every thread gets it
+template <int BLOCK>
+__device__ inline double block_total(double v, double* lds /* [BLOCK / 64] */)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
+    __syncthreads();
+    return s;
+}
+
+// The block's kAppRow float64 sums of the lanes' float32 partial sums: the 26
+// loss / count / theta columns by the recursive-halving block reduction, the
+// eight segment sums by a plain one (fixed order throughout).
+__device__ inline void store_row(const float* acc, const float* sacc, double* lds, double* row)
+{
+    double a64[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) a64[j] = (double)acc[j];
+    block_reduce_acc(a64, lds, row);
+    double s64[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s64[j] = (double)sacc[j];
+    block_sum<8>(s64, lds, row + kAcc);
+}
+
+// The one-pass sweep.  A block takes BLOCK consecutive applications and walks
+// them in application-aligned pieces of at most BLOCK rows, one row per
+// thread: the thread evaluates its row (kernel model with its derivative
+// terms) and keeps it in registers while the owner threads add their
+// applications' segment times from LDS in float64 and form the weights; then
+// each row thread adds its own row's weighted terms.  So every row is read
+// from HBM once.  An application longer than BLOCK rows is flagged in lflags
+// (one ballot word per 64 applications) for k_apps_long.  Near-switch rows are flagged in
+// rflags (one bit per row; cleared before the launch) with their weight in
+// wrow; near-T = m applications (MODE 1) in aflags (one ballot word per 64
+// applications, written once).  Per block one row of kAppRow float64 sums:
+// loss, count, theta gradient, segment-parameter sums.
+template <int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int64_t n_seg,
                                                     int64_t n_apps, Set S, SegSet Q,
                                                     const float* __restrict__ meas,
-                                                    const uint64_t* __restrict__ aflags,
-                                                    const double* __restrict__ rows1, int nrows1,
-                                                    float* __restrict__ wseg,
-                                                    double* __restrict__ rows2)
+                                                    double* __restrict__ rows, uint64_t* __restrict__ aflags,
+                                                    uint64_t* __restrict__ lflags, uint64_t* __restrict__ rflags,
+                                                    float* __restrict__ wrow)
 {
-    __shared__ double red[4 * kAppAcc];
-    double acc[kAppAcc];
+    __shared__ float ts[BLOCK];
+    __shared__ uint16_t own[BLOCK];
+    __shared__ int32_t lo_s[BLOCK], hi_s[BLOCK];
+    __shared__ float wa_s[BLOCK];
+    __shared__ double red[(BLOCK / 64) * kAppRow];
+    float acc[kAcc], sacc[8];   // the lane's partial sums; float64 from the block reduction on
 #pragma unroll
-    for (int j = 0; j < kAppAcc; ++j) acc[j] = 0.0;
-    for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < kAppAcc; ++j) acc[j] += rows1[(int64_t)r * kAppAcc + j];
+    for (int j = 0; j < 8; ++j) sacc[j] = 0.0f;
+    const int tid = threadIdx.x;
+    const float inf = __builtin_huge_valf();
+    const int64_t nchunks = (n_apps + BLOCK - 1) / BLOCK;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t a = ch * BLOCK + tid;
+        const int64_t left = n_apps - ch * BLOCK;
+        const int na = left < BLOCK ? (int)left : BLOCK;
+        int32_t lo = 0, hi = 0;
+        float mv = 0.0f;   // the application's measurement (MODE 1) or dL/dT_app (MODE 2)
+        if (tid < na) {
+            int64_t x = sg.off[a], y = sg.off[a + 1];
+            x = x < 0 ? 0 : (x > n_seg ? n_seg : x);
+            y = y < x ? x : (y > n_seg ? n_seg : y);
+            lo = (int32_t)x;
+            hi = (int32_t)y;
+            mv = meas[a];
+        }
+        lo_s[tid] = lo;
+        hi_s[tid] = hi;
+        __syncthreads();
+        bool near_mine = false, long_mine = false;
+        int t0 = 0;   // first application of the next piece (uniform over the block)
+        while (t0 < na) {
+            const int32_t p0 = lo_s[t0];
+            // an application longer than a piece becomes an empty piece here
+            // (one control path, so the loop-carried sums keep one register
+            // set) and is left to k_apps_long
+            const bool too_long = hi_s[t0] - p0 > BLOCK;
+            if (too_long && tid == t0) long_mine = true;
+            // the applications t0 .. t1 whose rows end within BLOCK rows of p0
+            int t1 = t0, hi_i = too_long ? t0 : na - 1;
+            while (t1 < hi_i) {
+                const int mid = (t1 + hi_i + 1) >> 1;
+                if (hi_s[mid] - p0 <= BLOCK) t1 = mid;
+                else hi_i = mid - 1;
+            }
+            int32_t pend = too_long ? p0 : hi_s[t1];
+            pend = pend < p0 ? p0 : (pend - p0 > BLOCK ? p0 + BLOCK : pend);
+            const int32_t j = p0 + tid;
+            const bool row = j < pend;
+            Eval<float> E;
+            SegRow r;
+            float tsv = 0.0f;
+            if (row) {
+                r = load_seg(sg, j);
+                evaluate<float, true>(S.st, S.cf, load_desc(d, j), E);
+                tsv = seg_time<float>(E.T, r, Q.f, S.cf.ov[0]);
+            }
+            ts[tid] = tsv;
+            own[tid] = 0xFFFFu;
+            __syncthreads();
+            if (!too_long && tid >= t0 && tid <= t1) {
+                const int32_t jb = lo > p0 ? lo : p0, je = hi < pend ? hi : pend;
+                double T = 0.0;
+                int32_t k = jb;
+                for (; k + 3 < je; k += 4) {   // four reads in flight, added in row order
+                    const float x0 = ts[k - p0], x1 = ts[k + 1 - p0], x2 = ts[k + 2 - p0], x3 = ts[k + 3 - p0];
+                    T += (double)x0;
+                    T += (double)x1;
+                    T += (double)x2;
+                    T += (double)x3;
+                }
+                for (; k < je; ++k) T += (double)ts[k - p0];
+                for (k = jb; k < je; ++k) own[k - p0] = (uint16_t)tid;
+                bool nr;
+                wa_s[tid] = app_weight<MODE>(T, mv, acc, nr);
+                near_mine = near_mine || nr;
+            }
+            __syncthreads();
+            if (row && own[tid] != 0xFFFFu) {
+                const float wa = wa_s[own[tid]];
+                if (wa != 0.0f && E.T < inf) app_row_terms(S, Q, E, r, wa, j, acc, sacc, rflags, wrow);
+            }
+            __syncthreads();   // ts, own and wa_s are rewritten by the next piece
+            t0 = t1 + 1;
+        }
+        const uint64_t lw = __ballot(long_mine);
+        if ((tid & 63) == 0 && a < n_apps) lflags[a >> 6] = lw;
+        if (MODE == 1) {
+            const uint64_t fw = __ballot(near_mine);
+            if ((tid & 63) == 0 && a < n_apps) aflags[a >> 6] = fw;
+        }
+        __syncthreads();   // lo_s / hi_s are rewritten by the next chunk
     }
+    store_row(acc, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
+}
+
+// Applications longer than a piece (flagged in lflags by the sweep), one at
+// a time per block: the block walks the rows once for the total, forms the
+// weight, and walks them again for the weighted terms.  Near-T = m
+// applications set their aflags bit (after the sweep wrote the words), near-
+// switch rows their rflags bit.  Per block one row of kAppRow float64 sums.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apps_long(DescPtrs d, SegPtrs sg, int64_t n_seg, int64_t n_apps,
+                                                    Set S, SegSet Q, const float* __restrict__ meas,
+                                                    const uint64_t* __restrict__ lflags,
+                                                    uint64_t* __restrict__ aflags, uint64_t* __restrict__ rflags,
+                                                    float* __restrict__ wrow, double* __restrict__ rows)
+{
+    __shared__ double red[4 * kAppRow];
+    __shared__ float wa_s;
+    __shared__ uint64_t words[256];
+    float acc[kAcc], sacc[8];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sacc[j] = 0.0f;
+    const float inf = __builtin_huge_valf();
     const int64_t nwords = (n_apps + 63) >> 6;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t wi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < nwords; wi += stride) {
-        uint64_t fw = aflags[wi];
+    // block b takes flag words [256 b, 256 b + 256), [256 (b + grid), ...),
+    // staged in LDS by one parallel load, then walked in index order
+    for (int64_t w0 = (int64_t)blockIdx.x * 256; w0 < nwords; w0 += (int64_t)gridDim.x * 256) {
+        const int64_t wt = w0 + threadIdx.x;
+        const uint64_t mine = wt < nwords ? lflags[wt] : 0ull;
+        words[threadIdx.x] = mine;
+        if (!__syncthreads_or(mine != 0ull)) continue;   // no long application in this group
+        for (int q = 0; q < 256; ++q) {
+        uint64_t fw = words[q];
+        const int64_t wi = w0 + q;
         while (fw) {
             const int bit = __builtin_ctzll(fw);
             fw &= fw - 1;
@@ -307,122 +401,205 @@ __global__ __launch_bounds__(256) void k_apps_redo(DescPtrs d, SegPtrs sg, int64
             int64_t lo = sg.off[a], hi = sg.off[a + 1];
             lo = lo < 0 ? 0 : (lo > n_seg ? n_seg : lo);
             hi = hi < lo ? lo : (hi > n_seg ? n_seg : hi);
-            double T = 0.0, sk[4] = {0.0, 0.0, 0.0, 0.0}, sl = 0.0, sh = 0.0, sd = 0.0, sn = 0.0;
-            for (int64_t j = lo; j < hi; ++j) {
-                Eval<double> E;
-                evaluate<double, false>(S.st, S.cd, widen(load_desc(d, j)), E);
-                const SegRow r = load_seg(sg, j);
-                T += seg_time<double>(E.T, r, Q.d, S.cd.ov[0]);
-                const double ne = r.ne;
-                const double v = ne * E.T;
-                sk[0] += r.c == 0 ? v : 0.0;
-                sk[1] += r.c == 1 ? v : 0.0;
-                sk[2] += r.c == 2 ? v : 0.0;
-                sk[3] += r.c == 3 ? v : 0.0;
-                sl += ne * (double)(r.nk - 1);
-                sh += r.h > 0.0f ? ne * (double)r.h : 0.0;
-                sd += r.dd > 0.0f ? ne * (double)r.dd : 0.0;
-                sn += ne * (double)((int)(r.h > 0.0f) + (int)(r.dd > 0.0f));
+            double part = 0.0;
+            for (int64_t j = lo + threadIdx.x; j < hi; j += 256) {
+                Eval<float> E;
+                evaluate<float, false>(S.st, S.cf, load_desc(d, j), E);
+                part += (double)seg_time<float>(E.T, load_seg(sg, j), Q.f, S.cf.ov[0]);
             }
-            const double m = meas[a], im = 1.0 / m;
-            float wa = 0.0f;
-            if (T - T == 0.0) {
-                const double w = T > m ? im : (T < m ? -im : 0.0);
-                acc[0] += __builtin_fabs(T - m) * im;
-                acc[1] += 1.0;
-                acc[2] += w * sl;
-                acc[3] += w * sk[0];
-                acc[4] += w * sk[1];
-                acc[5] += w * sk[2];
-                acc[6] += w * sk[3];
-                acc[7] += w * sh;
-                acc[8] += w * sd;
-                acc[9] += w * sn;
-                wa = (float)w;
+            const double T = block_total<256>(part, red);
+            if (threadIdx.x == 0) {
+                bool nr;
+                wa_s = app_weight<MODE>(T, meas[a], acc, nr);
+                if (MODE == 1 && nr) atomicOr((unsigned long long*)(aflags + wi), 1ull << bit);
             }
-            for (int64_t j = lo; j < hi; ++j)
-                wseg[j] = wa != 0.0f ? wa * sg.n_exec[j] * kappa_of(Q.f, sg.cls[j]) : 0.0f;
+            __syncthreads();
+            const float wa = wa_s;
+            __syncthreads();
+            if (wa == 0.0f) continue;
+            for (int64_t j = lo + threadIdx.x; j < hi; j += 256) {
+                Eval<float> E;
+                evaluate<float, true>(S.st, S.cf, load_desc(d, j), E);
+                if (E.T < inf) app_row_terms(S, Q, E, load_seg(sg, j), wa, j, acc, sacc, rflags, wrow);
+            }
         }
+        }
+        __syncthreads();   // words[] is rewritten by the next group
     }
-    block_sum<kAppAcc>(acc, red, rows2 + (int64_t)blockIdx.x * kAppAcc);
+    store_row(acc, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
 }
 
-// Final fixed-order reduction: the gradient sweep's nb2 rows of kAcc columns
-// (sum of wseg_j dTk_j/dtheta) and the application sweep's rows of kAppAcc
-// columns, into [loss, count, grad theta[24], grad seg params[7]] divided by
-// the count.
-__global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ grows, int ng,
-                                                     const double* __restrict__ arows, int na,
-                                                     SegSet Q, int vjp, double* __restrict__ out)
+// The float64 pass: block b folds the sweep's rows b, b + gridDim.x, ...
+// (fixed order); then (MODE 1) every application flagged near T = m is done
+// in full in float64 by one wave, its lanes over the rows -- total, weight,
+// loss, the rows' Jacobian terms and segment sums -- and every row flagged
+// near a max/min switch (in an
+// application decided in float32) adds its float64 Jacobian row times the
+// weight kept in wrow.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apps_grad_redo(DescPtrs d, SegPtrs sg, int64_t n_seg,
+                                                         int64_t n_apps, Set S, SegSet Q,
+                                                         const float* __restrict__ meas,
+                                                         const uint64_t* __restrict__ aflags,
+                                                         const uint64_t* __restrict__ rflags,
+                                                         const float* __restrict__ wrow,
+                                                         const double* __restrict__ rows1, int nrows1,
+                                                         double* __restrict__ rows2)
 {
-    __shared__ double red[4 * kAcc];
-    __shared__ double tg[kAcc], ta[kAppAcc];
-    {
-        double acc[kAcc];
+    __shared__ double red[4 * kAppRow];
+    double acc[kAppRow];
 #pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-        for (int r = threadIdx.x; r < ng; r += blockDim.x)
+    for (int j = 0; j < kAppRow; ++j) acc[j] = 0.0;
+    for (int r = blockIdx.x + gridDim.x * threadIdx.x; r < nrows1; r += gridDim.x * blockDim.x) {
 #pragma unroll
-            for (int j = 0; j < kAcc; ++j) acc[j] += grows[(int64_t)r * kAcc + j];
-        block_sum<kAcc>(acc, red, tg);
+        for (int j = 0; j < kAppRow; ++j) acc[j] += rows1[(int64_t)r * kAppRow + j];
     }
-    {
-        double acc[kAppAcc];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (MODE == 1) {
+        // one wave per flagged application, its lanes over the rows
+        const int lane = threadIdx.x & 63;
+        const int64_t nwords = (n_apps + 63) >> 6;
+        for (int64_t wi = t0 >> 6; wi < nwords; wi += stride >> 6) {
+            uint64_t fw = aflags[wi];
+            while (fw) {
+                const int bit = __builtin_ctzll(fw);
+                fw &= fw - 1;
+                const int64_t a = (wi << 6) + bit;
+                int64_t lo = sg.off[a], hi = sg.off[a + 1];
+                lo = lo < 0 ? 0 : (lo > n_seg ? n_seg : lo);
+                hi = hi < lo ? lo : (hi > n_seg ? n_seg : hi);
+                double part = 0.0;
+                for (int64_t j = lo + lane; j < hi; j += 64) {
+                    Eval<double> E;
+                    evaluate<double, false>(S.st, S.cd, widen(load_desc(d, j)), E);
+                    part += seg_time<double>(E.T, load_seg(sg, j), Q.d, S.cd.ov[0]);
+                }
+                // butterfly: every lane ends with the same (fixed-order) total
 #pragma unroll
-        for (int j = 0; j < kAppAcc; ++j) acc[j] = 0.0;
-        for (int r = threadIdx.x; r < na; r += blockDim.x)
-#pragma unroll
-            for (int j = 0; j < kAppAcc; ++j) acc[j] += arows[(int64_t)r * kAppAcc + j];
-        block_sum<kAppAcc>(acc, red, ta);
+                for (int m = 32; m >= 1; m >>= 1) part += __shfl_xor(part, m, 64);
+                const double T = part;
+                const double m = meas[a];
+                if (!(T - T == 0.0)) continue;
+                const double im = 1.0 / m;
+                const double w = T > m ? im : (T < m ? -im : 0.0);
+                if (lane == 0) {
+                    acc[0] += __builtin_fabs(T - m) * im;
+                    acc[1] += 1.0;
+                }
+                if (w == 0.0) continue;
+                for (int64_t j = lo + lane; j < hi; j += 64) {
+                    Eval<double> E;
+                    evaluate<double, true>(S.st, S.cd, widen(load_desc(d, j)), E);
+                    if (!(E.T < __builtin_huge_val())) continue;
+                    const SegRow r = load_seg(sg, j);
+                    const double ne = r.ne;
+                    accumulate_partials<double>(S.st, S.cd, E, w * ne * kappa_of(Q.d, r.c), acc);
+                    double* sa = acc + kAcc;
+                    sa[0] += w * (ne * (double)(r.nk - 1));
+                    const double v = w * (ne * E.T);
+                    sa[1] += r.c == 0 ? v : 0.0;
+                    sa[2] += r.c == 1 ? v : 0.0;
+                    sa[3] += r.c == 2 ? v : 0.0;
+                    sa[4] += r.c == 3 ? v : 0.0;
+                    if (r.h > 0.0f) {
+                        sa[5] += w * (ne * (double)r.h);
+                        sa[7] += w * ne;
+                    }
+                    if (r.dd > 0.0f) {
+                        sa[6] += w * (ne * (double)r.dd);
+                        sa[7] += w * ne;
+                    }
+                }
+            }
+        }
     }
+    const int64_t rwords = (n_seg + 63) >> 6;
+    for (int64_t wi = t0; wi < rwords; wi += stride) {
+        uint64_t fw = rflags[wi];
+        while (fw) {
+            const int bit = __builtin_ctzll(fw);
+            fw &= fw - 1;
+            const int64_t j = (wi << 6) + bit;
+            Eval<double> E;
+            evaluate<double, true>(S.st, S.cd, widen(load_desc(d, j)), E);
+            if (E.T < __builtin_huge_val()) accumulate_partials<double>(S.st, S.cd, E, (double)wrow[j], acc);
+        }
+    }
+    block_sum<kAppRow>(acc, red, rows2 + (int64_t)blockIdx.x * kAppRow);
+}
+
+// Final fixed-order reduction of the float64 pass's rows into [loss, count,
+// grad theta[24], grad seg params[7]] divided by the count (vjp = 0), or the
+// plain sums [grad theta[24], grad seg params[7]] (vjp = 1).
+__global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ rows, int nrows, SegSet Q,
+                                                     int vjp, double* __restrict__ out)
+{
+    __shared__ double red[4 * kAppRow];
+    __shared__ double tot[kAppRow];
+    double acc[kAppRow];
+#pragma unroll
+    for (int j = 0; j < kAppRow; ++j) acc[j] = 0.0;
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < kAppRow; ++j) acc[j] += rows[(int64_t)r * kAppRow + j];
+    block_sum<kAppRow>(acc, red, tot);
+    __syncthreads();
+    const double* sa = tot + kAcc;   // extra launches, kappa[4], h2d, d2h, transfers
     const int t = threadIdx.x;
     if (vjp) {
-        // [grad theta[24], grad seg params[7]], plain sums
         if (t >= kTheta + kSegParams) return;
         double v;
-        if (t < kTheta) v = tg[2 + t] + (t == 13 ? ta[2] : 0.0);
-        else if (t < kTheta + 4) v = ta[3 + (t - kTheta)];
-        else if (t == kTheta + 4) v = -ta[7] * Q.inv_bw2_h2d;
-        else if (t == kTheta + 5) v = -ta[8] * Q.inv_bw2_d2h;
-        else v = ta[9];
+        if (t < kTheta) v = tot[2 + t] + (t == 13 ? sa[0] : 0.0);
+        else if (t < kTheta + 4) v = sa[1 + (t - kTheta)];
+        else if (t == kTheta + 4) v = -sa[5] * Q.inv_bw2_h2d;
+        else if (t == kTheta + 5) v = -sa[6] * Q.inv_bw2_d2h;
+        else v = sa[7];
         out[t] = v;
         return;
     }
     if (t >= kAppsOut) return;
-    const double c = ta[1];
+    const double c = tot[1];
     const double ic = c > 0.0 ? 1.0 / c : 0.0;
     double v;
-    if (t == 0) v = ta[0] * ic;
+    if (t == 0) v = tot[0] * ic;
     else if (t == 1) v = c;
-    else if (t < kAcc) v = (tg[t] + (t == 2 + 13 ? ta[2] : 0.0)) * ic;
-    else if (t < kAcc + 4) v = ta[3 + (t - kAcc)] * ic;
-    else if (t == kAcc + 4) v = -ta[7] * Q.inv_bw2_h2d * ic;
-    else if (t == kAcc + 5) v = -ta[8] * Q.inv_bw2_d2h * ic;
-    else v = ta[9] * ic;
+    else if (t < kAcc) v = (tot[t] + (t == 2 + 13 ? sa[0] : 0.0)) * ic;
+    else if (t < kAcc + 4) v = sa[1 + (t - kAcc)] * ic;
+    else if (t == kAcc + 4) v = -sa[5] * Q.inv_bw2_h2d * ic;
+    else if (t == kAcc + 5) v = -sa[6] * Q.inv_bw2_d2h * ic;
+    else v = sa[7] * ic;
     out[t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_zero_words(uint64_t* __restrict__ w, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0;
 }
 
 template <int BLOCK, int MODE>
 static int apps_grid(int64_t n_apps, int grid_mult)
 {
     const int64_t chunks = (n_apps + BLOCK - 1) / BLOCK;
-    int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_apps<BLOCK, MODE>), BLOCK) *
-                (grid_mult < 1 ? 1 : grid_mult);
+    const void* k = MODE == 0 ? reinterpret_cast<const void*>(&k_apps<BLOCK, 0>)
+                              : (MODE == 1 ? reinterpret_cast<const void*>(&k_apps_grad<BLOCK, 1>)
+                                           : reinterpret_cast<const void*>(&k_apps_grad<BLOCK, 2>));
+    int64_t b = (int64_t)resident_blocks(k, BLOCK) * (grid_mult < 1 ? 1 : grid_mult);
     b = b < chunks ? b : chunks;
     b = b < kAppsMaxBlocks ? b : kAppsMaxBlocks;
     return (int)(b < 1 ? 1 : b);
 }
 
-template <int MODE>
-static hipError_t apps_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
-                         const Set& S, const SegSet& Q, const float* meas, float* T_app,
-                         float* T_seg, float* wseg, double* rows, uint64_t* aflags,
-                         const LaunchCfg& c, hipStream_t s)
+hipError_t launch_predict_apps(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                               const Set& S, const SegSet& Q, float* T_app, float* T_seg,
+                               const LaunchCfg& c, hipStream_t s)
 {
-#define WM_APPS_CASE(B)                                                                        \
-    case B:                                                                                    \
-        k_apps<B, MODE><<<apps_grid<B, MODE>(n_apps, c.grid_mult), B, 0, s>>>(                 \
-            d, sg, n_seg, n_apps, S, Q, meas, T_app, T_seg, wseg, rows, aflags);               \
+    if (n_apps <= 0) return hipSuccess;
+#define WM_APPS_CASE(B)                                                                               \
+    case B:                                                                                           \
+        k_apps<B, 0><<<apps_grid<B, 0>(n_apps, c.grid_mult), B, 0, s>>>(d, sg, n_seg, n_apps, S, Q,  \
+                                                                       T_app, T_seg);                \
         break;
     switch (c.block) {
         WM_APPS_CASE(64)
@@ -435,72 +612,71 @@ static hipError_t apps_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, in
     return hipGetLastError();
 }
 
-hipError_t launch_predict_apps(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
-                               const Set& S, const SegSet& Q, float* T_app, float* T_seg,
-                               const LaunchCfg& cfg, hipStream_t stream)
+int apps_redo_blocks(int64_t n_apps, int64_t n_seg)
 {
-    if (n_apps <= 0) return hipSuccess;
-    return apps_t<0>(d, sg, n_seg, n_apps, S, Q, nullptr, T_app, T_seg, nullptr, nullptr,
-                     nullptr, cfg, stream);
-}
-
-// Rows the application sweep of mode MODE writes for n_apps applications
-// (at least one).
-template <int MODE>
-static int apps_rows(int64_t n_apps, const LaunchCfg& c)
-{
-    switch (c.block) {
-    case 64: return apps_grid<64, MODE>(n_apps, c.grid_mult);
-    case 128: return apps_grid<128, MODE>(n_apps, c.grid_mult);
-    case 512: return apps_grid<512, MODE>(n_apps, c.grid_mult);
-    default: return apps_grid<256, MODE>(n_apps, c.grid_mult);
-    }
-}
-
-int apps_redo_blocks(int64_t n_apps)
-{
-    const int64_t b = ((n_apps + 63) / 64 + 255) / 256;
+    const int64_t words = ((n_apps > n_seg ? n_apps : n_seg) + 63) / 64;
+    const int64_t b = (words + 255) / 256;
     return (int)(b < 1 ? 1 : (b > kRedoMaxBlocks ? kRedoMaxBlocks : b));
 }
 
-hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg,
-                                 int64_t n_apps, const float* measured, const Set& S,
-                                 const SegSet& Q, float* wseg, double* app_rows, uint64_t* aflags,
-                                 double* partials, uint64_t* flags, const GradLayout& L,
-                                 const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
-                                 hipStream_t stream)
+template <int MODE>
+static hipError_t apps_grad_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                              const float* meas, const Set& S, const SegSet& Q, double* rows,
+                              uint64_t* aflags, uint64_t* lflags, uint64_t* rflags, float* wrow,
+                              const LaunchCfg& c, double* out, hipStream_t s)
 {
-    hipError_t e = apps_t<1>(d, sg, n_seg, n_apps, S, Q, measured, nullptr, nullptr, wseg,
-                             app_rows, aflags, cfg, stream);
+    const int64_t rwords = (n_seg + 63) / 64;
+    if (rwords > 0) {
+        const int64_t zb = (rwords + 255) / 256;
+        k_zero_words<<<(int)(zb < 1024 ? zb : 1024), 256, 0, s>>>(rflags, rwords);
+    }
+    int nb1 = 1;
+#define WM_APPS_CASE(B)                                                                               \
+    case B:                                                                                           \
+        nb1 = apps_grid<B, MODE>(n_apps, c.grid_mult);                                               \
+        k_apps_grad<B, MODE><<<nb1, B, 0, s>>>(d, sg, n_seg, n_apps, S, Q, meas, rows, aflags, lflags, \
+                                               rflags, wrow);                                        \
+        break;
+    switch (c.block) {
+        WM_APPS_CASE(64)
+        WM_APPS_CASE(128)
+        WM_APPS_CASE(256)
+        WM_APPS_CASE(512)
+    default: return hipErrorInvalidValue;
+    }
+#undef WM_APPS_CASE
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int na1 = apps_rows<1>(n_apps, cfg), na2 = apps_redo_blocks(n_apps);
-    double* rows2 = app_rows + (int64_t)na1 * kAppAcc;
-    k_apps_redo<<<na2, 256, 0, stream>>>(d, sg, n_seg, n_apps, S, Q, measured, aflags, app_rows,
-                                         na1, wseg, rows2);
+    k_apps_long<MODE><<<kAppsLongBlocks, 256, 0, s>>>(d, sg, n_seg, n_apps, S, Q, meas, lflags, aflags, rflags,
+                                                      wrow, rows + (int64_t)nb1 * kAppRow);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_grad(0, d, n_seg, wseg, S, nullptr, partials, flags, L, vjp_cfg, nullptr, stream);
+    const int nb2 = apps_redo_blocks(n_apps, n_seg);
+    const int nrows1 = nb1 + kAppsLongBlocks;
+    double* rows2 = rows + (int64_t)nrows1 * kAppRow;
+    k_apps_grad_redo<MODE><<<nb2, 256, 0, s>>>(d, sg, n_seg, n_apps, S, Q, meas, aflags, rflags, wrow, rows,
+                                               nrows1, rows2);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nb = grad_grid(0, false, n_seg, vjp_cfg);
-    k_apps_reduce<<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, rows2, na2, Q, 0, out);
+    k_apps_reduce<<<1, 256, 0, s>>>(rows2, nb2, Q, MODE == 2 ? 1 : 0, out);
     return hipGetLastError();
 }
 
-hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
-                           const float* w_app, const Set& S, const SegSet& Q, float* wseg,
-                           double* app_rows, double* partials, uint64_t* flags, const GradLayout& L,
-                           const LaunchCfg& cfg, const LaunchCfg& vjp_cfg, double* out,
-                           hipStream_t stream)
+hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                                 const float* measured, const Set& S, const SegSet& Q, double* rows,
+                                 uint64_t* aflags, uint64_t* lflags, uint64_t* rflags, float* wrow,
+                                 const LaunchCfg& cfg, double* out, hipStream_t stream)
 {
-    hipError_t e = apps_t<2>(d, sg, n_seg, n_apps, S, Q, w_app, nullptr, nullptr, wseg, app_rows,
-                             nullptr, cfg, stream);
-    if (e != hipSuccess) return e;
-    e = launch_grad(0, d, n_seg, wseg, S, nullptr, partials, flags, L, vjp_cfg, nullptr, stream);
-    if (e != hipSuccess) return e;
-    const int nb = grad_grid(0, false, n_seg, vjp_cfg);
-    k_apps_reduce<<<1, 256, 0, stream>>>(partials + (int64_t)nb * kAcc, L.nb2, app_rows,
-                                         apps_rows<2>(n_apps, cfg), Q, 1, out);
-    return hipGetLastError();
+    return apps_grad_t<1>(d, sg, n_seg, n_apps, measured, S, Q, rows, aflags, lflags, rflags, wrow, cfg, out,
+                          stream);
+}
+
+hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,
+                           const float* w_app, const Set& S, const SegSet& Q, double* rows, uint64_t* lflags,
+                           uint64_t* rflags, float* wrow, const LaunchCfg& cfg, double* out, hipStream_t stream)
+{
+    return apps_grad_t<2>(d, sg, n_seg, n_apps, w_app, S, Q, rows, nullptr, lflags, rflags, wrow, cfg, out,
+                          stream);
 }
 
 }  // namespace wm
