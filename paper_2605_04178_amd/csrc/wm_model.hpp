@@ -127,6 +127,19 @@ __device__ inline uint32_t udiv_small(uint32_t a, uint32_t b)
     return q;
 }
 
+// A copy of v in a vector register that the optimiser cannot see through.
+// A per-lane select among parameters (the peak of the descriptor's dtype,
+// the scale of a segment's class) written on such copies stays a register
+// select; on the parameters themselves the compiler may turn it into a
+// per-lane indexed load from the kernel-argument segment, a vector memory
+// access with its latency inside the evaluation.
+template <typename R>
+__device__ inline R vreg(R v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 template <typename R>
 struct Desc {
     R F, B, r1, r2, r3, K, u, W;
@@ -252,7 +265,7 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
         // value, no cancellation near C
         R x = reg == 1 ? (c.c_llc - Wm) * c.inv_span : c.c_llc * A::rcp(Wm);
         x = reg == 0 ? (R)1 : x;
-        const R y = reg == 1 ? c.alpha : c.beta;
+        const R y = reg == 1 ? vreg(c.alpha) : vreg(c.beta);
         const R l2 = A::lg2(x);
         h3 = x > (R)0 ? A::ex2(y * l2) : (R)0;
         E.llc_regime = reg;
@@ -278,11 +291,20 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
                       : s1 * c.latf[0] + s2 * c.latf[1] + s3 * c.latf[2] + sh * c.latf[3];
 
     // stage times
-    R ip = c.inv_peak[0];
-    ip = dt == 1 ? c.inv_peak[1] : ip;
-    ip = dt == 2 ? c.inv_peak[2] : ip;
-    ip = dt == 3 ? c.inv_peak[3] : ip;
-    ip = dt == 4 ? c.inv_peak[4] : ip;
+    R ip;
+    if (TILE) {   // dtype uniform over the wave: scalar selects
+        ip = c.inv_peak[0];
+        ip = dt == 1 ? c.inv_peak[1] : ip;
+        ip = dt == 2 ? c.inv_peak[2] : ip;
+        ip = dt == 3 ? c.inv_peak[3] : ip;
+        ip = dt == 4 ? c.inv_peak[4] : ip;
+    } else {
+        ip = vreg(c.inv_peak[0]);
+        ip = dt == 1 ? vreg(c.inv_peak[1]) : ip;
+        ip = dt == 2 ? vreg(c.inv_peak[2]) : ip;
+        ip = dt == 3 ? vreg(c.inv_peak[3]) : ip;
+        ip = dt == 4 ? vreg(c.inv_peak[4]) : ip;
+    }
     const R Tc = TILE ? d.F * ip : d.F * ip * A::rcp(d.u);
     const R iS = A::rcp(S);
     const R Tb = d.B * iS;

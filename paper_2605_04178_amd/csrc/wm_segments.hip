@@ -41,10 +41,10 @@ __device__ inline bool seg_row_valid(const SegRow& r)
 template <typename R>
 __device__ inline R kappa_of(const SegConst<R>& q, int32_t c)
 {
-    R k = q.kappa[0];
-    k = c == 1 ? q.kappa[1] : k;
-    k = c == 2 ? q.kappa[2] : k;
-    k = c == 3 ? q.kappa[3] : k;
+    R k = vreg(q.kappa[0]);
+    k = c == 1 ? vreg(q.kappa[1]) : k;
+    k = c == 2 ? vreg(q.kappa[2]) : k;
+    k = c == 3 ? vreg(q.kappa[3]) : k;
     return k;
 }
 
@@ -125,12 +125,15 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
         __syncthreads();
         const int32_t sb = lo_s[0], se = hi_s[na - 1];
         double tot = 0.0;
-        for (int32_t pb = sb; pb < se; pb += CAP) {
+        // row indices stay below n_seg < 2^31: loops step by offsets within
+        // a piece, so no sum can pass 2^31 - 1
+        for (int32_t pb = sb; pb < se; pb = se - pb > CAP ? pb + CAP : se) {
             const int32_t pe = se - pb < CAP ? se : pb + CAP;
             // rows are visited from a 64-row boundary so that every wave's
             // loads cover whole cache lines (the rows before pb are skipped)
-            for (int32_t j = (pb & ~63) + tid; j < pe; j += BLOCK) {
-                if (j < pb) continue;
+            for (int32_t jj = (pb & ~63) - pb + tid; jj < pe - pb; jj += BLOCK) {
+                if (jj < 0) continue;
+                const int32_t j = pb + jj;
                 const Desc<float> x = load_desc(d, j);
                 const SegRow r = load_seg(sg, j);
                 Eval<float> E;
@@ -188,16 +191,16 @@ __device__ inline float app_weight(double T, float mv, float* acc, bool& near)
 // acc -- or, within 1e-5 of one of its max/min switches, a flag for the
 // float64 pass with that weight kept in wrow[j] -- and the segment-parameter
 // sums into sacc.
-__device__ inline void app_row_terms(const Set& S, const SegSet& Q, const Eval<float>& E, const SegRow& r,
-                                     float wa, int64_t j, float* acc, float* sacc, uint64_t* rflags,
-                                     float* wrow)
+__device__ inline void app_row_terms(const Struct& st, const Const<float>& cf, const SegConst<float>& qf,
+                                     const Eval<float>& E, const SegRow& r, float wa, int64_t j, float* acc,
+                                     float* sacc, uint64_t* rflags, float* wrow)
 {
-    const float wr = wa * r.ne * kappa_of(Q.f, r.c);
+    const float wr = wa * r.ne * kappa_of(qf, r.c);
     if (E.near_kink) {
         wrow[j] = wr;
         atomicOr((unsigned long long*)(rflags + (j >> 6)), 1ull << (j & 63));
     } else {
-        accumulate_partials<float>(S.st, S.cf, E, wr, acc);
+        accumulate_partials<float>(st, cf, E, wr, acc);
     }
     sacc[0] += wa * (r.ne * (float)(r.nk - 1));
     const float v = wa * (r.ne * E.T);
@@ -304,17 +307,24 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
             // set) and is left to k_apps_long
             const bool too_long = hi_s[t0] - p0 > BLOCK;
             if (too_long && tid == t0) long_mine = true;
-            // the applications t0 .. t1 whose rows end within BLOCK rows of p0
-            int t1 = t0, hi_i = too_long ? t0 : na - 1;
-            while (t1 < hi_i) {
-                const int mid = (t1 + hi_i + 1) >> 1;
-                if (hi_s[mid] - p0 <= BLOCK) t1 = mid;
-                else hi_i = mid - 1;
+            // the applications t0 .. t1 whose rows end within BLOCK rows of
+            // p0: each wave tests 64 candidates per step and takes the run of
+            // fits from t0 (a prefix: the ends do not decrease)
+            int t1 = t0;
+            if (!too_long) {
+                for (int base = t0;; base += 64) {
+                    const int t = base + (tid & 63);
+                    const uint64_t miss = ~__ballot(t < na && hi_s[t] - p0 <= BLOCK);
+                    if (miss != 0ull) {
+                        t1 = base + __builtin_ctzll(miss) - 1;
+                        break;
+                    }
+                }
             }
             int32_t pend = too_long ? p0 : hi_s[t1];
             pend = pend < p0 ? p0 : (pend - p0 > BLOCK ? p0 + BLOCK : pend);
-            const int32_t j = p0 + tid;
-            const bool row = j < pend;
+            const bool row = tid < pend - p0;
+            const int64_t j = (int64_t)p0 + tid;
             Eval<float> E;
             SegRow r;
             float tsv = 0.0f;
@@ -330,7 +340,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
                 const int32_t jb = lo > p0 ? lo : p0, je = hi < pend ? hi : pend;
                 double T = 0.0;
                 int32_t k = jb;
-                for (; k + 3 < je; k += 4) {   // four reads in flight, added in row order
+                for (; je - k > 3; k += 4) {   // four reads in flight, added in row order
                     const float x0 = ts[k - p0], x1 = ts[k + 1 - p0], x2 = ts[k + 2 - p0], x3 = ts[k + 3 - p0];
                     T += (double)x0;
                     T += (double)x1;
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
             __syncthreads();
             if (row && own[tid] != 0xFFFFu) {
                 const float wa = wa_s[own[tid]];
-                if (wa != 0.0f && E.T < inf) app_row_terms(S, Q, E, r, wa, j, acc, sacc, rflags, wrow);
+                if (wa != 0.0f && E.T < inf) app_row_terms(S.st, S.cf, Q.f, E, r, wa, j, acc, sacc, rflags, wrow);
             }
             __syncthreads();   // ts, own and wa_s are rewritten by the next piece
             t0 = t1 + 1;
@@ -420,7 +430,7 @@ __global__ __launch_bounds__(256) void k_apps_long(DescPtrs d, SegPtrs sg, int64
             for (int64_t j = lo + threadIdx.x; j < hi; j += 256) {
                 Eval<float> E;
                 evaluate<float, true>(S.st, S.cf, load_desc(d, j), E);
-                if (E.T < inf) app_row_terms(S, Q, E, load_seg(sg, j), wa, j, acc, sacc, rflags, wrow);
+                if (E.T < inf) app_row_terms(S.st, S.cf, Q.f, E, load_seg(sg, j), wa, j, acc, sacc, rflags, wrow);
             }
         }
         }
@@ -429,13 +439,81 @@ __global__ __launch_bounds__(256) void k_apps_long(DescPtrs d, SegPtrs sg, int64
     store_row(acc, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
 }
 
+// Block sum of kAppRow float64 accumulators (fixed order): the first 26 by
+// the halving reduction, the eight segment sums by a plain one.
+__device__ inline void block_row(double* acc, double* lds, double* row)
+{
+    block_reduce_acc(acc, lds, row);
+    block_sum<8>(acc + kAcc, lds, row + kAcc);
+}
+
+// The final fixed-order reduction of the float64 pass's rows into [loss,
+// count, grad theta[24], grad seg params[7]] divided by the count (vjp =
+// false), or the plain sums [grad theta[24], grad seg params[7]] (vjp).
+// Thread (g, c) for c < kAppRow and g < 7 adds column c of rows g, g + 7,
+// ... (34 consecutive threads read one row: coalesced); column c is then the
+// sum of its seven partials in g order.  nrows <= kRedoMaxBlocks; called by
+// a whole block of 256.
+__device__ inline void apps_final(const double* rows, int nrows, const SegSet& Q, bool vjp,
+                                  double* part /* [7 * kAppRow] */, double* tot /* [kAppRow] */, double* out)
+{
+    constexpr int G = 256 / kAppRow;
+    constexpr int K = (kRedoMaxBlocks + G - 1) / G;   // rows per thread at most
+    const int t = threadIdx.x;
+    if (t < G * kAppRow) {
+        const int g = t / kAppRow, c = t - g * kAppRow;
+        double x[K];   // every load in flight before the in-order additions
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int r = g + k * G;
+            x[k] = r < nrows ? rows[(int64_t)r * kAppRow + c] : 0.0;
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v += x[k];
+        part[g * kAppRow + c] = v;
+    }
+    __syncthreads();
+    if (t < kAppRow) {
+        double v = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) v += part[g * kAppRow + t];
+        tot[t] = v;
+    }
+    __syncthreads();
+    const double* sa = tot + kAcc;   // extra launches, kappa[4], h2d, d2h, transfers
+    if (vjp) {
+        if (t >= kTheta + kSegParams) return;
+        double v;
+        if (t < kTheta) v = tot[2 + t] + (t == 13 ? sa[0] : 0.0);
+        else if (t < kTheta + 4) v = sa[1 + (t - kTheta)];
+        else if (t == kTheta + 4) v = -sa[5] * Q.inv_bw2_h2d;
+        else if (t == kTheta + 5) v = -sa[6] * Q.inv_bw2_d2h;
+        else v = sa[7];
+        out[t] = v;
+        return;
+    }
+    if (t >= kAppsOut) return;
+    const double c = tot[1];
+    const double ic = c > 0.0 ? 1.0 / c : 0.0;
+    double v;
+    if (t == 0) v = tot[0] * ic;
+    else if (t == 1) v = c;
+    else if (t < kAcc) v = (tot[t] + (t == 2 + 13 ? sa[0] : 0.0)) * ic;
+    else if (t < kAcc + 4) v = sa[1 + (t - kAcc)] * ic;
+    else if (t == kAcc + 4) v = -sa[5] * Q.inv_bw2_h2d * ic;
+    else if (t == kAcc + 5) v = -sa[6] * Q.inv_bw2_d2h * ic;
+    else v = sa[7] * ic;
+    out[t] = v;
+}
+
 // The float64 pass: block b folds the sweep's rows b, b + gridDim.x, ...
 // (fixed order); then (MODE 1) every application flagged near T = m is done
 // in full in float64 by one wave, its lanes over the rows -- total, weight,
 // loss, the rows' Jacobian terms and segment sums -- and every row flagged
-// near a max/min switch (in an
-// application decided in float32) adds its float64 Jacobian row times the
-// weight kept in wrow.
+// near a max/min switch (in an application decided in float32) adds its
+// float64 Jacobian row times the weight kept in wrow.  Each block writes one
+// row to rows2.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_apps_grad_redo(DescPtrs d, SegPtrs sg, int64_t n_seg,
                                                          int64_t n_apps, Set S, SegSet Q,
@@ -456,39 +534,55 @@ __global__ __launch_bounds__(256) void k_apps_grad_redo(DescPtrs d, SegPtrs sg, 
     }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     if (MODE == 1) {
-        // one wave per flagged application, its lanes over the rows
-        const int lane = threadIdx.x & 63;
+        // Each wave loads 64 flag words at once and takes their flagged
+        // applications in batches of up to eight, in flag order: lane group
+        // grp = lane / 8 does application grp of the batch -- total, weight,
+        // loss, the rows' Jacobian terms and segment sums -- its eight lanes
+        // over the rows.
         const int64_t nwords = (n_apps + 63) >> 6;
-        for (int64_t wi = t0 >> 6; wi < nwords; wi += stride >> 6) {
-            uint64_t fw = aflags[wi];
-            while (fw) {
-                const int bit = __builtin_ctzll(fw);
-                fw &= fw - 1;
-                const int64_t a = (wi << 6) + bit;
-                int64_t lo = sg.off[a], hi = sg.off[a + 1];
-                lo = lo < 0 ? 0 : (lo > n_seg ? n_seg : lo);
-                hi = hi < lo ? lo : (hi > n_seg ? n_seg : hi);
+        const int grp = lane >> 3, sub = lane & 7;
+        for (int64_t w0 = (t0 >> 6) << 6; w0 < nwords; w0 += stride) {
+            const int64_t wl = w0 + lane;
+            uint64_t rem = wl < nwords ? aflags[wl] : 0ull;   // this lane's flags not yet taken
+            for (uint64_t todo = __ballot(rem != 0ull); todo; todo = __ballot(rem != 0ull)) {
+                int64_t my_app = -1;
+                for (int nb = 0; nb < 8 && todo; ++nb) {
+                    const int q = __builtin_ctzll(todo);
+                    const uint64_t fw = __shfl(rem, q, 64);
+                    if (grp == nb) my_app = ((w0 + q) << 6) + __builtin_ctzll(fw);
+                    if (lane == q) rem &= rem - 1;
+                    if ((fw & (fw - 1)) == 0ull) todo &= todo - 1;   // lane q has no more
+                }
+                int64_t lo = 0, hi = 0;
+                if (my_app >= 0) {
+                    lo = sg.off[my_app];
+                    hi = sg.off[my_app + 1];
+                    lo = lo < 0 ? 0 : (lo > n_seg ? n_seg : lo);
+                    hi = hi < lo ? lo : (hi > n_seg ? n_seg : hi);
+                }
                 double part = 0.0;
-                for (int64_t j = lo + lane; j < hi; j += 64) {
+                for (int64_t j = lo + sub; j < hi; j += 8) {
                     Eval<double> E;
                     evaluate<double, false>(S.st, S.cd, widen(load_desc(d, j)), E);
                     part += seg_time<double>(E.T, load_seg(sg, j), Q.d, S.cd.ov[0]);
                 }
-                // butterfly: every lane ends with the same (fixed-order) total
-#pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) part += __shfl_xor(part, m, 64);
+                // the group's lanes end with the same (fixed-order) total
+                part += __shfl_xor(part, 4, 64);
+                part += __shfl_xor(part, 2, 64);
+                part += __shfl_xor(part, 1, 64);
                 const double T = part;
-                const double m = meas[a];
-                if (!(T - T == 0.0)) continue;
+                if (my_app < 0 || !(T - T == 0.0)) continue;
+                const double m = meas[my_app];
                 const double im = 1.0 / m;
                 const double w = T > m ? im : (T < m ? -im : 0.0);
-                if (lane == 0) {
+                if (sub == 0) {
                     acc[0] += __builtin_fabs(T - m) * im;
                     acc[1] += 1.0;
                 }
                 if (w == 0.0) continue;
-                for (int64_t j = lo + lane; j < hi; j += 64) {
+                for (int64_t j = lo + sub; j < hi; j += 8) {
                     Eval<double> E;
                     evaluate<double, true>(S.st, S.cd, widen(load_desc(d, j)), E);
                     if (!(E.T < __builtin_huge_val())) continue;
@@ -526,50 +620,15 @@ __global__ __launch_bounds__(256) void k_apps_grad_redo(DescPtrs d, SegPtrs sg, 
             if (E.T < __builtin_huge_val()) accumulate_partials<double>(S.st, S.cd, E, (double)wrow[j], acc);
         }
     }
-    block_sum<kAppRow>(acc, red, rows2 + (int64_t)blockIdx.x * kAppRow);
+    block_row(acc, red, rows2 + (int64_t)blockIdx.x * kAppRow);
 }
 
-// Final fixed-order reduction of the float64 pass's rows into [loss, count,
-// grad theta[24], grad seg params[7]] divided by the count (vjp = 0), or the
-// plain sums [grad theta[24], grad seg params[7]] (vjp = 1).
-__global__ __launch_bounds__(256) void k_apps_reduce(const double* __restrict__ rows, int nrows, SegSet Q,
-                                                     int vjp, double* __restrict__ out)
+__global__ __launch_bounds__(256) void k_apps_final(const double* __restrict__ rows, int nrows, SegSet Q,
+                                                    int vjp, double* __restrict__ out)
 {
-    __shared__ double red[4 * kAppRow];
+    __shared__ double part[(256 / kAppRow) * kAppRow];
     __shared__ double tot[kAppRow];
-    double acc[kAppRow];
-#pragma unroll
-    for (int j = 0; j < kAppRow; ++j) acc[j] = 0.0;
-    for (int r = threadIdx.x; r < nrows; r += blockDim.x)
-#pragma unroll
-        for (int j = 0; j < kAppRow; ++j) acc[j] += rows[(int64_t)r * kAppRow + j];
-    block_sum<kAppRow>(acc, red, tot);
-    __syncthreads();
-    const double* sa = tot + kAcc;   // extra launches, kappa[4], h2d, d2h, transfers
-    const int t = threadIdx.x;
-    if (vjp) {
-        if (t >= kTheta + kSegParams) return;
-        double v;
-        if (t < kTheta) v = tot[2 + t] + (t == 13 ? sa[0] : 0.0);
-        else if (t < kTheta + 4) v = sa[1 + (t - kTheta)];
-        else if (t == kTheta + 4) v = -sa[5] * Q.inv_bw2_h2d;
-        else if (t == kTheta + 5) v = -sa[6] * Q.inv_bw2_d2h;
-        else v = sa[7];
-        out[t] = v;
-        return;
-    }
-    if (t >= kAppsOut) return;
-    const double c = tot[1];
-    const double ic = c > 0.0 ? 1.0 / c : 0.0;
-    double v;
-    if (t == 0) v = tot[0] * ic;
-    else if (t == 1) v = c;
-    else if (t < kAcc) v = (tot[t] + (t == 2 + 13 ? sa[0] : 0.0)) * ic;
-    else if (t < kAcc + 4) v = sa[1 + (t - kAcc)] * ic;
-    else if (t == kAcc + 4) v = -sa[5] * Q.inv_bw2_h2d * ic;
-    else if (t == kAcc + 5) v = -sa[6] * Q.inv_bw2_d2h * ic;
-    else v = sa[7] * ic;
-    out[t] = v;
+    apps_final(rows, nrows, Q, vjp != 0, part, tot, out);
 }
 
 __global__ __launch_bounds__(256) void k_zero_words(uint64_t* __restrict__ w, int64_t n)
@@ -658,7 +717,7 @@ static hipError_t apps_grad_t(const DescPtrs& d, const SegPtrs& sg, int64_t n_se
                                                nrows1, rows2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_apps_reduce<<<1, 256, 0, s>>>(rows2, nb2, Q, MODE == 2 ? 1 : 0, out);
+    k_apps_final<<<1, 256, 0, s>>>(rows2, nb2, Q, MODE == 2 ? 1 : 0, out);
     return hipGetLastError();
 }
 
