@@ -58,7 +58,7 @@ def kernel_name(kind, cfg):
     if kind == "predict":
         return f"void wm::k_predict<{cfg['per_thread']}, {cfg['block']}>"
     if kind == "loss_grad":
-        return f"void wm::k_grad<1, false, {cfg['block']}>"
+        return f"void wm::k_grad<1, false, {cfg['block']}, false>"
     if kind == "predict_apps":
         return f"void wm::k_apps<{cfg['block']}, 0>"
     if kind == "apps_loss_grad":
@@ -66,9 +66,10 @@ def kernel_name(kind, cfg):
     return kind
 
 
-KERNEL_FILES = (("wm::k_apps", "wm_segments.hip"), ("wm::k_fuse_costs", "wm_planning.hip"),
-                ("wm::k_plan", "wm_planning.hip"), ("wm::k_fit_mult", "wm_planning.hip"),
-                ("wm::k_bw", "wm_blackwell.hip"), ("wm::k_select_tile", "wm_tile.hip"),
+KERNEL_FILES = (("wm::k_apps", "wm_segments.hip"), ("wm::k_zero_words", "wm_segments.hip"),
+                ("wm::k_fuse_costs", "wm_planning.hip"), ("wm::k_plan", "wm_planning.hip"),
+                ("wm::k_fit_mult", "wm_planning.hip"), ("wm::k_bw", "wm_blackwell.hip"),
+                ("wm::k_select_tile", "wm_tile.hip"), ("wm::k_tile_costs", "wm_tile.hip"),
                 ("wm::k_", "wm_kernels.hip"))
 
 
@@ -106,6 +107,104 @@ def counted_traffic(kernel_prefix):
                 return None
             return v["read_bytes"] + v["write_bytes"]
     return None
+
+
+def profile_summary(kt_dir, fetch_dir, write_dir, sq_dir=None):
+    """Summarise the three rocprofv3 runs of `bench.py --profile` (kernel
+    trace with --stats, --pmc FETCH_SIZE, --pmc WRITE_SIZE): writes
+    profiles/traffic.json (per kernel instance: HBM bytes read and written
+    per launch, average duration, source fingerprint) and prints the
+    markdown tables of durations and traffic.  Counter KiB are scaled by what
+    the same counter reads for the reference copy (1 GiB read, 1 GiB
+    written per launch)."""
+    import csv
+    import glob
+    import hashlib
+
+    def one(d, pat):
+        f = sorted(glob.glob(os.path.join(d, "**", pat), recursive=True))
+        if not f:
+            sys.exit(f"no {pat} under {d}")
+        return f[0]
+
+    def counter(d, name):
+        per = {}
+        for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
+            if r["Counter_Name"] == name:
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in per.items()}
+
+    stats = list(csv.DictReader(open(one(kt_dir, "*kernel_stats.csv"))))
+    fetch, write = counter(fetch_dir, "FETCH_SIZE"), counter(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy or copy[0] not in write:
+        sys.exit("the reference copy kernel is missing from the counter runs")
+    gib = float(1 << 30)
+    sf, sw = gib / (fetch[copy[0]] * 1024.0), gib / (write[copy[0]] * 1024.0)
+    rec = {"scale_fetch": sf, "scale_write": sw, "kernels": {}}
+    rows = []
+    for r in stats:
+        k = r["Name"]
+        avg_ns = float(r["AverageNs"])
+        rows.append((k, int(r["Calls"]), avg_ns / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+        if k.startswith("void wm::") or k.startswith("wm::"):
+            if k in fetch and k in write:
+                rec["kernels"][k] = {
+                    "read_bytes": fetch[k] * 1024.0 * sf, "write_bytes": write[k] * 1024.0 * sw,
+                    "avg_ns": avg_ns,
+                    "source_sha256_16": hashlib.sha256(kernel_sources(k)).hexdigest()[:16]}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    short = lambda k: k.split("(")[0]
+    print("| kernel instance | calls | average us | min us | max us |")
+    print("|---|---|---|---|---|")
+    for k, c, a, lo, hi in sorted(rows, key=lambda x: -x[2]):
+        print(f"| `{short(k)}` | {c} | {a:.1f} | {lo:.1f} | {hi:.1f} |")
+    print()
+    print(f"Counter scale (reference copy): FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f}")
+    print()
+    print("| kernel instance | read MB / launch | written MB / launch | average us | GB/s counted |")
+    print("|---|---|---|---|---|")
+    for k, v in sorted(rec["kernels"].items(), key=lambda x: -x[1]["avg_ns"]):
+        tot = v["read_bytes"] + v["write_bytes"]
+        print(f"| `{short(k)}` | {v['read_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+              f"{v['avg_ns'] / 1e3:.1f} | {tot / v['avg_ns']:.0f} |")
+    # per-unit figures of the streamed kernels of the profile run: (unit,
+    # units per launch, algorithmic bytes per unit)
+    rows_apps = 6817250   # 2^20 applications, seed 150
+    units = (("void wm::k_predict<", "descriptor", 1 << 24, FWD_BYTES),
+             ("void wm::k_grad<1, false,", "descriptor", 1 << 24, 52),
+             ("void wm::k_apps<", "row", rows_apps, 68 + 8 * (1 << 20) / rows_apps),
+             ("void wm::k_apps_grad<", "row", rows_apps, 68 + 8 * (1 << 20) / rows_apps),
+             ("void wm::k_bw_predict<", "descriptor", 1 << 24, 40),
+             ("void wm::k_bw_grad<1, false,", "descriptor", 1 << 24, 36))
+    print()
+    for k, v in sorted(rec["kernels"].items()):
+        for pre, unit, cnt, bpu in units:
+            if k.startswith(pre):
+                tot = v["read_bytes"] + v["write_bytes"]
+                gbs = bpu * cnt / v["avg_ns"]
+                print(f"* `{short(k)}`: {tot / cnt:.2f} B/{unit} counted vs {bpu:.2f} algorithmic; "
+                      f"average {v['avg_ns'] / 1e3:.1f} us -> {gbs:.0f} GB/s algorithmic = "
+                      f"{100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s")
+    if sq_dir:
+        # GRBM_GUI_ACTIVE sums the eight XCDs; VALU issue per CU-cycle =
+        # SQ_INSTS_VALU / (256 CUs x GUI cycles per XCD)
+        names = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS",
+                 "GRBM_GUI_ACTIVE")
+        c = {n: counter(sq_dir, n) for n in names}
+        print()
+        print("| kernel instance | waves | VALU wave-instr | SALU | VMEM reads | LDS | GUI cycles / XCD "
+              "| VALU per CU-cycle |")
+        print("|---|---|---|---|---|---|---|---|")
+        for k in sorted(c["SQ_INSTS_VALU"], key=lambda x: -c["SQ_INSTS_VALU"][x]):
+            if not (k.startswith("void wm::") or k.startswith("wm::")):
+                continue
+            g = c["GRBM_GUI_ACTIVE"].get(k, 0.0) / 8.0
+            v = c["SQ_INSTS_VALU"][k]
+            print(f"| `{short(k)}` | {c['SQ_WAVES'].get(k, 0):.0f} | {v:.4g} | {c['SQ_INSTS_SALU'].get(k, 0):.3g} "
+                  f"| {c['SQ_INSTS_VMEM_RD'].get(k, 0):.3g} | {c['SQ_INSTS_LDS'].get(k, 0):.3g} | {g:.4g} "
+                  f"| {v / (256.0 * g) if g else 0:.2f} |")
 
 
 def _rate(fn, units, seconds):
@@ -410,7 +509,14 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="run each hot kernel a few times, then a plain 1 GiB device copy whose "
                          "known traffic scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--profile-summary", nargs="+", metavar="DIR",
+                    help="KT_DIR FETCH_DIR WRITE_DIR [SQ_DIR]: summarise the rocprofv3 output folders "
+                         "of a --profile run into profiles/traffic.json and markdown tables (no GPU "
+                         "needed)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(*args.profile_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the batched model "
               "evaluation shards by descriptor range with no exchange, so run one process per GPU.",
