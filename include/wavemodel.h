@@ -107,15 +107,26 @@ typedef struct {
     int64_t n;
 } wm_shapes_t;
 
+/* Calibration options.  Optional constraints keep a fit physical: after
+ * every Adam update the fitted log-parameters are projected, first onto the
+ * level ordering of `order` (the closest ordered values in log space), then
+ * into the box [lo_j, hi_j] of each fitted slot.  Boxes of an ordered group
+ * must be ordered the same way (then the two steps together are the
+ * projection onto both constraints).  A zero-filled constraint part means
+ * none; the first update projects a p0 that lies outside. */
 typedef struct {
     int32_t steps;        /* Adam steps (>= 1) */
-    int32_t reserved;
+    int32_t order;        /* bit 0: BW_L1 >= BW_L2 >= BW_LLC >= BW_HBM (slots 0-3),
+                             bit 1: Lat_L1 <= Lat_L2 <= Lat_LLC <= Lat_HBM (slots 4-7);
+                             a set bit needs its group's four slots free; CDNA calls only */
     double lr;            /* initial learning rate on log(theta) (> 0) */
     double lr_final;      /* geometric decay to this rate at the last step; 0 = constant */
     double beta1, beta2;  /* Adam moment decay rates, in [0, 1) */
     double eps;           /* Adam epsilon (> 0) */
     uint32_t free_mask;   /* bit j set: slot j is fitted; the others stay fixed */
     uint32_t reserved2;
+    double lo[WM_N_THETA];  /* lower bound of fitted slot j (> 0), 0 = none; finite */
+    double hi[WM_N_THETA];  /* upper bound of fitted slot j (>= lo[j]), 0 = none; finite */
 } wm_calib_opts_t;
 
 /*

@@ -65,9 +65,12 @@ int32_t wmb_read_bw(const void *buf, int64_t bytes, int32_t passes, int32_t bloc
 
 /* Dependent-load latency: one lane follows i = next[i & (n_nodes - 1)] from
  * i = 0 for `steps` steps (n_nodes a power of two <= 2^32; any contents stay
- * in bounds), timed on the device wall clock; one untimed pass first.
- * sink: 1 uint32; ticks: 1 int64 (device scratch).  ns_per_step: host. */
-int32_t wmb_chase(const uint32_t *next, int64_t n_nodes, int64_t steps, uint32_t *sink,
+ * in bounds), timed on the device wall clock.  An untimed pass of
+ * warm_steps (>= 0) steps from i = 0 runs first, so a timed pass of at most
+ * warm_steps steps revisits lines the warm pass brought into the caches;
+ * warm_steps = 0 times a cold pass.  sink: 1 uint32; ticks: 1 int64 (device
+ * scratch).  ns_per_step: host. */
+int32_t wmb_chase(const uint32_t *next, int64_t n_nodes, int64_t steps, int64_t warm_steps, uint32_t *sink,
                   int64_t *ticks, void *stream, double *ns_per_step);
 
 /* Shader clock: `blocks` workgroups of one wave each run `spins` dependent

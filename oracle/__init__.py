@@ -45,9 +45,10 @@ class OrcTile(C.Structure):
 
 
 class OrcCalibOpts(C.Structure):
-    _fields_ = [("steps", C.c_int32), ("pad_", C.c_int32)] + [
+    _fields_ = [("steps", C.c_int32), ("order", C.c_int32)] + [
         (n, C.c_double) for n in ("lr", "lr_final", "beta1", "beta2", "eps")] + [
-        ("free_mask", C.c_uint32), ("pad2_", C.c_uint32)]
+        ("free_mask", C.c_uint32), ("pad2_", C.c_uint32),
+        ("lo", C.c_double * N_THETA), ("hi", C.c_double * N_THETA)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def load(path):
     L.orc_weighted_grad.argtypes = [P, D, vp, C.c_int, vp]
     L.orc_calibrate.argtypes = [P, D, vp, C.POINTER(OrcCalibOpts), P, vp]
     L.orc_calibrate.restype = C.c_int
+    L.orc_isotonic_inc.argtypes = [vp, C.c_int]
     L.orc_tile_derive.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32,
                                   C.c_int64, C.POINTER(OrcTile)]
     L.orc_tile_cost.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_uint32]
@@ -208,16 +210,29 @@ def loss_grad(p, d, measured):
 
 
 def calibrate(p0, d, measured, steps=500, lr=0.02, lr_final=0.0, beta1=0.9, beta2=0.999,
-              eps=1e-8, free_mask=0xFFFFFF):
+              eps=1e-8, free_mask=0xFFFFFF, lo=None, hi=None, order=0):
+    """Adam on log(theta); lo / hi per-slot boxes (0 = none), order bit 0:
+    slots 0-3 non-increasing, bit 1: slots 4-7 non-decreasing."""
     o, keep = _desc(d)
     m = np.ascontiguousarray(measured, dtype=np.float32)
-    opts = OrcCalibOpts(steps=steps, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2,
+    opts = OrcCalibOpts(steps=steps, order=order, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2,
                         eps=eps, free_mask=free_mask)
+    for j in range(N_THETA):
+        opts.lo[j] = 0.0 if lo is None else float(lo[j])
+        opts.hi[j] = 0.0 if hi is None else float(hi[j])
     pout = OrcParams()
     hist = np.zeros(max(steps, 1))
     rc = lib().orc_calibrate(C.byref(params(p0)), C.byref(o), m.ctypes.data, C.byref(opts),
                              C.byref(pout), hist.ctypes.data)
     return rc, theta_of(pout), hist[:steps]
+
+
+def isotonic_inc(y):
+    """The oracle's least-squares non-decreasing fit of y (pool adjacent
+    violators)."""
+    a = np.array(y, dtype=np.float64)
+    lib().orc_isotonic_inc(a.ctypes.data, len(a))
+    return a
 
 
 def tile_derive(M, N, K, t, code, wave=64):

@@ -461,10 +461,57 @@ void orc_weighted_grad(const orc_params_t *p, const orc_desc_t *d, const float *
 /* calibration: Adam on log(theta) over the free slots                  */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int32_t steps, pad_;
+    int32_t steps, order;   /* order: bit 0 slots 0-3 non-increasing, bit 1 slots 4-7 non-decreasing */
     double lr, lr_final, beta1, beta2, eps;
     uint32_t free_mask, pad2_;
+    double lo[N_THETA], hi[N_THETA];   /* box of fitted slot j; 0 = none */
 } orc_calib_opts_t;
+
+/*
+ * Least-squares projection of y[0..n) onto non-decreasing sequences by pool
+ * adjacent violators: values enter left to right as blocks; while a block's
+ * mean is below the mean of the block before it, the two merge.  Every
+ * element takes its block's mean.  (The calibration constraints, not a
+ * passage of the paper: they keep fitted cache levels in their physical
+ * order.)
+ */
+void orc_isotonic_inc(double *y, int n)
+{
+    double mean[N_THETA];
+    int cnt[N_THETA], nb = 0;
+    for (int i = 0; i < n; ++i) {
+        mean[nb] = y[i];
+        cnt[nb] = 1;
+        ++nb;
+        while (nb > 1 && mean[nb - 2] > mean[nb - 1]) {
+            const int c = cnt[nb - 2] + cnt[nb - 1];
+            mean[nb - 2] = (mean[nb - 2] * cnt[nb - 2] + mean[nb - 1] * cnt[nb - 1]) / c;
+            cnt[nb - 2] = c;
+            --nb;
+        }
+    }
+    for (int b = 0, k = 0; b < nb; ++b)
+        for (int c = 0; c < cnt[b]; ++c) y[k++] = mean[b];
+}
+
+/* The constraints of a calibration applied to log(theta) after an update:
+ * the orderings (a non-increasing fit is the non-decreasing fit of the
+ * negated values), then the boxes. */
+static void orc_project(const orc_calib_opts_t *o, double *phi)
+{
+    if (o->order & 1) {
+        double y[4];
+        for (int k = 0; k < 4; ++k) y[k] = -phi[k];
+        orc_isotonic_inc(y, 4);
+        for (int k = 0; k < 4; ++k) phi[k] = -y[k];
+    }
+    if (o->order & 2) orc_isotonic_inc(phi + 4, 4);
+    for (int j = 0; j < N_THETA; ++j) {
+        if (!(o->free_mask >> j & 1u)) continue;
+        if (o->lo[j] > 0.0 && phi[j] < log(o->lo[j])) phi[j] = log(o->lo[j]);
+        if (o->hi[j] > 0.0 && phi[j] > log(o->hi[j])) phi[j] = log(o->hi[j]);
+    }
+}
 
 /*
  * Returns 0 on success (p_out = theta after the last update) or 1 when the
@@ -503,6 +550,10 @@ int orc_calibrate(const orc_params_t *p0, const orc_desc_t *d, const float *m,
                 double mh = mom[j] / (1.0 - b1t);
                 double vh = vel[j] / (1.0 - b2t);
                 phi[j] -= lr * mh / (sqrt(vh) + o->eps);
+            }
+            orc_project(o, phi);
+            for (int j = 0; j < N_THETA; ++j) {
+                if (!(o->free_mask >> j & 1u)) continue;
                 next.theta[j] = exp(phi[j]);
                 ok = ok && isfinite(next.theta[j]) && next.theta[j] > 0.0;
             }

@@ -153,8 +153,29 @@ bool opts_ok(const wm_calib_opts_t* o)
     if (!(o->beta1 >= 0.0 && o->beta1 < 1.0 && o->beta2 >= 0.0 && o->beta2 < 1.0)) return false;
     if (!(fin(o->eps) && o->eps > 0.0)) return false;
     if ((o->free_mask >> WM_N_THETA) != 0u) return false;
+    // boxes: finite, non-negative, lo <= hi where both are set
+    for (int j = 0; j < WM_N_THETA; ++j) {
+        if (!(fin(o->lo[j]) && o->lo[j] >= 0.0 && fin(o->hi[j]) && o->hi[j] >= 0.0)) return false;
+        if (o->lo[j] > 0.0 && o->hi[j] > 0.0 && o->lo[j] > o->hi[j]) return false;
+    }
+    if ((o->order & ~3) != 0) return false;
+    // an ordered group: its four slots fitted, its boxes ordered the same way
+    const double inf = HUGE_VAL;
+    for (int g = 0; g < 2; ++g) {
+        if (!((o->order >> g) & 1)) continue;
+        const int b = 4 * g;
+        if (((o->free_mask >> b) & 15u) != 15u) return false;
+        for (int j = b; j < b + 3; ++j) {
+            const double lo0 = o->lo[j] > 0.0 ? o->lo[j] : -inf, lo1 = o->lo[j + 1] > 0.0 ? o->lo[j + 1] : -inf;
+            const double hi0 = o->hi[j] > 0.0 ? o->hi[j] : inf, hi1 = o->hi[j + 1] > 0.0 ? o->hi[j + 1] : inf;
+            // group 0 (bandwidths) non-increasing, group 1 (latencies) non-decreasing
+            if (g == 0 ? (lo0 < lo1 || hi0 < hi1) : (lo0 > lo1 || hi0 > hi1)) return false;
+        }
+    }
     return true;
 }
+
+static_assert(sizeof(wm_calib_opts_t) == 56 + 2 * 8 * WM_N_THETA, "wm_calib_opts_t layout");
 
 AdamOpts adam_of(const wm_calib_opts_t* o)
 {
@@ -167,6 +188,11 @@ AdamOpts adam_of(const wm_calib_opts_t* o)
     a.beta2 = o->beta2;
     a.eps = o->eps;
     a.free_mask = o->free_mask;
+    a.order = o->order;
+    for (int j = 0; j < kTheta; ++j) {
+        a.lo_log[j] = o->lo[j] > 0.0 ? std::log(o->lo[j]) : -HUGE_VAL;
+        a.hi_log[j] = o->hi[j] > 0.0 ? std::log(o->hi[j]) : HUGE_VAL;
+    }
     return a;
 }
 
@@ -821,8 +847,9 @@ int32_t wm_bw_calibrate(const wm_bw_desc_t* desc, const float* measured, const w
                         const wm_calib_opts_t* opts, wm_bw_params_t* p_out, double* loss_hist,
                         void* ws, size_t ws_bytes, void* stream)
 {
+    // the level orderings name CDNA slots
     if (!bw_desc_ok(desc) || (desc->n > 0 && !measured) || !bw_params_ok(p0) || !opts_ok(opts) ||
-        !p_out)
+        opts->order != 0 || !p_out)
         return WM_EINVAL;
     for (int j = 0; j < WM_N_THETA; ++j)
         if (((opts->free_mask >> j) & 1u) && !(p0->theta[j] > 0.0)) return WM_EINVAL;

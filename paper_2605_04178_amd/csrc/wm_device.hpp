@@ -104,6 +104,33 @@ __device__ inline void reduce_partials(const double* __restrict__ partials, int 
 // ---------------------------------------------------------------------------
 // device Adam on log(theta)
 // ---------------------------------------------------------------------------
+// Closest non-decreasing (INC) or non-increasing sequence, in the least-
+// squares sense, to the values of lanes base .. base + 3; lane base + i gets
+// element i, other lanes keep v.  Element i of the isotonic fit is
+// max over a <= i of min over b >= i of the mean of y[a..b] (non-decreasing;
+// min and max swap for non-increasing).  Called by all 64 lanes, converged.
+template <bool INC>
+__device__ inline double isotonic4(double v, int lane, int base)
+{
+    double y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = __shfl(v, base + k, 64);
+    const int i = lane - base;
+    if (i < 0 || i > 3) return v;
+    double best = INC ? -HUGE_VAL : HUGE_VAL;
+    for (int a = 0; a <= i; ++a) {
+        double inner = INC ? HUGE_VAL : -HUGE_VAL, sum = 0.0;
+        for (int b = a; b < 4; ++b) {
+            sum += y[b];
+            if (b < i) continue;
+            const double mean = sum / (double)(b - a + 1);
+            inner = INC ? fmin(inner, mean) : fmax(inner, mean);
+        }
+        best = INC ? fmax(best, inner) : fmin(best, inner);
+    }
+    return best;
+}
+
 __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const AdamOpts& o,
                                        double* loss_hist, double* th_out /* LDS [kTheta] */)
 {
@@ -138,7 +165,9 @@ __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const 
     const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
     double th_new = th;
     bool ok = true;
-    if (mine && ((o.free_mask >> lane) & 1u)) {
+    const bool fit = mine && ((o.free_mask >> lane) & 1u);
+    double phi = fit ? st->phi[lane] : 0.0;
+    if (fit) {
         const double gp = th * g;
         const double m = o.beta1 * st->m[lane] + (1.0 - o.beta1) * gp;
         const double v = o.beta2 * st->v[lane] + (1.0 - o.beta2) * gp * gp;
@@ -146,7 +175,14 @@ __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const 
         st->v[lane] = v;
         const double mh = m / (1.0 - b1t);
         const double vh = v / (1.0 - b2t);
-        const double phi = st->phi[lane] - lr * mh / (sqrt(vh) + o.eps);
+        phi -= lr * mh / (sqrt(vh) + o.eps);
+    }
+    // constraints: the level orderings (every slot of an ordered group is
+    // fitted), then the boxes
+    if (o.order & 1) phi = isotonic4<false>(phi, lane, 0);
+    if (o.order & 2) phi = isotonic4<true>(phi, lane, 4);
+    if (fit) {
+        phi = fmin(fmax(phi, o.lo_log[lane]), o.hi_log[lane]);
         st->phi[lane] = phi;
         th_new = exp(phi);
         ok = __builtin_isfinite(th_new) && th_new > 0.0;

@@ -75,9 +75,10 @@ struct ShapePtrs {
 };
 
 struct AdamOpts {
-    int32_t steps, pad_;
+    int32_t steps, order;   // order: bit 0 slots 0-3 non-increasing, bit 1 slots 4-7 non-decreasing
     double lr, lr_final, beta1, beta2, eps;
     uint32_t free_mask, pad2_;
+    double lo_log[kTheta], hi_log[kTheta];   // box on log(theta) of the fitted slots (+-inf: none)
 };
 
 // device-resident calibration state of one parameter set

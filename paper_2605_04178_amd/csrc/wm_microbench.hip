@@ -417,11 +417,11 @@ int32_t wmb_read_bw(const void* buf, int64_t bytes, int32_t passes, int32_t bloc
     }, seconds);
 }
 
-int32_t wmb_chase(const uint32_t* next, int64_t n_nodes, int64_t steps, uint32_t* sink,
+int32_t wmb_chase(const uint32_t* next, int64_t n_nodes, int64_t steps, int64_t warm_steps, uint32_t* sink,
                   int64_t* ticks, void* stream, double* ns_per_step)
 {
     if (!next || !sink || !ticks || !ns_per_step || n_nodes < 1 || (n_nodes & (n_nodes - 1)) ||
-        n_nodes > (1ll << 32) || steps < 1)
+        n_nodes > (1ll << 32) || steps < 1 || warm_steps < 0)
         return WMB_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int dev = 0, khz = 0;
@@ -429,9 +429,12 @@ int32_t wmb_chase(const uint32_t* next, int64_t n_nodes, int64_t steps, uint32_t
     WMB_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (khz <= 0) return WMB_EHIP;
     const uint32_t mask = (uint32_t)(n_nodes - 1);
-    // a warm-up pass over the chain, then the timed pass
-    k_mb_chase<<<1, 64, 0, s>>>(next, mask, steps, sink, ticks);
-    WMB_HIP(hipGetLastError());
+    // an untimed pass of warm_steps steps from node 0 (the timed pass then
+    // revisits the same nodes first), then the timed pass from node 0
+    if (warm_steps > 0) {
+        k_mb_chase<<<1, 64, 0, s>>>(next, mask, warm_steps, sink, ticks);
+        WMB_HIP(hipGetLastError());
+    }
     k_mb_chase<<<1, 64, 0, s>>>(next, mask, steps, sink, ticks);
     WMB_HIP(hipGetLastError());
     int64_t t = 0;

@@ -65,7 +65,7 @@ def lib():
         L.wmb_last_hip_error.restype = i32
         L.wmb_read_bw.argtypes = [vp, i64, i32, i32, i32, vp, i32, vp, dp]
         L.wmb_read_bw.restype = i32
-        L.wmb_chase.argtypes = [vp, i64, i64, vp, vp, vp, dp]
+        L.wmb_chase.argtypes = [vp, i64, i64, i64, vp, vp, vp, dp]
         L.wmb_chase.restype = i32
         L.wmb_clock.argtypes = [i32, i32, vp, vp, vp, dp]
         L.wmb_clock.restype = i32
@@ -197,22 +197,35 @@ def measure(quick: bool = False, log=print) -> dict:
     del big
 
     # --- dependent-load latency against working set ---
+    # Up to 256 MiB: a warm pass of 2^18 steps, then the same 2^18 lines
+    # (32 MiB, beyond an XCD's 4 MiB L2 from 32 MiB up, within the 256 MiB
+    # Infinity Cache) timed again: the level that holds the visited lines.
+    # From 512 MiB: the Infinity Cache is emptied of the chain by streaming a
+    # 1 GiB buffer, then a cold pass of 2^16 steps, each a line not cached
+    # anywhere: HBM (with the translation misses of a 0.5-2 GiB footprint).
     lat = []
     top_l = 28 if quick else 31
     ticks = torch.zeros(1, dtype=torch.int64, device=dev)
     sinku = torch.zeros(1, dtype=torch.int32, device=dev)
-    for lg in range(13, top_l + 1, 1 if quick else 1):
+    evict = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev) if top_l >= 29 else None
+    for lg in range(13, top_l + 1):
         W = 1 << lg
         stride = 32                                  # 128 B between nodes
         n_nodes = W // 128
         nxt = torch.from_numpy(chase_chain(n_nodes, stride, lg).view(np.int32)).to(dev)
-        steps = 1 << 16
+        cold = W >= (512 << 20)
+        steps = (1 << 16) if cold else (1 << 18)
+        if cold:
+            _check(L.wmb_read_bw(C.c_void_p(evict.data_ptr()), 1 << 30, 1, cus * 8, 0,
+                                 C.c_void_p(sinkf.data_ptr()), 1, st, C.byref(sec)), "wmb_read_bw")
         ns = C.c_double()
-        _check(L.wmb_chase(C.c_void_p(nxt.data_ptr()), nxt.numel(), steps, C.c_void_p(sinku.data_ptr()),
-                           C.c_void_p(ticks.data_ptr()), st, C.byref(ns)), "wmb_chase")
+        _check(L.wmb_chase(C.c_void_p(nxt.data_ptr()), nxt.numel(), steps, 0 if cold else steps,
+                           C.c_void_p(sinku.data_ptr()), C.c_void_p(ticks.data_ptr()), st, C.byref(ns)),
+               "wmb_chase")
         lat.append((W, ns.value))
-        log(f"latency W={W >> 10} KiB: {ns.value:.1f} ns")
+        log(f"latency W={W >> 10} KiB ({'cold' if cold else 'warm'}): {ns.value:.1f} ns")
         del nxt
+    del evict
     out["latency_ns"] = lat
 
     # --- throughput per data type ---

@@ -9,7 +9,10 @@ Steps (Section IV-D workflow, Section V-A scoring):
     and of the naive roofline with datasheet peaks; mean absolute relative
     error (MAE) of each against the measured times;
  4. calibration (wm_calibrate: Adam on log theta over the mean relative
-    error) on a training split of the validation kernels, MAE on the
+    error) on a training split of the validation kernels, held to physical
+    values: the cache bandwidths stay ordered L1 >= L2 >= LLC >= HBM and the
+    latencies L1 <= L2 <= LLC <= HBM, and every fitted slot stays within a
+    box around its microbenchmark value (calibration_bounds); MAE on the
     held-out split, before and after;
  5. per-family multipliers on top of the calibrated model
     (wm_fit_multipliers on the training split), MAE on the held-out split.
@@ -43,13 +46,46 @@ def predict(wm, p, cases):
     return T.cpu().numpy().astype(np.float64), occ.cpu().numpy()
 
 
+# box factors around the microbenchmark values: cache bandwidths and
+# latencies within 2x, fixed costs within 10x, the h_LLC exponents within
+# [0.1, 10]; the FP32 / BF16 peaks between half the measured value and the
+# datasheet figure
+BOX_HIERARCHY, BOX_OVERHEAD, EXPONENT_RANGE = 2.0, 10.0, (0.1, 10.0)
+
+
+def calibration_bounds(theta_mb, sheet=mb.MI355X_DATASHEET):
+    """(lo, hi, order) for wm_calibrate: boxes around the microbenchmark
+    theta, whose cache levels are first put in physical order (bandwidths
+    non-increasing, latencies non-decreasing from L1 to HBM: a running
+    minimum, a running maximum) so the boxes are ordered like the levels."""
+    th = np.array(theta_mb, dtype=np.float64)
+    th[0:4] = np.minimum.accumulate(th[0:4])
+    th[4:8] = np.maximum.accumulate(th[4:8])
+    lo, hi = np.zeros(24), np.zeros(24)
+    for j in range(8):
+        lo[j], hi[j] = th[j] / BOX_HIERARCHY, th[j] * BOX_HIERARCHY
+    for j, key in ((9, "fp32"), (10, "bf16")):
+        lo[j], hi[j] = th[j] / 2.0, max(th[j], sheet[key])
+    for j in (13, 14, 15):
+        lo[j], hi[j] = th[j] / BOX_OVERHEAD, th[j] * BOX_OVERHEAD
+    for j in (20, 21):
+        lo[j], hi[j] = EXPONENT_RANGE
+    return lo, hi, 3
+
+
 def calibrate(wm, p0, cases, steps=2000, lr=0.02):
     import torch
     d = mb.descriptors_of(cases)
     dd = wm.DeviceDescriptors.from_host(d)
     m = torch.tensor([c.seconds for c in cases], dtype=torch.float32, device="cuda")
     mask = FIT_MASK & ~sum(1 << j for j in range(24) if not p0.theta[j] > 0.0)
-    rc, th, hist = wm.calibrate(dd, m, p0, steps=steps, lr=lr, lr_final=1e-3, free_mask=mask)
+    lo, hi, order = calibration_bounds(p0.theta)
+    fit = [(mask >> j) & 1 for j in range(24)]
+    lo, hi = lo * fit, hi * fit
+    # the orderings need every slot of their group fitted
+    order &= (1 if (mask & 0xF) == 0xF else 0) | (2 if (mask >> 4 & 0xF) == 0xF else 0)
+    rc, th, hist = wm.calibrate(dd, m, p0, steps=steps, lr=lr, lr_final=1e-3, free_mask=mask,
+                                lo=lo, hi=hi, order=order)
     return rc, p0.copy(theta=[float(x) for x in th]), hist, mask
 
 
@@ -171,7 +207,9 @@ def main(argv=None):
         "theta_microbench": list(p_mb.theta),
         "theta_calibrated": list(p_cal.theta),
         "calibration": {"status": rc, "free_mask": mask, "steps": args.steps,
-                        "loss_first_last": [float(hist[0]), float(hist[-1])]},
+                        "loss_first_last": [float(hist[0]), float(hist[-1])],
+                        "bounds": [list(x) if isinstance(x, np.ndarray) else x
+                                   for x in calibration_bounds(p_mb.theta)]},
         "family_multipliers": fam_mult,
         "struct": {k: getattr(p_mb, k) for k in mb.MI355X_STRUCT},
         "cases": [dict(dataclasses.asdict(c), pred_microbench=float(T_mb[i]), pred_calibrated=float(T_cal[i]),

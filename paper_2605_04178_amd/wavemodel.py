@@ -97,9 +97,15 @@ class WmCalibState(C.Structure):
 
 
 class WmCalibOpts(C.Structure):
-    _fields_ = [("steps", C.c_int32), ("reserved", C.c_int32)] + [
+    _fields_ = [("steps", C.c_int32), ("order", C.c_int32)] + [
         (n, C.c_double) for n in ("lr", "lr_final", "beta1", "beta2", "eps")] + [
-        ("free_mask", C.c_uint32), ("reserved2", C.c_uint32)]
+        ("free_mask", C.c_uint32), ("reserved2", C.c_uint32),
+        ("lo", C.c_double * N_THETA), ("hi", C.c_double * N_THETA)]
+
+
+# order bits of a calibration: bandwidths L1 >= L2 >= LLC >= HBM (slots 0-3),
+# latencies L1 <= L2 <= LLC <= HBM (slots 4-7)
+ORDER_BW, ORDER_LAT = 1, 2
 
 
 _lib = None
@@ -613,10 +619,10 @@ def bw_loss_grad(desc: DeviceBwDescriptors, measured: torch.Tensor, params, ws=N
 
 
 def bw_calibrate(desc: DeviceBwDescriptors, measured: torch.Tensor, p0, steps=500, lr=0.05, lr_final=1e-3,
-                 beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None, stream=None):
+                 beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None, stream=None, lo=None, hi=None):
     """Device Adam on log(theta) for the Blackwell model.  Returns (status,
     theta float64 [24], loss history)."""
-    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask, lo=lo, hi=hi)
     if ws is None:
         ws = _workspace(bw_workspace_bytes(BW_OP_CALIBRATE, desc.n, steps), desc.device)
     pout = WmBwParams()
@@ -678,16 +684,23 @@ class WMPredictApps(torch.autograd.Function):
 
 
 def calib_opts(steps=500, lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-               free_mask=0xFFFFFF) -> WmCalibOpts:
-    return WmCalibOpts(steps=steps, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2, eps=eps,
-                       free_mask=free_mask)
+               free_mask=0xFFFFFF, lo=None, hi=None, order=0) -> WmCalibOpts:
+    """Calibration options; lo / hi: per-slot boxes (24 values, 0 = none),
+    order: ORDER_BW | ORDER_LAT level orderings."""
+    o = WmCalibOpts(steps=steps, order=order, lr=lr, lr_final=lr_final, beta1=beta1, beta2=beta2, eps=eps,
+                    free_mask=free_mask)
+    for j in range(N_THETA):
+        o.lo[j] = 0.0 if lo is None else float(lo[j])
+        o.hi[j] = 0.0 if hi is None else float(hi[j])
+    return o
 
 
 def calibrate(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps=500, lr=0.05,
               lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None,
-              stream=None, raise_on_diverged=False):
-    """Device Adam on log(theta).  Returns (status, theta float64 [24], loss history)."""
-    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+              stream=None, raise_on_diverged=False, lo=None, hi=None, order=0):
+    """Device Adam on log(theta), optionally projected onto per-slot boxes
+    and level orderings.  Returns (status, theta float64 [24], loss history)."""
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask, lo=lo, hi=hi, order=order)
     if ws is None:
         ws = _workspace(workspace_bytes(OP_CALIBRATE, desc.n, 1, steps), desc.device)
     pout = WmParams()
@@ -702,11 +715,11 @@ def calibrate(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps=500, lr
 
 def calibrate_resume(desc: DeviceDescriptors, measured: torch.Tensor, p0, steps, run_steps, state=None,
                      lr=0.05, lr_final=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, free_mask=0xFFFFFF, ws=None,
-                     stream=None):
+                     stream=None, lo=None, hi=None, order=0):
     """Run `run_steps` steps of a `steps`-step calibration from `state` (a
     WmCalibState; None = fresh start from p0).  Returns (status, theta, loss
     history of these steps, state after them)."""
-    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask)
+    opts = calib_opts(steps, lr, lr_final, beta1, beta2, eps, free_mask, lo=lo, hi=hi, order=order)
     if ws is None:
         ws = _workspace(workspace_bytes(OP_CALIBRATE, desc.n, 1, steps), desc.device)
     pout = WmParams()

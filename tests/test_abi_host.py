@@ -60,7 +60,7 @@ def test_struct_sizes_match_header(wmb):
     # 14 int32 + 3 double + 24 double
     assert C.sizeof(wmb.WmParams) == 14 * 4 + 3 * 8 + 24 * 8
     assert C.sizeof(wmb.WmDesc) == 12 * 8 + 8
-    assert C.sizeof(wmb.WmCalibOpts) == 4 + 4 + 5 * 8 + 4 + 4
+    assert C.sizeof(wmb.WmCalibOpts) == 4 + 4 + 5 * 8 + 4 + 4 + 2 * 24 * 8
 
 
 def test_strerror(wmb):
@@ -173,6 +173,34 @@ def test_argument_errors_before_any_hip_call(wmb):
     o = wmb.calib_opts(steps=5)
     assert L.wm_calibrate(C.byref(d), w, C.byref(p), C.byref(o), C.byref(pout), None, None, 0,
                           None) == wmb.WM_EWORKSPACE
+    # constraints: valid boxes and orderings pass validation (then the
+    # missing workspace is reported); each malformed one is rejected
+    th0 = np.array(synth.param_set(0).theta)
+    lo_ok, hi_ok = np.where(th0 > 0, th0 / 2, 0.0), np.where(th0 > 0, th0 * 2, 0.0)
+    ok = dict(steps=5, lo=lo_ok, hi=hi_ok, order=3, free_mask=synth.FIT_MASK_L4)
+    o = wmb.calib_opts(**ok)
+    assert L.wm_calibrate(C.byref(d), w, C.byref(p), C.byref(o), C.byref(pout), None, None, 0,
+                          None) == wmb.WM_EWORKSPACE
+
+    def with_(j, lo=None, hi=None):
+        a, b = lo_ok.copy(), hi_ok.copy()
+        if lo is not None:
+            a[j] = lo
+        if hi is not None:
+            b[j] = hi
+        return dict(ok, lo=a, hi=b)
+    bad = [with_(3, lo=hi_ok[3] * 1.5),                  # lo > hi
+           with_(13, lo=-1.0), with_(13, hi=float("nan")), with_(14, hi=float("inf")),
+           dict(ok, order=4),                            # unknown ordering bit
+           dict(ok, free_mask=synth.FIT_MASK_L4 & ~(1 << 2)),           # ordered group not all free
+           dict(ok, order=2, free_mask=synth.FIT_MASK_L4 & ~(1 << 7)),
+           with_(1, hi=hi_ok[0] * 1.5),                  # bandwidth boxes not non-increasing
+           with_(5, lo=lo_ok[6] * 1.5)]                  # latency boxes not non-decreasing
+    for kw in bad:
+        o = wmb.calib_opts(**kw)
+        rc = L.wm_calibrate(C.byref(d), w, C.byref(p), C.byref(o), C.byref(pout), None,
+                            C.c_void_p(0x10000), 1 << 30, None)
+        assert rc == wmb.WM_EINVAL, kw
     # a free slot must be positive (log-space update)
     th = list(synth.param_set(0).theta)
     th[13] = 0.0
@@ -310,6 +338,14 @@ def test_blackwell_calls_validate_before_any_hip_call(wmb):
     # measurements may be NULL only when there are no descriptors
     o = wmb.calib_opts(steps=5, free_mask=1 << 0)
     assert L.wm_bw_calibrate(C.byref(d), None, C.byref(ps), C.byref(o), C.byref(wmb.WmBwParams()), None,
+                             C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
+    # boxes apply to the Blackwell slots too; the level orderings name CDNA slots
+    lo = np.array([t / 2 if t > 0 else 0.0 for t in p.theta])
+    o = wmb.calib_opts(steps=5, free_mask=0xF, lo=lo)
+    assert L.wm_bw_calibrate(C.byref(d), x, C.byref(ps), C.byref(o), C.byref(wmb.WmBwParams()), None,
+                             None, 0, None) == wmb.WM_EWORKSPACE
+    o = wmb.calib_opts(steps=5, free_mask=0xFF, order=wmb.ORDER_BW)
+    assert L.wm_bw_calibrate(C.byref(d), x, C.byref(ps), C.byref(o), C.byref(wmb.WmBwParams()), None,
                              C.c_void_p(0x10000), 1 << 30, None) == wmb.WM_EINVAL
     assert L.wm_last_hip_error() == 0
 

@@ -121,6 +121,44 @@ def test_calibration_matches_oracle_adam_loss_history(wmb, orc):
     assert np.allclose(th, tho, rtol=1e-6, atol=0)
 
 
+def test_constrained_calibration_matches_oracle(wmb, orc):
+    """Boxes and level orderings: from a start that violates both orderings,
+    with one box binding (BW_L2 capped below its true value) and the others
+    around the truth, the device's projected Adam follows the oracle's (loss
+    history and theta to 1e-6 relative over 30 steps) and every slot ends
+    feasible; a resumed run in two pieces ends on the same theta."""
+    n = 1 << 16
+    ps, d, m, p0 = _problem(orc, n, sigma=0.05)
+    th = np.array(p0.theta)
+    th[0], th[1] = 0.6 * ps.theta[0], 1.7 * ps.theta[0]
+    th[6], th[7] = 1.8 * ps.theta[7], 0.7 * ps.theta[7]
+    p0 = ps.copy(theta=list(th))
+    tt = np.array(ps.theta)
+    lo = np.where(tt > 0, tt / 3, 0.0) * np.array([(MASK_L4 >> j) & 1 for j in range(24)])
+    hi = np.where(tt > 0, tt * 3, 0.0) * np.array([(MASK_L4 >> j) & 1 for j in range(24)])
+    hi[1] = 0.8 * tt[1]
+    # boxes ordered like the levels (bandwidths non-increasing, latencies
+    # non-decreasing), as the orderings require
+    lo[0:4], hi[0:4] = np.minimum.accumulate(lo[0:4]), np.minimum.accumulate(hi[0:4])
+    lo[4:8], hi[4:8] = np.maximum.accumulate(lo[4:8]), np.maximum.accumulate(hi[4:8])
+    kw = dict(steps=30, lr=0.05, lr_final=1e-3, free_mask=MASK_L4, lo=lo, hi=hi, order=3)
+    dd = wmb.DeviceDescriptors.from_host(d)
+    mt = torch.from_numpy(m).cuda()
+    rc, thg, hist = wmb.calibrate(dd, mt, p0, **kw)
+    rco, tho, histo = orc.calibrate(p0, d, m, **kw)
+    assert rc == 0 and rco == 0
+    assert np.allclose(hist, histo, rtol=1e-6, atol=0)
+    assert np.allclose(thg, tho, rtol=1e-6, atol=0)
+    assert thg[0] >= thg[1] >= thg[2] >= thg[3] and thg[4] <= thg[5] <= thg[6] <= thg[7]
+    f = [j for j in range(24) if MASK_L4 >> j & 1]
+    assert np.all(thg[f] >= lo[f] * (1 - 1e-12)) and np.all(thg[f] <= hi[f] * (1 + 1e-12))
+    assert thg[1] == pytest.approx(hi[1], rel=1e-12)
+    _, _, _, st = wmb.calibrate_resume(dd, mt, p0, 30, 11, **{k: v for k, v in kw.items() if k != "steps"})
+    _, th2, _, _ = wmb.calibrate_resume(dd, mt, p0, 30, 19, state=st,
+                                        **{k: v for k, v in kw.items() if k != "steps"})
+    assert np.array_equal(th2, thg)
+
+
 def test_calibration_divergence_returns_last_finite_theta(wmb, orc):
     n = 1 << 14
     ps, d, m, p0 = _problem(orc, n)

@@ -144,12 +144,13 @@ def test_microbenchmarks_run(mb):
     nxt = torch.from_numpy(mb.chase_chain(1024, 32, 0).view(np.int32)).cuda()
     ticks = torch.zeros(1, dtype=torch.int64, device="cuda")
     su = torch.zeros(1, dtype=torch.int32, device="cuda")
-    assert L.wmb_chase(C.c_void_p(nxt.data_ptr()), nxt.numel(), 4096, C.c_void_p(su.data_ptr()),
-                       C.c_void_p(ticks.data_ptr()), st, C.byref(sec)) == 0
-    say("chase ns/step", sec.value)
-    assert 1 < sec.value < 1e4
-    # after 4096 steps round a 1024-node cycle the chase is back at node 0
-    assert int(su.item()) == 0
+    for warm in (4096, 0):
+        assert L.wmb_chase(C.c_void_p(nxt.data_ptr()), nxt.numel(), 4096, warm, C.c_void_p(su.data_ptr()),
+                           C.c_void_p(ticks.data_ptr()), st, C.byref(sec)) == 0
+        say("chase ns/step, warm steps", warm, sec.value)
+        assert 1 < sec.value < 1e4
+        # after 4096 steps round a 1024-node cycle the chase is back at node 0
+        assert int(su.item()) == 0
     for kind in range(5):
         assert L.wmb_peak(kind, 16, 64, C.c_void_p(sink.data_ptr()), 2, st, C.byref(sec), C.byref(fl)) == 0
         say("peak", kind, fl.value / sec.value / 1e12, "TF/s (small grid)")
@@ -172,7 +173,7 @@ def test_shader_clock(mb):
 def test_shipped_mi355x_parameters_predict_held_out_kernels(mb):
     """The shipped parameter file is valid and, on the held-out validation
     kernels re-timed on this GPU, the calibrated model beats the naive
-    roofline."""
+    roofline and stays within 0.03 of the MAE recorded with the file."""
     import json
     import os
     from paper_2605_04178_amd import recalibrate as rc, wavemodel as wm
@@ -188,4 +189,6 @@ def test_shipped_mi355x_parameters_predict_held_out_kernels(mb):
     T, _ = rc.predict(wm, p, cases)
     e_model, e_roof = mb.mae(T, meas), mb.mae(mb.roofline_naive(cases), meas)
     say("held-out MAE calibrated", e_model, "roofline", e_roof, "recorded", rec["mae"]["calibrated_holdout"])
-    assert e_model < e_roof and e_model < 0.5
+    # re-timing the kernels moves the MAE by well under 0.01 between runs; a
+    # margin of 0.03 over the recorded figure still fails a real regression
+    assert e_model < e_roof and e_model <= rec["mae"]["calibrated_holdout"] + 0.03

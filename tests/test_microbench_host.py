@@ -175,7 +175,8 @@ def test_wmbench_argument_checks_without_a_gpu():
     assert L.wmb_read_bw(None, 1024, 1, 1, 0, C.c_void_p(0x100), 1, None, C.byref(d)) == -1
     assert L.wmb_read_bw(C.c_void_p(0x1000), 1000, 1, 1, 0, C.c_void_p(0x100), 1, None, C.byref(d)) == -1
     assert L.wmb_read_bw(C.c_void_p(0x1008), 1024, 1, 1, 0, C.c_void_p(0x100), 1, None, C.byref(d)) == -1
-    assert L.wmb_chase(C.c_void_p(0x1000), 1000, 10, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
+    assert L.wmb_chase(C.c_void_p(0x1000), 1000, 10, 0, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
+    assert L.wmb_chase(C.c_void_p(0x1000), 1024, 10, -1, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
     assert L.wmb_peak(7, 10, 1, C.c_void_p(0x100), 1, None, C.byref(d), C.byref(d)) == -1
     assert L.wmb_empty(1, 100, 0, C.c_void_p(0x100), 1, None, C.byref(d)) == -1
     assert L.wmb_clock(0, 10, C.c_void_p(0x100), C.c_void_p(0x200), None, C.byref(d)) == -1
@@ -228,3 +229,34 @@ def test_tile_choice_scores_predicted_against_measured_best():
     assert r["measured_best"] == "gemm16"
     assert r["calibrated_pick"] == "gemm32" and abs(r["calibrated_slowdown"] - 0.1) < 1e-12
     assert r["microbench_pick"] == "gemm8" and abs(r["microbench_slowdown"] - 0.5) < 1e-12
+
+
+def test_shipped_calibrated_parameters_are_physical():
+    """The shipped MI355X set keeps the cache levels in physical order
+    (bandwidths L1 >= L2 >= LLC >= HBM, latencies L1 <= ... <= HBM) and every
+    calibrated slot inside its box around the microbenchmark value."""
+    import json
+    import os
+    from paper_2605_04178_amd import recalibrate as rc
+    rec = json.load(open(os.path.join(os.path.dirname(mb.__file__), "params", "mi355x.json")))
+    th = np.array(rec["theta_calibrated"])
+    assert th[0] >= th[1] >= th[2] >= th[3]
+    assert th[4] <= th[5] <= th[6] <= th[7]
+    lo, hi, _ = rc.calibration_bounds(rec["theta_microbench"])
+    mask = rec["calibration"]["free_mask"]
+    for j in range(24):
+        if (mask >> j) & 1 and lo[j] > 0:
+            assert lo[j] * (1 - 1e-9) <= th[j] <= hi[j] * (1 + 1e-9), (j, th[j], lo[j], hi[j])
+
+
+def test_calibration_bounds_are_ordered_like_the_levels():
+    th = [36e12, 33e12, 6.7e12, 6.9e12, 60.0, 171.0, 495.0, 494.0] + [1.0] * 16
+    lo, hi, order = rc_bounds(th)
+    assert order == 3
+    assert np.all(np.diff(lo[0:4]) <= 0) and np.all(np.diff(hi[0:4]) <= 0)
+    assert np.all(np.diff(lo[4:8]) >= 0) and np.all(np.diff(hi[4:8]) >= 0)
+
+
+def rc_bounds(th):
+    from paper_2605_04178_amd import recalibrate as rc
+    return rc.calibration_bounds(th)
