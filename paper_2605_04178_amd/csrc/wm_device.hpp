@@ -10,6 +10,32 @@ namespace wm {
 template <typename T>
 __device__ inline T ntload(const T* p) { return __builtin_nontemporal_load(p); }
 
+// Parameters read through a pointer into memory that stays constant while
+// the kernel runs (a by-value kernel argument in the kernel-argument
+// segment, or a set in device memory), laundered so that the optimiser cannot
+// see through it: inside a sweep loop each parameter use is then a scalar
+// load, served by the scalar cache.  Kept in scalar registers across the loop
+// instead, the sixty-odd parameters overflow the 102 scalar registers; the
+// compiler spills them to vector-register lanes and reloads each with one
+// VALU instruction per descriptor.
+template <typename T>
+__device__ inline const T& uniform_const(const T* p)
+{
+    typedef __attribute__((address_space(4))) const T* CP;
+    CP q = (CP)p;
+    asm volatile("" : "+s"(q));
+    return *(const T*)q;
+}
+
+// The address of by-value kernel argument `member` in the kernel-argument
+// segment.  The arguments lie there in declaration order at their natural
+// alignment, as the members of a struct (Mirror) that declares the kernel's
+// parameters up to that argument do.  (A mismatch would feed every
+// evaluation wrong parameters, which each parity test would show.)
+#define WM_KERNARG_PTR(Mirror, member)                                                   \
+    reinterpret_cast<const decltype(Mirror::member)*>(                                  \
+        (const char*)__builtin_amdgcn_kernarg_segment_ptr() + __builtin_offsetof(Mirror, member))
+
 __device__ inline Desc<float> load_desc(const DescPtrs& d, int64_t i)
 {
     Desc<float> x;

@@ -223,6 +223,8 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
 {
     __shared__ double red[16 * kAcc];
     const Set& S = PTR ? *sp : sv;
+    struct Args { DescPtrs d; int64_t n; const float* wv; Set sv; };
+    const Set* sc = PTR ? sp : WM_KERNARG_PTR(Args, sv);   // the set, read in place
     // per-lane partial sums: float32 in the bulk sweep (each lane adds the
     // ~n / (grid threads) descriptors it visits), float64 in the exact
     // variant; float64 from the wave reduction on
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DescPtrs d, int64_t n, const flo
             const Desc<float> x = load_desc(d, i);
             const float w = ntload(wv + i);
             if constexpr (X64) grad_exact<MODE>(S, x, w, acc);
-            else redo = grad_fast<MODE>(S, x, w, acc);
+            else redo = grad_fast<MODE>(uniform_const(sc), x, w, acc);
         }
         const uint64_t m = __ballot(redo);
         if (lane == 0) flags[base >> 6] = m;
@@ -505,7 +507,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t end = end_items < nk ? end_items : nk;
         const DescPtrs d = sets[k];
         const float* m = meas[k];
-        const Set& S = S_all[k];
         uint64_t* fl = flags + flag_off[k];
         float acc[kAcc];
 #pragma unroll
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int64_t base = begin + (threadIdx.x & ~63); base < end; base += blockDim.x) {
             const int64_t i = base + lane;
             bool redo = false;
-            if (i < end) redo = grad_fast<1>(S, load_desc(d, i), ntload(m + i), acc);
+            if (i < end) redo = grad_fast<1>(uniform_const(S_all + k), load_desc(d, i), ntload(m + i), acc);
             const uint64_t msk = __ballot(redo);
             if (lane == 0) fl[base >> 6] = msk;
         }

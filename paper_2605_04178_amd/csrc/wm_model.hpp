@@ -127,14 +127,37 @@ __device__ inline uint32_t udiv_small(uint32_t a, uint32_t b)
     return q;
 }
 
-// A copy of v in a vector register that the optimiser cannot see through.
-// A per-lane select among parameters (the peak of the descriptor's dtype,
-// the scale of a segment's class) written on such copies stays a register
-// select; on the parameters themselves the compiler may turn it into a
-// per-lane indexed load from the kernel-argument segment, a vector memory
-// access with its latency inside the evaluation.
-template <typename R>
-__device__ inline R vreg(R v)
+// floor(a / b) for integers a < 2^21 and 1 <= b < 2^24 without a remainder
+// correction.  With q = floor(a / b), the value (a + 1/2) / b lies in
+// [q + 1/(2b), q + 1 - 1/(2b)].  a + 1/2 and b are exact in float, the
+// hardware reciprocal is within 1 ulp (2^-23 relative) and the product adds
+// one rounding (2^-24), so the estimate is within (a + 1/2)/b * 1.51 * 2^-23
+// of (a + 1/2) / b, which is below 1/(2b) whenever a + 1/2 < 2.7e6: the
+// estimate stays strictly inside (q, q + 1) and truncation gives q.
+__device__ inline uint32_t udiv21(uint32_t a, uint32_t b)
+{
+    return (uint32_t)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
+}
+
+// x finite and >= 0 (-0 included): one class test instead of two compares
+__device__ inline bool finite_nonneg(float x) { return __builtin_amdgcn_classf(x, 0x1E0); }
+__device__ inline bool finite_nonneg(double x) { return x >= 0.0 && x < __builtin_huge_val(); }
+
+// A copy of v in a register that the optimiser cannot see through.  A
+// per-lane select among parameters (the peak of the descriptor's dtype, the
+// h_LLC exponent of its regime, the scale of a segment's class) written on
+// such copies stays a register select; on the parameters themselves the
+// compiler may turn it into a per-lane indexed load from the kernel-argument
+// segment, a vector memory access with its latency inside the evaluation.
+// float (the bulk sweeps): a scalar register, which v_cndmask reads
+// directly -- the sweeps' parameter sets are wave-uniform, and a divergent
+// one would not compile; double (the rare re-evaluations): a vector register.
+__device__ inline float vreg(float v)
+{
+    asm("" : "+s"(v));
+    return v;
+}
+__device__ inline double vreg(double v)
 {
     asm("" : "+v"(v));
     return v;
@@ -155,17 +178,18 @@ struct Occ {
 
 __device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t g)
 {
-    // all quotients below are < 2^21 by the parameter limits (VGPR_SIMD <=
-    // 65536, N_SIMD * waves <= 1024), so udiv_small is exact
+    // the first two dividends are below 2^21 by the parameter limits
+    // (VGPR_SIMD <= 65536, N_SIMD * waves <= 1024): udiv21 is exact; the LDS
+    // dividend reaches 2^24 and takes udiv_small
     Occ r;
     r.k = (g + (1 << st.wave_shift) - 1) >> st.wave_shift;
     int32_t w = 0;
     if (v <= st.vgpr_simd) {
         int32_t va = (v + st.vgpr_gran_mask) & ~st.vgpr_gran_mask;
-        w = (int32_t)udiv_small((uint32_t)st.vgpr_simd, (uint32_t)va);
+        w = (int32_t)udiv21((uint32_t)st.vgpr_simd, (uint32_t)va);
         w = w < st.waves_simd ? w : st.waves_simd;
     }
-    int32_t o = (int32_t)udiv_small(__umul24((uint32_t)st.n_simd, (uint32_t)w), (uint32_t)r.k);
+    int32_t o = (int32_t)udiv21(__umul24((uint32_t)st.n_simd, (uint32_t)w), (uint32_t)r.k);
     if (s > 0) {
         int32_t ol = 0;
         if (s <= st.lds_cu) {
@@ -182,9 +206,8 @@ __device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t 
 template <typename R>
 __device__ inline bool desc_valid(const Desc<R>& d)
 {
-    const R inf = (R)__builtin_huge_val();
-    bool ok = (d.F >= (R)0) & (d.F < inf) & (d.B >= (R)0) & (d.B < inf) & (d.K >= (R)0) &
-              (d.K < inf) & (d.W >= (R)0) & (d.W < inf) & (d.u > (R)0) & (d.u <= (R)1) &
+    bool ok = finite_nonneg(d.F) & finite_nonneg(d.B) & finite_nonneg(d.K) & finite_nonneg(d.W) &
+              (d.u > (R)0) & (d.u <= (R)1) &
               (d.r1 >= (R)0) & (d.r1 <= (R)1) & (d.r2 >= (R)0) & (d.r2 <= (R)1) &
               (d.r3 >= (R)0) & (d.r3 <= (R)1) & (d.v >= 1) & (d.s >= 0) & (d.G >= 1) &
               ((uint32_t)d.gp < (1u << 25));
@@ -241,11 +264,11 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
     // n_cu <= 65536 and o <= 1024: 24-bit multiplies are exact
     const uint32_t per_round = __umul24((uint32_t)st.n_cu, (uint32_t)oc.o);
     const uint32_t num = (uint32_t)d.G + per_round - 1u;
-    // udiv_small is exact below 2^21; larger counts (grids beyond ~2^21
-    // workgroups) take an exact division, behind a branch that the whole
-    // wave skips unless one of its lanes needs it
+    // udiv21 is exact below 2^21 (per_round <= num is then below 2^21 too);
+    // larger counts (grids beyond ~2^21 workgroups) take an exact division,
+    // behind a branch that the whole wave skips unless one of its lanes needs it
     const bool big = num >= (1u << 21);
-    uint32_t nru = udiv_small(big ? 0u : num, per_round);
+    uint32_t nru = udiv21(big ? 0u : num, big ? 1u : per_round);
     if (__builtin_expect(__ballot(big) != 0, 0)) {
         if (big) nru = num / per_round;
     }

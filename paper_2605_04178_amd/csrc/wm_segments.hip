@@ -14,6 +14,15 @@
 
 namespace wm {
 
+// the leading parameters of the application kernels, as they lie in the
+// kernel-argument segment (the sets are read there in place)
+struct AppsArgs {
+    DescPtrs d;
+    SegPtrs sg;
+    int64_t n_seg, n_apps;
+    Set S;
+    SegSet Q;
+};
 
 struct SegRow {
     float ne, h, dd;
@@ -104,6 +113,8 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
 {
     static_assert(MODE == 0, "the loss and its gradient are k_apps_grad");
     constexpr int CAP = 8 * BLOCK;
+    const Set* sc = WM_KERNARG_PTR(AppsArgs, S);
+    const SegSet* qc = WM_KERNARG_PTR(AppsArgs, Q);
     __shared__ float ts[CAP];
     __shared__ int32_t lo_s[BLOCK], hi_s[BLOCK];
     const int tid = threadIdx.x;
@@ -136,9 +147,10 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
                 const int32_t j = pb + jj;
                 const Desc<float> x = load_desc(d, j);
                 const SegRow r = load_seg(sg, j);
+                const Set& Sx = uniform_const(sc);
                 Eval<float> E;
-                evaluate<float, false>(S.st, S.cf, x, E);
-                const float t = seg_time<float>(E.T, r, Q.f, S.cf.ov[0]);
+                evaluate<float, false>(Sx.st, Sx.cf, x, E);
+                const float t = seg_time<float>(E.T, r, uniform_const(qc).f, Sx.cf.ov[0]);
                 ts[j - pb] = t;
                 if (T_seg) __builtin_nontemporal_store(t, T_seg + j);
             }
@@ -273,6 +285,8 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
     __shared__ int32_t lo_s[BLOCK], hi_s[BLOCK];
     __shared__ float wa_s[BLOCK];
     __shared__ double red[(BLOCK / 64) * kAppRow];
+    const Set* sc = WM_KERNARG_PTR(AppsArgs, S);
+    const SegSet* qc = WM_KERNARG_PTR(AppsArgs, Q);
     float acc[kAcc], sacc[8];   // the lane's partial sums; float64 from the block reduction on
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
@@ -330,8 +344,9 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
             float tsv = 0.0f;
             if (row) {
                 r = load_seg(sg, j);
-                evaluate<float, true>(S.st, S.cf, load_desc(d, j), E);
-                tsv = seg_time<float>(E.T, r, Q.f, S.cf.ov[0]);
+                const Set& Sx = uniform_const(sc);
+                evaluate<float, true>(Sx.st, Sx.cf, load_desc(d, j), E);
+                tsv = seg_time<float>(E.T, r, uniform_const(qc).f, Sx.cf.ov[0]);
             }
             ts[tid] = tsv;
             own[tid] = 0xFFFFu;
@@ -356,7 +371,10 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
             __syncthreads();
             if (row && own[tid] != 0xFFFFu) {
                 const float wa = wa_s[own[tid]];
-                if (wa != 0.0f && E.T < inf) app_row_terms(S.st, S.cf, Q.f, E, r, wa, j, acc, sacc, rflags, wrow);
+                if (wa != 0.0f && E.T < inf) {
+                    const Set& Sx = uniform_const(sc);
+                    app_row_terms(Sx.st, Sx.cf, uniform_const(qc).f, E, r, wa, j, acc, sacc, rflags, wrow);
+                }
             }
             __syncthreads();   // ts, own and wa_s are rewritten by the next piece
             t0 = t1 + 1;
