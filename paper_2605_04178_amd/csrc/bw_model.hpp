@@ -113,6 +113,27 @@ __device__ inline bool bw_desc_valid(const BwDesc& d)
            (d.CR >= 1.0f) & (d.CR < inf) & (d.ob > 0.0f) & (d.ob < inf);
 }
 
+// a / b: the hardware reciprocal (1 ulp) in the float sweeps, IEEE
+// division in the float64 re-evaluations
+__device__ inline float bw_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double bw_div(double a, double b) { return a / b; }
+
+// min(floor(a / b), cap) for 1 <= b <= a < 2^30 and cap <= 64.  The float
+// estimate a * rcp(b) (a and b rounded to 24 bits, rcp 1 ulp, one product
+// rounding: relative error below 2^-21) is within one of floor(a / b)
+// whenever that quotient is below 2^20, and at or above cap + 1 whenever the
+// quotient is larger than cap + 1; so after clamping the estimate to cap + 1
+// one correction by the exact 64-bit remainder gives the quotient or a value
+// above cap, which the final min clamps.
+__device__ inline uint32_t udiv_capped(uint32_t a, uint32_t b, uint32_t cap)
+{
+    const float qf = (float)a * __builtin_amdgcn_rcpf((float)b);
+    uint32_t q = qf >= (float)(cap + 1u) ? cap + 1u : (uint32_t)qf;
+    const uint64_t prod = (uint64_t)q * b;
+    q = prod > a ? q - 1u : (a - prod >= b ? q + 1u : q);
+    return q < cap ? q : cap;
+}
+
 template <typename R, bool FULL>
 __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, const BwDesc& d,
                                    BwEval<R>& E)
@@ -137,18 +158,28 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
     // most 2^63, is exact in 64 unsigned bits.
     const bool too_wide = (uint32_t)d.bM > (uint32_t)st.tmem_bytes || (uint32_t)d.bN > (uint32_t)st.tmem_bytes;
     const uint64_t acc = too_wide ? ~(uint64_t)0 : (uint64_t)d.bM * (uint64_t)d.bN * (dt == 0 ? 8u : 4u);
-    uint32_t cta = acc > (uint64_t)st.tmem_bytes ? 0u : (uint32_t)st.tmem_bytes / (uint32_t)acc;
-    cta = cta < (uint32_t)st.max_cta ? cta : (uint32_t)st.max_cta;
+    const uint32_t cta = acc > (uint64_t)st.tmem_bytes
+                             ? 0u
+                             : udiv_capped((uint32_t)st.tmem_bytes, (uint32_t)acc, (uint32_t)st.max_cta);
     E.cta = (int32_t)cta;
     if (cta < 1) {
         E.T = (R)__builtin_huge_val();
         return;
     }
+    // rounds: per_round = n_sm * cta <= 2^22; udiv21 where the numerator is
+    // below 2^21, an exact division (behind a branch the wave skips unless a
+    // lane needs it) for the larger grids
     const uint32_t per_round = (uint32_t)st.n_sm * cta;
-    const uint32_t nr = ((uint32_t)d.G + per_round - 1u) / per_round;
+    const uint32_t num = (uint32_t)d.G + per_round - 1u;
+    const bool big = num >= (1u << 21);
+    uint32_t nr = udiv21(big ? 0u : num, big ? 1u : per_round);
+    if (__builtin_expect(__ballot(big) != 0, 0)) {
+        if (big) nr = num / per_round;
+    }
     E.nr = (int32_t)nr;
 
-    const R e = dt == 0 ? (R)8 : (dt == 1 ? (R)4 : (dt == 2 ? (R)2 : (dt == 3 ? (R)1 : (R)0.5)));
+    // element bytes 8, 4, 2, 1, 1/2 for dtypes 0..4 (exact powers of two)
+    const R e = (R)__builtin_ldexp(1.0, 3 - dt);
     const R Kt = (R)d.Kt;
     E.Kt = Kt;
     const R MA = (R)d.bM * (R)d.bK * e;
@@ -162,7 +193,7 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
     const R Dread = Dacc + (stratB ? MA : (R)0);
     E.Dread = Dread;
     const R Ttmem = Dread * c.inv_tr + c.lmma + Dacc * c.inv_tw;
-    const R Tmgmt = c.ltmgmt / Kt;
+    const R Tmgmt = bw_div(c.ltmgmt, Kt);
     const R fl = (R)2 * (R)d.bM * (R)d.bN * (R)d.bK;
     R inv_rtc = c.inv_rtc[0];
     inv_rtc = dt == 1 ? c.inv_rtc[1] : inv_rtc;
@@ -174,7 +205,7 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
     const R Tcomp = Tmma + Ttmem + Tmgmt;
 
     // Eq. (4), Eq. (6)
-    const R ta_tb = MA / (R)PA + (pair ? (R)0.5 * MB : MB) / (R)PB;
+    const R ta_tb = bw_div(MA, (R)PA) + bw_div(pair ? (R)0.5 * MB : MB, (R)PB);
     E.ta_tb = ta_tb;
     const R Ttma = c.ltma + ta_tb * c.inv_btma;
     const R Tdsm = pair ? (R)0.5 * MB * c.inv_dsm : (R)0;
@@ -182,7 +213,7 @@ __device__ inline void evaluate_bw(const BwStruct& st, const BwConst<R>& c, cons
     // Eq. (5)
     const R Dab = MA + MB;
     E.Dab = Dab;
-    const R Tde = comp ? Dab / (R)d.CR * c.inv_link * c.inv_eta : (R)0;
+    const R Tde = comp ? bw_div(Dab, (R)d.CR) * c.inv_link * c.inv_eta : (R)0;
     E.Tde = Tde;
     const R Tup = dt == 4 ? Dab * c.inv_rdec + c.lsetup : (R)0;
 
