@@ -49,9 +49,8 @@ __device__ inline bool derive_tile(int32_t M, int32_t N, int32_t Kd, int32_t t, 
     x.u = (R)1;
     x.W = (R)0;
     // VGPRs: accumulators and the panel share per thread (numerators below
-    // 2^19, divisors at most 4096: exact float-reciprocal quotients)
-    x.v = (int32_t)(udiv_small((acc << (lmt + lnt)) + g - 1u, g) +
-                    udiv_small(pan + 4u * g - 1u, 4u * g) + 16u);
+    // 2^19, divisors at most 4096: udiv21 is exact)
+    x.v = (int32_t)(udiv21((acc << (lmt + lnt)) + g - 1u, g) + udiv21(pan + 4u * g - 1u, 4u * g) + 16u);
     x.s = (int32_t)(2u * pan);
     x.gp = (int32_t)g | (t << 11);
     x.G = (int32_t)G;
