@@ -68,6 +68,7 @@ def kernel_name(kind, cfg):
 
 KERNEL_FILES = (("wm::k_apps", "wm_segments.hip"), ("wm::k_zero_words", "wm_segments.hip"),
                 ("wm::k_fuse_costs", "wm_planning.hip"), ("wm::k_plan", "wm_planning.hip"),
+                ("wm::k_redo_", "wm_planning.hip"),
                 ("wm::k_fit_mult", "wm_planning.hip"), ("wm::k_bw", "wm_blackwell.hip"),
                 ("wm::k_select_tile", "wm_tile.hip"), ("wm::k_tile_costs", "wm_tile.hip"),
                 ("wm::k_", "wm_kernels.hip"))
@@ -381,6 +382,7 @@ def planning_leg(wm, synth, args, dev, log):
     lens = np.diff(off).astype(np.int64)
     cands = int(sum(min(R, j + 1) for L in lens for j in range(L)))
     tot, unf, st = fp()
+    redone = wm.plan_redone(ws)
     gain = float((unf / tot).double().mean().item())
     goff, fac, noise, train, d2 = synth.grouped_measurements(1 << 16, 172)
     dd2 = wm.DeviceDescriptors.from_host(d2, dev)
@@ -395,11 +397,12 @@ def planning_leg(wm, synth, args, dev, log):
     wall_m, ev_m = timed(fm, args.steps, args.warmup)
     _, _, stt = fm()
     stt = stt.cpu().numpy()
-    log(f"planning: fusion {ev_p:.3f} ms ({cands / (ev_p * 1e-3):.3g} FP64 candidate runs/s), "
-        f"multipliers {ev_m:.3f} ms")
+    log(f"planning: fusion {ev_p:.3f} ms ({cands / (ev_p * 1e-3):.3g} candidate runs/s, "
+        f"{redone} of {len(lens)} chains redone in float64), multipliers {ev_m:.3f} ms")
     return {"fusion": {"chains": len(lens), "rows": int(d.n), "max_run": R, "candidate_runs": cands,
                        "ms_per_call": wall_p, "event_ms": ev_p,
                        "candidate_runs_per_s": cands / (ev_p * 1e-3), "chains_per_s": len(lens) / (ev_p * 1e-3),
+                       "chains_redone_fp64": redone,
                        "mean_unfused_over_planned": gain, "fused_share": float(1.0 - st.float().mean().item())},
             "multipliers": {"groups": 1 << 16, "rows": int(d2.n), "ms_per_call": wall_m, "event_ms": ev_m,
                             "rows_per_s": d2.n / (ev_m * 1e-3),

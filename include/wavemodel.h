@@ -457,8 +457,10 @@ int32_t wm_fit_multipliers(const float *T, const float *measured, const int32_t 
 /*
  * Kernel-fusion planning (Section IV-B: a fused kernel is modelled with the
  * combined flops and bytes plus tau_fusion).  Chain c owns descriptor rows
- * [chain_off[c], chain_off[c+1]) in execution order (CSR, clamped like the
- * other offsets); edge [n] float32: bytes row i hands to row i + 1 (read only
+ * [chain_off[c], chain_off[c+1]) in execution order (CSR, non-decreasing;
+ * offsets are clamped into [0, n]; with offsets that are not non-decreasing,
+ * a chain overlapping another can get NaN totals and leave its start flags
+ * unwritten); edge [n] float32: bytes row i hands to row i + 1 (read only
  * inside a chain).  A plan cuts each chain into runs of 1 .. R (<= 32)
  * consecutive kernels, each run modelled as one kernel whose descriptor
  * combines the rows: flops, steps and host syncs add; bytes add minus twice
@@ -466,11 +468,21 @@ int32_t wm_fit_multipliers(const float *T, const float *measured, const int32_t 
  * minus the edges; hit rates are byte-weighted; u keeps the summed compute
  * time at the dtype of the largest-flop row (capped at 1); VGPRs, LDS,
  * workgroup size, grid and concurrency take the maximum; the fused flag adds
- * tau_fusion.  Costs are float64 (+inf for invalid runs); the optimal plan
- * comes from the prefix dynamic programme (shortest run first on ties).
+ * tau_fusion.  The sums forming a combined descriptor are float64; each
+ * run's cost is the model evaluated in float32 on that descriptor (+inf for
+ * runs with an invalid row or edge); the optimal plan comes from the prefix
+ * dynamic programme over those costs in float64 (shortest run first on
+ * ties).  A chain is redone with float64 costs when one of its decisions is
+ * within 3e-5 relative of the runner-up, or when one of its runs has a cost
+ * float32 cannot carry (not finite for valid rows, negative, or a working set
+ * within 1e-6 relative of the LLC capacity, where the hit rate jumps): plans
+ * then match a float64 evaluation except at its own ties, and totals match
+ * it to the model's float32 error (float64 rounding for redone chains).
  * Outputs (device): total [n_chains] and unfused [n_chains] float64 (the
  * optimal and the all-singles sums), start [n] uint8 = 1 where a run of the
- * optimal plan begins.  Workspace: wm_plan_workspace_bytes(n, R).
+ * optimal plan begins.  Workspace: wm_plan_workspace_bytes(n, R); after the
+ * call, the uint32 that starts its last 256 bytes is the number of chains
+ * redone in float64.
  */
 size_t wm_plan_workspace_bytes(int64_t n, int32_t R);
 int32_t wm_plan_fusion(const wm_desc_t *desc, const float *edge, const int32_t *chain_off,

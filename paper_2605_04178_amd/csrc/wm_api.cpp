@@ -268,9 +268,10 @@ SegPtrs segptrs_of(const wm_segs_t* s)
     return p;
 }
 
-// fusion-planning workspace: candidate costs, prefix optima, run lengths
+// fusion-planning workspace: candidate costs, the redo queue, run lengths,
+// per-row coverage bytes, the queue's length (last)
 struct PlanWs {
-    size_t cost, best, cut, total;
+    size_t cost, redo, cut, cov, n_redo, total;
 };
 
 PlanWs plan_ws(int64_t n, int32_t R)
@@ -280,10 +281,14 @@ PlanWs plan_ws(int64_t n, int32_t R)
     const size_t nn = (size_t)(n > 0 ? n : 1);
     W.cost = off;
     off += up256(sizeof(double) * nn * (size_t)R);
-    W.best = off;
-    off += up256(sizeof(double) * nn);
+    W.redo = off;
+    off += up256(sizeof(int64_t) * nn);
     W.cut = off;
     off += up256(nn);
+    W.cov = off;
+    off += up256(nn);
+    W.n_redo = off;
+    off += 256;
     W.total = off;
     return W;
 }
@@ -933,9 +938,14 @@ int32_t wm_plan_fusion(const wm_desc_t* desc, const float* edge, const int32_t* 
     if (!ws_ok(ws, ws_bytes, W.total)) return WM_EWORKSPACE;
     char* base = (char*)ws;
     const Set S = make_set(params);
+    PlanBufs wb;
+    wb.cost = (double*)(base + W.cost);
+    wb.redo = (int64_t*)(base + W.redo);
+    wb.cut = (uint8_t*)(base + W.cut);
+    wb.cov = (uint8_t*)(base + W.cov);
+    wb.n_redo = (uint32_t*)(base + W.n_redo);
     WM_HIP(launch_plan_fusion(ptrs_of(desc), edge, chain_off, n_chains, desc->n, R, S,
-                              params->theta + 8, (double*)(base + W.cost), (double*)(base + W.best),
-                              (uint8_t*)(base + W.cut), total, unfused, start, (hipStream_t)stream));
+                              params->theta + 8, wb, total, unfused, start, (hipStream_t)stream));
     return WM_OK;
 }
 

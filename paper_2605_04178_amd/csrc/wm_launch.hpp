@@ -165,12 +165,20 @@ hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n
 hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32_t* off,
                                   int64_t n_groups, int64_t n, const uint8_t* train, double* mult,
                                   float* T_scaled, double* rows, double* stats, hipStream_t s);
-// Fusion plans of chains over n descriptor rows; cost (n x R doubles),
-// best (n doubles) and cut (n bytes) are workspace.
+// Fusion-planning workspace over n descriptor rows.
+struct PlanBufs {
+    double* cost;       // n x R run costs (row of the run's last kernel, length - 1)
+    int64_t* redo;      // n chains queued for the float64 redo
+    uint8_t* cut;       // n chosen run lengths (rows beyond the ones kept in registers)
+    uint8_t* cov;       // n: runs costed from each row (bits 0-5), bit 7 = one of them
+                        // is uncertain
+    uint32_t* n_redo;   // the queue's length
+};
+// Fusion plans of chains over n descriptor rows.
 hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_t* off,
                               int64_t n_chains, int64_t n, int32_t R, const Set& S,
-                              const double* peaks, double* cost, double* best, uint8_t* cut,
-                              double* total, double* unfused, uint8_t* start, hipStream_t s);
+                              const double* peaks, const PlanBufs& wb, double* total,
+                              double* unfused, uint8_t* start, hipStream_t s);
 // Vector-Jacobian product of the application totals: out [31] = sum_a
 // w_app[a] dT_a/d(theta[24], seg params[7]); workspace as the loss gradient.
 hipError_t launch_apps_vjp(const DescPtrs& d, const SegPtrs& sg, int64_t n_seg, int64_t n_apps,

@@ -206,8 +206,9 @@ __device__ inline Occ occupancy(const Struct& st, int32_t v, int32_t s, int32_t 
 template <typename R>
 __device__ inline bool desc_valid(const Desc<R>& d)
 {
-    bool ok = finite_nonneg(d.F) & finite_nonneg(d.B) & finite_nonneg(d.K) & finite_nonneg(d.W) &
-              (d.u > (R)0) & (d.u <= (R)1) &
+    const bool fF = finite_nonneg(d.F), fB = finite_nonneg(d.B), fK = finite_nonneg(d.K),
+               fW = finite_nonneg(d.W);
+    bool ok = fF & fB & fK & fW & (d.u > (R)0) & (d.u <= (R)1) &
               (d.r1 >= (R)0) & (d.r1 <= (R)1) & (d.r2 >= (R)0) & (d.r2 <= (R)1) &
               (d.r3 >= (R)0) & (d.r3 <= (R)1) & (d.v >= 1) & (d.s >= 0) & (d.G >= 1) &
               ((uint32_t)d.gp < (1u << 25));

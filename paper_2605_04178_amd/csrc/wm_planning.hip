@@ -9,10 +9,13 @@
 //
 // Fusion (Section IV-B: a fused kernel is modelled with the combined flops
 // and bytes plus tau_fusion): a chain of kernels is cut into runs of at most
-// R consecutive kernels; every (run end, run length) candidate is turned into
-// a combined descriptor and evaluated in float64 (one wave per chain, lanes
-// over candidates), then one thread per chain runs the prefix dynamic
-// programme over those costs.
+// R consecutive kernels.  One thread per row extends the fusion sums of the
+// runs starting there one row at a time (float64 sums) and evaluates each
+// run's combined descriptor in float32; one thread per chain runs the prefix
+// dynamic programme over those costs in float64.  Chains where float32 could
+// decide differently from float64 (a decision within a small relative
+// margin, or a run float32 cannot represent) are redone in float64, one wave
+// per chain, so plans match a float64 evaluation except at its own ties.
 #include "wm_device.hpp"
 
 namespace wm {
@@ -167,6 +170,26 @@ hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32
 // ---------------------------------------------------------------------------
 // fusion planning
 // ---------------------------------------------------------------------------
+// One descriptor row through the caches: the fusion kernels read each row
+// once per run that holds it, so these loads are not marked streaming.
+__device__ inline Desc<float> load_row(const DescPtrs& d, int64_t i)
+{
+    Desc<float> x;
+    x.F = d.F[i];
+    x.B = d.B[i];
+    x.r1 = d.r1[i];
+    x.r2 = d.r2[i];
+    x.r3 = d.r3[i];
+    x.K = d.K[i];
+    x.u = d.u[i];
+    x.W = d.W[i];
+    x.v = d.vgpr[i];
+    x.s = d.lds[i];
+    x.gp = d.gpack[i];
+    x.G = d.grid[i];
+    return x;
+}
+
 // The combined descriptor of rows a .. a+len-1 (len >= 2), float64:
 //   F = sum F;  B = max(sum B - 2 sum edges, 0);  r_l byte-weighted;
 //   K = sum K;  W = max(sum W - sum edges, 0);  dtype of the first row with
@@ -183,7 +206,7 @@ __device__ inline bool fuse_rows(const DescPtrs& d, const float* __restrict__ ed
     int32_t v = 0, s = 0, g = 0, G = 0, nc = 0, nd = 0, ns = 0, dt = 0;
     for (int32_t q = 0; q < len; ++q) {
         const int64_t k = a + q;
-        const Desc<float> x = load_desc(d, k);
+        const Desc<float> x = load_row(d, k);
         if (!desc_valid(x)) return false;
         if (q < len - 1) {
             const float ek = edge[k];
@@ -237,114 +260,706 @@ struct Peaks {
     double p[5];
 };
 
-// One wave per chain: cost[(row) * R + len - 1] for every run of len rows
-// ending at that row (float64; +inf for runs that leave the chain or hold an
-// invalid row or edge, and for NaN times).
+// Running float64 sums of a run of rows, extended one row at a time in row
+// order (the order fuse_rows adds them in, so a run's sums are the same).
+struct FuseSum {
+    double F, Bs, E, r1, r2, r3, K, Ws, tc;
+    float Fmax;
+    int32_t v, s, g, G, nc, nd, ns, dt;
+};
+
+__device__ inline void fuse_begin(FuseSum& a)
+{
+    a.F = a.Bs = a.E = a.r1 = a.r2 = a.r3 = a.K = a.Ws = a.tc = 0.0;
+    a.Fmax = -1.0f;
+    a.v = a.s = a.g = a.G = a.nc = a.nd = a.ns = a.dt = 0;
+}
+
+// Adds row x; tk = its compute time F / (u P_dtype) (float32, only summed).
+__device__ inline void fuse_add(FuseSum& a, const Desc<float>& x, float tk)
+{
+#pragma clang fp contract(off)
+    const double Bk = x.B;
+    const int32_t gp = x.gp;
+    const int32_t dtk = (gp >> 11) & 7;
+    a.F += (double)x.F;
+    a.Bs += Bk;
+    a.r1 += (double)x.r1 * Bk;
+    a.r2 += (double)x.r2 * Bk;
+    a.r3 += (double)x.r3 * Bk;
+    a.K += (double)x.K;
+    a.Ws += (double)x.W;
+    if (x.F > 0.0f) a.tc += (double)tk;
+    if (x.F > a.Fmax) {
+        a.Fmax = x.F;
+        a.dt = dtk;
+    }
+    a.v = x.v > a.v ? x.v : a.v;
+    a.s = x.s > a.s ? x.s : a.s;
+    a.g = (gp & 2047) > a.g ? (gp & 2047) : a.g;
+    a.G = x.G > a.G ? x.G : a.G;
+    a.nc = ((gp >> 14) & 7) > a.nc ? ((gp >> 14) & 7) : a.nc;
+    a.nd = ((gp >> 17) & 7) > a.nd ? ((gp >> 17) & 7) : a.nd;
+    a.ns += (gp >> 21) & 15;
+}
+
+// The fused descriptor of the run so far (two or more rows), formed in
+// float64 as fuse_rows does and rounded to float32; Wd gets the float64
+// working set.
+__device__ inline Desc<float> fuse_narrow(const FuseSum& a, double peak_dt, double& Wd)
+{
+#pragma clang fp contract(off)
+    Desc<float> o;
+    o.F = (float)a.F;
+    o.B = (float)(a.Bs - 2.0 * a.E > 0.0 ? a.Bs - 2.0 * a.E : 0.0);
+    const double iB = a.Bs > 0.0 ? 1.0 / a.Bs : 0.0;
+    o.r1 = (float)(a.r1 * iB);
+    o.r2 = (float)(a.r2 * iB);
+    o.r3 = (float)(a.r3 * iB);
+    o.K = (float)a.K;
+    Wd = a.Ws - a.E > 0.0 ? a.Ws - a.E : 0.0;
+    o.W = (float)Wd;
+    if (a.F > 0.0) {
+        const double u = a.F / (peak_dt * a.tc);
+        o.u = (float)(u < 1.0 ? u : 1.0);
+    } else {
+        o.u = 1.0f;
+    }
+    o.v = a.v;
+    o.s = a.s;
+    o.G = a.G;
+    const int32_t ns = a.ns < 15 ? a.ns : 15;
+    o.gp = a.g | (a.dt << 11) | (a.nc << 14) | (a.nd << 17) | (1 << 20) | (ns << 21);
+    return o;
+}
+
+// Coverage byte per row: bits 0-5 the number of runs costed from the row
+// (at most 32), bit 7 set when one of them is uncertain in float32.
+constexpr uint8_t kPlanCount = 0x3f;
+constexpr uint8_t kPlanUncertain = 0x80;
+
+// One thread per row s: the runs of 1 .. m rows starting at s, m = min(R,
+// rows left in s's chain), their fusion sums extended one row per step in
+// float64 and each fused descriptor evaluated in float32 (the row itself for
+// the run of one); cost[(s + len - 1) * R + len - 1] gets the time (+inf for
+// runs holding an invalid row or edge and for NaN).  A run is uncertain when
+// float32 cannot stand for float64: its float32 time is not finite while its
+// rows are valid (and the kernel is not simply infeasible), the time is
+// negative, or its working set lies within 1e-6 of the LLC capacity, where
+// the hit rate of Table "hlcc-piecewise" jumps.
+struct FuseArgs {   // k_fuse_costs's parameters, in order
+    DescPtrs d;
+    const float* edge;
+    const int32_t* off;
+    int64_t n_chains, n;
+    int32_t R;
+    Set S;
+    Peaks pk;
+    PlanBufs wb;
+};
+
 __global__ __launch_bounds__(256) void k_fuse_costs(DescPtrs d, const float* __restrict__ edge,
                                                      const int32_t* __restrict__ off,
                                                      int64_t n_chains, int64_t n, int32_t R, Set S,
-                                                     Peaks pk, double* __restrict__ cost)
+                                                     Peaks pk, PlanBufs wb)
+{
+    // parameters read in place (scalar loads at each use), not held in
+    // scalar registers across the run loop
+    const Set* sc = WM_KERNARG_PTR(FuseArgs, S);
+    const Peaks* pc = WM_KERNARG_PTR(FuseArgs, pk);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) *wb.n_redo = 0u;   // the queue of the planning pass that follows
+    if (s >= n) return;
+    // the chain holding s: the last c with off[c] <= s (offsets clamped into
+    // [0, n] and non-decreasing)
+    auto at = [&](int64_t c) -> int64_t {
+        const int64_t v = off[c];
+        return v < 0 ? 0 : (v > n ? n : v);
+    };
+    int32_t m = 0;
+    if (at(0) <= s) {
+        int64_t lo = 0, hi = n_chains;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (at(mid) <= s) lo = mid; else hi = mid;
+        }
+        const int64_t b = at(lo + 1);
+        if (s < b) m = (int32_t)(b - s < (int64_t)R ? b - s : (int64_t)R);
+    }
+    const float inf = __builtin_huge_valf();
+    FuseSum fs;
+    fuse_begin(fs);
+    bool ok = true, unc = false;
+    // the next row (and the edge into it) is loaded while this one is
+    // evaluated
+    Desc<float> xn;
+    float en = 0.0f;
+    if (m > 0) xn = load_row(d, s);
+    for (int32_t q = 0; q < m; ++q) {
+        const int64_t k = s + q;
+        const Desc<float> x = xn;
+        const float ek = en;
+        if (q + 1 < m) {
+            xn = load_row(d, k + 1);
+            en = edge[k];
+        }
+        if (q > 0) {
+            ok = ok && ek >= 0.0f && ek < inf;
+            fs.E += (double)ek;
+        }
+        ok = ok && desc_valid(x);
+        float t = inf;
+        if (ok) {
+            const Set& P = uniform_const(sc);
+            const Peaks& K = uniform_const(pc);
+            const int32_t dtk = (x.gp >> 11) & 7;
+            double pkk = vreg(K.p[0]);
+            pkk = dtk == 1 ? vreg(K.p[1]) : pkk;
+            pkk = dtk == 2 ? vreg(K.p[2]) : pkk;
+            pkk = dtk == 3 ? vreg(K.p[3]) : pkk;
+            pkk = dtk == 4 ? vreg(K.p[4]) : pkk;
+            fuse_add(fs, x, x.F / (x.u * (float)pkk));
+            double Wd = (double)x.W;
+            Desc<float> y = x;
+            if (q > 0) {
+                double pd = vreg(K.p[0]);
+                pd = fs.dt == 1 ? vreg(K.p[1]) : pd;
+                pd = fs.dt == 2 ? vreg(K.p[2]) : pd;
+                pd = fs.dt == 3 ? vreg(K.p[3]) : pd;
+                pd = fs.dt == 4 ? vreg(K.p[4]) : pd;
+                y = fuse_narrow(fs, pd, Wd);
+            }
+            Eval<float> E;
+            evaluate<float, false>(P.st, P.cf, y, E);
+            t = E.T;
+            const bool fin = __builtin_isfinite(t);
+            unc = unc || (!fin && E.occ != 0) || (fin && t < 0.0f);
+            if (P.st.n_levels == 4 && Wd > 0.0) {
+                const double c_llc = P.cd.c_llc;
+                const double dw = Wd * (1.0 / 1048576.0) - c_llc;
+                unc = unc || (dw < 0.0 ? -dw : dw) <= 1e-6 * c_llc;
+            }
+            t = t == t ? t : inf;
+        }
+        wb.cost[k * R + q] = (double)t;
+    }
+    wb.cov[s] = (uint8_t)(m | (unc ? kPlanUncertain : 0));
+}
+
+// Decision margin below which a float32 plan is re-decided in float64: the
+// window of the tile selection, far above the float32 model's relative error
+// (a decision compares two sums of run times, each off by at most that error
+// relative to itself).
+constexpr double kPlanWindow = (double)kTileWindow;
+
+// The dynamic programme runs on groups of GS lanes (GS the power of two >= R),
+// one chain per group: lane gl of a group stands for the run of gl + 1 rows
+// ending at the current row j and holds prev = best over the rows before
+// that run, so that a step is prev + cost, a group minimum (shortest run on
+// ties, as a sequential scan with strict improvement picks) and a shift of
+// prev by one lane.  Groups of one wave step together over their chains.
+template <int GS>
+struct PlanGroup {
+    int gl, base;   // lane in group, group's first lane
+    int64_t c;      // chain (or -1)
+    int64_t a, L;   // first row, rows
+};
+
+template <int GS>
+__device__ inline PlanGroup<GS> plan_group(int64_t c, int64_t n_chains, const int32_t* off,
+                                           int64_t n)
+{
+    PlanGroup<GS> g;
+    const int lane = threadIdx.x & 63;
+    g.gl = lane & (GS - 1);
+    g.base = lane - g.gl;
+    g.c = c >= 0 && c < n_chains ? c : -1;
+    g.a = 0;
+    g.L = 0;
+    if (g.c >= 0) {
+        int64_t a = off[c], b = off[c + 1];
+        a = a < 0 ? 0 : (a > n ? n : a);
+        b = b < a ? a : (b > n ? n : b);
+        g.a = a;
+        g.L = b - a;
+    }
+    return g;
+}
+
+template <int GS>
+__device__ inline uint64_t group_mask(const PlanGroup<GS>& g)
+{
+    return (GS == 64 ? ~0ull : ((1ull << GS) - 1ull)) << g.base;
+}
+
+// Lane moves inside a row of 16 lanes (DPP): CTRL 0x140 mirrors the row,
+// 0x141 mirrors each half row, 0x4E and 0xB1 swap lanes 2 and 1 apart in each
+// quad; 0x138 shifts the wave up by one lane (lane 0 keeps its value).
+template <int CTRL>
+__device__ inline int32_t dpp32(int32_t x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ inline double dpp64(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)dpp32<CTRL>((int32_t)(uint32_t)u);
+    const uint32_t hi = (uint32_t)dpp32<CTRL>((int32_t)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The partner of step k of the group reduction: lanes 16 apart (GS = 32),
+// the row mirror (GS >= 16), the half-row mirror (GS >= 8), then 2 and 1 apart
+// in the quad; each step doubles the lanes a value covers.
+template <int STEP>
+__device__ inline double partner(double v)
+{
+    if constexpr (STEP == 16) return __shfl_xor(v, 16, 64);
+    else if constexpr (STEP == 8) return dpp64<0x140>(v);
+    else if constexpr (STEP == 4) return dpp64<0x141>(v);
+    else if constexpr (STEP == 2) return dpp64<0x4E>(v);
+    else return dpp64<0xB1>(v);
+}
+
+template <int STEP>
+__device__ inline int32_t partner(int32_t v)
+{
+    if constexpr (STEP == 16) return __shfl_xor(v, 16, 64);
+    else if constexpr (STEP == 8) return dpp32<0x140>(v);
+    else if constexpr (STEP == 4) return dpp32<0x141>(v);
+    else if constexpr (STEP == 2) return dpp32<0x4E>(v);
+    else return dpp32<0xB1>(v);
+}
+
+template <int STEP>
+__device__ inline void argmin_step(double& v, int32_t& len)
+{
+    const double ov = partner<STEP>(v);
+    const int32_t ol = partner<STEP>(len);
+    const bool take = (ov < v) | ((ov == v) & (ol < len));
+    v = take ? ov : v;
+    len = take ? ol : len;
+}
+
+// Minimum of (v, len) over the group, ties to the shorter run.
+template <int GS>
+__device__ inline void group_argmin(double& v, int32_t& len)
+{
+    if constexpr (GS >= 32) argmin_step<16>(v, len);
+    if constexpr (GS >= 16) argmin_step<8>(v, len);
+    if constexpr (GS >= 8) argmin_step<4>(v, len);
+    if constexpr (GS >= 4) argmin_step<2>(v, len);
+    if constexpr (GS >= 2) argmin_step<1>(v, len);
+}
+
+template <int GS>
+__device__ inline double group_min(double v)
+{
+    if constexpr (GS >= 32) { const double o = partner<16>(v); v = o < v ? o : v; }
+    if constexpr (GS >= 16) { const double o = partner<8>(v); v = o < v ? o : v; }
+    if constexpr (GS >= 8) { const double o = partner<4>(v); v = o < v ? o : v; }
+    if constexpr (GS >= 4) { const double o = partner<2>(v); v = o < v ? o : v; }
+    if constexpr (GS >= 2) { const double o = partner<1>(v); v = o < v ? o : v; }
+    return v;
+}
+
+// Rows of costs a group loads ahead of its steps (one wait per batch), and
+// windows of GS rows whose cut lengths stay in registers (cut bytes of
+// rows beyond them go through memory).
+constexpr int kPlanBatch = 16;
+constexpr int kPlanRegWin = 4;
+
+// Per-lane state of a group's programme: prev (best over the rows before
+// this lane's run), the all-singles sum (first lane), best[j], the cut
+// length of row w * GS + gl in cutw[w].
+struct PlanState {
+    double prev, single, best;
+    int32_t cutw[kPlanRegWin];
+};
+
+// One step of the programme at row j of the group's chain (all lanes of the
+// wave call it; `live` marks groups still inside their chain).  t is this
+// lane's run cost (ignored where the run is longer than R or than j + 1
+// rows).  Updates prev, the all-singles sum (on the group's first lane, whose
+// run is the row alone), best and the cut length of row j; with MARGIN,
+// `close` is set when the runner-up is within kPlanWindow.
+template <int GS, bool MARGIN>
+__device__ inline void plan_step(const PlanGroup<GS>& g, int32_t R, int64_t j, bool live,
+                                 double t, PlanState& ps, bool& close, uint8_t* __restrict__ cut)
+{
+    const double inf = __builtin_huge_val();
+    const int32_t len = g.gl + 1;
+    const bool valid = live & (len <= R) & (len <= j + 1);
+    const double v = valid ? ps.prev + t : inf;
+    if (valid && g.gl == 0) ps.single += t;
+    double bj = v;
+    int32_t cj = len;
+    group_argmin<GS>(bj, cj);
+    if (MARGIN) {
+        const double sj = group_min<GS>(len == cj ? inf : v);
+        close = close | (live & (sj < inf) & (sj - bj <= kPlanWindow * sj));
+    }
+    if (live) {
+        if (j < (int64_t)kPlanRegWin * GS) {
+#pragma unroll
+            for (int w = 0; w < kPlanRegWin; ++w)
+                if (j == (int64_t)w * GS + g.gl) ps.cutw[w] = cj;
+        } else if (g.gl == 0) {
+            cut[g.a + j] = (uint8_t)cj;
+        }
+        ps.best = bj;
+    }
+    const double up = dpp64<0x138>(ps.prev);   // lane - 1's prev
+    ps.prev = g.gl == 0 ? bj : up;
+}
+
+// The programme over the group's chain, costs from wb.cost.  With COV, the
+// chain's coverage bytes are read with the first batch of costs and `run`
+// is narrowed to covered chains without an uncertain run (covered and unc
+// report them); without, `run` is taken as given.
+template <int GS, bool MARGIN, bool COV>
+__device__ inline void plan_run(const PlanGroup<GS>& g, bool& run, int32_t R, const PlanBufs& wb,
+                                PlanState& ps, bool& close, bool& covered, bool& unc)
+{
+    const double inf = __builtin_huge_val();
+    const int32_t len = g.gl + 1;
+    ps.prev = ps.single = ps.best = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPlanRegWin; ++w) ps.cutw[w] = 1;
+    covered = true;
+    unc = false;
+    for (int64_t j0 = 0; __ballot(run && j0 < g.L) != 0ull; j0 += kPlanBatch) {
+        double t[kPlanBatch];
+#pragma unroll
+        for (int k = 0; k < kPlanBatch; ++k) {
+            const int64_t j = j0 + k;
+            t[k] = run && j < g.L && len <= R && len <= j + 1 ? wb.cost[(g.a + j) * R + g.gl] : inf;
+        }
+        if (COV && j0 == 0) {
+            // coverage and uncertain runs, GS rows at a time (loads in flight
+            // with the costs above)
+            const uint64_t gm = group_mask(g);
+            bool bad = false, u = false;
+            for (int64_t i = g.gl; i < g.L; i += GS) {
+                const uint8_t cv = wb.cov[g.a + i];
+                const int64_t want = g.L - i < (int64_t)R ? g.L - i : (int64_t)R;
+                bad = bad || (int64_t)(cv & kPlanCount) != want;
+                u = u || (cv & kPlanUncertain) != 0;
+            }
+            covered = (__ballot(bad) & gm) == 0ull;
+            unc = (__ballot(u) & gm) != 0ull;
+            run = run && covered && !unc;
+        }
+#pragma unroll 1
+        for (int k = 0; k < kPlanBatch; ++k) {
+            const int64_t j = j0 + k;
+            plan_step<GS, MARGIN>(g, R, j, run && j < g.L, t[k], ps, close, wb.cut);
+        }
+    }
+}
+
+// Start flags of the chosen plan: the run starts found by following the cut
+// lengths back from the chain's end, window by window (rows w * GS .. w * GS
+// + GS - 1, the window's cut lengths in the group's lanes, the chase by
+// shuffles).  `live` marks groups that write their chain's flags.
+template <int GS>
+__device__ inline void plan_starts(const PlanGroup<GS>& g, bool live, const PlanState& ps,
+                                   const uint8_t* __restrict__ cut, uint8_t* __restrict__ start)
+{
+    const int64_t nw = live ? (g.L + GS - 1) / GS : 0;   // windows of the chain
+    // cut bytes beyond the register windows were stored by the group's first
+    // lanes: make them visible to the loads below
+    if (__ballot(nw > kPlanRegWin) != 0ull) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    int64_t w = nw - 1;
+    int64_t jj = live ? g.L : 0;   // the next run start found (row in the chain)
+    while (__ballot(w >= 0) != 0ull) {
+        const int64_t w0 = w >= 0 ? w * GS : 0;
+        const int64_t row = w0 + g.gl;
+        const bool mine = w >= 0 && row < g.L;
+        int32_t cv = 1;
+#pragma unroll
+        for (int k = 0; k < kPlanRegWin; ++k) cv = w == k ? ps.cutw[k] : cv;
+        if (mine && w >= kPlanRegWin) cv = cut[g.a + row];
+        bool flag = mine && row == jj;
+        while (__ballot(w >= 0 && jj > w0) != 0ull) {
+            const int64_t r = w >= 0 && jj > w0 ? jj - 1 - w0 : 0;
+            const int32_t Lr = __shfl(cv, g.base + (int)r, 64);
+            if (w >= 0 && jj > w0) {
+                jj -= Lr;
+                flag = flag || (mine && row == jj);
+            }
+        }
+        if (mine) start[g.a + row] = flag ? 1 : 0;
+        --w;
+    }
+}
+
+// Float32 pass: one group per chain steps through the costs of
+// k_fuse_costs.  A chain whose rows were not all costed as its own (offsets
+// that are not non-decreasing) gets NaN totals and no start flags; a chain
+// holding an uncertain run or a close decision is queued for the float64
+// redo; the rest get their totals and start flags.
+constexpr int kPlanBlock = 1024;   // threads per block of the planning pass
+
+template <int GS>
+__global__ __launch_bounds__(kPlanBlock) void k_plan(const int32_t* __restrict__ off,
+                                                      int64_t n_chains, int64_t n, int32_t R,
+                                                      PlanBufs wb, double* __restrict__ total,
+                                                      double* __restrict__ unfused,
+                                                      uint8_t* __restrict__ start)
+{
+    __shared__ uint32_t wave_q[kPlanBlock / 64 + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GS;
+    const PlanGroup<GS> g = plan_group<GS>(gid, n_chains, off, n);
+    const uint64_t gm = group_mask(g);
+    PlanState ps;
+    bool run = g.c >= 0, close = false, covered, unc;
+    plan_run<GS, true, true>(g, run, R, wb, ps, close, covered, unc);
+    close = unc || (__ballot(close) & gm) != 0ull;
+    const bool done = g.c >= 0 && covered && !close;
+    // queue slots: one atomic per block, the waves' shares by a prefix in LDS
+    const bool queue = g.c >= 0 && covered && close && g.gl == 0;
+    const uint64_t qm = __ballot(queue);
+    if (lane == 0) wave_q[wid] = (uint32_t)__builtin_popcountll(qm);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0u;
+        for (int w = 0; w < kPlanBlock / 64; ++w) {
+            const uint32_t c = wave_q[w];
+            wave_q[w] = sum;
+            sum += c;
+        }
+        wave_q[kPlanBlock / 64] = sum != 0u ? atomicAdd(wb.n_redo, sum) : 0u;
+    }
+    __syncthreads();
+    const uint32_t slot = wave_q[kPlanBlock / 64] + wave_q[wid] +
+                          (uint32_t)__builtin_popcountll(qm & ((1ull << lane) - 1ull));
+    if (g.c >= 0 && g.gl == 0) {
+        if (!covered) {
+            total[g.c] = __builtin_nan("");
+            unfused[g.c] = __builtin_nan("");
+        } else if (done) {
+            total[g.c] = ps.best;
+            unfused[g.c] = ps.single;
+        } else if ((int64_t)slot < n) {
+            // non-empty chains that partition the rows number at most n
+            wb.redo[slot] = g.c;
+        } else {
+            total[g.c] = __builtin_nan("");
+            unfused[g.c] = __builtin_nan("");
+        }
+    }
+    plan_starts(g, done, ps, wb.cut, start);
+}
+
+// The queue's length, clamped to what the queue can hold.
+__device__ inline int64_t redo_count(const PlanBufs& wb, int64_t n_chains, int64_t n)
+{
+    int64_t nq = *wb.n_redo;
+    nq = nq < n_chains ? nq : n_chains;
+    return nq < n ? nq : n;
+}
+
+// Float64 redo, costs: each wave takes E <= kRedoChains queued chains (E
+// the queue's length over the grid's waves, so that every wave has work
+// before any takes several) and lays their (run length, run end) candidates
+// end to end over its lanes, ordered by length so that neighbouring lanes
+// fuse the same number of rows; each run is formed by fuse_rows and
+// evaluated with the float64 model, and the costs replace the chains'
+// float32 ones.
+constexpr int kRedoChains = 8;
+
+// Lane k's value of x (k wave-uniform); every lane active.
+__device__ inline int64_t read_lane64(int64_t x, int k)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+struct RedoArgs {   // k_redo_costs's parameters, in order
+    DescPtrs d;
+    const float* edge;
+    const int32_t* off;
+    int64_t n_chains, n;
+    int32_t R;
+    Set S;
+    Peaks pk;
+};
+
+__global__ __launch_bounds__(256) void k_redo_costs(DescPtrs d, const float* __restrict__ edge,
+                                                     const int32_t* __restrict__ off,
+                                                     int64_t n_chains, int64_t n, int32_t R, Set S,
+                                                     Peaks pk, PlanBufs wb)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const double inf = __builtin_huge_val();
-    for (int64_t c = wave; c < n_chains; c += nwaves) {
-        int64_t a = off[c], b = off[c + 1];
-        a = a < 0 ? 0 : (a > n ? n : a);
-        b = b < a ? a : (b > n ? n : b);
-        const int64_t ncand = (b - a) * R;
-        for (int64_t q = lane; q < ncand; q += 64) {
-            const int64_t j = q / R;                 // row in the chain (run end)
-            const int32_t len = (int32_t)(q - j * R) + 1;
-            double t = inf;
-            if (len <= j + 1) {
-                const int64_t s0 = a + j - len + 1;
-                Desc<double> x;
-                bool ok;
-                if (len == 1) {
-                    x = widen(load_desc(d, s0));
-                    ok = true;
-                } else {
-                    ok = fuse_rows(d, edge, pk.p, s0, len, x);
-                }
-                if (ok) {
-                    Eval<double> E;
-                    evaluate<double, false>(S.st, S.cd, x, E);
-                    t = E.T == E.T ? E.T : inf;
+    const int64_t nq = redo_count(wb, n_chains, n);
+    int64_t E = (nq + nwaves - 1) / nwaves;
+    E = E < 1 ? 1 : (E > kRedoChains ? kRedoChains : E);
+    for (int64_t e0 = wave * E; e0 < nq; e0 += nwaves * E) {
+        // lanes 0 .. E-1: a chain each, its rows and candidate count
+        int64_t a = 0, L = 0, cnt = 0;
+        if (lane < E && e0 + lane < nq) {
+            const int64_t c = wb.redo[e0 + lane];
+            if (c >= 0 && c < n_chains) {
+                a = off[c];
+                int64_t b = off[c + 1];
+                a = a < 0 ? 0 : (a > n ? n : a);
+                b = b < a ? a : (b > n ? n : b);
+                L = b - a;
+                const int64_t r = L < (int64_t)R ? L : (int64_t)R;
+                cnt = r * L - r * (r - 1) / 2;   // sum over len <= r of L - len + 1
+            }
+        }
+        // inclusive prefix of the counts over the first kRedoChains lanes
+        int64_t inc = cnt;
+#pragma unroll
+        for (int m = 1; m < kRedoChains; m <<= 1) {
+            const int64_t o = __shfl_up(inc, m, 64);
+            inc += lane >= m ? o : 0;
+        }
+        // the chains' running ends, first rows and lengths, read while every
+        // lane is active (wave-uniform, so in scalar registers)
+        int64_t ends[kRedoChains], as[kRedoChains], Ls[kRedoChains];
+#pragma unroll
+        for (int k = 0; k < kRedoChains; ++k) {
+            ends[k] = read_lane64(inc, k);
+            as[k] = read_lane64(a, k);
+            Ls[k] = read_lane64(L, k);
+        }
+        for (int64_t q = lane; q < ends[kRedoChains - 1]; q += 64) {
+            int64_t r = q, ca = as[0], cL = Ls[0];
+#pragma unroll
+            for (int i = 1; i < kRedoChains; ++i) {
+                if (q >= ends[i - 1]) {
+                    r = q - ends[i - 1];
+                    ca = as[i];
+                    cL = Ls[i];
                 }
             }
-            cost[(a + j) * R + (len - 1)] = t;
+            // r -> (len, j): lengths in increasing order, ends j = len-1 .. L-1
+            int32_t len = 1;
+            while (len < R && r >= cL - len + 1) {
+                r -= cL - len + 1;
+                ++len;
+            }
+            const int64_t j = len - 1 + r;
+            if (j >= cL) continue;   // r is below the chain's count, so never
+            const int64_t s0 = ca + j - len + 1;
+            Desc<double> x;
+            bool ok;
+            if (len == 1) {
+                x = widen(load_row(d, s0));
+                ok = true;
+            } else {
+                ok = fuse_rows(d, edge, uniform_const(WM_KERNARG_PTR(RedoArgs, pk)).p, s0, len, x);
+            }
+            double t = inf;
+            if (ok) {
+                const Set& P = uniform_const(WM_KERNARG_PTR(RedoArgs, S));
+                Eval<double> E;
+                evaluate<double, false>(P.st, P.cd, x, E);
+                t = E.T == E.T ? E.T : inf;
+            }
+            wb.cost[(ca + j) * R + (len - 1)] = t;
         }
     }
 }
 
-// One thread per chain: best[j] = min over len (1 .. R, shortest first,
-// strict improvement) of best[j - len] + cost(run of len rows ending at j).
-// The run lengths of the chosen plan are kept in `cut` (one byte per row of
-// workspace) for the backward pass that writes the start flags.
-__global__ __launch_bounds__(256) void k_plan(const int32_t* __restrict__ off, int64_t n_chains,
-                                               int64_t n, int32_t R,
-                                               const double* __restrict__ cost,
-                                               double* __restrict__ best_ws,
-                                               uint8_t* __restrict__ cut,
-                                               double* __restrict__ total,
-                                               double* __restrict__ unfused,
-                                               uint8_t* __restrict__ start)
+// Float64 redo, plans: one group per queued chain, the programme over the
+// float64 costs.
+template <int GS>
+__global__ __launch_bounds__(256) void k_redo_plan(const int32_t* __restrict__ off,
+                                                    int64_t n_chains, int64_t n, int32_t R,
+                                                    PlanBufs wb, double* __restrict__ total,
+                                                    double* __restrict__ unfused,
+                                                    uint8_t* __restrict__ start)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_chains) return;
-    int64_t a = off[c], b = off[c + 1];
-    a = a < 0 ? 0 : (a > n ? n : a);
-    b = b < a ? a : (b > n ? n : b);
-    const double inf = __builtin_huge_val();
-    double single = 0.0;
-    // best_ws[a + j] holds best over the first j + 1 rows
-    for (int64_t j = 0; j < b - a; ++j) {
-        double bj = inf;
-        int32_t cj = 1;
-        for (int32_t len = 1; len <= R && len <= j + 1; ++len) {
-            const double t = cost[(a + j) * R + (len - 1)];
-            if (len == 1) single += t;
-            const double prev = j + 1 - len == 0 ? 0.0 : best_ws[a + j - len];
-            const double v = prev + t;
-            if (v < bj) {
-                bj = v;
-                cj = len;
-            }
+    const int64_t nq = redo_count(wb, n_chains, n);
+    const int64_t gpw = 64 / GS;   // groups per wave
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int64_t e0 = wave * gpw; e0 < nq; e0 += nwaves * gpw) {
+        const int64_t e = e0 + lane / GS;
+        const int64_t c = e < nq ? wb.redo[e] : -1;
+        const PlanGroup<GS> g = plan_group<GS>(c, n_chains, off, n);
+        PlanState ps;
+        bool run = g.c >= 0, unused = false, covered, unc;
+        plan_run<GS, false, false>(g, run, R, wb, ps, unused, covered, unc);
+        if (g.c >= 0 && g.gl == 0) {
+            total[g.c] = ps.best;
+            unfused[g.c] = ps.single;
         }
-        best_ws[a + j] = bj;
-        cut[a + j] = (uint8_t)cj;
+        plan_starts(g, g.c >= 0, ps, wb.cut, start);
     }
-    total[c] = b > a ? best_ws[b - 1] : 0.0;
-    unfused[c] = single;
-    for (int64_t i = a; i < b; ++i) start[i] = 0;
-    int64_t j = b - a;
-    while (j > 0) {
-        const int32_t L = cut[a + j - 1];
-        start[a + j - L] = 1;
-        j -= L;
+}
+
+template <int GS>
+static hipError_t plan_launch(const int32_t* off, int64_t n_chains, int64_t n, int32_t R,
+                              const PlanBufs& wb, double* total, double* unfused, uint8_t* start,
+                              bool redo, hipStream_t s)
+{
+    if (!redo) {
+        const int64_t per_block = kPlanBlock / GS;   // chains per block
+        const int64_t nb = (n_chains + per_block - 1) / per_block;
+        k_plan<GS><<<(unsigned)nb, kPlanBlock, 0, s>>>(off, n_chains, n, R, wb, total, unfused,
+                                                        start);
+    } else {
+        const int64_t want = (n_chains + 256 / GS - 1) / (256 / GS);
+        int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_redo_plan<GS>), 256);
+        b = b < want ? b : want;
+        b = b < 1 ? 1 : b;
+        k_redo_plan<GS><<<(unsigned)b, 256, 0, s>>>(off, n_chains, n, R, wb, total, unfused, start);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t plan_dispatch(int32_t gs, const int32_t* off, int64_t n_chains, int64_t n,
+                                int32_t R, const PlanBufs& wb, double* total, double* unfused,
+                                uint8_t* start, bool redo, hipStream_t s)
+{
+    switch (gs) {
+    case 1: return plan_launch<1>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
+    case 2: return plan_launch<2>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
+    case 4: return plan_launch<4>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
+    case 8: return plan_launch<8>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
+    case 16: return plan_launch<16>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
+    default: return plan_launch<32>(off, n_chains, n, R, wb, total, unfused, start, redo, s);
     }
 }
 
 hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_t* off,
                               int64_t n_chains, int64_t n, int32_t R, const Set& S,
-                              const double* peaks, double* cost, double* best, uint8_t* cut,
-                              double* total, double* unfused, uint8_t* start, hipStream_t s)
+                              const double* peaks, const PlanBufs& wb, double* total,
+                              double* unfused, uint8_t* start, hipStream_t s)
 {
     if (n_chains <= 0) return hipSuccess;
     Peaks pk;
     for (int t = 0; t < 5; ++t) pk.p[t] = peaks[t];
-    const int64_t want = (n_chains + 3) / 4;
-    int64_t nb = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_fuse_costs), 256) * 2;
-    nb = nb < want ? nb : want;
-    nb = nb < 1 ? 1 : nb;
-    k_fuse_costs<<<(int)nb, 256, 0, s>>>(d, edge, off, n_chains, n, R, S, pk, cost);
+    int32_t gs = 1;
+    while (gs < R) gs <<= 1;   // R <= 32
+    // at least one block, so that the queue's length is cleared even with no rows
+    const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+    k_fuse_costs<<<(unsigned)nb, 256, 0, s>>>(d, edge, off, n_chains, n, R, S, pk, wb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t nb2 = (n_chains + 255) / 256;
-    k_plan<<<(unsigned)nb2, 256, 0, s>>>(off, n_chains, n, R, cost, best, cut, total, unfused, start);
-    return hipGetLastError();
+    e = plan_dispatch(gs, off, n_chains, n, R, wb, total, unfused, start, false, s);
+    if (e != hipSuccess) return e;
+    const int64_t want = (n_chains + 3) / 4;
+    int64_t nb3 = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_redo_costs), 256) * 2;
+    nb3 = nb3 < want ? nb3 : want;
+    nb3 = nb3 < 1 ? 1 : nb3;
+    k_redo_costs<<<(unsigned)nb3, 256, 0, s>>>(d, edge, off, n_chains, n, R, S, pk, wb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return plan_dispatch(gs, off, n_chains, n, R, wb, total, unfused, start, true, s);
 }
 
 }  // namespace wm

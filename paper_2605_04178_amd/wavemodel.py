@@ -517,6 +517,13 @@ def plan_workspace_bytes(n: int, R: int) -> int:
     return int(lib().wm_plan_workspace_bytes(n, R))
 
 
+def plan_redone(ws: torch.Tensor) -> int:
+    """Diagnostic: the number of chains the last plan_fusion call with this
+    workspace redid in float64 (the uint32 that starts the workspace's last
+    256 bytes)."""
+    return int(ws[-256:-252].cpu().numpy().view(np.uint32)[0])
+
+
 def plan_fusion(desc: DeviceDescriptors, edge: torch.Tensor, chain_off: torch.Tensor, params, R: int = 8,
                 ws=None, stream=None):
     """Optimal fusion plans: (total float64 [n_chains], unfused float64
