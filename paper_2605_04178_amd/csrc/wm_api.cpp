@@ -293,7 +293,7 @@ PlanWs plan_ws(int64_t n, int32_t R)
     return W;
 }
 
-constexpr size_t kFitMultWs = sizeof(double) * 4 * 4 * (size_t)kFitMultMaxBlocks;
+constexpr size_t kFitMultWs = sizeof(double) * 4 * (size_t)kFitMultMaxBlocks;
 
 // ---- Blackwell family helpers ----
 bool bw_params_ok(const wm_bw_params_t* p)

@@ -67,7 +67,7 @@ constexpr int kAppRow = kAcc + 8;             // loss, count, grad theta[24], th
 constexpr int kAppsOut = kAcc + kSegParams;   // loss, count, grad theta[24], grad seg params[7]
 constexpr int kAppsMaxBlocks = 4096;          // partial-row cap of the application sweep
 constexpr int kAppsLongBlocks = 64;           // blocks of the pass over applications longer than a piece
-constexpr int kFitMultMaxBlocks = 1024;       // multiplier sweep: rows = 4 x blocks
+constexpr int kFitMultMaxBlocks = 4096;       // multiplier sweep: one row per block
 constexpr int kPlanMaxRun = 32;               // longest fused run
 
 struct ShapePtrs {
@@ -160,8 +160,8 @@ hipError_t launch_apps_loss_grad(const DescPtrs& d, const SegPtrs& sg, int64_t n
                                  const float* measured, const Set& S, const SegSet& Q, double* rows,
                                  uint64_t* aflags, uint64_t* lflags, uint64_t* rflags, float* wrow,
                                  const LaunchCfg& cfg, double* out, hipStream_t stream);
-// Per-group weighted-median multipliers; rows: 4 x kFitMultMaxBlocks x 4
-// doubles of workspace; stats [4] float64 device.
+// Per-group weighted-median multipliers; rows: kFitMultMaxBlocks x 4
+// doubles of workspace (one row per block); stats [4] float64 device.
 hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32_t* off,
                                   int64_t n_groups, int64_t n, const uint8_t* train, double* mult,
                                   float* T_scaled, double* rows, double* stats, hipStream_t s);

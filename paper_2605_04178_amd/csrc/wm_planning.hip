@@ -41,12 +41,45 @@ __device__ inline void wave_sum(double* acc)
     }
 }
 
+// The wave's index in the grid, in a form the compiler sees as the same on
+// every lane (so that what depends on it stays in scalar registers and
+// loops over it are scalar-controlled).
+__device__ inline int64_t wave_id()
+{
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    return (int64_t)blockIdx.x * (int64_t)(blockDim.x >> 6) + w;
+}
+
+// Lane k's value of x (k wave-uniform); every lane active.
+__device__ inline int64_t read_lane64(int64_t x, int k)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline double read_lane_f64(double x, int k)
+{
+    return __builtin_bit_cast(double, read_lane64(__builtin_bit_cast(int64_t, x), k));
+}
+
+__device__ inline float read_lane_f32(float x, int k)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, x), k));
+}
+
 // One wave per group (persistent).  Candidate k (a valid training row) is
 // the multiplier when its cumulative weight C_k = sum of w_i over valid
 // training rows with (x_i, i) <= (x_k, k) reaches half the total and no
-// smaller candidate does; the smallest such (x_k, k) wins.  Per wave the
-// stats (training loss, count, held-out loss, count) accumulate in float64;
-// lane 0 of each wave writes them to its row.
+// smaller candidate does; the smallest such (x_k, k) wins.  Lanes take 64
+// candidates at a time and the group's rows 64 at a time: a lane prepares
+// its row once (x_i = m/T in float32 and float64, w_i = T/m in float64, 0
+// for rows that do not count), then every row is broadcast to the lanes by
+// lane reads.  The order (x_i, i) <= (x_k, k) is decided on the float32
+// ratios, which round monotonically, and on the float64 ratios where the
+// float32 ones tie; C_k and the total are float64 sums in row order.  Per
+// wave the stats (training loss, count, held-out loss, count) accumulate in
+// float64 and each block writes their sums to its row.
 __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
                                                    const float* __restrict__ meas,
                                                    const int32_t* __restrict__ off,
@@ -57,40 +90,72 @@ __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
                                                    double* __restrict__ rows)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const double dinf = __builtin_huge_val();
+    const float finf = __builtin_huge_valf();
     double st[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t g = wave; g < n_groups; g += nwaves) {
         int64_t a = off[g], b = off[g + 1];
         a = a < 0 ? 0 : (a > n ? n : a);
         b = b < a ? a : (b > n ? n : b);
-        // total training weight (row order)
-        double Wt = 0.0;
-        for (int64_t i = a + lane; i < b; i += 64) {
-            const double t = T[i], m = meas[i];
-            if (train[i] && mult_ok(t, m)) Wt += t / m;
-        }
-        {
-            double v[1] = {Wt};
-            wave_sum<1>(v);
-            Wt = v[0];
-        }
-        // best candidate: smallest (x_k, k) with C_k >= W/2
-        double bx = __builtin_huge_val();
+        double Wt = 0.0;   // total training weight, row order
+        double bx = dinf;
         int64_t bk = INT64_MAX;
-        for (int64_t k = a + lane; k < b; k += 64) {
-            const double tk = T[k], mk = meas[k];
-            if (!(train[k] && mult_ok(tk, mk))) continue;
-            const double xk = mk / tk;
-            double C = 0.0;
-            for (int64_t i = a; i < b; ++i) {
-                const double t = T[i], m = meas[i];
-                if (!(train[i] && mult_ok(t, m))) continue;
-                const double xi = m / t;
-                if (xi < xk || (xi == xk && i <= k)) C += t / m;
+        float tk = 0.0f, mk = 0.0f;   // the lane's candidate row (the last chunk's)
+        uint8_t trk = 0;
+        for (int64_t k0 = a; k0 < b; k0 += 64) {
+            // this lane's candidate
+            const int64_t k = k0 + lane;
+            float xfk = finf;
+            double xdk = dinf, wk = 0.0;
+            tk = mk = 0.0f;
+            trk = 0;
+            if (k < b) {
+                tk = T[k];
+                mk = meas[k];
+                trk = train[k];
+                if (trk && mult_ok(tk, mk)) {
+                    xfk = mk / tk;
+                    xdk = (double)mk / (double)tk;
+                    wk = (double)tk / (double)mk;
+                }
             }
-            if (C >= 0.5 * Wt && (xk < bx || (xk == bx && k < bk))) {
-                bx = xk;
+            double C = 0.0;
+            for (int64_t i0 = a; i0 < b; i0 += 64) {
+                // this lane's row (the candidate's own when the chunks coincide)
+                const int64_t i = i0 + lane;
+                float xfi = xfk;
+                double xdi = xdk, wi = wk;
+                if (i0 != k0) {
+                    xfi = finf;
+                    xdi = dinf;
+                    wi = 0.0;
+                    if (i < b) {
+                        const float ti = T[i], mi = meas[i];
+                        if (train[i] && mult_ok(ti, mi)) {
+                            xfi = mi / ti;
+                            xdi = (double)mi / (double)ti;
+                            wi = (double)ti / (double)mi;
+                        }
+                    }
+                }
+                const int cnt = b - i0 < 64 ? (int)(b - i0) : 64;
+                for (int r = 0; r < cnt; ++r) {
+                    const float xf = read_lane_f32(xfi, r);
+                    const double w = read_lane_f64(wi, r);
+                    if (k0 == a) Wt += w;
+                    bool before = xf < xfk;
+                    const bool tie = xf == xfk;
+                    if (__ballot(tie) != 0ull) {
+                        const double xd = read_lane_f64(xdi, r);
+                        if (tie) before = xd < xdk || (xd == xdk && i0 + r <= k);
+                    }
+                    C += before ? w : 0.0;
+                }
+            }
+            if (xdk < dinf && C >= 0.5 * Wt && (xdk < bx || (xdk == bx && k < bk))) {
+                bx = xdk;
                 bk = k;
             }
         }
@@ -105,12 +170,15 @@ __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
         }
         const double mu = bk == INT64_MAX ? 1.0 : bx;
         if (lane == 0) mult[g] = mu;
+        // a group of one chunk still has its rows in the candidate registers
+        const bool one = b - a <= 64;
         for (int64_t i = a + lane; i < b; i += 64) {
-            const double t = T[i], m = meas[i];
+            const double t = one ? tk : T[i], m = one ? mk : meas[i];
+            const bool tr = one ? trk != 0 : train[i] != 0;
             T_scaled[i] = (float)(mu * t);
             if (!mult_ok(t, m)) continue;
             const double e = __builtin_fabs(mu * t - m) / m;
-            if (train[i]) {
+            if (tr) {
                 st[0] += e;
                 st[1] += 1.0;
             } else {
@@ -119,10 +187,18 @@ __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
             }
         }
     }
+    // the block's four waves, then one row per block (fixed order)
+    __shared__ double red[4][4];
     wave_sum<4>(st);
     if (lane == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) rows[wave * 4 + j] = st[j];
+        for (int j = 0; j < 4; ++j) red[threadIdx.x >> 6][j] = st[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        rows[(int64_t)blockIdx.x * 4 + threadIdx.x] = v;
     }
 }
 
@@ -163,7 +239,7 @@ hipError_t launch_fit_multipliers(const float* T, const float* meas, const int32
     k_fit_mult<<<nb, 256, 0, s>>>(T, meas, off, n_groups, n, train, mult, T_scaled, rows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_fit_mult_reduce<<<1, 256, 0, s>>>(rows, (int64_t)nb * 4, stats);
+    k_fit_mult_reduce<<<1, 256, 0, s>>>(rows, (int64_t)nb, stats);
     return hipGetLastError();
 }
 
@@ -772,14 +848,6 @@ __device__ inline int64_t redo_count(const PlanBufs& wb, int64_t n_chains, int64
 // float32 ones.
 constexpr int kRedoChains = 8;
 
-// Lane k's value of x (k wave-uniform); every lane active.
-__device__ inline int64_t read_lane64(int64_t x, int k)
-{
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, k);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), k);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 struct RedoArgs {   // k_redo_costs's parameters, in order
     DescPtrs d;
     const float* edge;
@@ -796,7 +864,7 @@ __global__ __launch_bounds__(256) void k_redo_costs(DescPtrs d, const float* __r
                                                      Peaks pk, PlanBufs wb)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const double inf = __builtin_huge_val();
     const int64_t nq = redo_count(wb, n_chains, n);
@@ -883,7 +951,7 @@ __global__ __launch_bounds__(256) void k_redo_plan(const int32_t* __restrict__ o
 {
     const int64_t nq = redo_count(wb, n_chains, n);
     const int64_t gpw = 64 / GS;   // groups per wave
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int lane = threadIdx.x & 63;
     for (int64_t e0 = wave * gpw; e0 < nq; e0 += nwaves * gpw) {
