@@ -184,6 +184,34 @@ def test_fusion_near_ties_follow_float64(wmb, orc):
     assert np.all(np.abs(tot[near] - otot[near]) <= 1e-12 * otot[near])
 
 
+def test_fusion_float32_cost_error_bounds_the_window(wmb, orc):
+    # A plan decision compares two sums of run costs, each off by at most the
+    # float32 model's relative error e, so it can only flip when the
+    # runner-up is within 2e; decisions within 3e-5 are redone in float64.
+    # Measure e on the run costs themselves (the workspace starts with the
+    # n x R float64 cost array; chains redone in float64 hold float64 costs)
+    # and require 3e-5 >= 4 x 2e.
+    p = synth.param_set(0)
+    off, d, e = synth.chains(4000, 168)
+    R = 8
+    ws = wmb._workspace(wmb.plan_workspace_bytes(d.n, R), "cuda")
+    wmb.plan_fusion(wmb.DeviceDescriptors.from_host(d), torch.from_numpy(e).cuda(),
+                    torch.from_numpy(off).cuda(), p, R, ws=ws)
+    cost = ws[:8 * d.n * R].cpu().numpy().view(np.float64).reshape(d.n, R)
+    err = []
+    for c in range(0, 4000, 8):
+        a, b = int(off[c]), int(off[c + 1])
+        for j in range(b - a):
+            for ln in range(1, min(R, j + 1) + 1):
+                t = orc.fused_cost(p, d, e, a + j - ln + 1, ln)
+                if np.isfinite(t) and t > 0:
+                    err.append(abs(cost[a + j, ln - 1] - t) / t)
+    err = np.array(err)
+    say("fused-run costs checked", len(err), "max float32 relative error", err.max())
+    assert len(err) > 5000
+    assert 4 * 2 * err.max() <= 3e-5
+
+
 def test_fusion_offsets_not_non_decreasing(wmb, orc):
     # chain 2 starts inside chain 0: its rows were costed as chain 0's, so it
     # reports NaN; chain 0 is planned as usual and chain 1 is empty
