@@ -212,6 +212,47 @@ def test_fusion_float32_cost_error_bounds_the_window(wmb, orc):
     assert 4 * 2 * err.max() <= 3e-5
 
 
+def test_fusion_uncertain_runs_are_redone(wmb, orc):
+    # Pairs whose fused run float32 cannot carry: (a) working sets summing to
+    # just above the LLC capacity (2^28 B = 256 MiB): float64 sees W > C and
+    # the streaming regime of Table "hlcc-piecewise", while float32 rounds
+    # 2^28 + 16 down to 2^28, the transition regime with a hit rate of 0;
+    # (b) flops that add up past the float32 range.  Both kinds must be
+    # redone in float64, totals to 1e-12.  Plans: the oracle's for (a); for
+    # (b) the run times dwarf every overhead, so fusing costs the unfused sum
+    # to the last bit (float64 ties), and a plan that differs must cost the
+    # optimum.
+    p = synth.param_set(0)
+    assert p.n_levels == 4 and p.c_llc_mib == 256.0
+    n = 400
+    off, d, e = synth.chains(n, 169, lmin=2, lmax=2)
+    a = off[:-1].astype(np.int64)
+    llc, big = a[: n // 2], a[n // 2:]
+    d.W[llc] = np.float32(2 ** 27)
+    d.W[llc + 1] = np.float32(2 ** 27 + 16)
+    e[llc] = 0.0
+    d.F[big] = np.float32(3e38)
+    d.F[big + 1] = np.float32(3e38)
+    ws = wmb._workspace(wmb.plan_workspace_bytes(d.n, 2), "cuda")
+    tot, unf, st = wmb.plan_fusion(wmb.DeviceDescriptors.from_host(d), torch.from_numpy(e).cuda(),
+                                   torch.from_numpy(off).cuda(), p, 2, ws=ws)
+    tot, st = tot.cpu().numpy(), st.cpu().numpy()
+    otot, _, ost = orc.plan_fusion(p, d, e, off, 2)
+    redone = wmb.plan_redone(ws)
+    say("uncertain-run chains", n, "redone", redone, "fused", int(n * 2 - st.sum()))
+    assert redone >= n
+    assert np.all(np.isfinite(otot)) and np.all(np.abs(tot - otot) <= 1e-12 * otot)
+    nl = 2 * (n // 2)
+    assert np.array_equal(st[:nl], ost[:nl])
+    for c in range(n // 2, n):
+        s0 = int(a[c])
+        if np.array_equal(st[s0:s0 + 2], ost[s0:s0 + 2]):
+            continue
+        cost = (orc.fused_cost(p, d, e, s0, 2) if st[s0 + 1] == 0 else
+                orc.fused_cost(p, d, e, s0, 1) + orc.fused_cost(p, d, e, s0 + 1, 1))
+        assert abs(cost - otot[c]) <= 1e-12 * otot[c], (c, cost, otot[c])
+
+
 def test_fusion_offsets_not_non_decreasing(wmb, orc):
     # chain 2 starts inside chain 0: its rows were costed as chain 0's, so it
     # reports NaN; chain 0 is planned as usual and chain 1 is empty
