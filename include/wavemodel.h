@@ -186,7 +186,9 @@ int32_t wm_validate_params(const wm_params_t *params);
  *  WM_OP_PREDICT, WM_OP_ROOFLINE, WM_OP_SELECT_TILE: 0.
  *  WM_OP_VJP, WM_OP_LOSS_GRAD: per-block FP64 partial sums for n descriptors.
  *  WM_OP_CALIBRATE: device parameter set, Adam state, a `steps`-entry loss
- *      history and the partial sums for n descriptors.
+ *      history, the per-step Adam schedule (learning rate and the two bias
+ *      corrections, formed on the host) and the partial sums for n
+ *      descriptors.
  *  WM_OP_CALIBRATE_BATCHED: the same for n_sets sets holding n descriptors
  *      in total, plus the per-set pointer tables and item offsets.
  *  WM_OP_PREDICT_APPS: 0.

@@ -177,6 +177,15 @@ bool opts_ok(const wm_calib_opts_t* o)
 
 static_assert(sizeof(wm_calib_opts_t) == 56 + 2 * 8 * WM_N_THETA, "wm_calib_opts_t layout");
 
+// The per-step Adam schedule of a run, formed on the host (one table for
+// every step index, so a resumed run reads the same values).
+std::vector<double> adam_table(const AdamOpts& o)
+{
+    std::vector<double> t((size_t)3 * (size_t)(o.steps > 0 ? o.steps : 0));
+    for (int32_t k = 0; k < o.steps; ++k) adam_schedule(o, k, &t[3 * k], &t[3 * k + 1], &t[3 * k + 2]);
+    return t;
+}
+
 AdamOpts adam_of(const wm_calib_opts_t* o)
 {
     AdamOpts a;
@@ -385,7 +394,7 @@ AppsWs apps_ws(int64_t n, int64_t n_apps)
 }
 
 struct CalibLayout {
-    size_t set, state, hist, grad, total;
+    size_t set, state, hist, sched, grad, total;
     GradWs g;
 };
 
@@ -393,13 +402,16 @@ CalibLayout calib_layout(int64_t n, int32_t steps, size_t set_bytes = sizeof(Set
 {
     CalibLayout L;
     L.g = grad_ws(n);
+    const size_t ns = (size_t)(steps > 0 ? steps : 1);
     size_t off = 0;
     L.set = off;
     off += up256(set_bytes);
     L.state = off;
     off += up256(sizeof(CalibState));
     L.hist = off;
-    off += up256(sizeof(double) * (size_t)(steps > 0 ? steps : 1));
+    off += up256(sizeof(double) * ns);
+    L.sched = off;
+    off += up256(3 * sizeof(double) * ns);
     L.grad = off;
     off += L.g.total;
     L.total = off;
@@ -877,9 +889,13 @@ int32_t wm_bw_calibrate(const wm_bw_desc_t* desc, const float* measured, const w
         st0.theta_ok[j] = p0->theta[j];
         st0.phi[j] = ((opts->free_mask >> j) & 1u) ? std::log(p0->theta[j]) : 0.0;
     }
-    const AdamOpts ao = adam_of(opts);
+    AdamOpts ao = adam_of(opts);
+    const std::vector<double> sched = adam_table(ao);
+    ao.sched = (const double*)(base + L.sched);
     WM_HIP(hipMemcpyAsync(S_dev, &S, sizeof(S), hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(st_dev, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(base + L.sched, sched.data(), sizeof(double) * sched.size(),
+                          hipMemcpyHostToDevice, s));
     WM_HIP(hipStreamSynchronize(s));
     const BwDescPtrs dp = bw_ptrs_of(desc);
     const int64_t n = desc->n;
@@ -1158,9 +1174,13 @@ int32_t wm_calibrate_resume(const wm_desc_t* desc, const float* measured, const 
     double* part_dev = (double*)(base + L.grad + L.g.partials);
     uint64_t* flags_dev = (uint64_t*)(base + L.grad + L.g.flags);
     const Set S = make_set(&pc);
-    const AdamOpts ao = adam_of(opts);
+    AdamOpts ao = adam_of(opts);
+    const std::vector<double> sched = adam_table(ao);
+    ao.sched = (const double*)(base + L.sched);
     WM_HIP(hipMemcpyAsync(S_dev, &S, sizeof(S), hipMemcpyHostToDevice, s));
     WM_HIP(hipMemcpyAsync(st_dev, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    WM_HIP(hipMemcpyAsync(base + L.sched, sched.data(), sizeof(double) * sched.size(),
+                          hipMemcpyHostToDevice, s));
     WM_HIP(hipStreamSynchronize(s));
 
     const DescPtrs dp = ptrs_of(desc);

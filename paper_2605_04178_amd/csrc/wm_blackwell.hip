@@ -240,7 +240,8 @@ hipError_t launch_bw_grad(int mode, const BwDescPtrs& d, int64_t n, const float*
 hipError_t launch_bw_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o,
                           BwSet* S, double* loss_hist, hipStream_t s)
 {
-    k_bw_adam<<<1, 256, 0, s>>>(partials, rows, st, o, S, loss_hist);
+    // one wave when it holds every row (no cross-wave steps in the reduction)
+    k_bw_adam<<<1, rows <= 64 ? 64 : 256, 0, s>>>(partials, rows, st, o, S, loss_hist);
     return hipGetLastError();
 }
 

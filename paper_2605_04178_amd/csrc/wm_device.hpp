@@ -184,11 +184,16 @@ __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const 
     }
     const double th = mine ? st->theta[lane] : 1.0;
     if (mine) st->theta_ok[lane] = th;
-    const double t = (double)(step_index + 1);
-    double lr = o.lr;
-    if (o.lr_final > 0.0 && o.steps > 1)
-        lr = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
-    const double b1t = pow(o.beta1, t), b2t = pow(o.beta2, t);
+    // the step's schedule: from the host's table (three loads) where there is
+    // one, else formed here (three pow calls on the wave's critical path)
+    double lr, c1, c2;
+    if (o.sched && step_index < o.steps) {
+        lr = o.sched[3 * step_index];
+        c1 = o.sched[3 * step_index + 1];
+        c2 = o.sched[3 * step_index + 2];
+    } else {
+        adam_schedule(o, step_index, &lr, &c1, &c2);
+    }
     double th_new = th;
     bool ok = true;
     const bool fit = mine && ((o.free_mask >> lane) & 1u);
@@ -199,8 +204,8 @@ __device__ inline bool adam_theta_step(CalibState* st, const double* tot, const 
         const double v = o.beta2 * st->v[lane] + (1.0 - o.beta2) * gp * gp;
         st->m[lane] = m;
         st->v[lane] = v;
-        const double mh = m / (1.0 - b1t);
-        const double vh = v / (1.0 - b2t);
+        const double mh = m / c1;
+        const double vh = v / c2;
         phi -= lr * mh / (sqrt(vh) + o.eps);
     }
     // constraints: the level orderings (every slot of an ordered group is

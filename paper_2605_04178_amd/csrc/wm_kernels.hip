@@ -469,7 +469,8 @@ __global__ __launch_bounds__(256) void k_adam(const double* __restrict__ partial
 hipError_t launch_adam(const double* partials, int rows, CalibState* st, const AdamOpts& o, Set* S,
                        double* loss_hist, hipStream_t stream)
 {
-    k_adam<<<1, 256, 0, stream>>>(partials, rows, st, o, S, loss_hist);
+    // one wave when it holds every row (no cross-wave steps in the reduction)
+    k_adam<<<1, rows <= 64 ? 64 : 256, 0, stream>>>(partials, rows, st, o, S, loss_hist);
     return hipGetLastError();
 }
 

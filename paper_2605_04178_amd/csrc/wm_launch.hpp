@@ -79,7 +79,25 @@ struct AdamOpts {
     double lr, lr_final, beta1, beta2, eps;
     uint32_t free_mask, pad2_;
     double lo_log[kTheta], hi_log[kTheta];   // box on log(theta) of the fitted slots (+-inf: none)
+    // per step s < steps, {learning rate, 1 - beta1^(s+1), 1 - beta2^(s+1)}
+    // (device, formed on the host), or null to form them on the device
+    const double* sched;
 };
+
+// The Adam schedule of one step: the learning rate (decayed geometrically
+// from lr to lr_final over the steps when lr_final > 0) and the two bias
+// corrections.  One definition for the host table and the device fallback.
+WM_HD void adam_schedule(const AdamOpts& o, int32_t step_index, double* lr, double* c1,
+                                double* c2)
+{
+    const double t = (double)(step_index + 1);
+    double l = o.lr;
+    if (o.lr_final > 0.0 && o.steps > 1)
+        l = o.lr * pow(o.lr_final / o.lr, (double)step_index / (double)(o.steps - 1));
+    *lr = l;
+    *c1 = 1.0 - pow(o.beta1, t);
+    *c2 = 1.0 - pow(o.beta2, t);
+}
 
 // device-resident calibration state of one parameter set
 struct CalibState {
