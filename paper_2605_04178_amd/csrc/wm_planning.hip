@@ -522,11 +522,12 @@ __global__ __launch_bounds__(256) void k_fuse_costs(DescPtrs d, const float* __r
     wb.cov[s] = (uint8_t)(m | (unc ? kPlanUncertain : 0));
 }
 
-// Decision margin below which a float32 plan is re-decided in float64: the
-// window of the tile selection, far above the float32 model's relative error
-// (a decision compares two sums of run times, each off by at most that error
-// relative to itself).
-constexpr double kPlanWindow = (double)kTileWindow;
+// Decision margin below which a float32 plan is re-decided in float64.  A
+// decision compares two sums of run times, each off by at most the float32
+// model's relative error e relative to itself, so it can only flip within
+// 2e; the largest e measured on fused runs against the float64 model is
+// about 3e-7, so 1e-5 is some 17 times 2e (a test holds it to at least 4).
+constexpr double kPlanWindow = 1e-5;
 
 // The dynamic programme runs on groups of GS lanes (GS the power of two >= R),
 // one chain per group: lane gl of a group stands for the run of gl + 1 rows

@@ -168,8 +168,12 @@ def test_fusion_near_ties_follow_float64(wmb, orc):
             v1, v2 = f1 + T[s + 2], T[s] + orc.fused_cost(p, d, e, s + 1, 2)
             margin[c] = abs(v1 - v2) / v2
     near = np.flatnonzero((margin > 1e-10) & (margin < 2e-5))
-    say("near-tie chains", len(near), "below 1e-7:", int(np.sum(margin[near] < 1e-7)))
-    assert len(near) >= 100
+    # well within the window (float32 moves a margin by a few per cent of
+    # 1e-5 at most): redone in float64
+    inside = near[margin[near] < 0.9e-5]
+    say("near-tie chains", len(near), "below 1e-7:", int(np.sum(margin[near] < 1e-7)),
+        "inside the window:", len(inside))
+    assert len(near) >= 100 and len(inside) >= 50
     tot, unf, st = _check_plan(wmb, orc, p, off, d, e, 2, "near ties")
     # every one of them went through the float64 redo
     ws = wmb._workspace(wmb.plan_workspace_bytes(d.n, 2), "cuda")
@@ -177,20 +181,20 @@ def test_fusion_near_ties_follow_float64(wmb, orc):
                     torch.from_numpy(off).cuda(), p, 2, ws=ws)
     redone = wmb.plan_redone(ws)
     say("  chains redone in float64:", redone)
-    assert redone >= len(near)
+    assert redone >= len(inside)
     otot, _, ost = orc.plan_fusion(p, d, e, off, 2)
-    for c in near:
+    for c in near:   # inside the window by the float64 redo, beyond it in float32
         assert np.array_equal(st[a[c]:a[c] + 3], ost[a[c]:a[c] + 3]), (c, margin[c])
-    assert np.all(np.abs(tot[near] - otot[near]) <= 1e-12 * otot[near])
+    assert np.all(np.abs(tot[inside] - otot[inside]) <= 1e-12 * otot[inside])
 
 
 def test_fusion_float32_cost_error_bounds_the_window(wmb, orc):
     # A plan decision compares two sums of run costs, each off by at most the
     # float32 model's relative error e, so it can only flip when the
-    # runner-up is within 2e; decisions within 3e-5 are redone in float64.
+    # runner-up is within 2e; decisions within 1e-5 are redone in float64.
     # Measure e on the run costs themselves (the workspace starts with the
     # n x R float64 cost array; chains redone in float64 hold float64 costs)
-    # and require 3e-5 >= 4 x 2e.
+    # and require 1e-5 >= 4 x 2e.
     p = synth.param_set(0)
     off, d, e = synth.chains(4000, 168)
     R = 8
@@ -209,7 +213,7 @@ def test_fusion_float32_cost_error_bounds_the_window(wmb, orc):
     err = np.array(err)
     say("fused-run costs checked", len(err), "max float32 relative error", err.max())
     assert len(err) > 5000
-    assert 4 * 2 * err.max() <= 3e-5
+    assert 4 * 2 * err.max() <= 1e-5
 
 
 def test_fusion_uncertain_runs_are_redone(wmb, orc):
