@@ -477,7 +477,7 @@ int32_t wm_fit_multipliers(const float *T, const float *measured, const int32_t 
  * runs with an invalid row or edge); the optimal plan comes from the prefix
  * dynamic programme over those costs in float64 (shortest run first on
  * ties).  A chain is redone with float64 costs when one of its decisions is
- * within 3e-5 relative of the runner-up, or when one of its runs has a cost
+ * within 1e-5 relative of the runner-up, or when one of its runs has a cost
  * float32 cannot carry (not finite for valid rows, negative, or a working set
  * within 1e-6 relative of the LLC capacity, where the hit rate jumps): plans
  * then match a float64 evaluation except at its own ties, and totals match
