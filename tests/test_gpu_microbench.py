@@ -172,8 +172,8 @@ def test_shader_clock(mb):
 
 def test_shipped_mi355x_parameters_predict_held_out_kernels(mb):
     """The shipped parameter file is valid and, on the held-out validation
-    kernels re-timed on this GPU, the calibrated model beats the naive
-    roofline and stays within 0.03 of the MAE recorded with the file."""
+    kernels re-timed on this GPU, the calibrated model's MAE is at most 0.6 of
+    the naive roofline's and within 0.06 of the MAE recorded with the file."""
     import json
     import os
     from paper_2605_04178_amd import recalibrate as rc, wavemodel as wm
@@ -189,6 +189,10 @@ def test_shipped_mi355x_parameters_predict_held_out_kernels(mb):
     T, _ = rc.predict(wm, p, cases)
     e_model, e_roof = mb.mae(T, meas), mb.mae(mb.roofline_naive(cases), meas)
     say("held-out MAE calibrated", e_model, "roofline", e_roof, "recorded", rec["mae"]["calibrated_holdout"])
-    # re-timing the kernels moves the MAE by well under 0.01 between runs; a
-    # margin of 0.03 over the recorded figure still fails a real regression
-    assert e_model < e_roof and e_model <= rec["mae"]["calibrated_holdout"] + 0.03
+    # re-timing the kernels moves the MAE by well under 0.01 between runs on
+    # one machine, but the recorded figure comes from another MI355X: across
+    # machines the held-out MAE has read 0.186 to 0.223 (clocks and memory
+    # timings differ by several per cent per kernel).  0.06 over the recorded
+    # figure, and a bound relative to the roofline measured on this machine,
+    # still fail a real regression.
+    assert e_model <= 0.6 * e_roof and e_model <= rec["mae"]["calibrated_holdout"] + 0.06
