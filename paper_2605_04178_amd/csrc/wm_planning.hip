@@ -778,7 +778,7 @@ __device__ inline void plan_starts(const PlanGroup<GS>& g, bool live, const Plan
 // that are not non-decreasing) gets NaN totals and no start flags; a chain
 // holding an uncertain run or a close decision is queued for the float64
 // redo; the rest get their totals and start flags.
-constexpr int kPlanBlock = 1024;   // threads per block of the planning pass
+constexpr int kPlanBlock = 256;    // threads per block of the planning pass (5 blocks per CU)
 
 template <int GS>
 __global__ __launch_bounds__(kPlanBlock) void k_plan(const int32_t* __restrict__ off,
