@@ -446,12 +446,14 @@ int32_t wm_predict_apps_vjp(const wm_desc_t *desc, const wm_segs_t *segs, const 
  * whose cumulative weight reaches half the total.  Groups without a valid
  * training row get 1.  Outputs (device): mult [n_groups] float64, T_scaled
  * [n] float32 = mult * T, stats [4] float64 = training error sum, training
- * rows, held-out error sum, held-out rows.  Ratios are ordered in float32
- * (the rounding is monotone) and in float64 where the float32 ratios tie;
- * weights are float64 and cumulative weights float64 sums in row order, so a
- * multiplier can differ from a sort-based one only where two candidates'
- * objectives tie to rounding.
- * Cost O(s^2 / 64) per group of s rows (one wave per group).
+ * rows, held-out error sum, held-out rows.  Ratios and weights are float64;
+ * a group of up to 64 rows is sorted by (ratio, row) across one wave's lanes
+ * (two groups of up to 32 rows share a wave) and its cumulative weights are
+ * a float64 prefix sum in tree order; larger groups compare every candidate
+ * with every row (float32 ratio order, float64 where those tie, float64 sums
+ * in row order).  Either way a multiplier can differ from the sequential
+ * sorted-order one only where two candidates' objectives tie to rounding.
+ * Cost O(log^2 s) lane steps per group of s <= 64 rows, O(s^2 / 64) beyond.
  * Workspace: wm_workspace_bytes(WM_OP_FIT_MULTIPLIERS, n, 1, 0).
  */
 int32_t wm_fit_multipliers(const float *T, const float *measured, const int32_t *group_off,

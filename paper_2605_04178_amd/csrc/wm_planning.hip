@@ -68,8 +68,25 @@ __device__ inline float read_lane_f32(float x, int k)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, x), k));
 }
 
-// One wave per group (persistent).  Candidate k (a valid training row) is
-// the multiplier when its cumulative weight C_k = sum of w_i over valid
+// Rows i in [a, b) of one group: the training loss and count, the held-out
+// loss and count (float64, per lane), and T_scaled = mu T_i.
+__device__ inline void mult_apply(double mu, float t, float m, bool tr, int64_t i,
+                                  float* __restrict__ T_scaled, double* st)
+{
+    T_scaled[i] = (float)(mu * (double)t);
+    if (!mult_ok(t, m)) return;
+    const double e = __builtin_fabs(mu * (double)t - (double)m) / (double)m;
+    if (tr) {
+        st[0] += e;
+        st[1] += 1.0;
+    } else {
+        st[2] += e;
+        st[3] += 1.0;
+    }
+}
+
+// A group of any size on the whole wave.  Candidate k (a valid training row)
+// is the multiplier when its cumulative weight C_k = sum of w_i over valid
 // training rows with (x_i, i) <= (x_k, k) reaches half the total and no
 // smaller candidate does; the smallest such (x_k, k) wins.  Lanes take 64
 // candidates at a time and the group's rows 64 at a time: a lane prepares
@@ -77,9 +94,168 @@ __device__ inline float read_lane_f32(float x, int k)
 // for rows that do not count), then every row is broadcast to the lanes by
 // lane reads.  The order (x_i, i) <= (x_k, k) is decided on the float32
 // ratios, which round monotonically, and on the float64 ratios where the
-// float32 ones tie; C_k and the total are float64 sums in row order.  Per
-// wave the stats (training loss, count, held-out loss, count) accumulate in
-// float64 and each block writes their sums to its row.
+// float32 ones tie; C_k and the total are float64 sums in row order.
+__device__ inline void fit_group_scan(int64_t g, int64_t a, int64_t b, const float* __restrict__ T,
+                                      const float* __restrict__ meas, const uint8_t* __restrict__ train,
+                                      double* __restrict__ mult, float* __restrict__ T_scaled, double* st)
+{
+    const int lane = threadIdx.x & 63;
+    const double dinf = __builtin_huge_val();
+    const float finf = __builtin_huge_valf();
+    double Wt = 0.0;   // total training weight, row order
+    double bx = dinf;
+    int64_t bk = INT64_MAX;
+    for (int64_t k0 = a; k0 < b; k0 += 64) {
+        // this lane's candidate
+        const int64_t k = k0 + lane;
+        float xfk = finf;
+        double xdk = dinf, wk = 0.0;
+        if (k < b) {
+            const float tk = T[k], mk = meas[k];
+            if (train[k] && mult_ok(tk, mk)) {
+                xfk = mk / tk;
+                xdk = (double)mk / (double)tk;
+                wk = (double)tk / (double)mk;
+            }
+        }
+        double C = 0.0;
+        for (int64_t i0 = a; i0 < b; i0 += 64) {
+            // this lane's row (the candidate's own when the chunks coincide)
+            const int64_t i = i0 + lane;
+            float xfi = xfk;
+            double xdi = xdk, wi = wk;
+            if (i0 != k0) {
+                xfi = finf;
+                xdi = dinf;
+                wi = 0.0;
+                if (i < b) {
+                    const float ti = T[i], mi = meas[i];
+                    if (train[i] && mult_ok(ti, mi)) {
+                        xfi = mi / ti;
+                        xdi = (double)mi / (double)ti;
+                        wi = (double)ti / (double)mi;
+                    }
+                }
+            }
+            const int cnt = b - i0 < 64 ? (int)(b - i0) : 64;
+            for (int r = 0; r < cnt; ++r) {
+                const float xf = read_lane_f32(xfi, r);
+                const double w = read_lane_f64(wi, r);
+                if (k0 == a) Wt += w;
+                bool before = xf < xfk;
+                const bool tie = xf == xfk;
+                if (__ballot(tie) != 0ull) {
+                    const double xd = read_lane_f64(xdi, r);
+                    if (tie) before = xd < xdk || (xd == xdk && i0 + r <= k);
+                }
+                C += before ? w : 0.0;
+            }
+        }
+        if (xdk < dinf && C >= 0.5 * Wt && (xdk < bx || (xdk == bx && k < bk))) {
+            bx = xdk;
+            bk = k;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const double ox = __shfl_xor(bx, m, 64);
+        const int64_t ok = __shfl_xor(bk, m, 64);
+        if (ox < bx || (ox == bx && ok < bk)) {
+            bx = ox;
+            bk = ok;
+        }
+    }
+    const double mu = bk == INT64_MAX ? 1.0 : bx;
+    if (lane == 0) mult[g] = mu;
+    for (int64_t i = a + lane; i < b; i += 64) mult_apply(mu, T[i], meas[i], train[i] != 0, i, T_scaled, st);
+}
+
+// Groups of at most W rows (W = 32: two groups side by side in the wave
+// halves; W = 64: one group), row a_s + l on lane l of segment s.  The
+// segment sorts its keys (x_i, i) ascending by a bitonic network across its
+// lanes (rows that do not count carry x = +inf and w = 0, so they sort
+// last), takes each sorted key's weight from its row's lane, and forms the
+// inclusive cumulative weights by a float64 prefix sum; the multiplier is the
+// first sorted x whose cumulative weight reaches half the segment's total.
+// The prefix sum adds in tree order, so C can differ from the row-order sum
+// in the last bits; where that moves the choice, the two ratios' objectives
+// are equal to rounding (the objective is flat between them when C equals
+// half the total).  g1 < 0: the upper half has no group.
+template <int W>
+__device__ inline void fit_groups_sorted(int64_t g0, int64_t a0, int64_t b0, int64_t g1, int64_t a1,
+                                         int64_t b1, const float* __restrict__ T,
+                                         const float* __restrict__ meas, const uint8_t* __restrict__ train,
+                                         double* __restrict__ mult, float* __restrict__ T_scaled, double* st)
+{
+    const int lane = threadIdx.x & 63;
+    const int seg = W == 64 ? 0 : lane >> 5;
+    const int l = lane & (W - 1);
+    const int64_t g = seg ? g1 : g0, a = seg ? a1 : a0, b = seg ? b1 : b0;
+    const int64_t i = a + l;
+    const bool in = g >= 0 && i < b;
+    const double dinf = __builtin_huge_val();
+    float t = 0.0f, m = 0.0f;
+    bool tr = false;
+    double x = dinf, w = 0.0;
+    if (in) {
+        t = T[i];
+        m = meas[i];
+        tr = train[i] != 0;
+        if (tr && mult_ok(t, m)) {
+            x = (double)m / (double)t;
+            w = (double)t / (double)m;
+        }
+    }
+    // bitonic sort of the unique keys (x, l) within each segment
+    double sx = x;
+    int si = l;
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const double px = __shfl_xor(sx, j, 64);
+            const int pi = __shfl_xor(si, j, 64);
+            const bool p_less = px < sx || (px == sx && pi < si);
+            // the lower lane of a pair keeps the smaller key in an ascending
+            // block, the larger one in a descending block
+            const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
+            if (keep_min == p_less) {
+                sx = px;
+                si = pi;
+            }
+        }
+    }
+    const int base = seg * W;
+    double c = __shfl(w, base + si, 64);
+#pragma unroll
+    for (int d = 1; d < W; d <<= 1) {
+        const double u = __shfl_up(c, d, W);
+        if (l >= d) c += u;
+    }
+    const double tot = __shfl(c, base + W - 1, 64);
+    uint64_t hit = __ballot(sx < dinf && c >= 0.5 * tot);
+    if (W == 32) hit = (hit >> base) & 0xFFFFFFFFull;
+    const int jl = hit != 0ull ? __builtin_ctzll(hit) : 0;
+    const double xj = __shfl(sx, base + jl, 64);
+    const double mu = hit != 0ull ? xj : 1.0;
+    if (g >= 0 && l == 0) mult[g] = mu;
+    if (in) mult_apply(mu, t, m, tr, i, T_scaled, st);
+}
+
+// One wave per pair of consecutive groups (persistent): two groups of at
+// most 32 rows share the wave by halves; otherwise each group in turn, up to
+// 64 rows by the sorted form, beyond by the candidate scan.  Group bounds are
+// clamped into [0, n].  Per wave the stats (training loss, count, held-out
+// loss, count) accumulate in float64 and each block writes their sums to
+// its row.
+__device__ inline void group_bounds(const int32_t* __restrict__ off, int64_t g, int64_t n, int64_t& a, int64_t& b)
+{
+    a = off[g];
+    b = off[g + 1];
+    a = a < 0 ? 0 : (a > n ? n : a);
+    b = b < a ? a : (b > n ? n : b);
+}
+
 __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
                                                    const float* __restrict__ meas,
                                                    const int32_t* __restrict__ off,
@@ -92,99 +268,24 @@ __global__ __launch_bounds__(256) void k_fit_mult(const float* __restrict__ T,
     const int lane = threadIdx.x & 63;
     const int64_t wave = wave_id();
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const double dinf = __builtin_huge_val();
-    const float finf = __builtin_huge_valf();
+    const int64_t npairs = (n_groups + 1) >> 1;
     double st[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t g = wave; g < n_groups; g += nwaves) {
-        int64_t a = off[g], b = off[g + 1];
-        a = a < 0 ? 0 : (a > n ? n : a);
-        b = b < a ? a : (b > n ? n : b);
-        double Wt = 0.0;   // total training weight, row order
-        double bx = dinf;
-        int64_t bk = INT64_MAX;
-        float tk = 0.0f, mk = 0.0f;   // the lane's candidate row (the last chunk's)
-        uint8_t trk = 0;
-        for (int64_t k0 = a; k0 < b; k0 += 64) {
-            // this lane's candidate
-            const int64_t k = k0 + lane;
-            float xfk = finf;
-            double xdk = dinf, wk = 0.0;
-            tk = mk = 0.0f;
-            trk = 0;
-            if (k < b) {
-                tk = T[k];
-                mk = meas[k];
-                trk = train[k];
-                if (trk && mult_ok(tk, mk)) {
-                    xfk = mk / tk;
-                    xdk = (double)mk / (double)tk;
-                    wk = (double)tk / (double)mk;
-                }
-            }
-            double C = 0.0;
-            for (int64_t i0 = a; i0 < b; i0 += 64) {
-                // this lane's row (the candidate's own when the chunks coincide)
-                const int64_t i = i0 + lane;
-                float xfi = xfk;
-                double xdi = xdk, wi = wk;
-                if (i0 != k0) {
-                    xfi = finf;
-                    xdi = dinf;
-                    wi = 0.0;
-                    if (i < b) {
-                        const float ti = T[i], mi = meas[i];
-                        if (train[i] && mult_ok(ti, mi)) {
-                            xfi = mi / ti;
-                            xdi = (double)mi / (double)ti;
-                            wi = (double)ti / (double)mi;
-                        }
-                    }
-                }
-                const int cnt = b - i0 < 64 ? (int)(b - i0) : 64;
-                for (int r = 0; r < cnt; ++r) {
-                    const float xf = read_lane_f32(xfi, r);
-                    const double w = read_lane_f64(wi, r);
-                    if (k0 == a) Wt += w;
-                    bool before = xf < xfk;
-                    const bool tie = xf == xfk;
-                    if (__ballot(tie) != 0ull) {
-                        const double xd = read_lane_f64(xdi, r);
-                        if (tie) before = xd < xdk || (xd == xdk && i0 + r <= k);
-                    }
-                    C += before ? w : 0.0;
-                }
-            }
-            if (xdk < dinf && C >= 0.5 * Wt && (xdk < bx || (xdk == bx && k < bk))) {
-                bx = xdk;
-                bk = k;
-            }
+    for (int64_t q = wave; q < npairs; q += nwaves) {
+        const int64_t g0 = 2 * q, g1 = 2 * q + 1 < n_groups ? 2 * q + 1 : -1;
+        int64_t a0, b0, a1 = 0, b1 = 0;
+        group_bounds(off, g0, n, a0, b0);
+        if (g1 >= 0) group_bounds(off, g1, n, a1, b1);
+        if (b0 - a0 <= 32 && b1 - a1 <= 32) {
+            fit_groups_sorted<32>(g0, a0, b0, g1, a1, b1, T, meas, train, mult, T_scaled, st);
+            continue;
         }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            const double ox = __shfl_xor(bx, m, 64);
-            const int64_t ok = __shfl_xor(bk, m, 64);
-            if (ox < bx || (ox == bx && ok < bk)) {
-                bx = ox;
-                bk = ok;
-            }
-        }
-        const double mu = bk == INT64_MAX ? 1.0 : bx;
-        if (lane == 0) mult[g] = mu;
-        // a group of one chunk still has its rows in the candidate registers
-        const bool one = b - a <= 64;
-        for (int64_t i = a + lane; i < b; i += 64) {
-            const double t = one ? tk : T[i], m = one ? mk : meas[i];
-            const bool tr = one ? trk != 0 : train[i] != 0;
-            T_scaled[i] = (float)(mu * t);
-            if (!mult_ok(t, m)) continue;
-            const double e = __builtin_fabs(mu * t - m) / m;
-            if (tr) {
-                st[0] += e;
-                st[1] += 1.0;
-            } else {
-                st[2] += e;
-                st[3] += 1.0;
-            }
+        for (int h = 0; h < 2; ++h) {
+            const int64_t g = h ? g1 : g0, a = h ? a1 : a0, b = h ? b1 : b0;
+            if (g < 0) continue;
+            if (b - a <= 64)
+                fit_groups_sorted<64>(g, a, b, -1, 0, 0, T, meas, train, mult, T_scaled, st);
+            else
+                fit_group_scan(g, a, b, T, meas, train, mult, T_scaled, st);
         }
     }
     // the block's four waves, then one row per block (fixed order)
@@ -224,7 +325,7 @@ __global__ __launch_bounds__(256) void k_fit_mult_reduce(const double* __restric
 
 int fit_mult_grid(int64_t n_groups)
 {
-    const int64_t want = (n_groups + 3) / 4;  // 4 waves per block
+    const int64_t want = ((n_groups + 1) / 2 + 3) / 4;  // a pair of groups per wave, 4 waves per block
     int64_t b = (int64_t)resident_blocks(reinterpret_cast<const void*>(&k_fit_mult), 256) * 2;
     b = b < want ? b : want;
     b = b < kFitMultMaxBlocks ? b : kFitMultMaxBlocks;

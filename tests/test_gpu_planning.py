@@ -91,6 +91,26 @@ def test_multipliers_edge_cases(wmb, orc):
     assert np.array_equal(st.cpu().numpy(), np.zeros(4))
 
 
+def test_multipliers_group_size_limits(wmb, orc):
+    # sizes at the limits of each form: pairs of groups of at most 32 rows
+    # (wave halves), one group of 33-64 rows per wave, the candidate scan
+    # above 64 rows, pairs mixing them, an empty group, and an odd group
+    # count (the last wave's upper half has no group); exact ratio ties and
+    # invalid rows inside the sorted groups
+    rng = np.random.default_rng(11)
+    sizes = [32, 32, 33, 1, 64, 0, 65, 64, 31, 32, 17, 64, 64, 2, 40, 40, 129]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(off[-1])
+    T = rng.uniform(1e-5, 1e-2, n)
+    m = T * rng.choice([0.5, 0.8, 1.0, 1.25, 2.0], n)        # many equal ratios
+    m[off[10]:off[11]] = T[off[10]:off[11]] * rng.uniform(0.5, 2.0, sizes[10])
+    train = (rng.random(n) < 0.75).astype(np.uint8)
+    T[off[4] + 3] = np.nan
+    m[off[7] + 63] = 0.0
+    T[off[0] + 31] = np.inf
+    _check_mult(wmb, orc, T, m, off, train, "size limits")
+
+
 # plan totals and all-singles sums: float32 run costs (the model's prediction
 # tolerance), summed in float64
 PLAN_RTOL = 1e-5
