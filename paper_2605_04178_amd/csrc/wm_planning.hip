@@ -535,7 +535,10 @@ struct FuseArgs {   // k_fuse_costs's parameters, in order
     PlanBufs wb;
 };
 
-__global__ __launch_bounds__(256) void k_fuse_costs(DescPtrs d, const float* __restrict__ edge,
+constexpr int kFuseBlock = 256;   // k_fuse_costs' block: one row per thread
+constexpr int kFuseTileR = 8;     // run lengths up to this many are staged in LDS
+
+__global__ __launch_bounds__(kFuseBlock) void k_fuse_costs(DescPtrs d, const float* __restrict__ edge,
                                                      const int32_t* __restrict__ off,
                                                      int64_t n_chains, int64_t n, int32_t R, Set S,
                                                      Peaks pk, PlanBufs wb)
@@ -544,24 +547,38 @@ __global__ __launch_bounds__(256) void k_fuse_costs(DescPtrs d, const float* __r
     // scalar registers across the run loop
     const Set* sc = WM_KERNARG_PTR(FuseArgs, S);
     const Peaks* pc = WM_KERNARG_PTR(FuseArgs, pk);
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tl = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * kFuseBlock;
+    const int64_t s = s0 + tl;
     if (s == 0) *wb.n_redo = 0u;   // the queue of the planning pass that follows
-    if (s >= n) return;
+    // R <= kFuseTileR: the block's costs are staged in LDS and written out
+    // row by row (consecutive lanes, consecutive addresses); a lane's own
+    // stores to rows s .. s + R - 1 at entry q would touch R * 8-byte pieces
+    // of 64 lines each and leave the L2 as that many partial writes
+    __shared__ double tile[(kFuseBlock + kFuseTileR - 1) * kFuseTileR];
+    __shared__ uint8_t m_s[kFuseBlock], h0_s[kFuseBlock];
+    const bool staged = R <= kFuseTileR;
     // the chain holding s: the last c with off[c] <= s (offsets clamped into
     // [0, n] and non-decreasing)
     auto at = [&](int64_t c) -> int64_t {
         const int64_t v = off[c];
         return v < 0 ? 0 : (v > n ? n : v);
     };
-    int32_t m = 0;
-    if (at(0) <= s) {
+    // h0: row s's entries q >= h0 would end runs that start before its chain
+    // (never read; written +inf when staged, so that the rows go out whole)
+    int32_t m = 0, h0 = 0;
+    if (s < n && at(0) <= s) {
         int64_t lo = 0, hi = n_chains;
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
             if (at(mid) <= s) lo = mid; else hi = mid;
         }
         const int64_t b = at(lo + 1);
-        if (s < b) m = (int32_t)(b - s < (int64_t)R ? b - s : (int64_t)R);
+        if (s < b) {
+            m = (int32_t)(b - s < (int64_t)R ? b - s : (int64_t)R);
+            const int64_t back = s - at(lo) + 1;
+            h0 = back < (int64_t)R ? (int32_t)back : R;
+        }
     }
     const float inf = __builtin_huge_valf();
     FuseSum fs;
@@ -618,9 +635,35 @@ __global__ __launch_bounds__(256) void k_fuse_costs(DescPtrs d, const float* __r
             }
             t = t == t ? t : inf;
         }
-        wb.cost[k * R + q] = (double)t;
+        if (staged) tile[(tl + q) * R + q] = (double)t;
+        else wb.cost[k * R + q] = (double)t;
     }
-    wb.cov[s] = (uint8_t)(m | (unc ? kPlanUncertain : 0));
+    if (s < n) wb.cov[s] = (uint8_t)(m | (unc ? kPlanUncertain : 0));
+    if (!staged) return;
+    if (s < n)
+        for (int32_t q = h0; q < R; ++q) tile[tl * R + q] = __builtin_huge_val();
+    m_s[tl] = (uint8_t)m;
+    h0_s[tl] = (uint8_t)h0;
+    __syncthreads();
+    // Entry (r, q) of a row here comes from the run starting at r - q: from
+    // this tile when q <= r (a run of a start here, or row r's +inf when that
+    // run leaves its chain) or when q >= h0[r] (+inf); the previous block
+    // writes the rest (runs that start in its rows).  r = idx / R exactly
+    // (idx < 2^12, R <= 8: the float quotient is at least 1/16 from an integer).
+    const float inv_r = 1.0f / (float)R;
+    const int64_t left = n - s0;
+    const int nrow = left < kFuseBlock ? (int)left : kFuseBlock;
+    for (int idx = tl; idx < nrow * R; idx += kFuseBlock) {
+        const int r = (int)(((float)idx + 0.5f) * inv_r), q = idx - r * R;
+        if (q <= r || q >= (int)h0_s[r]) wb.cost[s0 * R + idx] = tile[idx];
+    }
+    // runs that start here and end in the next block's first R - 1 rows
+    for (int idx = tl; idx < (R - 1) * R; idx += kFuseBlock) {
+        const int i = (int)(((float)idx + 0.5f) * inv_r), q = idx - i * R;
+        const int st = kFuseBlock + i - q;   // their start, a row here when q > i
+        if (q > i && q < (int)m_s[st] && s0 + kFuseBlock + i < n)
+            wb.cost[(s0 + kFuseBlock + i) * R + q] = tile[(kFuseBlock + i) * R + q];
+    }
 }
 
 // Decision margin below which a float32 plan is re-decided in float64.  A
@@ -1116,8 +1159,8 @@ hipError_t launch_plan_fusion(const DescPtrs& d, const float* edge, const int32_
     int32_t gs = 1;
     while (gs < R) gs <<= 1;   // R <= 32
     // at least one block, so that the queue's length is cleared even with no rows
-    const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
-    k_fuse_costs<<<(unsigned)nb, 256, 0, s>>>(d, edge, off, n_chains, n, R, S, pk, wb);
+    const int64_t nb = n > 0 ? (n + kFuseBlock - 1) / kFuseBlock : 1;
+    k_fuse_costs<<<(unsigned)nb, kFuseBlock, 0, s>>>(d, edge, off, n_chains, n, R, S, pk, wb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = plan_dispatch(gs, off, n_chains, n, R, wb, total, unfused, start, false, s);
