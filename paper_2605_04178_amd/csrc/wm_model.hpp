@@ -407,18 +407,22 @@ __device__ inline void evaluate(const Struct& st, const Const<R>& c, const Desc<
 // The weight is folded into each stage's coefficient once, so every slot
 // costs one multiply-add.  R is the accumulator type too: float for the
 // bulk sweeps (per-lane partial sums, reduced in float64 across lanes,
-// waves and blocks), double for the float64 re-evaluations.
-template <typename R>
-__device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E, R w, R* acc)
+// waves and blocks), double for the float64 re-evaluations.  The split form
+// adds the seven overhead slots (acc[15 .. 21]) into ovh[0 .. 6] instead, so
+// that a sweep can keep those sums apart (in LDS); acc and ovh are anything
+// indexable by slot.
+template <typename R, typename A, typename B>
+__device__ inline void accumulate_partials_split(const Struct& st, const Const<R>& c, const Eval<R>& E, R w, A acc,
+                                                 B ovh)
 {
     // overhead slots: data only
-    acc[2 + 13] += w;
-    acc[2 + 14] += w * (R)E.G;
-    acc[2 + 15] += w * E.nrK;
-    acc[2 + 16] += w * (R)E.cnt[0];
-    acc[2 + 17] += w * (R)E.cnt[1];
-    acc[2 + 18] += w * (R)E.cnt[2];
-    acc[2 + 19] += w * (R)E.cnt[3];
+    ovh[0] += w;
+    ovh[1] += w * (R)E.G;
+    ovh[2] += w * E.nrK;
+    ovh[3] += w * (R)E.cnt[0];
+    ovh[4] += w * (R)E.cnt[1];
+    ovh[5] += w * (R)E.cnt[2];
+    ovh[6] += w * (R)E.cnt[3];
     // compute: d(F/(uP))/dP = -T_c / P
     const R gP = -(w * E.wc) * E.Tc * E.ip;
     acc[2 + 8] += E.dt == 0 ? gP : (R)0;
@@ -449,6 +453,12 @@ __device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, 
     const R gh = dTdh * E.h3 * E.base_log;
     acc[2 + 20] += E.llc_regime == 1 ? gh : (R)0;
     acc[2 + 21] += E.llc_regime == 2 ? gh : (R)0;
+}
+
+template <typename R>
+__device__ inline void accumulate_partials(const Struct& st, const Const<R>& c, const Eval<R>& E, R w, R* acc)
+{
+    accumulate_partials_split<R>(st, c, E, w, acc, acc + 15);
 }
 
 }  // namespace wm

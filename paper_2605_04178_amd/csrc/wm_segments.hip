@@ -178,8 +178,8 @@ __global__ __launch_bounds__(BLOCK) void k_apps(DescPtrs d, SegPtrs sg, int64_t 
 // (the derivatives of the segment time, Eq. (15)).  In MODE 1 a total within
 // 1e-5 of its measurement gets weight 0 here and is flagged for the float64
 // pass (returned in `near`).
-template <int MODE>
-__device__ inline float app_weight(double T, float mv, float* acc, bool& near)
+template <int MODE, typename LC>
+__device__ inline float app_weight(double T, float mv, LC acc, bool& near)
 {
     near = false;
     if (!(T - T == 0.0)) return 0.0f;   // NaN or infinite total
@@ -198,21 +198,31 @@ __device__ inline float app_weight(double T, float mv, float* acc, bool& near)
     return (float)(T > m ? im : (T < m ? -im : 0.0));
 }
 
+// A lane's column of per-lane sums kept in LDS: sum j at p[j * STRIDE], p
+// already offset by the lane (STRIDE = the block size, so the lanes of a wave
+// hit consecutive words).  Only the lane itself touches its column.
+template <int STRIDE>
+struct LdsSums {
+    float* p;
+    __device__ float& operator[](int j) const { return p[j * STRIDE]; }
+};
+
 // One row's terms for an application weight wa != 0 and an evaluated
 // (finite) kernel: the kernel model's Jacobian row times wa n_exec kappa into
-// acc -- or, within 1e-5 of one of its max/min switches, a flag for the
-// float64 pass with that weight kept in wrow[j] -- and the segment-parameter
-// sums into sacc.
+// acc, its seven overhead slots into ovh -- or, within 1e-5 of one of its
+// max/min switches, a flag for the float64 pass with that weight kept in
+// wrow[j] -- and the segment-parameter sums into sacc.
+template <typename OV, typename SA>
 __device__ inline void app_row_terms(const Struct& st, const Const<float>& cf, const SegConst<float>& qf,
                                      const Eval<float>& E, const SegRow& r, float wa, int64_t j, float* acc,
-                                     float* sacc, uint64_t* rflags, float* wrow)
+                                     OV ovh, SA sacc, uint64_t* rflags, float* wrow)
 {
     const float wr = wa * r.ne * kappa_of(qf, r.c);
     if (E.near_kink) {
         wrow[j] = wr;
         atomicOr((unsigned long long*)(rflags + (j >> 6)), 1ull << (j & 63));
     } else {
-        accumulate_partials<float>(st, cf, E, wr, acc);
+        accumulate_partials_split<float>(st, cf, E, wr, acc, ovh);
     }
     sacc[0] += wa * (r.ne * (float)(r.nk - 1));
     const float v = wa * (r.ne * E.T);
@@ -246,13 +256,15 @@ __device__ inline double block_total(double v, double* lds /* [BLOCK / 64] */)
 }
 
 // The block's kAppRow float64 sums of the lanes' float32 partial sums: the 26
-// loss / count / theta columns by the recursive-halving block reduction, the
-// eight segment sums by a plain one (fixed order throughout).
-__device__ inline void store_row(const float* acc, const float* sacc, double* lds, double* row)
+// loss / count / theta columns (slots 0 and 1 from lc, 15 .. 21 from ovh, the
+// rest from acc) by the recursive-halving block reduction, the eight segment
+// sums by a plain one (fixed order throughout).
+template <typename LC, typename OV, typename SA>
+__device__ inline void store_row(const float* acc, LC lc, OV ovh, SA sacc, double* lds, double* row)
 {
     double a64[kAcc];
 #pragma unroll
-    for (int j = 0; j < kAcc; ++j) a64[j] = (double)acc[j];
+    for (int j = 0; j < kAcc; ++j) a64[j] = (double)(j < 2 ? lc[j] : (j >= 15 && j <= 21 ? ovh[j - 15] : acc[j]));
     block_reduce_acc(a64, lds, row);
     double s64[8];
 #pragma unroll
@@ -271,14 +283,16 @@ __device__ inline void store_row(const float* acc, const float* sacc, double* ld
 // rflags (one bit per row; cleared before the launch) with their weight in
 // wrow; near-T = m applications (MODE 1) in aflags (one ballot word per 64
 // applications, written once).  Per block one row of kAppRow float64 sums:
-// loss, count, theta gradient, segment-parameter sums.
+// loss, count, theta gradient, segment-parameter sums.  Of the lane's float32
+// partial sums, the loss and count, the seven overhead slots and the eight
+// segment sums sit in LDS columns (they take one add per row or per
+// application), the other 17 in registers: 95 VGPRs, five waves per SIMD
+// (101 and four with all of them in registers).
 template <int BLOCK, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int64_t n_seg,
-                                                    int64_t n_apps, Set S, SegSet Q,
-                                                    const float* __restrict__ meas,
-                                                    double* __restrict__ rows, uint64_t* __restrict__ aflags,
-                                                    uint64_t* __restrict__ lflags, uint64_t* __restrict__ rflags,
-                                                    float* __restrict__ wrow)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
+void k_apps_grad(DescPtrs d, SegPtrs sg, int64_t n_seg, int64_t n_apps, Set S, SegSet Q,
+                 const float* __restrict__ meas, double* __restrict__ rows, uint64_t* __restrict__ aflags,
+                 uint64_t* __restrict__ lflags, uint64_t* __restrict__ rflags, float* __restrict__ wrow)
 {
     __shared__ float ts[BLOCK];
     __shared__ uint16_t own[BLOCK];
@@ -287,12 +301,18 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
     __shared__ double red[(BLOCK / 64) * kAppRow];
     const Set* sc = WM_KERNARG_PTR(AppsArgs, S);
     const SegSet* qc = WM_KERNARG_PTR(AppsArgs, Q);
-    float acc[kAcc], sacc[8];   // the lane's partial sums; float64 from the block reduction on
+    __shared__ float sacc_s[8 * BLOCK], lc_s[2 * BLOCK], ov_s[7 * BLOCK];
+    float acc[kAcc];   // the lane's partial sums; float64 from the block reduction on
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0f;
+    const int tid = threadIdx.x;
+    const LdsSums<BLOCK> sacc{sacc_s + tid}, lc{lc_s + tid}, ovh{ov_s + tid};
 #pragma unroll
     for (int j = 0; j < 8; ++j) sacc[j] = 0.0f;
-    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) lc[j] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) ovh[j] = 0.0f;
     const float inf = __builtin_huge_valf();
     const int64_t nchunks = (n_apps + BLOCK - 1) / BLOCK;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
@@ -365,7 +385,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
                 for (; k < je; ++k) T += (double)ts[k - p0];
                 for (k = jb; k < je; ++k) own[k - p0] = (uint16_t)tid;
                 bool nr;
-                wa_s[tid] = app_weight<MODE>(T, mv, acc, nr);
+                wa_s[tid] = app_weight<MODE>(T, mv, lc, nr);
                 near_mine = near_mine || nr;
             }
             __syncthreads();
@@ -373,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
                 const float wa = wa_s[own[tid]];
                 if (wa != 0.0f && E.T < inf) {
                     const Set& Sx = uniform_const(sc);
-                    app_row_terms(Sx.st, Sx.cf, uniform_const(qc).f, E, r, wa, j, acc, sacc, rflags, wrow);
+                    app_row_terms(Sx.st, Sx.cf, uniform_const(qc).f, E, r, wa, j, acc, ovh, sacc, rflags, wrow);
                 }
             }
             __syncthreads();   // ts, own and wa_s are rewritten by the next piece
@@ -387,7 +407,7 @@ __global__ __launch_bounds__(BLOCK) void k_apps_grad(DescPtrs d, SegPtrs sg, int
         }
         __syncthreads();   // lo_s / hi_s are rewritten by the next chunk
     }
-    store_row(acc, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
+    store_row(acc, lc, ovh, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
 }
 
 // Applications longer than a piece (flagged in lflags by the sweep), one at
@@ -448,13 +468,13 @@ __global__ __launch_bounds__(256) void k_apps_long(DescPtrs d, SegPtrs sg, int64
             for (int64_t j = lo + threadIdx.x; j < hi; j += 256) {
                 Eval<float> E;
                 evaluate<float, true>(S.st, S.cf, load_desc(d, j), E);
-                if (E.T < inf) app_row_terms(S.st, S.cf, Q.f, E, load_seg(sg, j), wa, j, acc, sacc, rflags, wrow);
+                if (E.T < inf) app_row_terms(S.st, S.cf, Q.f, E, load_seg(sg, j), wa, j, acc, acc + 15, sacc, rflags, wrow);
             }
         }
         }
         __syncthreads();   // words[] is rewritten by the next group
     }
-    store_row(acc, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
+    store_row(acc, acc, acc + 15, sacc, red, rows + (int64_t)blockIdx.x * kAppRow);
 }
 
 // Block sum of kAppRow float64 accumulators (fixed order): the first 26 by
