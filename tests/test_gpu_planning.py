@@ -140,7 +140,7 @@ def _check_plan(wmb, orc, p, off, d, e, R, tag):
     return tot, unf, st
 
 
-@pytest.mark.parametrize("R", [1, 4, 8, 32])
+@pytest.mark.parametrize("R", [1, 3, 4, 6, 8, 32])
 def test_fusion_plan_parity(wmb, orc, R):
     p = synth.param_set(2)
     off, d, e = synth.chains(3000, 162)
